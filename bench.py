@@ -1,0 +1,160 @@
+"""Throughput of the fused reduced ES-BGK + rotational-energy LB step on one GPU.
+
+Workload (default): 3D Taylor-Green vortex on 256^3 bcc cells
+(33,554,432 sites), Ma = 0.1, Re = 1600, delta = 2 (gamma = 7/5), Pr = 0.71,
+mu_b/mu = 0.6; populations stored in FP32 as deviations from the rest
+weights, per-site solve and reductions in FP64; CN reading, F3 equilibrium.
+Synthetic analytic initial field, resident in HBM before the timed region.
+
+Prints one JSON line.  MLUPS = 1e-6 x site updates per second (a cell holds
+two sites).  The roofline object is for the dominant kernel (the fused
+pull-collide kernel), timed live with HIP events on its own stream.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+THETA0 = 0.2948964908710633
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS + % of HBM roofline (fused step)"
+
+
+def algorithmic_bytes(precision):
+    """Bytes the method must move per site update.
+
+    Whole step: every population read and written once (2 x 41 x elt) and
+    theta_R read and written once (2 x 8).  Fused pull-collide kernel alone:
+    the populations plus the theta_R read.
+    """
+    elt = 4 if precision == 1 else 8
+    return dict(step=2 * 41 * elt + 16, k_lb=2 * 41 * elt + 8)
+
+
+def tgv_params(n, Ma=0.1, Re=1600.0, gamma=1.4):
+    U = Ma * math.sqrt(gamma * THETA0)
+    nu = U * (n / (2 * math.pi)) / Re
+    return U, nu
+
+
+def cpu_baseline(n_cpu, steps_cpu):
+    import numpy as np  # noqa: F401
+
+    import oracle
+    from oracle.params import resolve
+    from paper_2201_05280_amd import inputs
+    U, nu = tgv_params(n_cpu)
+    p = resolve(nu, 0.71, 0.6, 2.0)
+    o = oracle.Oracle(n_cpu, n_cpu, n_cpu)
+    o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    f = inputs.taylor_green(n_cpu, U)
+    o.init(f["rho"], f["u"], f["thT"], f["thR"])
+    o.step(1)  # first touch
+    t0 = time.perf_counter()
+    o.step(steps_cpu)
+    dt = time.perf_counter() - t0
+    ns = 2 * n_cpu ** 3
+    return dict(value=ns * steps_cpu / dt / 1e6, unit="MLUPS", cores=oracle.threads(), kind="oracle",
+                sample="Taylor-Green %d^3 cells (%d sites, same Ma and Re), FP64 oracle, %d steps, %.1f s"
+                       % (n_cpu, ns, steps_cpu, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256, help="cells per axis")
+    ap.add_argument("--precision", choices=["fp32dev", "fp64"], default="fp32dev")
+    ap.add_argument("--cpu-n", type=int, default=64)
+    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the z-slab decomposition is a design note); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2201_05280_amd as pgk
+    from paper_2201_05280_amd import inputs
+
+    precision = pgk.FP32DEV if args.precision == "fp32dev" else pgk.FP64
+    n = args.n
+    U, nu = tgv_params(n)
+    p = pgk.resolve(nu, 0.71, 0.6, 2.0)
+    print("# resolved", {k: round(v, 6) for k, v in p.items()}, file=sys.stderr, flush=True)
+    s = pgk.Solver(n, n, n, precision=precision)
+    s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    f = inputs.taylor_green(n, U)
+    s.init(f["rho"], f["u"], f["thT"], f["thR"])
+    del f
+    ns = s.ns
+    print("# init done, %d sites" % ns, file=sys.stderr, flush=True)
+
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    c0 = s.conserved()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = s.kernel_times()
+    s.set_timing(False)
+    c1 = s.conserved()
+    print("# timed %d steps in %.3f s; kernels %s" % (args.steps, dt, kt), file=sys.stderr, flush=True)
+
+    ms_step = 1e3 * dt / args.steps
+    mlups = ns * args.steps / dt / 1e6
+    ab = algorithmic_bytes(precision)
+    lb_ms, lb_n = kt["k_lb"]
+    lb_avg_s = lb_ms / lb_n / 1e3
+    achieved = ab["k_lb"] * ns / lb_avg_s / 1e9
+    step_gbs = ab["step"] * ns / (dt / args.steps) / 1e9
+    drift = [(c1[i] - c0[i]) / c0[0] for i in range(4)] + [(c1[4] - c0[4]) / c0[4]]
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if precision == pgk.FP32DEV else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "3D Taylor-Green vortex, %d^3 bcc cells (%d sites), Ma 0.1, Re 1600, "
+                        "delta 2, Pr 0.71, mu_b/mu 0.6, %s populations, CN, F3" % (n, ns, args.precision),
+            "cells": n ** 3, "sites": ns, "tau": p["tau"], "tau1": p["tau1"], "b": p["b"], "k_r": p["kr"],
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": "k_lb (fused pull-moments-solve-F3-collide)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_site": ab["k_lb"], "avg_launch_ms": round(lb_avg_s * 1e3, 4),
+        },
+        "step_roofline": {"algorithmic_bytes_per_site": ab["step"], "achieved_GBs": round(step_gbs, 1),
+                          "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
+        "kernels_ms_avg": {k: round(v[0] / max(v[1], 1), 4) for k, v in kt.items()},
+        "conservation_drift": drift,
+    }
+    s.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * pgk.h -- C ABI of the MI355X library for the reduced polyatomic ES-BGK
+ * lattice-Boltzmann step (Kolluru, Atif & Ansumali, "Reduced kinetic model of
+ * polyatomic gases", arXiv:2201.05280).
+ *
+ * One step advances, on a body-centred-cubic grid with the 41-velocity RD3Q41
+ * set (Sec. 5, Table of velocities and weights):
+ *   - the auxiliary populations g_i = f_i - (dt/2) Omega_i of the translational
+ *     distribution (Sec. 5, trapezoid rule), whose collision relaxes f towards
+ *     an ES-BGK target at rate 1/tau and a BGK target at rate 1/tau1 (Sec. 4,
+ *     kinetic equation of the reduced model), followed by pull streaming;
+ *   - the rotational temperature theta_R, split into half relaxation,
+ *     MacCormack advection, FTCS diffusion and a second half relaxation
+ *     (Sec. 5, the four steps of the theta_Rot solver).
+ *
+ * Conventions
+ *   status    every call returns PGK_OK (0) or a negative PGK_E* code; the
+ *             context keeps a message for pgk_last_error().  Nothing throws.
+ *   sites     a grid of nx*ny*nz cells holds ns = 2*nx*ny*nz sites: corner
+ *             sites (sub 0) at integer positions and body-centre sites (sub 1)
+ *             offset by (1/2,1/2,1/2).  Every per-site array is ordered
+ *             [sub][z][y][x] (x fastest); vector fields are [3][ns] and the
+ *             pressure tensor [6][ns] (xx, yy, zz, xy, xz, yz).
+ *   memory    the caller owns every buffer.  pgk_buffer_sizes() tells how many
+ *             bytes each of the PGK_NBUF device buffers needs; the caller
+ *             allocates them (e.g. as torch tensors) and hands them over with
+ *             pgk_bind().  The library allocates no device memory and never
+ *             frees caller memory.  Field arrays passed to pgk_init_fields()
+ *             and pgk_read_moments() are device pointers to doubles.
+ *   streams   all work is enqueued on the HIP stream given to pgk_create()
+ *             (0 = the null stream); calls return before the work finishes,
+ *             except pgk_conserved() and the error checks it implies.
+ *   threads   one context per host thread at a time.
+ */
+#ifndef PGK_H
+#define PGK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PGK_OK           0
+#define PGK_EINVAL      -1   /* bad argument (null pointer, size, enum value) */
+#define PGK_ENOMEM      -2   /* a bound buffer is too small */
+#define PGK_EDEVICE     -3   /* a HIP call failed */
+#define PGK_EINFEASIBLE -4   /* requested transport coefficients cannot be reached */
+#define PGK_ENOTBOUND   -6   /* buffers not bound yet */
+
+/* population storage (Sec. 5 populations; the FP32 form stores deviations) */
+#define PGK_FP64     0       /* g_i in double precision */
+#define PGK_FP32DEV  1       /* h_i = g_i - w_i in single precision; moments,
+                                per-site solve and reductions in double */
+
+/* second half of the theta_R relaxation and the diffusion form */
+#define PGK_CN   0           /* explicit complement of the first half (Crank-Nicolson
+                                overall) and flux-form diffusion: the exchange with the
+                                translational energy conserves E_T + E_R exactly */
+#define PGK_LIT  1           /* backward Euler and D_R lap(theta_R), as printed */
+
+/* discrete equilibrium (Sec. 5 leaves it open) */
+#define PGK_F3   0           /* third-order Hermite projection of the anisotropic Gaussian */
+
+/* boundary kinds of the two x faces (y and z are periodic) */
+#define PGK_PERIODIC   0
+#define PGK_WALL       1     /* diffuse (Maxwell) wall at u_w, theta_w */
+#define PGK_DIRICHLET  2     /* equilibrium ghost state rho, u, theta */
+
+/* device buffers the caller allocates */
+#define PGK_BUF_POP0   0     /* 41*ns populations (ping) */
+#define PGK_BUF_POP1   1     /* 41*ns populations (pong) */
+#define PGK_BUF_THETAR 2     /* ns doubles: theta_R */
+#define PGK_BUF_AUX    3     /* per-site fields handed from the collision to the theta_R
+                                transport, reduction partials, wall densities */
+#define PGK_NBUF       4
+
+typedef struct pgk_ctx pgk_ctx;
+
+typedef struct {
+    int nx, ny, nz;          /* cells per axis, each >= 1 */
+    int precision;           /* PGK_FP64 | PGK_FP32DEV */
+    int variant;             /* PGK_CN | PGK_LIT */
+    int equilibrium;         /* PGK_F3 */
+    int bc_x[2];             /* kind of the low and high x faces */
+} pgk_grid;
+
+/* The model parameters of Sec. 4: relaxation times tau (ES-BGK part) and tau1
+ * (BGK part and rotational relaxation), ES parameter b, k_r = kappa_R/kappa_T,
+ * rotational degrees of freedom delta, lattice reference temperature theta0
+ * (0 selects the printed value 0.2948964908710633). */
+typedef struct {
+    double tau, tau1, b, kr, delta, theta0;
+} pgk_params;
+
+/* Targets for the parameter map of Sec. 4 (hydrodynamics): kinematic shear
+ * viscosity nu = eta/rho at theta0, Prandtl number, bulk-to-shear viscosity
+ * ratio, rotational dof.  b and kr may be NaN (free) or fixed. */
+typedef struct {
+    double nu, Pr, mub_over_mu, delta, b, kr, theta0;
+} pgk_targets;
+
+/* derived constants of one step (filled by pgk_resolve / pgk_set_params) */
+typedef struct {
+    double tau, tau1, b, kr, delta, theta0;
+    double tau_star;         /* 1/tau* = 1/tau + 1/tau1 */
+    double beta;             /* dt/(2 tau* + dt) */
+    double X, Y;             /* 3/(2 tau1 (3+delta)), delta/(2 tau1 (3+delta)) */
+    double s_sigma;          /* sigma(g) = sigma(f) s_sigma */
+    double B;                /* 1 + tau/tau1 */
+    double nu, mub_over_mu, Pr, gamma;  /* transport coefficients these imply */
+    double D_R;              /* rotational diffusivity 2 kappa_R/(rho delta) at theta0 */
+} pgk_resolved;
+
+/* Parameter map (Sec. 4, shear and bulk viscosity, Prandtl number).  Rule when
+ * b is NaN: start from k_r = delta/5 (or the fixed kr), solve b from Pr, clamp b
+ * to the ES range [-1/2, 1] (Sec. 2), then tau1/tau from the viscosity ratio,
+ * k_r from Pr and tau from nu.  Returns PGK_EINFEASIBLE when mub_over_mu is at
+ * or below the floor 2 delta / (3 (3+delta)) or k_r would be negative.  Host only. */
+int pgk_resolve(const pgk_targets *t, pgk_resolved *out);
+
+/* Bytes needed for each device buffer of this grid. */
+int pgk_buffer_sizes(const pgk_grid *g, size_t sizes[PGK_NBUF]);
+
+/* Create a context for grid g on HIP stream `stream` (a hipStream_t, may be 0). */
+int pgk_create(const pgk_grid *g, void *stream, pgk_ctx **out);
+
+/* Bind caller-allocated device buffers (see PGK_BUF_*); bytes[] are their sizes. */
+int pgk_bind(pgk_ctx *ctx, void *const bufs[PGK_NBUF], const size_t bytes[PGK_NBUF]);
+
+/* Set the resolved parameters; `out` (may be NULL) receives the derived constants.
+ * Returns PGK_EINVAL for tau, tau1 <= 0, delta < 0 or b outside [-1/2, 1]. */
+int pgk_set_params(pgk_ctx *ctx, const pgk_params *p, pgk_resolved *out);
+
+/* Boundary data of x face `side` (0 low, 1 high): wall velocity and temperature
+ * for PGK_WALL (rho ignored), ghost state for PGK_DIRICHLET. */
+int pgk_set_bc_x(pgk_ctx *ctx, int side, double rho, const double u[3], double theta);
+
+/* Initial state from device fields rho[ns], u[3][ns], theta_T[ns], theta_R[ns]:
+ * g_i = F_i(rho, u, theta_T I) and the rotational temperature theta_R. */
+int pgk_init_fields(pgk_ctx *ctx, const double *rho, const double *u,
+                    const double *theta_T, const double *theta_R);
+
+/* Advance n time steps (asynchronous on the context stream). */
+int pgk_step(pgk_ctx *ctx, int64_t n);
+
+/* Moments of the translational distribution f at the current time level
+ * (after the g -> f map of Sec. 5) into device arrays; any pointer may be
+ * NULL.  theta_T is theta_T(f), theta_R the stored rotational temperature,
+ * P the pressure tensor of f. */
+int pgk_read_moments(pgk_ctx *ctx, double *rho, double *u, double *theta_T,
+                     double *theta_R, double *P);
+
+/* Totals over the grid at the current time level: mass, momentum (3) and
+ * total energy sum(1/2 sum_i g_i c_i^2 + delta rho theta_R / 2).  Synchronises
+ * the context stream; `out` is host memory. */
+int pgk_conserved(pgk_ctx *ctx, double out[5]);
+
+/* Per-kernel timing with HIP events on the context stream.  While enabled,
+ * pgk_step records an event before its first launch and after every launch.
+ * pgk_kernel_times() waits for the stream, returns the summed milliseconds and
+ * the launch counts of [0] the fused pull-collide kernel, [1] the MacCormack
+ * advection, [2] the diffusion and second half relaxation, [3] the x ghost
+ * fill, and clears the record.  Event handles are created on demand and kept
+ * until pgk_destroy. */
+#define PGK_NKERNEL 4
+int pgk_set_timing(pgk_ctx *ctx, int enable);
+int pgk_kernel_times(pgk_ctx *ctx, double ms[PGK_NKERNEL], int64_t launches[PGK_NKERNEL]);
+
+/* Steps taken since the last pgk_init_fields. */
+int64_t pgk_steps_done(const pgk_ctx *ctx);
+
+/* Message of the last failed call on this context (never NULL). */
+const char *pgk_last_error(const pgk_ctx *ctx);
+
+void pgk_destroy(pgk_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PGK_H */

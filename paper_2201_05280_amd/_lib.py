@@ -1,0 +1,115 @@
+"""ctypes binding of libpgk.so (the C ABI declared in include/pgk.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of the library.  Importing this module does not need a GPU; loading the
+library does need the built libpgk.so, and creating a solver needs a HIP
+device.  There is no fallback: a missing library or device raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpgk.so")
+
+PGK_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EINFEASIBLE", -6: "ENOTBOUND"}
+FP64, FP32DEV = 0, 1
+CN, LIT = 0, 1
+F3 = 0
+PERIODIC, WALL, DIRICHLET = 0, 1, 2
+NBUF = 4
+
+# every symbol include/pgk.h declares
+EXPORTS = ["pgk_resolve", "pgk_buffer_sizes", "pgk_create", "pgk_bind", "pgk_set_params",
+           "pgk_set_bc_x", "pgk_init_fields", "pgk_step", "pgk_read_moments", "pgk_conserved",
+           "pgk_set_timing", "pgk_kernel_times", "pgk_steps_done", "pgk_last_error", "pgk_destroy"]
+NKERNEL = 4
+KERNEL_NAMES = ["k_lb", "k_mc", "k_dif", "k_bc"]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("precision", ctypes.c_int), ("variant", ctypes.c_int), ("equilibrium", ctypes.c_int),
+                ("bc_x", ctypes.c_int * 2)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("tau", "tau1", "b", "kr", "delta", "theta0")]
+
+
+class Targets(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("nu", "Pr", "mub_over_mu", "delta", "b", "kr", "theta0")]
+
+
+class Resolved(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "tau", "tau1", "b", "kr", "delta", "theta0", "tau_star", "beta", "X", "Y", "s_sigma", "B",
+        "nu", "mub_over_mu", "Pr", "gamma", "D_R")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libpgk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libpgk.so is not built: run `python -m paper_2201_05280_amd.build` "
+                           "(or __graft_entry__.build()) first")
+    # torch ships its own HIP runtime under the same soname as /opt/rocm's;
+    # let torch load and initialise it first so that one runtime serves both
+    import torch
+    if torch.cuda.is_available():
+        torch.cuda.init()
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64
+    sz = ctypes.c_size_t
+    L.pgk_resolve.argtypes = [ctypes.POINTER(Targets), ctypes.POINTER(Resolved)]
+    L.pgk_buffer_sizes.argtypes = [ctypes.POINTER(Grid), sz * NBUF]
+    L.pgk_create.argtypes = [ctypes.POINTER(Grid), vp, ctypes.POINTER(vp)]
+    L.pgk_bind.argtypes = [vp, vp * NBUF, sz * NBUF]
+    L.pgk_set_params.argtypes = [vp, ctypes.POINTER(Params), ctypes.POINTER(Resolved)]
+    L.pgk_set_bc_x.argtypes = [vp, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double]
+    L.pgk_init_fields.argtypes = [vp, vp, vp, vp, vp]
+    L.pgk_step.argtypes = [vp, i64]
+    L.pgk_read_moments.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.pgk_conserved.argtypes = [vp, dp]
+    L.pgk_set_timing.argtypes = [vp, ctypes.c_int]
+    L.pgk_kernel_times.argtypes = [vp, ctypes.c_double * NKERNEL, ctypes.c_int64 * NKERNEL]
+    L.pgk_steps_done.argtypes = [vp]
+    L.pgk_steps_done.restype = i64
+    L.pgk_last_error.argtypes = [vp]
+    L.pgk_last_error.restype = ctypes.c_char_p
+    L.pgk_destroy.argtypes = [vp]
+    L.pgk_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("pgk_steps_done", "pgk_last_error", "pgk_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def resolve(nu, Pr, mub_over_mu, delta, b=float("nan"), kr=float("nan"), theta0=0.0):
+    """Parameter map of the library (host only): targets -> resolved constants."""
+    L = load()
+    t = Targets(nu, Pr, mub_over_mu, delta, b, kr, theta0)
+    r = Resolved()
+    rc = L.pgk_resolve(ctypes.byref(t), ctypes.byref(r))
+    if rc != PGK_OK:
+        raise ValueError("pgk_resolve failed: %s" % ERRORS.get(rc, rc))
+    return r.as_dict()
+
+
+def buffer_sizes(nx, ny, nz, precision=FP64, variant=CN, bc_x=(PERIODIC, PERIODIC)):
+    L = load()
+    g = Grid(nx, ny, nz, precision, variant, F3, (ctypes.c_int * 2)(*bc_x))
+    out = (ctypes.c_size_t * NBUF)()
+    rc = L.pgk_buffer_sizes(ctypes.byref(g), out)
+    if rc != PGK_OK:
+        raise ValueError("bad grid: %s" % ERRORS.get(rc, rc))
+    return list(out)

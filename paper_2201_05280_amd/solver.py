@@ -1,0 +1,136 @@
+"""Python front end of the HIP library: device buffers and streams from torch.
+
+Every numerical step runs inside libpgk.so; this class only allocates the
+device buffers the library asks for (as torch tensors), passes pointers, and
+moves numpy fields to and from the device.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import CN, FP64, PERIODIC
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device: the reduced ES-BGK solver runs only on the GPU")
+    return torch
+
+
+class Solver:
+    """One grid of nx*ny*nz bcc cells (2 sites per cell) on one GPU.
+
+    precision: _lib.FP64 or _lib.FP32DEV; variant: _lib.CN or _lib.LIT;
+    bc_x: kinds of the low and high x faces (y and z are periodic).
+    """
+
+    def __init__(self, nx, ny, nz, precision=FP64, variant=CN, bc_x=(PERIODIC, PERIODIC),
+                 device=0, stream=None):
+        torch = _torch()
+        self.torch = torch
+        self.L = _lib.load()
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.ns = 2 * nx * ny * nz
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        g = _lib.Grid(nx, ny, nz, precision, variant, _lib.F3, (ctypes.c_int * 2)(*bc_x))
+        sizes = (ctypes.c_size_t * _lib.NBUF)()
+        self._check(self.L.pgk_buffer_sizes(ctypes.byref(g), sizes), None)
+        h = ctypes.c_void_p()
+        self._check(self.L.pgk_create(ctypes.byref(g), ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(h)), None)
+        self.h = h
+        # caller-owned device memory: raw byte tensors
+        self.bufs = [torch.empty(int(n), dtype=torch.uint8, device=self.device) for n in sizes]
+        ptrs = (ctypes.c_void_p * _lib.NBUF)(*[b.data_ptr() for b in self.bufs])
+        self._check(self.L.pgk_bind(self.h, ptrs, sizes))
+        self.resolved = None
+
+    def _check(self, rc, h="self"):
+        if rc != _lib.PGK_OK:
+            msg = ""
+            if h is not None and getattr(self, "h", None):
+                msg = self.L.pgk_last_error(self.h).decode()
+            raise RuntimeError("pgk error %s: %s" % (_lib.ERRORS.get(rc, rc), msg))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.torch.cuda.synchronize(self.device)
+            self.L.pgk_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- setup -----------------------------------------------------------
+    def set_params(self, tau, tau1, b, kr, delta, theta0=0.0):
+        p = _lib.Params(tau, tau1, b, kr, delta, theta0)
+        r = _lib.Resolved()
+        self._check(self.L.pgk_set_params(self.h, ctypes.byref(p), ctypes.byref(r)))
+        self.resolved = r.as_dict()
+        return self.resolved
+
+    def set_bc_x(self, side, rho=1.0, u=(0.0, 0.0, 0.0), theta=0.2948964908710633):
+        uu = (ctypes.c_double * 3)(*u)
+        self._check(self.L.pgk_set_bc_x(self.h, side, float(rho), uu, float(theta)))
+
+    def _dev(self, a, shape):
+        t = self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(shape),
+                                 device=self.device)
+        return t.contiguous()
+
+    def init(self, rho, u, thT, thR):
+        ns = self.ns
+        f = [self._dev(rho, (ns,)), self._dev(u, (3, ns)), self._dev(thT, (ns,)), self._dev(thR, (ns,))]
+        with self.torch.cuda.stream(self.stream):
+            self._check(self.L.pgk_init_fields(self.h, *[t.data_ptr() for t in f]))
+        self.stream.synchronize()
+
+    def init_device(self, rho, u, thT, thR):
+        """Fields already on the device (float64 tensors)."""
+        self._check(self.L.pgk_init_fields(self.h, rho.data_ptr(), u.data_ptr(), thT.data_ptr(),
+                                           thR.data_ptr()))
+
+    # ---- run -------------------------------------------------------------
+    def step(self, n=1):
+        self._check(self.L.pgk_step(self.h, int(n)))
+
+    def set_timing(self, enable=True):
+        self._check(self.L.pgk_set_timing(self.h, 1 if enable else 0))
+
+    def kernel_times(self):
+        """{kernel: (total ms, launches)} since timing was enabled or last read."""
+        ms = (ctypes.c_double * _lib.NKERNEL)()
+        n = (ctypes.c_int64 * _lib.NKERNEL)()
+        self._check(self.L.pgk_kernel_times(self.h, ms, n))
+        return {name: (ms[i], int(n[i])) for i, name in enumerate(_lib.KERNEL_NAMES)}
+
+    def steps_done(self):
+        return int(self.L.pgk_steps_done(self.h))
+
+    def moments_device(self):
+        torch, ns = self.torch, self.ns
+        out = dict(rho=torch.empty(ns, dtype=torch.float64, device=self.device),
+                   u=torch.empty(3, ns, dtype=torch.float64, device=self.device),
+                   thT=torch.empty(ns, dtype=torch.float64, device=self.device),
+                   thR=torch.empty(ns, dtype=torch.float64, device=self.device),
+                   P=torch.empty(6, ns, dtype=torch.float64, device=self.device))
+        self._check(self.L.pgk_read_moments(self.h, out["rho"].data_ptr(), out["u"].data_ptr(),
+                                            out["thT"].data_ptr(), out["thR"].data_ptr(),
+                                            out["P"].data_ptr()))
+        return out
+
+    def moments(self):
+        d = self.moments_device()
+        self.stream.synchronize()
+        return {k: v.cpu().numpy() for k, v in d.items()}
+
+    def conserved(self):
+        out = (ctypes.c_double * 5)()
+        self._check(self.L.pgk_conserved(self.h, out))
+        return np.array(list(out))

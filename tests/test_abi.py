@@ -1,0 +1,98 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, and its parameter map and argument checks behave (no GPU needed)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2201_05280_amd import _lib
+from tests.conftest import ROOT, read_golden
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pgk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pgk_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.load()
+    names = _declared()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_resolver_matches_shear_wave_parameters():
+    r = _lib.resolve(0.01, 0.71, 0.6, 2.0)
+    assert abs(r["tau"] - 0.091558) < 1e-6
+    assert abs(r["tau1"] - 0.076298) < 1e-6
+    assert r["b"] == -0.5
+    assert abs(r["kr"] - 0.606677) < 1e-6
+    assert abs(2 * r["beta"] - 1.846323) < 1e-6
+    assert abs(r["X"] - 3.931953) < 1e-6
+    assert abs(r["D_R"] - 0.018614) < 1e-6
+    assert abs(r["nu"] - 0.01) < 1e-15 and abs(r["Pr"] - 0.71) < 1e-14
+    assert abs(r["mub_over_mu"] - 0.6) < 1e-14 and abs(r["gamma"] - 1.4) < 1e-15
+
+
+def test_resolver_landau_table_case():
+    # tau = 3 tau1/5, k_r = 0: eta_b/eta = 224/(225 Pr) and La/Kn as printed
+    for Pr, La in read_golden("landau_table.txt"):
+        Pr, La = float(Pr), float(La)
+        lb = 224.0 / (225.0 * Pr)
+        # fix b so that tau/tau1 = 0.6: B = 1.6, b = B - 1.4 B / Pr
+        b = 1.6 - 1.6 * 1.4 / Pr
+        if b > 1.0:
+            # the printed cases Pr = 5, 10 need b > 1, outside the ES range
+            with pytest.raises(ValueError):
+                _lib.resolve(0.01, Pr, lb, 2.0, b=b)
+            continue
+        r = _lib.resolve(0.01, Pr, lb, 2.0, b=b)
+        assert abs(r["tau"] / r["tau1"] - 0.6) < 1e-12
+        assert abs(r["kr"]) < 1e-12
+        la = 1e-3 * (4 / 3 + r["mub_over_mu"]) + 1e-3 * (r["gamma"] - 1) / r["Pr"]
+        assert abs(la - La) < 0.5e-7
+
+
+def test_resolver_rejects_infeasible():
+    with pytest.raises(ValueError):
+        _lib.resolve(0.01, 0.71, 0.2, 2.0)       # below the floor 4/15
+    with pytest.raises(ValueError):
+        _lib.resolve(-1.0, 0.71, 0.6, 2.0)
+
+
+def test_buffer_sizes_and_bad_grids():
+    s = _lib.buffer_sizes(64, 64, 1, precision=_lib.FP32DEV)
+    ns = 2 * 64 * 64
+    assert s[0] == s[1] == 41 * ns * 4
+    assert s[2] == ns * 8
+    s64 = _lib.buffer_sizes(64, 64, 1, precision=_lib.FP64)
+    assert s64[0] == 41 * ns * 8
+    with pytest.raises(ValueError):
+        _lib.buffer_sizes(0, 4, 4)
+    with pytest.raises(ValueError):
+        _lib.buffer_sizes(8, 1, 1, bc_x=(_lib.WALL, _lib.PERIODIC))   # faces must pair
+    with pytest.raises(ValueError):
+        _lib.buffer_sizes(8, 1, 1, precision=7)
+
+
+def test_null_arguments_are_errors_not_crashes():
+    L = _lib.load()
+    assert L.pgk_create(None, None, None) == -1
+    assert L.pgk_step(None, 1) == -1
+    assert L.pgk_conserved(None, None) == -1
+    assert L.pgk_last_error(None) == b"null context"
+    out = ctypes.c_void_p()
+    g = _lib.Grid(4, 4, 4, 0, 0, 0, (ctypes.c_int * 2)(0, 0))
+    assert L.pgk_create(ctypes.byref(g), None, ctypes.byref(out)) == 0
+    # not bound / not initialised: errors, no device work
+    assert L.pgk_step(out, 1) == -1
+    assert b"not initialised" in L.pgk_last_error(out)
+    p = _lib.Params(-1.0, 1.0, 0.0, 0.0, 2.0, 0.0)
+    assert L.pgk_set_params(out, ctypes.byref(p), None) == -1
+    L.pgk_destroy(out)
+    assert not math.isnan(1.0)

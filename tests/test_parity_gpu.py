@@ -1,0 +1,176 @@
+"""Parity of the HIP path with the FP64 oracle (GPU only).
+
+Both sides start from the same seeded fields and the same resolved
+parameters; the comparison is element by element on the f-moments
+rho, u, theta_T, theta_R and the pressure tensor.  Error measure per field:
+max |gpu - oracle| / max(max |oracle|, floor), floor = 1e-2 for u (the
+perturbation scale) and the field's own magnitude otherwise.
+Bars: FP64 storage 1e-12, FP32 deviation storage 1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.params import resolve
+from paper_2201_05280_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FLOOR = dict(rho=0.0, u=1e-2, thT=0.0, thR=0.0, P=0.0)
+
+
+def _solver(*a, **kw):
+    import paper_2201_05280_amd as pgk
+    return pgk.Solver(*a, **kw)
+
+
+def rel_err(g, o):
+    out = {}
+    for k in ("rho", "u", "thT", "thR", "P"):
+        den = max(np.abs(o[k]).max(), FLOOR[k])
+        out[k] = float(np.abs(g[k] - o[k]).max() / den)
+    return out
+
+
+def run_pair(nx, ny, nz, fields, p, steps, precision, variant=0, bc=None, checkpoints=None):
+    import paper_2201_05280_amd as pgk
+    bc_kind = (pgk.PERIODIC, pgk.PERIODIC) if bc is None else (bc[0][0], bc[1][0])
+    s = _solver(nx, ny, nz, precision=precision, variant=variant, bc_x=bc_kind)
+    s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    o = oracle.Oracle(nx, ny, nz, variant=variant)
+    o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    if bc is not None:
+        for side in (0, 1):
+            kind, rho, u, th = bc[side]
+            s.set_bc_x(side, rho, u, th)
+            o.set_bc_x(side, kind, rho, u, th)
+    s.init(fields["rho"], fields["u"], fields["thT"], fields["thR"])
+    o.init(fields["rho"], fields["u"], fields["thT"], fields["thR"])
+    errs = []
+    done = 0
+    for n in (checkpoints or [steps]):
+        s.step(n - done)
+        o.step(n - done)
+        done = n
+        errs.append(rel_err(s.moments(), o.moments()))
+    cons = (s.conserved(), o.conserved())
+    s.close()
+    return errs, cons
+
+
+def _assert_bar(errs, bar, label=""):
+    for e in errs:
+        for k, v in e.items():
+            assert v <= bar, (label, k, v, e)
+
+
+P_SHEAR = resolve(0.01, 0.71, 0.6, 2.0)
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
+def test_shear_wave_64x64_2000_steps(precision, bar):
+    # the 2D shear-wave workload at full size: 64x64 cells, 8192 sites
+    f = inputs.shear_wave(64, 64, 1, amp=0.01)
+    errs, (cg, co) = run_pair(64, 64, 1, f, P_SHEAR, 2000, precision, checkpoints=[1, 10, 500, 2000])
+    print("shear parity", precision, errs)
+    _assert_bar(errs, bar, "shear")
+    assert abs(cg[0] - co[0]) <= bar * co[0]
+    assert abs(cg[4] - co[4]) <= bar * co[4]
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
+@pytest.mark.parametrize("dims", [(7, 5, 3), (13, 1, 1), (1, 9, 4), (2, 2, 2), (33, 17, 1)])
+def test_random_fields_ragged_grids(precision, bar, dims):
+    # grids whose site counts are not multiples of the 256-thread block, with
+    # axes of length 1 and 2 (wrap-around onto the same cell)
+    nx, ny, nz = dims
+    p = resolve(0.02, 0.8, 0.7, 3.0)
+    f = inputs.random_smooth(nx, ny, nz, seed=sum(dims))
+    errs, _ = run_pair(nx, ny, nz, f, p, 60, precision, checkpoints=[1, 7, 60])
+    print("random parity", dims, precision, errs)
+    _assert_bar(errs, bar, dims)
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
+def test_printed_variant(precision, bar):
+    f = inputs.random_smooth(12, 10, 3, seed=5)
+    errs, _ = run_pair(12, 10, 3, f, P_SHEAR, 100, precision, variant=1, checkpoints=[1, 100])
+    _assert_bar(errs, bar, "LIT")
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
+def test_taylor_green_small(precision, bar):
+    # the 3D Taylor-Green workload at reduced size (same Mach, same Reynolds scaling)
+    n = 16
+    U = 0.1 * np.sqrt(1.4 * oracle.THETA0)
+    nu = U * (n / (2 * np.pi)) / 1600.0
+    p = resolve(nu, 0.71, 0.6, 2.0)
+    f = inputs.taylor_green(n, U)
+    errs, (cg, co) = run_pair(n, n, n, f, p, 200, precision, checkpoints=[1, 50, 200])
+    print("tgv parity", precision, errs)
+    _assert_bar(errs, bar, "tgv")
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
+def test_diffuse_walls_couette(precision, bar):
+    import paper_2201_05280_amd as pgk
+    th0 = oracle.THETA0
+    U = 0.05
+    bc = [(pgk.WALL, 1.0, (0.0, 0.0, 0.0), th0), (pgk.WALL, 1.0, (0.0, U, 0.0), th0 * 1.02)]
+    f = inputs.uniform(24, 1, 1)
+    p = resolve(0.05, 0.71, 0.8, 2.0)
+    errs, _ = run_pair(24, 1, 1, f, p, 300, precision, bc=bc, checkpoints=[1, 2, 30, 300])
+    print("couette parity", precision, errs)
+    _assert_bar(errs, bar, "couette")
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
+def test_diffuse_walls_3d_columns(precision, bar):
+    import paper_2201_05280_amd as pgk
+    th0 = oracle.THETA0
+    bc = [(pgk.WALL, 1.0, (0.0, 0.02, 0.01), th0), (pgk.WALL, 1.0, (0.0, -0.02, 0.0), th0)]
+    f = inputs.random_smooth(6, 5, 3, seed=9)
+    p = resolve(0.03, 0.9, 0.9, 2.0)
+    errs, _ = run_pair(6, 5, 3, f, p, 40, precision, bc=bc, checkpoints=[1, 3, 40])
+    _assert_bar(errs, bar, "walls3d")
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
+def test_dirichlet_faces(precision, bar):
+    import paper_2201_05280_amd as pgk
+    th0 = oracle.THETA0
+    bc = [(pgk.DIRICHLET, 1.02, (0.03, 0.0, 0.0), th0 * 1.01), (pgk.DIRICHLET, 0.99, (0.03, 0.0, 0.0), th0)]
+    f = inputs.uniform(32, 1, 1, u=(0.03, 0, 0))
+    p = resolve(0.05, 0.71, 0.8, 2.0)
+    errs, _ = run_pair(32, 1, 1, f, p, 200, precision, bc=bc, checkpoints=[1, 2, 200])
+    _assert_bar(errs, bar, "dirichlet")
+
+
+def test_conservation_on_gpu_fp64():
+    # mass and momentum exact to round-off through the GPU reductions
+    f = inputs.random_smooth(10, 9, 8, seed=3)
+    p = resolve(0.02, 0.71, 0.6, 2.0)
+    s = _solver(10, 9, 8, precision=0)
+    s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    s.init(f["rho"], f["u"], f["thT"], f["thR"])
+    c0 = s.conserved()
+    s.step(200)
+    c1 = s.conserved()
+    eps = np.finfo(float).eps
+    assert (np.abs(c1[:4] - c0[:4]) <= 4 * eps * 200 * c0[0]).all(), c1 - c0
+    s.close()
+
+
+def test_bitwise_determinism_fp64():
+    f = inputs.random_smooth(9, 8, 7, seed=4)
+    p = resolve(0.02, 0.71, 0.6, 2.0)
+    outs = []
+    for _ in range(2):
+        s = _solver(9, 8, 7, precision=0)
+        s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+        s.init(f["rho"], f["u"], f["thT"], f["thR"])
+        s.step(50)
+        outs.append(s.moments())
+        s.close()
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
