@@ -42,19 +42,103 @@ struct Consts {
     double thbc[2], rhobc[2];
     double Fbc[2][NQ];      // wall equilibrium at unit density / Dirichlet equilibrium
     double in_col[2];       // re-emitted mass per ghost column at unit wall density
+    // division by nx, ny, nz: q = (umulhi(n, m) + n) >> sh for n < 2^31
+    unsigned mx, my, mz;
+    int shx, shy, shz;
+    // per-step constants computed once on the host
+    double inv1X, inv1XY, inv3d;  // 1/(1+X), 1/(1+X+Y), 1/(3+delta)
+    double wt1, wt, bs;           // tau1/(tau+tau1), tau/(tau+tau1), b/s_sigma
+    double it, i2t, ih2, i6t3, i2t3, it2;  // 1/t, 1/(2t), 1/(2t^2), 1/(6t^3), 1/(2t^3), 1/t^2 with t = theta0
 };
 
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned fdiv(unsigned n, unsigned m, int sh)
+{
+    return (__umulhi(n, m) + n) >> sh;
+}
+
 __device__ __forceinline__ void decode(int s, const Consts &k, int &x, int &y, int &z, int &sub)
 {
-    x = s % k.nx;
-    int t = s / k.nx;
-    y = t % k.ny;
-    t /= k.ny;
-    z = t % k.nz;
-    sub = t / k.nz;
+    unsigned t = fdiv((unsigned)s, k.mx, k.shx);
+    x = s - (int)t * k.nx;
+    unsigned t2 = fdiv(t, k.my, k.shy);
+    y = (int)t - (int)t2 * k.ny;
+    unsigned t3 = fdiv(t2, k.mz, k.shz);
+    z = (int)t2 - (int)t3 * k.nz;
+    sub = (int)t3;
+}
+
+// wrap x + d into [0, n) for |d| <= 2 and any n >= 1
+__device__ __forceinline__ int wrap2(int v, int n)
+{
+    v += (v < 0) ? n : 0;
+    v += (v < 0) ? n : 0;
+    v -= (v >= n) ? n : 0;
+    v -= (v >= n) ? n : 0;
+    return v;
+}
+
+// Offsets of the pull sources of one site on a periodic grid.  Integer
+// velocities stay on the own sublattice at coordinate offsets -c (|c| <= 2);
+// half velocities come from the other sublattice, at offset -1 or 0 along an
+// axis for corner sites and 0 or +1 for body-centre sites.
+struct Off5 {
+    int m2, m1, z0, p1, p2;
+    template <int D> __device__ __forceinline__ int at() const
+    {
+        if constexpr (D == -2) return m2;
+        else if constexpr (D == -1) return m1;
+        else if constexpr (D == 0) return z0;
+        else if constexpr (D == 1) return p1;
+        else return p2;
+    }
+};
+
+struct PullMap {
+    int own, oth;                 // offsets of the own and the other sublattice
+    Off5 X, Y, Z;                 // wrapped x, y*nx, z*nx*ny for offsets -2..2
+    int hx[2], hy[2], hz[2];      // half velocities: [0] for c > 0, [1] for c < 0
+};
+
+__device__ __forceinline__ PullMap pull_map(int x, int y, int z, int sub, const Consts &k)
+{
+    PullMap p;
+    int plane = k.nx * k.ny, subsz = plane * k.nz;
+    p.own = sub * subsz;
+    p.oth = (1 - sub) * subsz;
+    p.X = {wrap2(x - 2, k.nx), wrap2(x - 1, k.nx), x, wrap2(x + 1, k.nx), wrap2(x + 2, k.nx)};
+    p.Y = {wrap2(y - 2, k.ny) * k.nx, wrap2(y - 1, k.ny) * k.nx, y * k.nx, wrap2(y + 1, k.ny) * k.nx,
+           wrap2(y + 2, k.ny) * k.nx};
+    p.Z = {wrap2(z - 2, k.nz) * plane, wrap2(z - 1, k.nz) * plane, z * plane, wrap2(z + 1, k.nz) * plane,
+           wrap2(z + 2, k.nz) * plane};
+    bool b = sub != 0;
+    p.hx[0] = b ? p.X.z0 : p.X.m1; p.hx[1] = b ? p.X.p1 : p.X.z0;
+    p.hy[0] = b ? p.Y.z0 : p.Y.m1; p.hy[1] = b ? p.Y.p1 : p.Y.z0;
+    p.hz[0] = b ? p.Z.z0 : p.Z.m1; p.hz[1] = b ? p.Z.p1 : p.Z.z0;
+    return p;
+}
+
+template <int Q>
+__device__ __forceinline__ unsigned pull_off(const PullMap &p)
+{
+    constexpr int cx = c2(Q, 0), cy = c2(Q, 1), cz = c2(Q, 2);
+    if constexpr ((cx & 1) == 0) {
+        return (unsigned)(p.own + p.Z.template at<-cz / 2>() + p.Y.template at<-cy / 2>() + p.X.template at<-cx / 2>());
+    } else {
+        return (unsigned)(p.oth + p.hz[cz > 0 ? 0 : 1] + p.hy[cy > 0 ? 0 : 1] + p.hx[cx > 0 ? 0 : 1]);
+    }
+}
+
+template <typename S, int Q = 0>
+__device__ __forceinline__ void load_periodic(const S *__restrict__ src, const PullMap &p, int ns, S *v)
+{
+    if constexpr (Q < NQ) {
+        const S *__restrict__ base = src + (size_t)Q * ns;
+        v[Q] = base[pull_off<Q>(p)];
+        load_periodic<S, Q + 1>(src, p, ns, v);
+    }
 }
 
 __device__ __forceinline__ int wrapc(int i, int n)
@@ -186,17 +270,14 @@ __device__ __forceinline__ Solve site_solve(const Mom &m, double r, const Consts
     s.sg[5] = m.P[5] - m.rho * s.u[1] * s.u[2];
     s.r = r;
     // a = T + Y (T - R),  R = (r + X T)/(1 + X)
-    s.T = (s.a * (1.0 + k.X) + k.Y * r) / (1.0 + k.X + k.Y);
-    s.R = (r + k.X * s.T) / (1.0 + k.X);
-    s.theta = (3.0 * s.T + k.delta * s.R) / (3.0 + k.delta);
+    s.T = (s.a * (1.0 + k.X) + k.Y * r) * k.inv1XY;
+    s.R = (r + k.X * s.T) * k.inv1X;
+    s.theta = (3.0 * s.T + k.delta * s.R) * k.inv3d;
     // lam_ES = T I + b sigma(f)/rho, sigma(f) = sigma(g)/s_sigma;
     // lam_F = (tau1 lam_ES + tau theta I)/(tau + tau1)
-    double cb = k.b / (k.ssig * m.rho);
-    double wt1 = k.tau1 / (k.tau + k.tau1), wt = k.tau / (k.tau + k.tau1);
-    for (int i = 0; i < 6; i++) {
-        double iso = i < 3 ? (wt1 * s.T + wt * s.theta) : 0.0;
-        s.lamF[i] = iso + wt1 * cb * s.sg[i];
-    }
+    double cb = k.wt1 * k.bs * ir;
+    double iso = k.wt1 * s.T + k.wt * s.theta;
+    for (int i = 0; i < 6; i++) s.lamF[i] = (i < 3 ? iso : 0.0) + cb * s.sg[i];
     return s;
 }
 
@@ -230,12 +311,12 @@ __device__ __forceinline__ Eq<R> make_eq(const Solve &s, const Consts &k)
     e.Du1 = (R)(D[3] * s.u[0] + D[1] * s.u[1] + D[5] * s.u[2]);
     e.Du2 = (R)(D[4] * s.u[0] + D[5] * s.u[1] + D[2] * s.u[2]);
     e.D0 = (R)D[0]; e.D1 = (R)D[1]; e.D2 = (R)D[2]; e.D3 = (R)D[3]; e.D4 = (R)D[4]; e.D5 = (R)D[5];
-    e.k0 = (R)((uu + trD) / (2.0 * t));
-    e.A1 = (R)(1.0 / t - (uu + trD) / (2.0 * t * t));
-    e.k2 = (R)(1.0 / (2.0 * t * t));
-    e.k3 = (R)(1.0 / (6.0 * t * t * t));
-    e.k4 = (R)(1.0 / (2.0 * t * t * t));
-    e.k5 = (R)(1.0 / (t * t));
+    e.k0 = (R)((uu + trD) * k.i2t);
+    e.A1 = (R)(k.it - (uu + trD) * k.ih2);
+    e.k2 = (R)k.ih2;
+    e.k3 = (R)k.i6t3;
+    e.k4 = (R)k.i2t3;
+    e.k5 = (R)k.it2;
     e.rho = (R)s.rho;
     e.drho = (R)(s.rho - 1.0);
     e.omb = (R)(1.0 - 2.0 * k.beta);
@@ -321,14 +402,15 @@ __global__ __launch_bounds__(WG) void k_lb(const S *__restrict__ src, S *__restr
         int x, y, z, sub;
         decode(s, k, x, y, z, sub);
         S v[NQ];
-        load_all<S, BOUNDED>(src, gh, x, y, z, sub, k, v);
+        if constexpr (BOUNDED) load_all<S, true>(src, gh, x, y, z, sub, k, v);
+        else load_periodic<S>(src, pull_map(x, y, z, sub, k), k.ns, v);
         double r = thR[s];
         Mom m = moments<S>(v, k);
         Solve so = site_solve(m, r, k);
         Eq<S> e = make_eq<S>(so, k);
         collide_store<S>(v, e, k, dst, s);
         that_[s] = so.R;                                  // theta_R after step 1
-        thR[s] = (VAR == PGK_CN) ? so.R - so.r : so.T;     // for step 4
+        if (VAR == PGK_LIT) thR[s] = so.T;                // the printed second half needs theta_T
         aux[s] = (A)so.u[0];
         aux[(size_t)k.ns + s] = (A)so.u[1];
         aux[(size_t)2 * k.ns + s] = (A)so.u[2];
@@ -400,8 +482,8 @@ __global__ __launch_bounds__(WG) void k_mc(const double *__restrict__ that_, con
 }
 
 template <typename A, int VAR, bool BOUNDED>
-__global__ __launch_bounds__(WG) void k_dif(const double *__restrict__ tmc, const A *__restrict__ aux,
-                                            double *__restrict__ thR, Consts k)
+__global__ __launch_bounds__(WG) void k_dif(const double *__restrict__ tmc, const double *__restrict__ that_,
+                                            const A *__restrict__ aux, double *__restrict__ thR, Consts k)
 {
     int s = blockIdx.x * WG + threadIdx.x;
     if (s >= k.ns) return;
@@ -429,10 +511,193 @@ __global__ __launch_bounds__(WG) void k_dif(const double *__restrict__ tmc, cons
         }
     double v = thR[s];
     if (VAR == PGK_CN) {
-        thR[s] = t + 2.0 * flux / (rho * k.delta) + v;
+        // second half: repeat the first-half increment R - r
+        thR[s] = t + 2.0 * flux / (rho * k.delta) + (that_[s] - v);
     } else {
         double DR = 2.0 * ks / (rho * k.delta);
         thR[s] = (t + DR * lap + k.X * v) / (1.0 + k.X);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_tr: fused theta_R transport on periodic grids (steps 2-4 in one pass).
+// A work-group owns a TX x TY tile of one sublattice and marches through TZ
+// z-planes.  Rolling LDS rings hold the planes each stage needs:
+//   theta_hat  (planes z, z+1)   region [-2, TX+2) x [-2, TY+2)
+//   theta*     (planes z-1, z)   region [-2, TX+1) x [-2, TY+1)
+//   theta^mc   (planes z-2..z)   region [-1, TX+1) x [-1, TY+1)
+//   rho*theta  (planes z-2..z)   region [-1, TX+1) x [-1, TY+1)
+//   u          (plane z)         region [-2, TX+1) x [-2, TY+1)
+// At plane z the group computes theta*(z), theta^mc(z) and the diffused,
+// fully relaxed theta_R at plane z-1.  Every value entering a stencil is
+// staged once per group; HBM sees each field about once.
+// ---------------------------------------------------------------------------
+constexpr int TX = 64, TY = 4, TZ = 32;
+constexpr int HX = TX + 4, HY = TY + 4;     // theta_hat plane (origin -2)
+constexpr int SX = TX + 3, SY = TY + 3;     // theta* and u plane (origin -2)
+constexpr int MX = TX + 2, MY = TY + 2;     // theta^mc and rho*theta plane (origin -1)
+constexpr int NH = (HX * HY + WG - 1) / WG; // staged points per thread
+constexpr int NS = (SX * SY + WG - 1) / WG;
+constexpr int NM = (MX * MY + WG - 1) / WG;
+
+__device__ __forceinline__ int wrapn(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+template <typename A, int VAR>
+__global__ __launch_bounds__(WG) void k_tr(const double *__restrict__ that_, const A *__restrict__ aux,
+                                           double *__restrict__ thR, Consts k)
+{
+    __shared__ double l_th[2][HY * HX];
+    __shared__ double l_ts[2][SY * SX];
+    __shared__ double l_mc[3][MY * MX];
+    __shared__ A l_pt[3][MY * MX];
+    __shared__ A l_u[3][SY * SX];
+
+    const int nbx = (k.nx + TX - 1) / TX, nby = (k.ny + TY - 1) / TY, nbz = (k.nz + TZ - 1) / TZ;
+    int b = blockIdx.x;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nby;
+    b /= nby;
+    const int bz = b % nbz;
+    const int sub = b / nbz;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+    const int zend = min(z0 + TZ, k.nz);   // planes [z0, zend) are produced
+    const int plane = k.nx * k.ny;
+    const int subo = sub * plane * k.nz;
+    const int tid = threadIdx.x;
+
+    // plane-invariant (x, y) offsets of the points this thread stages
+    int oh[NH], os[NS], om[NM];
+#pragma unroll
+    for (int j = 0; j < NH; j++) {
+        int i = min(tid + j * WG, HX * HY - 1);
+        int ly = i / HX, lx = i - ly * HX;
+        oh[j] = wrapn(y0 + ly - 2, k.ny) * k.nx + wrapn(x0 + lx - 2, k.nx);
+    }
+#pragma unroll
+    for (int j = 0; j < NS; j++) {
+        int i = min(tid + j * WG, SX * SY - 1);
+        int ly = i / SX, lx = i - ly * SX;
+        os[j] = wrapn(y0 + ly - 2, k.ny) * k.nx + wrapn(x0 + lx - 2, k.nx);
+    }
+#pragma unroll
+    for (int j = 0; j < NM; j++) {
+        int i = min(tid + j * WG, MX * MY - 1);
+        int ly = i / MX, lx = i - ly * MX;
+        om[j] = wrapn(y0 + ly - 1, k.ny) * k.nx + wrapn(x0 + lx - 1, k.nx);
+    }
+    const int lxo = tid % TX, lyo = tid / TX;
+    const bool outv = (x0 + lxo < k.nx) && (y0 + lyo < k.ny);
+    const int oo = outv ? (y0 + lyo) * k.nx + (x0 + lxo) : 0;
+    auto zoff = [&](int z) { return subo + wrapn(z, k.nz) * plane; };
+
+    // registers carrying the next plane's data
+    double r_th[NH];
+    A r_u[3][NS], r_pt[NM];
+    auto fetch = [&](int zth, int zu) {
+        int zt = zoff(zth), zuo = zoff(zu);
+#pragma unroll
+        for (int j = 0; j < NH; j++) r_th[j] = that_[zt + oh[j]];
+#pragma unroll
+        for (int j = 0; j < NS; j++) {
+            r_u[0][j] = aux[zuo + os[j]];
+            r_u[1][j] = aux[(size_t)k.ns + zuo + os[j]];
+            r_u[2][j] = aux[(size_t)2 * k.ns + zuo + os[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < NM; j++) r_pt[j] = aux[(size_t)4 * k.ns + zuo + om[j]];
+    };
+    auto stash = [&](int slot_th, int slot3) {
+#pragma unroll
+        for (int j = 0; j < NH; j++)
+            if (tid + j * WG < HX * HY) l_th[slot_th][tid + j * WG] = r_th[j];
+#pragma unroll
+        for (int j = 0; j < NS; j++)
+            if (tid + j * WG < SX * SY) {
+                l_u[0][tid + j * WG] = r_u[0][j];
+                l_u[1][tid + j * WG] = r_u[1][j];
+                l_u[2][tid + j * WG] = r_u[2][j];
+            }
+#pragma unroll
+        for (int j = 0; j < NM; j++)
+            if (tid + j * WG < MX * MY) l_pt[slot3][tid + j * WG] = r_pt[j];
+    };
+
+    // prologue: theta_hat(z0-2) straight into its slot, then the data of plane z0-2
+    {
+        int zt = zoff(z0 - 2);
+#pragma unroll
+        for (int j = 0; j < NH; j++)
+            if (tid + j * WG < HX * HY) l_th[(z0 + 2) & 1][tid + j * WG] = that_[zt + oh[j]];
+    }
+    fetch(z0 - 1, z0 - 2);
+    double o_rho = 0.0, o_v = 0.0, o_th = 0.0;
+
+    for (int zz = z0 - 2; zz <= zend; zz++) {
+        const int rz = zz + 4;                          // non-negative ring index
+        stash((rz + 1) & 1, rz % 3);                   // theta_hat(zz+1), u(zz), rho theta(zz)
+        if (zz < zend) fetch(zz + 2, zz + 1);          // in flight during this plane
+        const int zo = zz - 1;                          // output plane of this iteration
+        if (zz >= z0 + 1 && outv) {
+            int g = zoff(zo) + oo;
+            o_rho = (double)aux[(size_t)3 * k.ns + g];
+            o_v = thR[g];
+            o_th = that_[g];
+        }
+        __syncthreads();
+        // predictor theta*(zz) = th - sum_a u_a (th(+e_a) - th), region origin -2
+        for (int i = tid; i < SY * SX; i += WG) {
+            int ly = i / SX, lx = i - ly * SX;
+            int h = ly * HX + lx;
+            double t = l_th[rz & 1][h];
+            double adv = (double)l_u[0][i] * (l_th[rz & 1][h + 1] - t)
+                       + (double)l_u[1][i] * (l_th[rz & 1][h + HX] - t)
+                       + (double)l_u[2][i] * (l_th[(rz + 1) & 1][h] - t);
+            l_ts[rz & 1][i] = t - adv;
+        }
+        __syncthreads();
+        // corrector theta^mc(zz) = 1/2 [th + th* - sum_a u_a (th* - th*(-e_a))], origin -1
+        if (zz > z0 - 2) {
+            for (int i = tid; i < MY * MX; i += WG) {
+                int ly = i / MX, lx = i - ly * MX;
+                int sI = (ly + 1) * SX + lx + 1, hI = (ly + 1) * HX + lx + 1;
+                double ts = l_ts[rz & 1][sI];
+                double adv = (double)l_u[0][sI] * (ts - l_ts[rz & 1][sI - 1])
+                           + (double)l_u[1][sI] * (ts - l_ts[rz & 1][sI - SX])
+                           + (double)l_u[2][sI] * (ts - l_ts[(rz + 1) & 1][sI]);
+                l_mc[rz % 3][i] = 0.5 * (l_th[rz & 1][hI] + ts - adv);
+            }
+        }
+        __syncthreads();
+        // diffusion and second half at plane zz-1
+        if (zz >= z0 + 1 && outv) {
+            const int rc = (rz + 2) % 3, rm = (rz + 1) % 3, rp = rz % 3;
+            int c = (lyo + 1) * MX + lxo + 1;
+            double t = l_mc[rc][c];
+            double ks = k.kfac * (double)l_pt[rc][c];
+            double tq[6] = {l_mc[rc][c - 1], l_mc[rc][c + 1], l_mc[rc][c - MX], l_mc[rc][c + MX],
+                            l_mc[rm][c], l_mc[rp][c]};
+            double kq[6] = {(double)l_pt[rc][c - 1], (double)l_pt[rc][c + 1], (double)l_pt[rc][c - MX],
+                            (double)l_pt[rc][c + MX], (double)l_pt[rm][c], (double)l_pt[rp][c]};
+            double flux = 0.0, lap = 0.0;
+#pragma unroll
+            for (int q = 0; q < 6; q++) {
+                flux += 0.5 * (ks + k.kfac * kq[q]) * (tq[q] - t);
+                lap += tq[q] - t;
+            }
+            int g = zoff(zo) + oo;
+            if (VAR == PGK_CN) {
+                thR[g] = t + 2.0 * flux / (o_rho * k.delta) + (o_th - o_v);
+            } else {
+                double DR = 2.0 * ks / (o_rho * k.delta);
+                thR[g] = (t + DR * lap + k.X * o_v) * k.inv1X;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -548,7 +813,8 @@ __global__ __launch_bounds__(WG) void k_moments(const S *__restrict__ src, const
         int x, y, z, sub;
         decode(s, k, x, y, z, sub);
         S v[NQ];
-        load_all<S, BOUNDED>(src, gh, x, y, z, sub, k, v);
+        if constexpr (BOUNDED) load_all<S, true>(src, gh, x, y, z, sub, k, v);
+        else load_periodic<S>(src, pull_map(x, y, z, sub, k), k.ns, v);
         double r = thR[s];
         Mom m = moments<S>(v, k);
         if (REDUCE) {
@@ -653,6 +919,15 @@ static void mark(pgk_ctx *c, int id)
     (void)hipEventRecord(c->events[c->nev], c->stream);
     c->marks[c->nev] = id;
     c->nev++;
+}
+
+// magic numbers for q = (umulhi(n, m) + n) >> sh = n / d, valid for n < 2^31
+static void magic_div(unsigned d, unsigned &m, int &sh)
+{
+    int s = 0;
+    while ((1ull << s) < d) s++;
+    m = (unsigned)((((1ull << 32) * ((1ull << s) - d)) / d) + 1);
+    sh = s;
 }
 
 static int fail(pgk_ctx *c, int code, const std::string &msg)
@@ -768,6 +1043,9 @@ extern "C" int pgk_create(const pgk_grid *g, void *stream, pgk_ctx **out)
     c->k.nx = g->nx; c->k.ny = g->ny; c->k.nz = g->nz;
     c->k.ns = 2 * g->nx * g->ny * g->nz;
     c->k.bc[0] = g->bc_x[0]; c->k.bc[1] = g->bc_x[1];
+    magic_div((unsigned)g->nx, c->k.mx, c->k.shx);
+    magic_div((unsigned)g->ny, c->k.my, c->k.shy);
+    magic_div((unsigned)g->nz, c->k.mz, c->k.shz);
     c->nblk = (c->k.ns + WG - 1) / WG;
     *out = c;
     return PGK_OK;
@@ -840,6 +1118,19 @@ extern "C" int pgk_set_params(pgk_ctx *c, const pgk_params *p, pgk_resolved *out
     k.Y = p->delta / (2.0 * p->tau1 * (3.0 + p->delta));
     k.ssig = 1.0 + 1.0 / (2.0 * taus) - p->b / (2.0 * p->tau);
     k.kfac = p->kr * 5.0 * p->tau / (2.0 * B);
+    k.inv1X = 1.0 / (1.0 + k.X);
+    k.inv1XY = 1.0 / (1.0 + k.X + k.Y);
+    k.inv3d = 1.0 / (3.0 + p->delta);
+    k.wt1 = p->tau1 / (p->tau + p->tau1);
+    k.wt = p->tau / (p->tau + p->tau1);
+    k.bs = p->b / k.ssig;
+    double t = k.th0;
+    k.it = 1.0 / t;
+    k.i2t = 1.0 / (2.0 * t);
+    k.ih2 = 1.0 / (2.0 * t * t);
+    k.i6t3 = 1.0 / (6.0 * t * t * t);
+    k.i2t3 = 1.0 / (2.0 * t * t * t);
+    k.it2 = 1.0 / (t * t);
     pgk_resolved r{};
     r.tau = p->tau; r.tau1 = p->tau1; r.b = p->b; r.kr = p->kr; r.delta = p->delta; r.theta0 = k.th0;
     r.tau_star = taus; r.beta = k.beta; r.X = k.X; r.Y = k.Y; r.s_sigma = k.ssig; r.B = B;
@@ -914,11 +1205,18 @@ static int step_t(pgk_ctx *c, int64_t n)
         hipLaunchKernelGGL((k_lb<S, A, VAR, BND, false>), grid, block, 0, c->stream, src, dst, (const S *)c->gh,
                            (double *)c->buf[PGK_BUF_THETAR], c->that_, (A *)c->aux, c->partial, c->k);
         mark(c, 0);
-        hipLaunchKernelGGL((k_mc<A, BND>), grid, block, 0, c->stream, c->that_, (const A *)c->aux, c->tmc, c->k);
-        mark(c, 1);
-        hipLaunchKernelGGL((k_dif<A, VAR, BND>), grid, block, 0, c->stream, c->tmc, (const A *)c->aux,
-                           (double *)c->buf[PGK_BUF_THETAR], c->k);
-        mark(c, 2);
+        if constexpr (BND) {
+            hipLaunchKernelGGL((k_mc<A, BND>), grid, block, 0, c->stream, c->that_, (const A *)c->aux, c->tmc, c->k);
+            mark(c, 1);
+            hipLaunchKernelGGL((k_dif<A, VAR, BND>), grid, block, 0, c->stream, c->tmc, c->that_,
+                               (const A *)c->aux, (double *)c->buf[PGK_BUF_THETAR], c->k);
+            mark(c, 2);
+        } else {
+            int ntile = ((c->k.nx + TX - 1) / TX) * ((c->k.ny + TY - 1) / TY) * ((c->k.nz + TZ - 1) / TZ) * 2;
+            hipLaunchKernelGGL((k_tr<A, VAR>), dim3(ntile), block, 0, c->stream, c->that_, (const A *)c->aux,
+                               (double *)c->buf[PGK_BUF_THETAR], c->k);
+            mark(c, 1);
+        }
         c->cur = 1 - c->cur;
         c->steps++;
     }
