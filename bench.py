@@ -64,6 +64,63 @@ def cpu_baseline(n_cpu, steps_cpu):
                        % (n_cpu, ns, steps_cpu, dt))
 
 
+def counter_traffic(n, precision):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy kernel),
+    or None when the kernel source changed since the counters were taken or
+    the workload differs."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_lb_tgv256_fp32dev.md")
+    src = os.path.join(ROOT, "paper_2201_05280_amd", "csrc", "pgk.hip")
+    if n != 256 or precision != 1 or not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(path):
+        line = line.strip()
+        for key in ("k_lb traffic_bytes_per_launch:", "source_sha256_16:"):
+            if line.startswith(key):
+                vals[key] = line[len(key):].split()[0]
+    if vals.get("source_sha256_16:") != sha:
+        return None
+    return float(vals["k_lb traffic_bytes_per_launch:"])
+
+
+def copy_probe(torch, nbytes=4 << 30, reps=10):
+    """Plain device copies of nbytes (n read + n written) timed with events:
+    the runtime's own copy and the project's float4 copy kernels."""
+    import ctypes
+    L = ctypes.CDLL(os.path.join(ROOT, "paper_2201_05280_amd", "libpgk_probe.so"))
+    L.pgk_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_void_p]
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {"bytes_moved": 2 * nbytes}
+    variants = [("runtime", None)] + [("float4_b%d" % nb, (0, nb)) for nb in (512, 1024, 2048)] + \
+               [("float4_nt_b%d" % nb, (1, nb)) for nb in (1024,)] + [("float1", (2, 0))] + \
+               [("float4_x%d" % u, (v, 0)) for u, v in ((4, 3), (8, 4), (16, 5))]
+    for name, v in variants:
+        def run():
+            if v is None:
+                b.copy_(a)
+            else:
+                rc = L.pgk_probe_copy(b.data_ptr(), a.data_ptr(), nbytes, v[0], v[1], stream)
+                assert rc == 0
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name + "_GBs"] = round(2 * nbytes / ms / 1e6, 1)
+    del a, b
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +131,8 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also time a plain device copy (torch) as the achievable-bandwidth reference")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -142,7 +201,7 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": "k_lb (fused pull-moments-solve-F3-collide)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(n, precision),
             "bytes_per_site": ab["k_lb"], "avg_launch_ms": round(lb_avg_s * 1e3, 4),
         },
         "step_roofline": {"algorithmic_bytes_per_site": ab["step"], "achieved_GBs": round(step_gbs, 1),
@@ -151,6 +210,8 @@ def main():
         "conservation_drift": drift,
     }
     s.close()
+    if args.copy_probe:
+        out["copy_probe"] = copy_probe(torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)
     print(json.dumps(out), flush=True)

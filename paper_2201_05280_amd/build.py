@@ -7,6 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpgk.so")
 SOURCES = [os.path.join(HERE, "csrc", "pgk.hip")]
+PROBE_LIB = os.path.join(HERE, "libpgk_probe.so")
+PROBE_SOURCES = [os.path.join(HERE, "csrc", "probe.hip")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -17,15 +19,21 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose=True, extra=()):
+def _hipcc(out, sources, extra=(), verbose=True):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     cmd = [hipcc] + HIPCC_FLAGS + list(extra) + ["-I", os.path.join(ROOT, "include"),
                                                  "-I", os.path.join(HERE, "csrc"),
-                                                 "-o", LIB + ".tmp"] + SOURCES
+                                                 "-o", out + ".tmp"] + sources
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(out + ".tmp", out)
+
+
+def build(verbose=True, extra=()):
+    """libpgk.so (the method) and libpgk_probe.so (bandwidth reference copies)."""
+    _hipcc(LIB, SOURCES, extra, verbose)
+    _hipcc(PROBE_LIB, PROBE_SOURCES, extra, verbose)
     return LIB
 
 

@@ -345,24 +345,26 @@ __device__ __forceinline__ void collide_store(S *v, const Eq<S> &e, const Consts
             S wh = k.whi[Lattice::SHELL[P]], wl = k.wlo[Lattice::SHELL[P]];
             S Xp = e.drho + e.rho * (even + odd), Xm = e.drho + e.rho * (even - odd);
             S Fp = wh * Xp + wl * Xp, Fm = wh * Xm + wl * Xm;
-            dst[(size_t)(1 + P) * k.ns + s] = v[1 + P] + e.tb * (Fp - v[1 + P]);
-            dst[(size_t)(1 + NPAIR + P) * k.ns + s] = v[1 + NPAIR + P] + e.tb * (Fm - v[1 + NPAIR + P]);
+            // the next read of these values is a step away: stream them past the caches
+            __builtin_nontemporal_store(v[1 + P] + e.tb * (Fp - v[1 + P]), &dst[(size_t)(1 + P) * k.ns + s]);
+            __builtin_nontemporal_store(v[1 + NPAIR + P] + e.tb * (Fm - v[1 + NPAIR + P]),
+                                        &dst[(size_t)(1 + NPAIR + P) * k.ns + s]);
         } else {
             S w = (S)k.w[Lattice::SHELL[P]];
             S Fp = w * e.rho * ((S)1 + even + odd);
             S Fm = w * e.rho * ((S)1 + even - odd);
-            dst[(size_t)(1 + P) * k.ns + s] = e.omb * v[1 + P] + e.tb * Fp;
-            dst[(size_t)(1 + NPAIR + P) * k.ns + s] = e.omb * v[1 + NPAIR + P] + e.tb * Fm;
+            __builtin_nontemporal_store(e.omb * v[1 + P] + e.tb * Fp, &dst[(size_t)(1 + P) * k.ns + s]);
+            __builtin_nontemporal_store(e.omb * v[1 + NPAIR + P] + e.tb * Fm, &dst[(size_t)(1 + NPAIR + P) * k.ns + s]);
         }
         collide_store<S, P + 1>(v, e, k, dst, s);
     } else {
         if constexpr (sizeof(S) == 4) {
             S X0 = e.drho - e.rho * e.k0;
             S F0 = k.whi[0] * X0 + k.wlo[0] * X0;
-            dst[s] = v[0] + e.tb * (F0 - v[0]);
+            __builtin_nontemporal_store(v[0] + e.tb * (F0 - v[0]), &dst[s]);
         } else {
             S w0 = (S)k.w[0];
-            dst[s] = e.omb * v[0] + e.tb * (w0 * e.rho * ((S)1 - e.k0));
+            __builtin_nontemporal_store(e.omb * v[0] + e.tb * (w0 * e.rho * ((S)1 - e.k0)), &dst[s]);
         }
     }
 }
@@ -557,7 +559,14 @@ __global__ __launch_bounds__(WG) void k_tr(const double *__restrict__ that_, con
     __shared__ A l_u[3][SY * SX];
 
     const int nbx = (k.nx + TX - 1) / TX, nby = (k.ny + TY - 1) / TY, nbz = (k.nz + TZ - 1) / TZ;
-    int b = blockIdx.x;
+    // work-groups are dispatched round-robin over the 8 XCDs (each with its own
+    // L2); give every XCD a contiguous run of tiles so that the halos shared by
+    // neighbouring tiles are fetched into one L2
+    int b;
+    {
+        const int n = gridDim.x, q = n / 8, r = n % 8, i = blockIdx.x, xcd = i % 8, kk = i / 8;
+        b = xcd < r ? xcd * (q + 1) + kk : r * (q + 1) + (xcd - r) * q + kk;
+    }
     const int bx = b % nbx;
     b /= nbx;
     const int by = b % nby;

@@ -1,0 +1,46 @@
+"""Parity at the Taylor-Green workload's full size (256^3 cells, 33,554,432
+sites) in the launch configuration the benchmark times, against the FP64
+oracle run on the host for a few steps from the same seeded field."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.params import resolve
+from paper_2201_05280_amd import inputs
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+N = 256
+STEPS = 2
+
+
+@pytest.fixture(scope="module")
+def reference():
+    U = 0.1 * np.sqrt(1.4 * oracle.THETA0)
+    nu = U * (N / (2 * np.pi)) / 1600.0
+    p = resolve(nu, 0.71, 0.6, 2.0)
+    f = inputs.taylor_green(N, U)
+    o = oracle.Oracle(N, N, N)
+    o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    o.init(f["rho"], f["u"], f["thT"], f["thR"])
+    o.step(STEPS)
+    m = o.moments()
+    del o
+    return p, f, m
+
+
+@pytest.mark.parametrize("precision,bar", [(1, 1e-5), (0, 1e-12)])
+def test_taylor_green_256_full_grid(reference, precision, bar):
+    import paper_2201_05280_amd as pgk
+    p, f, ref = reference
+    s = pgk.Solver(N, N, N, precision=precision)
+    s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    s.init(f["rho"], f["u"], f["thT"], f["thR"])
+    s.step(STEPS)
+    got = s.moments()
+    s.close()
+    for k in ("rho", "u", "thT", "thR", "P"):
+        den = max(np.abs(ref[k]).max(), 1e-2 if k == "u" else 0.0)
+        err = float(np.abs(got[k] - ref[k]).max() / den)
+        print("full-size parity precision=%d %s %.3e" % (precision, k, err), flush=True)
+        assert err <= bar, (k, err)
