@@ -169,6 +169,69 @@ int pgk_conserved(pgk_ctx *ctx, double out[5]);
 int pgk_set_timing(pgk_ctx *ctx, int enable);
 int pgk_kernel_times(pgk_ctx *ctx, double ms[PGK_NKERNEL], int64_t launches[PGK_NKERNEL]);
 
+/* ------------------------------------------------------------------------
+ * Batched sweep: many independent 1D cases (one cell in y and z, x faces
+ * bounded) in double precision.  Each case is a Couette layer between two
+ * diffuse walls or a stationary normal shock between two Dirichlet faces
+ * (Sec. 6 uses Couette flows; shocks are outside the paper's tests).  One
+ * persistent launch advances every running case by K steps, one work-group
+ * per case; the launch is captured once in a HIP graph and replayed.  After
+ * each chunk a case is checked:
+ *   residual = max over phi in {rho, u_axis, theta_T, theta_R} of
+ *              ||phi^n - phi^(n-1)||_2 / ||phi^n||_2   (one-step change)
+ * and is frozen when it falls to `tol` (CONVERGED), when a density or a
+ * temperature turns non-positive or non-finite (DIVERGED), or at max_steps.
+ * Work-group size and K come from a built-in autotuner (timed first chunks,
+ * cached as JSON in $PGK_TUNE_CACHE or ~/.cache/pgk_tune.json) unless set.
+ * ------------------------------------------------------------------------ */
+#define PGK_CASE_RUNNING   0
+#define PGK_CASE_CONVERGED 1
+#define PGK_CASE_DIVERGED  2
+#define PGK_CASE_MAXSTEPS  3
+
+typedef struct {
+    int L;                   /* cells along x, 4 <= L <= 8192 */
+    int bc;                  /* PGK_WALL or PGK_DIRICHLET, both faces */
+    int vel_axis;            /* velocity component used by the residual (0, 1, 2) */
+    int variant;             /* PGK_CN | PGK_LIT */
+    pgk_params p;            /* resolved model parameters of this case */
+    double rho[2];           /* Dirichlet densities (ignored for walls) */
+    double u[2][3];          /* face velocities (walls: tangential only) */
+    double theta[2];         /* face temperatures */
+} pgk_case;
+
+typedef struct pgk_batch pgk_batch;
+
+/* Bytes of the single device buffer a batch of n cases needs. */
+int pgk_batch_bytes(const pgk_case *cases, int n, size_t *bytes);
+
+/* Create a batch on `stream` over the caller's device buffer `buf` (256-byte
+ * aligned, at least pgk_batch_bytes).  Case c owns sites [off_c, off_c + 2 L_c)
+ * of every per-site field; pgk_batch_offsets() returns off_0..off_n. */
+int pgk_batch_create(const pgk_case *cases, int n, void *stream, void *buf, size_t bytes, pgk_batch **out);
+int pgk_batch_offsets(const pgk_batch *b, int64_t *off);
+
+/* Initial state of every case from device fields over all sites (same meaning
+ * and [3][ns_total] layout as pgk_init_fields); resets steps and status. */
+int pgk_batch_init(pgk_batch *b, const double *rho, const double *u, const double *theta_T,
+                   const double *theta_R);
+
+/* Fix the work-group size (256 or 512) and chunk length K (>= 2); 0, 0 = autotune. */
+int pgk_batch_config(pgk_batch *b, int wg, int K);
+
+/* Run until every case has stopped or max_steps per case.  Host arrays of n
+ * entries receive the steps taken, the last residual and the status. */
+int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_t *steps, double *resid, int *status);
+
+/* Work-group size, K and measured nanoseconds per site update of the chosen config. */
+int pgk_batch_tuned(const pgk_batch *b, int *wg, int *K, double *ns_per_site_update);
+
+/* f-moments of every case into device arrays over all sites (NULL = skip). */
+int pgk_batch_read_moments(pgk_batch *b, double *rho, double *u, double *theta_T, double *theta_R);
+
+const char *pgk_batch_last_error(const pgk_batch *b);
+void pgk_batch_destroy(pgk_batch *b);
+
 /* Steps taken since the last pgk_init_fields. */
 int64_t pgk_steps_done(const pgk_ctx *ctx);
 

@@ -63,6 +63,8 @@ def lib():
         L.pgko_collide_site.argtypes = [vp, dp, ctypes.c_double, dp, dp]
         L.pgko_get_state.argtypes = [vp, dp, dp]
         L.pgko_set_state.argtypes = [vp, dp, dp]
+        L.pgko_substeps.argtypes = [vp]
+        L.pgko_substeps.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -162,6 +164,10 @@ class Oracle:
         out = np.zeros(5)
         lib().pgko_conserved(self._h, _p(out))
         return out
+
+    def substeps(self):
+        """FTCS sub-steps the theta_R diffusion takes per time step."""
+        return int(lib().pgko_substeps(self._h))
 
     def collide_site(self, g, er):
         g = np.ascontiguousarray(g, dtype=np.float64)

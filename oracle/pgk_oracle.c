@@ -302,6 +302,7 @@ typedef struct pgko {
     int bc[2];
     double bc_rho[2], bc_u[2][3], bc_th[2];
     int e2_fail;
+    int nsub;          /* FTCS sub-steps of the theta_R diffusion */
 } pgko;
 
 static int site_index(const pgko *o, int sub, int z, int y, int x)
@@ -674,42 +675,69 @@ static void transport(pgko *o)
         }
         tm[s] = 0.5 * (th[s] + ts[s] - adv);
     }
+    /* diffusion in nsub equal FTCS sub-steps (ping-pong between tm and ts) */
+    double *cur = tm, *nxt = ts;
+    double frac = 1.0 / o->nsub;
+    for (int it = 0; it < o->nsub; it++) {
+        int last = it == o->nsub - 1;
 #pragma omp parallel for
-    for (int s = 0; s < ns; s++) {
-        double k_s = kappaR(o, o->rho[s], o->theta[s]);
-        double flux = 0.0, lap = 0.0;
-        for (int a = 0; a < 3; a++)
-            for (int dir = -1; dir <= 1; dir += 2) {
-                int q = nb(o, s, a, dir);
-                double tq, kq;
-                if (q >= 0) {
-                    tq = tm[q];
-                    kq = kappaR(o, o->rho[q], o->theta[q]);
-                } else {
-                    ghost gh = ghost_of(o, q == -1 ? 0 : 1, s);
-                    tq = gh.th;
-                    kq = gh.kap;
+        for (int s = 0; s < ns; s++) {
+            double k_s = kappaR(o, o->rho[s], o->theta[s]);
+            double flux = 0.0, lap = 0.0;
+            for (int a = 0; a < 3; a++)
+                for (int dir = -1; dir <= 1; dir += 2) {
+                    int q = nb(o, s, a, dir);
+                    double tq, kq;
+                    if (q >= 0) {
+                        tq = cur[q];
+                        kq = kappaR(o, o->rho[q], o->theta[q]);
+                    } else {
+                        ghost gh = ghost_of(o, q == -1 ? 0 : 1, s);
+                        tq = gh.th;
+                        kq = gh.kap;
+                    }
+                    flux += 0.5 * (k_s + kq) * (tq - cur[s]);
+                    lap += tq - cur[s];
                 }
-                flux += 0.5 * (k_s + kq) * (tq - tm[s]);
-                lap += tq - tm[s];
+            double tdif;
+            if (o->variant == VAR_CN) tdif = cur[s] + frac * 2.0 * flux / (o->rho[s] * o->delta);
+            else tdif = cur[s] + frac * 2.0 * k_s / (o->rho[s] * o->delta) * lap;
+            if (!last) {
+                nxt[s] = tdif;
+            } else if (o->variant == VAR_CN) {
+                o->er[s] = tdif + o->d[s];                            /* second half, CN */
+            } else {
+                o->er[s] = (tdif + o->X * o->T[s]) / (1.0 + o->X);    /* second half, as printed */
             }
-        if (o->variant == VAR_CN) {
-            double tdif = tm[s] + 2.0 * flux / (o->rho[s] * o->delta);
-            o->er[s] = tdif + o->d[s];
-        } else {
-            double DR = 2.0 * k_s / (o->rho[s] * o->delta);
-            double tdif = tm[s] + DR * lap;
-            o->er[s] = (tdif + o->X * o->T[s]) / (1.0 + o->X);
         }
+        double *t = cur; cur = nxt; nxt = t;
     }
 }
 
 /* ------------------------------------------------------------------------ */
 /* Time step                                                                */
 /* ------------------------------------------------------------------------ */
+/* Number of equal FTCS sub-steps that keeps the explicit diffusion stable:
+ * FTCS needs 2 dim D_R dt <= dx^2 with D_R = 2 kappa_R/(rho delta)
+ * = 5 k_r theta tau/(B delta); evaluated at 1.5 times the largest of theta0
+ * and the face temperatures.  One sub-step is the printed scheme. */
+static int diffusion_substeps(const pgko *o)
+{
+    int dim = (o->nx > 1) + (o->ny > 1) + (o->nz > 1);
+    double th = o->th0;
+    for (int side = 0; side < 2; side++)
+        if (o->bc[side] != BC_PERIODIC && o->bc_th[side] > th) th = o->bc_th[side];
+    double DR = o->delta > 0 ? 5.0 * o->kr * th * o->tau / (o->B * o->delta) : 0.0;
+    int n = (int)ceil(2.0 * dim * DR * 1.5);
+    return n < 1 ? 1 : n;
+}
+
+int pgko_substeps(pgko *o) { return diffusion_substeps(o); }
+
 int pgko_step(pgko *o, long nsteps)
 {
     int ns = o->ns;
+    o->nsub = diffusion_substeps(o);
     for (long n = 0; n < nsteps; n++) {
         int fail = 0;
 #pragma omp parallel for reduction(+ : fail)

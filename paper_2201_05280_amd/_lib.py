@@ -22,7 +22,11 @@ NBUF = 4
 # every symbol include/pgk.h declares
 EXPORTS = ["pgk_resolve", "pgk_buffer_sizes", "pgk_create", "pgk_bind", "pgk_set_params",
            "pgk_set_bc_x", "pgk_init_fields", "pgk_step", "pgk_read_moments", "pgk_conserved",
-           "pgk_set_timing", "pgk_kernel_times", "pgk_steps_done", "pgk_last_error", "pgk_destroy"]
+           "pgk_set_timing", "pgk_kernel_times", "pgk_steps_done", "pgk_last_error", "pgk_destroy",
+           "pgk_batch_bytes", "pgk_batch_create", "pgk_batch_offsets", "pgk_batch_init", "pgk_batch_config",
+           "pgk_batch_run", "pgk_batch_tuned", "pgk_batch_read_moments", "pgk_batch_last_error",
+           "pgk_batch_destroy"]
+CASE_RUNNING, CASE_CONVERGED, CASE_DIVERGED, CASE_MAXSTEPS = 0, 1, 2, 3
 NKERNEL = 4
 KERNEL_NAMES = ["k_lb", "k_mc", "k_dif", "k_bc"]
 
@@ -48,6 +52,12 @@ class Resolved(ctypes.Structure):
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class Case(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int), ("bc", ctypes.c_int), ("vel_axis", ctypes.c_int), ("variant", ctypes.c_int),
+                ("p", Params), ("rho", ctypes.c_double * 2), ("u", (ctypes.c_double * 3) * 2),
+                ("theta", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -87,8 +97,22 @@ def load():
     L.pgk_last_error.restype = ctypes.c_char_p
     L.pgk_destroy.argtypes = [vp]
     L.pgk_destroy.restype = None
+    cp = ctypes.POINTER(Case)
+    L.pgk_batch_bytes.argtypes = [cp, ctypes.c_int, ctypes.POINTER(sz)]
+    L.pgk_batch_create.argtypes = [cp, ctypes.c_int, vp, vp, sz, ctypes.POINTER(vp)]
+    L.pgk_batch_offsets.argtypes = [vp, ctypes.POINTER(i64)]
+    L.pgk_batch_init.argtypes = [vp, vp, vp, vp, vp]
+    L.pgk_batch_config.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.pgk_batch_run.argtypes = [vp, i64, ctypes.c_double, ctypes.POINTER(i64), dp, ctypes.POINTER(ctypes.c_int)]
+    L.pgk_batch_tuned.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), dp]
+    L.pgk_batch_read_moments.argtypes = [vp, vp, vp, vp, vp]
+    L.pgk_batch_last_error.argtypes = [vp]
+    L.pgk_batch_last_error.restype = ctypes.c_char_p
+    L.pgk_batch_destroy.argtypes = [vp]
+    L.pgk_batch_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("pgk_steps_done", "pgk_last_error", "pgk_destroy"):
+        if name not in ("pgk_steps_done", "pgk_last_error", "pgk_destroy", "pgk_batch_last_error",
+                        "pgk_batch_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -1,0 +1,650 @@
+// batch.hip -- batched sweep of independent 1D cases in one persistent launch.
+//
+// Each work-group owns one case (a line of L cells, 2L sites, x faces bounded)
+// and advances it K steps: ghost fill, fused pull-collide, MacCormack and
+// diffusion of theta_R, separated by work-group barriers.  At the last two
+// steps of a chunk it takes the f-moments, so the one-step change of rho,
+// u_axis, theta_T and theta_R gives the residual; a case whose residual falls
+// to the tolerance, or whose density or temperature turns non-positive or
+// non-finite, freezes itself.  The host replays one HIP graph per chunk and
+// reads back only the small per-case status arrays.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <sys/stat.h>
+#include <vector>
+
+#include "device.hpp"
+
+namespace pgk {
+
+struct BatchCase {
+    Consts k;
+    long long off;      // first site of the case
+    int vel_axis, variant;
+};
+
+struct BatchArgs {
+    const BatchCase *cases;
+    const int *order;   // slot -> case, longest first
+    int *status;
+    long long *steps;
+    int *cur;
+    double *resid;
+    double *popA, *popB, *thR, *that_, *tmc, *tmc2, *aux, *snap, *gh;
+    long long max_steps;
+    double tol;
+};
+
+constexpr int GHOSTS_PER_CASE = 2 * NQ * NSLOT;   // ny = nz = 1
+
+template <int NV, int NTH>
+__device__ __forceinline__ void block_sum_n(double *val)
+{
+    // sum over the work-group; every thread gets the result
+    __shared__ double red[NTH / 64][NV];
+    for (int off = 32; off > 0; off >>= 1)
+        for (int c = 0; c < NV; c++) val[c] += __shfl_xor(val[c], off, 64);
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int c = 0; c < NV; c++) red[wv][c] = val[c];
+    __syncthreads();
+    for (int c = 0; c < NV; c++) {
+        double t = 0.0;
+        for (int i = 0; i < NTH / 64; i++) t += red[i][c];
+        val[c] = t;
+    }
+    __syncthreads();
+}
+
+template <int VAR, int NTH>
+__global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
+{
+    const int c = a.order[blockIdx.x];
+    if (a.status[c] != PGK_CASE_RUNNING) return;
+    const BatchCase &bc = a.cases[c];
+    const Consts &k = bc.k;
+    const long long off = bc.off;
+    double *pA = a.popA + (size_t)NQ * off, *pB = a.popB + (size_t)NQ * off;
+    double *thR = a.thR + off, *that_ = a.that_ + off, *tmc = a.tmc + off, *tmc2 = a.tmc2 + off;
+    double *aux = a.aux + (size_t)5 * off, *snap = a.snap + (size_t)4 * off;
+    double *gh = a.gh + (size_t)c * GHOSTS_PER_CASE;
+    const int ns = k.ns, tid = threadIdx.x;
+    int cur = a.cur[c];
+    long long steps = a.steps[c];
+    double resid = a.resid[c];
+    bool bad = false;
+
+    for (int j = 0; j < K; j++) {
+        const double *src = cur ? pB : pA;
+        double *dst = cur ? pA : pB;
+        if (steps > 0 && tid < 2) bc_column<double>(tid, 0, src, gh, k);
+        __syncthreads();
+        for (int s = tid; s < ns; s += NTH) {
+            double r;
+            lb_site<double, double, VAR, true>(s, src, dst, gh, thR, that_, aux, k, r);
+        }
+        __syncthreads();
+        for (int s = tid; s < ns; s += NTH) mc_site<double, true>(s, that_, aux, tmc, k);
+        __syncthreads();
+        {
+            double *tin = tmc, *tout = tmc2;
+            for (int it = 0; it + 1 < k.nsub; it++) {
+                for (int s = tid; s < ns; s += NTH) dif_site<double, VAR, true, false>(s, tin, tout, that_, aux, thR, k);
+                __syncthreads();
+                double *t = tin;
+                tin = tout;
+                tout = t;
+            }
+            for (int s = tid; s < ns; s += NTH) dif_site<double, VAR, true, true>(s, tin, tout, that_, aux, thR, k);
+        }
+        __syncthreads();
+        cur ^= 1;
+        steps++;
+        if (j >= K - 2) {
+            // moments of the new state: refresh the ghosts it pulls from
+            const double *nsrc = cur ? pB : pA;
+            if (tid < 2) bc_column<double>(tid, 0, nsrc, gh, k);
+            __syncthreads();
+            double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            for (int s = tid; s < ns; s += NTH) {
+                Mom m;
+                Solve so = moments_site<double, true>(s, nsrc, gh, thR, k, m);
+                double ua = bc.vel_axis == 0 ? so.u[0] : (bc.vel_axis == 1 ? so.u[1] : so.u[2]);
+                double phi[4] = {so.rho, ua, so.T, so.r};
+                if (!(so.rho > 0.0) || !(so.T > 0.0) || !(so.r > 0.0) || !isfinite(so.u[0]) ||
+                    !isfinite(so.u[1]) || !isfinite(so.u[2]))
+                    acc[8] = 1.0;
+                if (j == K - 2) {
+                    for (int i = 0; i < 4; i++) snap[(size_t)i * ns + s] = phi[i];
+                } else {
+                    for (int i = 0; i < 4; i++) {
+                        double d = phi[i] - snap[(size_t)i * ns + s];
+                        acc[i] += d * d;
+                        acc[4 + i] += phi[i] * phi[i];
+                    }
+                }
+            }
+            block_sum_n<9, NTH>(acc);
+            if (acc[8] > 0.0) bad = true;
+            if (j == K - 1) {
+                resid = 0.0;
+                for (int i = 0; i < 4; i++) resid = fmax(resid, sqrt(acc[i] / fmax(acc[4 + i], 1e-300)));
+            }
+        }
+    }
+    if (tid == 0) {
+        a.cur[c] = cur;
+        a.steps[c] = steps;
+        a.resid[c] = resid;
+        int st = PGK_CASE_RUNNING;
+        if (bad || !isfinite(resid)) st = PGK_CASE_DIVERGED;
+        else if (resid <= a.tol) st = PGK_CASE_CONVERGED;
+        else if (steps >= a.max_steps) st = PGK_CASE_MAXSTEPS;
+        a.status[c] = st;
+    }
+}
+
+template <int NTH>
+__global__ __launch_bounds__(NTH) void k_batch_init(BatchArgs a, const double *__restrict__ rho,
+                                                    const double *__restrict__ u, const double *__restrict__ thT,
+                                                    const double *__restrict__ thRin, long long ns_total)
+{
+    const int c = blockIdx.x;
+    const BatchCase &bc = a.cases[c];
+    const Consts &k = bc.k;
+    const long long off = bc.off;
+    double *dst = a.popA + (size_t)NQ * off;
+    double *gh = a.gh + (size_t)c * GHOSTS_PER_CASE;
+    // the case's slices of the input fields; u is [3][ns_total]
+    for (int s = threadIdx.x; s < k.ns; s += NTH)
+        init_site<double, true>(s, dst, gh, a.thR + off, rho + off, u + off, thT + off, thRin + off, k,
+                                (size_t)ns_total);
+    if (threadIdx.x == 0) {
+        a.status[c] = PGK_CASE_RUNNING;
+        a.steps[c] = 0;
+        a.cur[c] = 0;
+        a.resid[c] = 1.0;
+    }
+}
+
+template <int NTH>
+__global__ __launch_bounds__(NTH) void k_batch_moments(BatchArgs a, double *__restrict__ orho,
+                                                       double *__restrict__ ou, double *__restrict__ othT,
+                                                       double *__restrict__ othR, long long ns_total)
+{
+    const int c = blockIdx.x;
+    const BatchCase &bc = a.cases[c];
+    const Consts &k = bc.k;
+    const long long off = bc.off;
+    const double *src = (a.cur[c] ? a.popB : a.popA) + (size_t)NQ * off;
+    double *gh = a.gh + (size_t)c * GHOSTS_PER_CASE;
+    if (a.steps[c] > 0 && threadIdx.x < 2) bc_column<double>(threadIdx.x, 0, src, gh, k);
+    __syncthreads();
+    for (int s = threadIdx.x; s < k.ns; s += NTH) {
+        Mom m;
+        Solve so = moments_site<double, true>(s, src, gh, a.thR + off, k, m);
+        if (orho) orho[off + s] = so.rho;
+        if (ou)
+            for (int i = 0; i < 3; i++) ou[i * ns_total + off + s] = so.u[i];
+        if (othT) othT[off + s] = so.T;
+        if (othR) othR[off + s] = so.r;
+    }
+}
+
+}  // namespace pgk
+
+using namespace pgk;
+
+struct pgk_batch {
+    int n = 0;
+    long long ns_total = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<BatchCase> host_cases;
+    std::vector<long long> off;
+    BatchArgs args{};
+    int wg = 0, K = 0;            // fixed config (0 = tune)
+    int tuned_wg = 0, tuned_K = 0;
+    double tuned_ns = 0.0;
+    std::map<long long, hipGraphExec_t> graphs;   // key wg*100000 + K
+    int *h_status = nullptr;
+    long long *h_steps = nullptr;
+    double *h_resid = nullptr;
+    std::string err;
+    ~pgk_batch()
+    {
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
+        if (h_status) (void)hipHostFree(h_status);
+        if (h_steps) (void)hipHostFree(h_steps);
+        if (h_resid) (void)hipHostFree(h_resid);
+        if (own_stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+static int bfail(pgk_batch *b, int code, const std::string &m)
+{
+    if (b) b->err = m;
+    return code;
+}
+
+#define BHIP(b, call)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return bfail(b, PGK_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct BatchLayout {
+    size_t cases, order, status, steps, cur, resid, popA, popB, thR, that_, tmc, tmc2, aux, snap, gh, total;
+};
+
+static BatchLayout layout(int n, long long ns)
+{
+    BatchLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o += al256(bytes); return at; };
+    L.cases = take(sizeof(BatchCase) * n);
+    L.order = take(sizeof(int) * n);
+    L.status = take(sizeof(int) * n);
+    L.steps = take(sizeof(long long) * n);
+    L.cur = take(sizeof(int) * n);
+    L.resid = take(sizeof(double) * n);
+    L.popA = take(8ull * NQ * ns);
+    L.popB = take(8ull * NQ * ns);
+    L.thR = take(8ull * ns);
+    L.that_ = take(8ull * ns);
+    L.tmc = take(8ull * ns);
+    L.tmc2 = take(8ull * ns);
+    L.aux = take(8ull * 5 * ns);
+    L.snap = take(8ull * 4 * ns);
+    L.gh = take(8ull * GHOSTS_PER_CASE * n);
+    L.total = o;
+    return L;
+}
+
+static bool case_ok(const pgk_case &c)
+{
+    if (c.L < 4 || c.L > 8192) return false;
+    if (c.bc != PGK_WALL && c.bc != PGK_DIRICHLET) return false;
+    if (c.vel_axis < 0 || c.vel_axis > 2) return false;
+    if (c.variant != PGK_CN && c.variant != PGK_LIT) return false;
+    const pgk_params &p = c.p;
+    if (!(p.tau > 0) || !(p.tau1 > 0) || !(p.delta > 0) || p.b < -0.5 || p.b > 1.0 || !(p.kr >= 0)) return false;
+    for (int s = 0; s < 2; s++) {
+        if (!(c.theta[s] > 0)) return false;
+        if (c.bc == PGK_DIRICHLET && !(c.rho[s] > 0)) return false;
+        if (c.bc == PGK_WALL && c.u[s][0] != 0.0) return false;
+    }
+    return true;
+}
+
+extern "C" int pgk_batch_bytes(const pgk_case *cases, int n, size_t *bytes)
+{
+    if (!cases || n <= 0 || !bytes) return PGK_EINVAL;
+    long long ns = 0;
+    for (int i = 0; i < n; i++) {
+        if (!case_ok(cases[i])) return PGK_EINVAL;
+        ns += 2LL * cases[i].L;
+    }
+    *bytes = layout(n, ns).total;
+    return PGK_OK;
+}
+
+// model constants of one case, as pgk_set_params derives them for a grid
+static Consts case_consts(const pgk_case &cs)
+{
+    Consts k{};
+    k.nx = cs.L; k.ny = 1; k.nz = 1; k.ns = 2 * cs.L;
+    k.bc[0] = k.bc[1] = cs.bc;
+    magic_div((unsigned)k.nx, k.mx, k.shx);
+    magic_div(1u, k.my, k.shy);
+    magic_div(1u, k.mz, k.shz);
+    const pgk_params &p = cs.p;
+    k.th0 = p.theta0 > 0 ? p.theta0 : THETA0_PRINTED;
+    shell_weights(k.th0, k.w);
+    for (int i = 0; i < 6; i++) {
+        k.whi[i] = (float)k.w[i];
+        k.wlo[i] = (float)(k.w[i] - (double)k.whi[i]);
+    }
+    k.tau = p.tau; k.tau1 = p.tau1; k.b = p.b; k.delta = p.delta;
+    double taus = p.tau * p.tau1 / (p.tau + p.tau1), B = 1.0 + p.tau / p.tau1;
+    k.beta = 1.0 / (2.0 * taus + 1.0);
+    k.X = 3.0 / (2.0 * p.tau1 * (3.0 + p.delta));
+    k.Y = p.delta / (2.0 * p.tau1 * (3.0 + p.delta));
+    k.ssig = 1.0 + 1.0 / (2.0 * taus) - p.b / (2.0 * p.tau);
+    k.kfac = p.kr * 5.0 * p.tau / (2.0 * B);
+    k.inv1X = 1.0 / (1.0 + k.X);
+    k.inv1XY = 1.0 / (1.0 + k.X + k.Y);
+    k.inv3d = 1.0 / (3.0 + p.delta);
+    k.wt1 = p.tau1 / (p.tau + p.tau1);
+    k.wt = p.tau / (p.tau + p.tau1);
+    k.bs = p.b / k.ssig;
+    double t = k.th0;
+    k.it = 1.0 / t; k.i2t = 1.0 / (2.0 * t); k.ih2 = 1.0 / (2.0 * t * t);
+    k.i6t3 = 1.0 / (6.0 * t * t * t); k.i2t3 = 1.0 / (2.0 * t * t * t); k.it2 = 1.0 / (t * t);
+    for (int side = 0; side < 2; side++) {
+        k.thbc[side] = cs.theta[side];
+        k.rhobc[side] = cs.bc == PGK_WALL ? 1.0 : cs.rho[side];
+        f3_host(k.th0, k.w, k.rhobc[side], cs.u[side], k.thbc[side], k.Fbc[side]);
+        double in = 0.0;
+        for (int q = 0; q < NQ; q++)
+            for (int sub = 0; sub < 2; sub++)
+                for (int x = 0; x < k.nx; x++) {
+                    int qx = 2 * x + sub - c2(q, 0);
+                    if (side == 0 ? qx < 0 : qx > 2 * k.nx - 1) in += k.Fbc[side][q];
+                }
+        k.in_col[side] = in;
+    }
+    k.nsub = diffusion_substeps(k, p.kr);
+    k.isub = 1.0 / k.nsub;
+    return k;
+}
+
+extern "C" int pgk_batch_create(const pgk_case *cases, int n, void *stream, void *buf, size_t bytes, pgk_batch **out)
+{
+    if (!out) return PGK_EINVAL;
+    *out = nullptr;
+    size_t need;
+    int rc = pgk_batch_bytes(cases, n, &need);
+    if (rc) return rc;
+    if (!buf || bytes < need || ((uintptr_t)buf & 255)) return PGK_EINVAL;
+    pgk_batch *b = new pgk_batch();
+    b->n = n;
+    b->stream = (hipStream_t)stream;
+    if (!b->stream) {
+        // graph capture needs a stream other than the null stream
+        if (hipStreamCreate(&b->stream) != hipSuccess) { delete b; return PGK_EDEVICE; }
+        b->own_stream = true;
+    }
+    long long o = 0;
+    b->off.resize(n + 1);
+    for (int i = 0; i < n; i++) {
+        BatchCase bc{};
+        bc.k = case_consts(cases[i]);
+        bc.off = o;
+        bc.vel_axis = cases[i].vel_axis;
+        bc.variant = cases[i].variant;
+        b->host_cases.push_back(bc);
+        b->off[i] = o;
+        o += 2LL * cases[i].L;
+    }
+    b->off[n] = o;
+    b->ns_total = o;
+    BatchLayout L = layout(n, o);
+    char *base = (char *)buf;
+    BatchArgs &a = b->args;
+    a.cases = (const BatchCase *)(base + L.cases);
+    a.order = (const int *)(base + L.order);
+    a.status = (int *)(base + L.status);
+    a.steps = (long long *)(base + L.steps);
+    a.cur = (int *)(base + L.cur);
+    a.resid = (double *)(base + L.resid);
+    a.popA = (double *)(base + L.popA);
+    a.popB = (double *)(base + L.popB);
+    a.thR = (double *)(base + L.thR);
+    a.that_ = (double *)(base + L.that_);
+    a.tmc = (double *)(base + L.tmc);
+    a.tmc2 = (double *)(base + L.tmc2);
+    a.aux = (double *)(base + L.aux);
+    a.snap = (double *)(base + L.snap);
+    a.gh = (double *)(base + L.gh);
+    // slots ordered by size, longest first (the cost model: work per step)
+    std::vector<int> order(n);
+    for (int i = 0; i < n; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cases[x].L > cases[y].L; });
+    hipError_t e1 = hipMemcpyAsync((void *)a.cases, b->host_cases.data(), sizeof(BatchCase) * n,
+                                   hipMemcpyHostToDevice, b->stream);
+    hipError_t e2 = hipMemcpyAsync((void *)a.order, order.data(), sizeof(int) * n, hipMemcpyHostToDevice, b->stream);
+    hipError_t e3 = hipStreamSynchronize(b->stream);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) { delete b; return PGK_EDEVICE; }
+    if (hipHostMalloc((void **)&b->h_status, sizeof(int) * n) != hipSuccess ||
+        hipHostMalloc((void **)&b->h_steps, sizeof(long long) * n) != hipSuccess ||
+        hipHostMalloc((void **)&b->h_resid, sizeof(double) * n) != hipSuccess) {
+        delete b;
+        return PGK_EDEVICE;
+    }
+    *out = b;
+    return PGK_OK;
+}
+
+extern "C" int pgk_batch_offsets(const pgk_batch *b, int64_t *off)
+{
+    if (!b || !off) return PGK_EINVAL;
+    for (int i = 0; i <= b->n; i++) off[i] = b->off[i];
+    return PGK_OK;
+}
+
+extern "C" int pgk_batch_init(pgk_batch *b, const double *rho, const double *u, const double *thT, const double *thR)
+{
+    if (!b || !rho || !u || !thT || !thR) return PGK_EINVAL;
+    hipLaunchKernelGGL(k_batch_init<256>, dim3(b->n), dim3(256), 0, b->stream, b->args, rho, u, thT, thR,
+                       b->ns_total);
+    BHIP(b, hipGetLastError());
+    BHIP(b, hipStreamSynchronize(b->stream));
+    return PGK_OK;
+}
+
+extern "C" int pgk_batch_config(pgk_batch *b, int wg, int K)
+{
+    if (!b) return PGK_EINVAL;
+    if (!(wg == 0 && K == 0) && !((wg == 256 || wg == 512) && K >= 2)) return bfail(b, PGK_EINVAL, "bad config");
+    b->wg = wg;
+    b->K = K;
+    return PGK_OK;
+}
+
+static int chunk(pgk_batch *b, int wg, int K, int variant)
+{
+    long long key = (long long)wg * 100000 + K * 10 + variant;
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+        hipGraph_t g;
+        BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        if (variant == PGK_CN) {
+            if (wg == 256) hipLaunchKernelGGL((k_batch<PGK_CN, 256>), dim3(b->n), dim3(256), 0, b->stream, b->args, K);
+            else hipLaunchKernelGGL((k_batch<PGK_CN, 512>), dim3(b->n), dim3(512), 0, b->stream, b->args, K);
+        } else {
+            if (wg == 256) hipLaunchKernelGGL((k_batch<PGK_LIT, 256>), dim3(b->n), dim3(256), 0, b->stream, b->args, K);
+            else hipLaunchKernelGGL((k_batch<PGK_LIT, 512>), dim3(b->n), dim3(512), 0, b->stream, b->args, K);
+        }
+        BHIP(b, hipStreamEndCapture(b->stream, &g));
+        hipGraphExec_t ge;
+        BHIP(b, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        it = b->graphs.emplace(key, ge).first;
+    }
+    BHIP(b, hipGraphLaunch(it->second, b->stream));
+    return PGK_OK;
+}
+
+static int readback(pgk_batch *b)
+{
+    BHIP(b, hipMemcpyAsync(b->h_status, b->args.status, sizeof(int) * b->n, hipMemcpyDeviceToHost, b->stream));
+    BHIP(b, hipMemcpyAsync(b->h_steps, b->args.steps, sizeof(long long) * b->n, hipMemcpyDeviceToHost, b->stream));
+    BHIP(b, hipMemcpyAsync(b->h_resid, b->args.resid, sizeof(double) * b->n, hipMemcpyDeviceToHost, b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    return PGK_OK;
+}
+
+// ---- autotuner cache: a flat JSON object {"key": [wg, K], ...} ----------------
+static std::string cache_path()
+{
+    const char *p = getenv("PGK_TUNE_CACHE");
+    if (p && *p) return p;
+    const char *h = getenv("HOME");
+    return std::string(h ? h : "/tmp") + "/.cache/pgk_tune.json";
+}
+
+static std::map<std::string, std::pair<int, int>> cache_load()
+{
+    std::map<std::string, std::pair<int, int>> m;
+    FILE *f = fopen(cache_path().c_str(), "r");
+    if (!f) return m;
+    std::string s;
+    char buf[4096];
+    size_t r;
+    while ((r = fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, r);
+    fclose(f);
+    size_t i = 0;
+    while ((i = s.find('"', i)) != std::string::npos) {
+        size_t j = s.find('"', i + 1);
+        if (j == std::string::npos) break;
+        std::string key = s.substr(i + 1, j - i - 1);
+        int wg = 0, K = 0;
+        if (sscanf(s.c_str() + j + 1, " : [ %d , %d ]", &wg, &K) == 2) m[key] = {wg, K};
+        i = j + 1;
+    }
+    return m;
+}
+
+static void cache_store(const std::map<std::string, std::pair<int, int>> &m)
+{
+    std::string path = cache_path();
+    size_t slash = path.rfind('/');
+    if (slash != std::string::npos) (void)mkdir(path.substr(0, slash).c_str(), 0755);
+    FILE *f = fopen(path.c_str(), "w");
+    if (!f) return;
+    fprintf(f, "{\n");
+    size_t i = 0;
+    for (auto &e : m) fprintf(f, "  \"%s\": [%d, %d]%s\n", e.first.c_str(), e.second.first, e.second.second,
+                              ++i < m.size() ? "," : "");
+    fprintf(f, "}\n");
+    fclose(f);
+}
+
+static std::string tune_key(const pgk_batch *b)
+{
+    hipDeviceProp_t prop;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipGetDeviceProperties(&prop, dev);
+    long long maxL = 0;
+    for (auto &c : b->host_cases) maxL = std::max<long long>(maxL, c.k.nx);
+    char key[256];
+    // arch, number of cases (log2 bucket), longest case (log2 bucket), variant
+    int nb = 0, lb = 0;
+    while ((1 << nb) < b->n) nb++;
+    while ((1LL << lb) < maxL) lb++;
+    snprintf(key, sizeof key, "%s/batch/n%d/L%d/v%d", prop.gcnArchName, nb, lb, b->host_cases[0].variant);
+    for (char *p = key; *p; p++)
+        if (*p == '"' || *p == ':') *p = '_';
+    return key;
+}
+
+extern "C" int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_t *steps, double *resid, int *status)
+{
+    if (!b || max_steps < 1 || !(tol >= 0)) return PGK_EINVAL;
+    int variant = b->host_cases[0].variant;
+    for (auto &c : b->host_cases)
+        if (c.variant != variant) return bfail(b, PGK_EINVAL, "one variant per batch");
+    b->args.max_steps = max_steps;
+    b->args.tol = tol;
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);   // args changed
+    b->graphs.clear();
+    int rc = readback(b);
+    if (rc) return rc;
+    auto running = [&]() {
+        long long act = 0;
+        for (int i = 0; i < b->n; i++)
+            if (b->h_status[i] == PGK_CASE_RUNNING) act += b->host_cases[i].k.ns;
+        return act;
+    };
+    int wg = b->wg, K = b->K;
+    if (wg == 0) {
+        std::string key = tune_key(b);
+        auto cache = cache_load();
+        auto hit = cache.find(key);
+        if (hit != cache.end()) {
+            wg = hit->second.first;
+            K = hit->second.second;
+        } else {
+            // time one chunk of every candidate on the live state
+            const int cand[][2] = {{256, 32}, {512, 32}, {256, 128}, {512, 128}};
+            double best = 1e300;
+            hipEvent_t e0, e1;
+            BHIP(b, hipEventCreate(&e0));
+            BHIP(b, hipEventCreate(&e1));
+            for (auto &cd : cand) {
+                long long act = running();
+                if (act == 0) break;
+                BHIP(b, hipEventRecord(e0, b->stream));
+                rc = chunk(b, cd[0], cd[1], variant);
+                if (rc) return rc;
+                BHIP(b, hipEventRecord(e1, b->stream));
+                BHIP(b, hipEventSynchronize(e1));
+                float ms = 0.f;
+                BHIP(b, hipEventElapsedTime(&ms, e0, e1));
+                double nsps = ms * 1e6 / ((double)act * cd[1]);
+                if (nsps < best) { best = nsps; wg = cd[0]; K = cd[1]; }
+                rc = readback(b);
+                if (rc) return rc;
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            if (wg == 0) { wg = 256; K = 128; }
+            b->tuned_ns = best;
+            cache[key] = {wg, K};
+            cache_store(cache);
+        }
+    }
+    b->tuned_wg = wg;
+    b->tuned_K = K;
+    // replay chunks until every case has stopped
+    hipEvent_t t0, t1;
+    BHIP(b, hipEventCreate(&t0));
+    BHIP(b, hipEventCreate(&t1));
+    double site_updates = 0.0, ms_total = 0.0;
+    while (true) {
+        long long act = running();
+        if (act == 0) break;
+        BHIP(b, hipEventRecord(t0, b->stream));
+        rc = chunk(b, wg, K, variant);
+        if (rc) return rc;
+        BHIP(b, hipEventRecord(t1, b->stream));
+        rc = readback(b);
+        if (rc) return rc;
+        float ms = 0.f;
+        BHIP(b, hipEventElapsedTime(&ms, t0, t1));
+        ms_total += ms;
+        site_updates += (double)act * K;
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (site_updates > 0) b->tuned_ns = ms_total * 1e6 / site_updates;
+    for (int i = 0; i < b->n; i++) {
+        if (steps) steps[i] = b->h_steps[i];
+        if (resid) resid[i] = b->h_resid[i];
+        if (status) status[i] = b->h_status[i];
+    }
+    return PGK_OK;
+}
+
+extern "C" int pgk_batch_tuned(const pgk_batch *b, int *wg, int *K, double *ns)
+{
+    if (!b) return PGK_EINVAL;
+    if (wg) *wg = b->tuned_wg;
+    if (K) *K = b->tuned_K;
+    if (ns) *ns = b->tuned_ns;
+    return PGK_OK;
+}
+
+extern "C" int pgk_batch_read_moments(pgk_batch *b, double *rho, double *u, double *thT, double *thR)
+{
+    if (!b) return PGK_EINVAL;
+    hipLaunchKernelGGL(k_batch_moments<256>, dim3(b->n), dim3(256), 0, b->stream, b->args, rho, u, thT, thR,
+                       b->ns_total);
+    BHIP(b, hipGetLastError());
+    return PGK_OK;
+}
+
+extern "C" const char *pgk_batch_last_error(const pgk_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+extern "C" void pgk_batch_destroy(pgk_batch *b) { delete b; }

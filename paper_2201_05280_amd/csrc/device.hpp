@@ -1,0 +1,654 @@
+// device.hpp -- device code shared by the single-grid kernels (pgk.hip) and
+// the batched kernel (batch.hip): constants, pull indexing, moments, the
+// per-site solve, the F3 equilibrium and collide, theta_R transport stencils,
+// boundary ghosts, initial state and moments.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdint>
+
+#include "pgk.h"
+#include "lattice.hpp"
+
+namespace pgk {
+
+constexpr int WG = 256;
+constexpr int NSLOT = 4;  // ghost slots per x face: doubled x offsets 1..4 beyond the face
+
+struct Consts {
+    int nx, ny, nz, ns;
+    int bc[2];
+    double th0;
+    double w[6];            // shell weights
+    float whi[6], wlo[6];   // the same as float hi + lo parts (w = whi + wlo to ~1e-15)
+    double tau, tau1, b, delta;
+    double X, Y, ssig, beta, kfac;
+    double thbc[2], rhobc[2];
+    double Fbc[2][NQ];      // wall equilibrium at unit density / Dirichlet equilibrium
+    double in_col[2];       // re-emitted mass per ghost column at unit wall density
+    // division by nx, ny, nz: q = (umulhi(n, m) + n) >> sh for n < 2^31
+    unsigned mx, my, mz;
+    int shx, shy, shz;
+    // per-step constants computed once on the host
+    double inv1X, inv1XY, inv3d;  // 1/(1+X), 1/(1+X+Y), 1/(3+delta)
+    double wt1, wt, bs;           // tau1/(tau+tau1), tau/(tau+tau1), b/s_sigma
+    double it, i2t, ih2, i6t3, i2t3, it2;  // 1/t, 1/(2t), 1/(2t^2), 1/(6t^3), 1/(2t^3), 1/t^2 with t = theta0
+    int nsub;                     // FTCS sub-steps of the theta_R diffusion per step
+    double isub;                  // 1/nsub
+};
+
+// Sub-steps that keep the explicit (FTCS) diffusion of theta_R stable: it
+// needs 2 dim D_R dt <= dx^2, D_R = 2 kappa_R/(rho delta) = 5 k_r theta tau/(B delta),
+// taken at 1.5 times the largest of theta0 and the face temperatures.  One
+// sub-step is the printed scheme.
+__host__ inline int diffusion_substeps(const Consts &k, double kr)
+{
+    int dim = (k.nx > 1) + (k.ny > 1) + (k.nz > 1);
+    double th = k.th0;
+    for (int side = 0; side < 2; side++)
+        if (k.bc[side] != PGK_PERIODIC && k.thbc[side] > th) th = k.thbc[side];
+    double B = 1.0 + k.tau / k.tau1;
+    double DR = k.delta > 0 ? 5.0 * kr * th * k.tau / (B * k.delta) : 0.0;
+    int n = (int)std::ceil(2.0 * dim * DR * 1.5);
+    return n < 1 ? 1 : n;
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned fdiv(unsigned n, unsigned m, int sh)
+{
+    return (__umulhi(n, m) + n) >> sh;
+}
+
+__device__ __forceinline__ void decode(int s, const Consts &k, int &x, int &y, int &z, int &sub)
+{
+    unsigned t = fdiv((unsigned)s, k.mx, k.shx);
+    x = s - (int)t * k.nx;
+    unsigned t2 = fdiv(t, k.my, k.shy);
+    y = (int)t - (int)t2 * k.ny;
+    unsigned t3 = fdiv(t2, k.mz, k.shz);
+    z = (int)t2 - (int)t3 * k.nz;
+    sub = (int)t3;
+}
+
+// wrap x + d into [0, n) for |d| <= 2 and any n >= 1
+__device__ __forceinline__ int wrap2(int v, int n)
+{
+    v += (v < 0) ? n : 0;
+    v += (v < 0) ? n : 0;
+    v -= (v >= n) ? n : 0;
+    v -= (v >= n) ? n : 0;
+    return v;
+}
+
+// Offsets of the pull sources of one site on a periodic grid.  Integer
+// velocities stay on the own sublattice at coordinate offsets -c (|c| <= 2);
+// half velocities come from the other sublattice, at offset -1 or 0 along an
+// axis for corner sites and 0 or +1 for body-centre sites.
+struct Off5 {
+    int m2, m1, z0, p1, p2;
+    template <int D> __device__ __forceinline__ int at() const
+    {
+        if constexpr (D == -2) return m2;
+        else if constexpr (D == -1) return m1;
+        else if constexpr (D == 0) return z0;
+        else if constexpr (D == 1) return p1;
+        else return p2;
+    }
+};
+
+struct PullMap {
+    int own, oth;                 // offsets of the own and the other sublattice
+    Off5 X, Y, Z;                 // wrapped x, y*nx, z*nx*ny for offsets -2..2
+    int hx[2], hy[2], hz[2];      // half velocities: [0] for c > 0, [1] for c < 0
+};
+
+__device__ __forceinline__ PullMap pull_map(int x, int y, int z, int sub, const Consts &k)
+{
+    PullMap p;
+    int plane = k.nx * k.ny, subsz = plane * k.nz;
+    p.own = sub * subsz;
+    p.oth = (1 - sub) * subsz;
+    p.X = {wrap2(x - 2, k.nx), wrap2(x - 1, k.nx), x, wrap2(x + 1, k.nx), wrap2(x + 2, k.nx)};
+    p.Y = {wrap2(y - 2, k.ny) * k.nx, wrap2(y - 1, k.ny) * k.nx, y * k.nx, wrap2(y + 1, k.ny) * k.nx,
+           wrap2(y + 2, k.ny) * k.nx};
+    p.Z = {wrap2(z - 2, k.nz) * plane, wrap2(z - 1, k.nz) * plane, z * plane, wrap2(z + 1, k.nz) * plane,
+           wrap2(z + 2, k.nz) * plane};
+    bool b = sub != 0;
+    p.hx[0] = b ? p.X.z0 : p.X.m1; p.hx[1] = b ? p.X.p1 : p.X.z0;
+    p.hy[0] = b ? p.Y.z0 : p.Y.m1; p.hy[1] = b ? p.Y.p1 : p.Y.z0;
+    p.hz[0] = b ? p.Z.z0 : p.Z.m1; p.hz[1] = b ? p.Z.p1 : p.Z.z0;
+    return p;
+}
+
+template <int Q>
+__device__ __forceinline__ unsigned pull_off(const PullMap &p)
+{
+    constexpr int cx = c2(Q, 0), cy = c2(Q, 1), cz = c2(Q, 2);
+    if constexpr ((cx & 1) == 0) {
+        return (unsigned)(p.own + p.Z.template at<-cz / 2>() + p.Y.template at<-cy / 2>() + p.X.template at<-cx / 2>());
+    } else {
+        return (unsigned)(p.oth + p.hz[cz > 0 ? 0 : 1] + p.hy[cy > 0 ? 0 : 1] + p.hx[cx > 0 ? 0 : 1]);
+    }
+}
+
+template <typename S, int Q = 0>
+__device__ __forceinline__ void load_periodic(const S *__restrict__ src, const PullMap &p, int ns, S *v)
+{
+    if constexpr (Q < NQ) {
+        const S *__restrict__ base = src + (size_t)Q * ns;
+        v[Q] = base[pull_off<Q>(p)];
+        load_periodic<S, Q + 1>(src, p, ns, v);
+    }
+}
+
+__device__ __forceinline__ int wrapc(int i, int n)
+{
+    // offsets are at most 2 cells: one correction suffices for n >= 2; n == 1 maps to 0
+    if (n == 1) return 0;
+    i += (i < 0) ? n : 0;
+    i -= (i >= n) ? n : 0;
+    if (i < 0) i += n;      // n == 2 with offset -2
+    if (i >= n) i -= n;
+    return i;
+}
+
+
+// Index of the population q pulled by site (x,y,z,sub): returns the array
+// index and sets `ghost` (0 = interior, 1 = low-x ghost, 2 = high-x ghost).
+template <int Q, bool BOUNDED>
+__device__ __forceinline__ int pull_index(int x, int y, int z, int sub, const Consts &k, int &ghost)
+{
+    constexpr int cx = c2(Q, 0), cy = c2(Q, 1), cz = c2(Q, 2);
+    int qx = 2 * x + sub - cx, qy = 2 * y + sub - cy, qz = 2 * z + sub - cz;
+    int ssub = qx & 1;
+    int sx = (qx - ssub) >> 1, sy = wrapc((qy - ssub) >> 1, k.ny), sz = wrapc((qz - ssub) >> 1, k.nz);
+    ghost = 0;
+    if (BOUNDED) {
+        if (qx < 0 && k.bc[0] != PGK_PERIODIC) {
+            ghost = 1;
+            int slot = -qx - 1;
+            return ((0 * NQ + Q) * NSLOT + slot) * k.nz * k.ny + sz * k.ny + sy;
+        }
+        if (qx > 2 * k.nx - 1 && k.bc[1] != PGK_PERIODIC) {
+            ghost = 2;
+            int slot = qx - 2 * k.nx;
+            return ((1 * NQ + Q) * NSLOT + slot) * k.nz * k.ny + sz * k.ny + sy;
+        }
+    }
+    sx = wrapc(sx, k.nx);
+    return ((ssub * k.nz + sz) * k.ny + sy) * k.nx + sx;
+}
+
+template <typename S, bool BOUNDED, int Q>
+__device__ __forceinline__ void load_one(const S *__restrict__ src, const S *__restrict__ gh,
+                                         int x, int y, int z, int sub, const Consts &k, S *v)
+{
+    int ghost;
+    int idx = pull_index<Q, BOUNDED>(x, y, z, sub, k, ghost);
+    if (BOUNDED && ghost) v[Q] = gh[idx];
+    else v[Q] = src[(size_t)Q * k.ns + idx];
+}
+
+template <typename S, bool BOUNDED, int Q = 0>
+__device__ __forceinline__ void load_all(const S *__restrict__ src, const S *__restrict__ gh,
+                                         int x, int y, int z, int sub, const Consts &k, S *v)
+{
+    if constexpr (Q < NQ) {
+        load_one<S, BOUNDED, Q>(src, gh, x, y, z, sub, k, v);
+        load_all<S, BOUNDED, Q + 1>(src, gh, x, y, z, sub, k, v);
+    }
+}
+
+// Sums over the stored values v (g, or h = g - w): rho, j, Pi.
+struct Mom {
+    double rho, j[3], P[6];  // P: xx yy zz xy xz yz
+};
+
+template <typename S, int P = 0>
+__device__ __forceinline__ void accumulate(const S *v, Mom &m)
+{
+    if constexpr (P < NPAIR) {
+        constexpr int cx = Lattice::REP2[P][0], cy = Lattice::REP2[P][1], cz = Lattice::REP2[P][2];
+        double a = (double)v[1 + P], b = (double)v[1 + NPAIR + P];
+        double s = a + b, d = a - b;
+        m.rho += s;
+        if (cx) m.j[0] += (0.5 * cx) * d;
+        if (cy) m.j[1] += (0.5 * cy) * d;
+        if (cz) m.j[2] += (0.5 * cz) * d;
+        if (cx) m.P[0] += (0.25 * cx * cx) * s;
+        if (cy) m.P[1] += (0.25 * cy * cy) * s;
+        if (cz) m.P[2] += (0.25 * cz * cz) * s;
+        if (cx * cy) m.P[3] += (0.25 * cx * cy) * s;
+        if (cx * cz) m.P[4] += (0.25 * cx * cz) * s;
+        if (cy * cz) m.P[5] += (0.25 * cy * cz) * s;
+        accumulate<S, P + 1>(v, m);
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ Mom moments(const S *v, const Consts &k)
+{
+    Mom m;
+    m.rho = (double)v[0];
+    m.j[0] = m.j[1] = m.j[2] = 0.0;
+    for (int i = 0; i < 6; i++) m.P[i] = 0.0;
+    accumulate<S>(v, m);
+    if (sizeof(S) == 4) {
+        // deviations from w_i (rho0 = 1): add the moments of the weights
+        m.rho += 1.0;
+        m.P[0] += k.th0;
+        m.P[1] += k.th0;
+        m.P[2] += k.th0;
+    }
+    return m;
+}
+
+// Per-site solve (Sec. 5): g->f temperature map with the backward-Euler half
+// relaxation, stress rescale, ES and BGK targets.  Everything in double.
+struct Solve {
+    double rho, u[3], a, r, T, R, theta;
+    double sg[6];   // sigma(g)
+    double lamF[6]; // covariance of the gain term F
+};
+
+__device__ __forceinline__ Solve site_solve(const Mom &m, double r, const Consts &k)
+{
+    Solve s;
+    s.rho = m.rho;
+    double ir = 1.0 / m.rho;
+    for (int a = 0; a < 3; a++) s.u[a] = m.j[a] * ir;
+    double uu = s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2];
+    s.a = (m.P[0] + m.P[1] + m.P[2] - m.rho * uu) * ir * (1.0 / 3.0);
+    s.sg[0] = m.P[0] - m.rho * s.u[0] * s.u[0] - m.rho * s.a;
+    s.sg[1] = m.P[1] - m.rho * s.u[1] * s.u[1] - m.rho * s.a;
+    s.sg[2] = m.P[2] - m.rho * s.u[2] * s.u[2] - m.rho * s.a;
+    s.sg[3] = m.P[3] - m.rho * s.u[0] * s.u[1];
+    s.sg[4] = m.P[4] - m.rho * s.u[0] * s.u[2];
+    s.sg[5] = m.P[5] - m.rho * s.u[1] * s.u[2];
+    s.r = r;
+    // a = T + Y (T - R),  R = (r + X T)/(1 + X)
+    s.T = (s.a * (1.0 + k.X) + k.Y * r) * k.inv1XY;
+    s.R = (r + k.X * s.T) * k.inv1X;
+    s.theta = (3.0 * s.T + k.delta * s.R) * k.inv3d;
+    // lam_ES = T I + b sigma(f)/rho, sigma(f) = sigma(g)/s_sigma;
+    // lam_F = (tau1 lam_ES + tau theta I)/(tau + tau1)
+    double cb = k.wt1 * k.bs * ir;
+    double iso = k.wt1 * s.T + k.wt * s.theta;
+    for (int i = 0; i < 6; i++) s.lamF[i] = (i < 3 ? iso : 0.0) + cb * s.sg[i];
+    return s;
+}
+
+// F3 coefficients in compute precision R.
+template <typename R>
+struct Eq {
+    R u0, u1, u2;       // velocity
+    R Du0, Du1, Du2;    // (lam - theta0 I) u
+    R D0, D1, D2, D3, D4, D5;
+    R k0;               // (u^2 + tr D)/(2 theta0)
+    R A1;               // 1/theta0 - (u^2 + tr D)/(2 theta0^2)
+    R k2;               // 1/(2 theta0^2)
+    R k3;               // 1/(6 theta0^3)
+    R k4;               // 1/(2 theta0^3)
+    R k5;               // 1/theta0^2
+    R rho, drho;        // rho, rho - 1
+    R omb, tb;          // 1 - 2 beta, 2 beta
+};
+
+template <typename R>
+__device__ __forceinline__ Eq<R> make_eq(const Solve &s, const Consts &k)
+{
+    double t = k.th0;
+    double D[6];
+    for (int i = 0; i < 6; i++) D[i] = s.lamF[i] - (i < 3 ? t : 0.0);
+    double uu = s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2];
+    double trD = D[0] + D[1] + D[2];
+    Eq<R> e;
+    e.u0 = (R)s.u[0]; e.u1 = (R)s.u[1]; e.u2 = (R)s.u[2];
+    e.Du0 = (R)(D[0] * s.u[0] + D[3] * s.u[1] + D[4] * s.u[2]);
+    e.Du1 = (R)(D[3] * s.u[0] + D[1] * s.u[1] + D[5] * s.u[2]);
+    e.Du2 = (R)(D[4] * s.u[0] + D[5] * s.u[1] + D[2] * s.u[2]);
+    e.D0 = (R)D[0]; e.D1 = (R)D[1]; e.D2 = (R)D[2]; e.D3 = (R)D[3]; e.D4 = (R)D[4]; e.D5 = (R)D[5];
+    e.k0 = (R)((uu + trD) * k.i2t);
+    e.A1 = (R)(k.it - (uu + trD) * k.ih2);
+    e.k2 = (R)k.ih2;
+    e.k3 = (R)k.i6t3;
+    e.k4 = (R)k.i2t3;
+    e.k5 = (R)k.it2;
+    e.rho = (R)s.rho;
+    e.drho = (R)(s.rho - 1.0);
+    e.omb = (R)(1.0 - 2.0 * k.beta);
+    e.tb = (R)(2.0 * k.beta);
+    return e;
+}
+
+// Collide the pair (+c_P, -c_P) and the rest population, write the own site.
+template <typename S, int P = 0>
+__device__ __forceinline__ void collide_store(S *v, const Eq<S> &e, const Consts &k, S *__restrict__ dst, int s)
+{
+    if constexpr (P < NPAIR) {
+        constexpr int cx = Lattice::REP2[P][0], cy = Lattice::REP2[P][1], cz = Lattice::REP2[P][2];
+        constexpr S hx = (S)(0.5 * cx), hy = (S)(0.5 * cy), hz = (S)(0.5 * cz);
+        S cu = hx * e.u0 + hy * e.u1 + hz * e.u2;
+        S cDc = hx * hx * e.D0 + hy * hy * e.D1 + hz * hz * e.D2
+              + (S)2 * (hx * hy * e.D3 + hx * hz * e.D4 + hy * hz * e.D5);
+        S cDu = hx * e.Du0 + hy * e.Du1 + hz * e.Du2;
+        S even = (cu * cu + cDc) * e.k2 - e.k0;
+        S odd = cu * e.A1 + cu * cu * cu * e.k3 + cDc * cu * e.k4 - cDu * e.k5;
+        if constexpr (sizeof(S) == 4) {
+            // deviation form: F - w = w [(rho - 1) + rho (even +- odd)], with w
+            // carried as hi + lo floats so the rounding of w adds no bias to the
+            // moments of F; h* = h + 2 beta (F - w - h) conserves the moments of
+            // the collision whatever the rounding of 2 beta
+            S wh = k.whi[Lattice::SHELL[P]], wl = k.wlo[Lattice::SHELL[P]];
+            S Xp = e.drho + e.rho * (even + odd), Xm = e.drho + e.rho * (even - odd);
+            S Fp = wh * Xp + wl * Xp, Fm = wh * Xm + wl * Xm;
+            // the next read of these values is a step away: stream them past the caches
+            __builtin_nontemporal_store(v[1 + P] + e.tb * (Fp - v[1 + P]), &dst[(size_t)(1 + P) * k.ns + s]);
+            __builtin_nontemporal_store(v[1 + NPAIR + P] + e.tb * (Fm - v[1 + NPAIR + P]),
+                                        &dst[(size_t)(1 + NPAIR + P) * k.ns + s]);
+        } else {
+            S w = (S)k.w[Lattice::SHELL[P]];
+            S Fp = w * e.rho * ((S)1 + even + odd);
+            S Fm = w * e.rho * ((S)1 + even - odd);
+            __builtin_nontemporal_store(e.omb * v[1 + P] + e.tb * Fp, &dst[(size_t)(1 + P) * k.ns + s]);
+            __builtin_nontemporal_store(e.omb * v[1 + NPAIR + P] + e.tb * Fm, &dst[(size_t)(1 + NPAIR + P) * k.ns + s]);
+        }
+        collide_store<S, P + 1>(v, e, k, dst, s);
+    } else {
+        if constexpr (sizeof(S) == 4) {
+            S X0 = e.drho - e.rho * e.k0;
+            S F0 = k.whi[0] * X0 + k.wlo[0] * X0;
+            __builtin_nontemporal_store(v[0] + e.tb * (F0 - v[0]), &dst[s]);
+        } else {
+            S w0 = (S)k.w[0];
+            __builtin_nontemporal_store(e.omb * v[0] + e.tb * (w0 * e.rho * ((S)1 - e.k0)), &dst[s]);
+        }
+    }
+}
+
+// block-wide sum of NV doubles; thread 0 of the block gets the result
+template <int NV>
+__device__ __forceinline__ void block_sum(double *val, double *out)
+{
+    __shared__ double red[WG / 64][NV];
+    for (int off = 32; off > 0; off >>= 1)
+        for (int c = 0; c < NV; c++) val[c] += __shfl_xor(val[c], off, 64);
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int c = 0; c < NV; c++) red[wv][c] = val[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < NV; c++) {
+            double t = 0.0;
+            for (int i = 0; i < WG / 64; i++) t += red[i][c];
+            out[c] = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-site bodies shared by the single-grid kernels and the batched kernel
+// ---------------------------------------------------------------------------
+// fused pull - moments - solve - equilibrium - collide of site s; returns the
+// moments of g (time level n) and the stored theta_R in r_out
+template <typename S, typename A, int VAR, bool BOUNDED>
+__device__ __forceinline__ Mom lb_site(int s, const S *__restrict__ src, S *__restrict__ dst,
+                                       const S *__restrict__ gh, double *__restrict__ thR,
+                                       double *__restrict__ that_, A *__restrict__ aux, const Consts &k,
+                                       double &r_out)
+{
+    int x, y, z, sub;
+    decode(s, k, x, y, z, sub);
+    S v[NQ];
+    if constexpr (BOUNDED) load_all<S, true>(src, gh, x, y, z, sub, k, v);
+    else load_periodic<S>(src, pull_map(x, y, z, sub, k), k.ns, v);
+    double r = thR[s];
+    Mom m = moments<S>(v, k);
+    Solve so = site_solve(m, r, k);
+    Eq<S> e = make_eq<S>(so, k);
+    collide_store<S>(v, e, k, dst, s);
+    that_[s] = so.R;                                  // theta_R after step 1
+    if (VAR == PGK_LIT) thR[s] = so.T;                // the printed second half needs theta_T
+    aux[s] = (A)so.u[0];
+    aux[(size_t)k.ns + s] = (A)so.u[1];
+    aux[(size_t)2 * k.ns + s] = (A)so.u[2];
+    aux[(size_t)3 * k.ns + s] = (A)so.rho;
+    aux[(size_t)4 * k.ns + s] = (A)(so.rho * so.theta);
+    r_out = r;
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// theta_R transport
+// ---------------------------------------------------------------------------
+// same-sublattice neighbour along axis a (0,1,2) by dir (+-1); returns -1 / -2
+// for the low / high x ghost of a bounded face
+template <bool BOUNDED>
+__device__ __forceinline__ int nbr(int x, int y, int z, int sub, int a, int dir, const Consts &k)
+{
+    if (a == 0) {
+        x += dir;
+        if (BOUNDED) {
+            if (x < 0 && k.bc[0] != PGK_PERIODIC) return -1;
+            if (x >= k.nx && k.bc[1] != PGK_PERIODIC) return -2;
+        }
+        x = wrapc(x, k.nx);
+    } else if (a == 1) {
+        y = wrapc(y + dir, k.ny);
+    } else {
+        z = wrapc(z + dir, k.nz);
+    }
+    return ((sub * k.nz + z) * k.ny + y) * k.nx + x;
+}
+
+template <typename A, bool BOUNDED>
+__device__ __forceinline__ double theta_star(const double *__restrict__ th, const A *__restrict__ aux,
+                                             int idx, const Consts &k)
+{
+    // predictor at site idx (forward differences); ghosts keep their value
+    if (BOUNDED && idx < 0) return idx == -1 ? k.thbc[0] : k.thbc[1];
+    int x, y, z, sub;
+    decode(idx, k, x, y, z, sub);
+    double t = th[idx], adv = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        int p = nbr<BOUNDED>(x, y, z, sub, a, +1, k);
+        double tp = (BOUNDED && p < 0) ? (p == -1 ? k.thbc[0] : k.thbc[1]) : th[p];
+        adv += (double)aux[(size_t)a * k.ns + idx] * (tp - t);
+    }
+    return t - adv;
+}
+
+template <typename A, bool BOUNDED>
+__device__ __forceinline__ void mc_site(int s, const double *__restrict__ that_, const A *__restrict__ aux,
+                                        double *__restrict__ tmc, const Consts &k)
+{
+    int x, y, z, sub;
+    decode(s, k, x, y, z, sub);
+    double ts = theta_star<A, BOUNDED>(that_, aux, s, k);
+    double adv = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        int m = nbr<BOUNDED>(x, y, z, sub, a, -1, k);
+        double tm = theta_star<A, BOUNDED>(that_, aux, m, k);
+        adv += (double)aux[(size_t)a * k.ns + s] * (ts - tm);
+    }
+    tmc[s] = 0.5 * (that_[s] + ts - adv);
+}
+
+// one FTCS sub-step of the theta_R diffusion from tin; the last sub-step
+// (FINAL) also applies the second half of the relaxation and writes theta_R
+template <typename A, int VAR, bool BOUNDED, bool FINAL>
+__device__ __forceinline__ void dif_site(int s, const double *__restrict__ tin, double *__restrict__ tout,
+                                         const double *__restrict__ that_, const A *__restrict__ aux,
+                                         double *__restrict__ thR, const Consts &k)
+{
+    int x, y, z, sub;
+    decode(s, k, x, y, z, sub);
+    double rho = (double)aux[(size_t)3 * k.ns + s];
+    double ks = k.kfac * (double)aux[(size_t)4 * k.ns + s];
+    double t = tin[s];
+    double flux = 0.0, lap = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int dir = -1; dir <= 1; dir += 2) {
+            int q = nbr<BOUNDED>(x, y, z, sub, a, dir, k);
+            double tq, kq;
+            if (BOUNDED && q < 0) {
+                bool hi = q == -2;
+                tq = hi ? k.thbc[1] : k.thbc[0];
+                bool wall = (hi ? k.bc[1] : k.bc[0]) == PGK_WALL;
+                double rg = wall ? rho : (hi ? k.rhobc[1] : k.rhobc[0]);
+                kq = k.kfac * rg * tq;
+            } else {
+                tq = tin[q];
+                kq = k.kfac * (double)aux[(size_t)4 * k.ns + q];
+            }
+            flux += 0.5 * (ks + kq) * (tq - t);
+            lap += tq - t;
+        }
+    double tdif = VAR == PGK_CN ? t + k.isub * 2.0 * flux / (rho * k.delta)
+                                : t + k.isub * 2.0 * ks / (rho * k.delta) * lap;
+    if constexpr (!FINAL) {
+        tout[s] = tdif;
+    } else {
+        double v = thR[s];
+        if (VAR == PGK_CN) thR[s] = tdif + (that_[s] - v);   // second half: repeat R - r
+        else thR[s] = (tdif + k.X * v) * k.inv1X;            // backward Euler, as printed
+    }
+}
+
+// ghost populations of x face `side`, column col (diffuse wall: density of the
+// re-emitted populations from zero net mass flux through the face in the last
+// collision; Dirichlet: the equilibrium of the ghost state)
+template <typename S>
+__device__ __forceinline__ void bc_column(int side, int col, const S *__restrict__ src, S *__restrict__ gh,
+                                          const Consts &k)
+{
+    int ncol = k.ny * k.nz;
+    if (k.bc[side] == PGK_PERIODIC) return;
+    int gy = col % k.ny, gz = col / k.ny;
+    double scale = 1.0;
+    if (k.bc[side] == PGK_WALL) {
+        double out = 0.0;
+        for (int q = 1; q < NQ; q++) {
+            int cx = c2(q, 0), cy = c2(q, 1), cz = c2(q, 2);
+            if ((side == 0 && cx >= 0) || (side == 1 && cx <= 0)) continue;
+            for (int sub = 0; sub < 2; sub++)
+                for (int xi = 0; xi < 2; xi++) {
+                    int x = side == 0 ? xi : k.nx - 1 - xi;
+                    if (x < 0 || x >= k.nx) continue;
+                    if (xi == 1 && k.nx == 1) continue;
+                    int dx = 2 * x + sub + cx;
+                    bool crosses = side == 0 ? dx < 0 : dx > 2 * k.nx - 1;
+                    if (!crosses) continue;
+                    // ghost column of the destination: floor((2y + sub + cy)/2) = y + floor((sub + cy)/2)
+                    int ky = (sub + cy) >= 0 ? (sub + cy) / 2 : -((-(sub + cy) + 1) / 2);
+                    int kz = (sub + cz) >= 0 ? (sub + cz) / 2 : -((-(sub + cz) + 1) / 2);
+                    int y = wrapc(gy - ky, k.ny), z = wrapc(gz - kz, k.nz);
+                    if (k.ny == 1) y = 0;
+                    if (k.nz == 1) z = 0;
+                    int s = ((sub * k.nz + z) * k.ny + y) * k.nx + x;
+                    out += (double)src[(size_t)q * k.ns + s] + (sizeof(S) == 4 ? k.w[shell_of(q)] : 0.0);
+                }
+        }
+        scale = out / k.in_col[side];
+    }
+    for (int q = 0; q < NQ; q++) {
+        double val = scale * k.Fbc[side][q] - (sizeof(S) == 4 ? k.w[shell_of(q)] : 0.0);
+        for (int slot = 0; slot < NSLOT; slot++)
+            gh[((side * NQ + q) * NSLOT + slot) * ncol + col] = (S)val;
+    }
+}
+
+// push F_i(rho, u, theta_T I) of site s to where the next pull reads it:
+// population i of site x is read from position x - c_i (a ghost slot when that
+// lies beyond a bounded face)
+template <typename S, bool BOUNDED>
+__device__ __forceinline__ void init_site(int s, S *__restrict__ dst, S *__restrict__ gh, double *__restrict__ thR,
+                                          const double *__restrict__ rho, const double *__restrict__ u,
+                                          const double *__restrict__ thT, const double *__restrict__ thRin,
+                                          const Consts &k, size_t ustride)
+{
+    int x, y, z, sub;
+    decode(s, k, x, y, z, sub);
+    Solve so;
+    so.rho = rho[s];
+    so.u[0] = u[s];
+    so.u[1] = u[ustride + s];
+    so.u[2] = u[2 * ustride + s];
+    for (int i = 0; i < 6; i++) so.lamF[i] = i < 3 ? thT[s] : 0.0;
+    Eq<double> e = make_eq<double>(so, k);
+    thR[s] = thRin[s];
+    for (int q = 0; q < NQ; q++) {
+        int cx = c2(q, 0), cy = c2(q, 1), cz = c2(q, 2);
+        double hx = 0.5 * cx, hy = 0.5 * cy, hz = 0.5 * cz;
+        double cu = hx * e.u0 + hy * e.u1 + hz * e.u2;
+        double cDc = hx * hx * e.D0 + hy * hy * e.D1 + hz * hz * e.D2 + 2.0 * (hx * hy * e.D3 + hx * hz * e.D4 + hy * hz * e.D5);
+        double cDu = hx * e.Du0 + hy * e.Du1 + hz * e.Du2;
+        double even = (cu * cu + cDc) * e.k2 - e.k0;
+        double odd = cu * e.A1 + cu * cu * cu * e.k3 + cDc * cu * e.k4 - cDu * e.k5;
+        double w = k.w[shell_of(q)];
+        double F = w * e.rho * (1.0 + even + odd);
+        S val = (S)(sizeof(S) == 4 ? w * (e.drho + e.rho * (even + odd)) : F);
+        // destination: position x - c_q
+        int qx = 2 * x + sub - cx, qy = 2 * y + sub - cy, qz = 2 * z + sub - cz;
+        int ssub = qx & 1;
+        int sy = wrapc((qy - ssub) >> 1, k.ny), sz = wrapc((qz - ssub) >> 1, k.nz);
+        if (BOUNDED && qx < 0 && k.bc[0] != PGK_PERIODIC) {
+            gh[((0 * NQ + q) * NSLOT + (-qx - 1)) * k.nz * k.ny + sz * k.ny + sy] = val;
+        } else if (BOUNDED && qx > 2 * k.nx - 1 && k.bc[1] != PGK_PERIODIC) {
+            gh[((1 * NQ + q) * NSLOT + (qx - 2 * k.nx)) * k.nz * k.ny + sz * k.ny + sy] = val;
+        } else {
+            int sx = wrapc((qx - ssub) >> 1, k.nx);
+            dst[(size_t)q * k.ns + ((ssub * k.nz + sz) * k.ny + sy) * k.nx + sx] = val;
+        }
+    }
+}
+
+// f-moments of site s at the current time level (after the g -> f map)
+template <typename S, bool BOUNDED>
+__device__ __forceinline__ Solve moments_site(int s, const S *__restrict__ src, const S *__restrict__ gh,
+                                              const double *__restrict__ thR, const Consts &k, Mom &m)
+{
+    int x, y, z, sub;
+    decode(s, k, x, y, z, sub);
+    S v[NQ];
+    if constexpr (BOUNDED) load_all<S, true>(src, gh, x, y, z, sub, k, v);
+    else load_periodic<S>(src, pull_map(x, y, z, sub, k), k.ns, v);
+    m = moments<S>(v, k);
+    return site_solve(m, thR[s], k);
+}
+
+// F3 on the host for boundary equilibria: rho, u, isotropic temperature theta
+static inline void f3_host(double th0, const double w6[6], double rho, const double u[3], double theta, double F[NQ])
+{
+    double D = theta - th0;
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double trD = 3.0 * D;
+    for (int q = 0; q < NQ; q++) {
+        double c[3] = {0.5 * c2(q, 0), 0.5 * c2(q, 1), 0.5 * c2(q, 2)};
+        double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+        double cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+        double cDc = D * cc, cDu = D * cu;
+        double a2 = cu * cu + cDc - th0 * (uu + trD);
+        double a3 = cu * cu * cu + 3.0 * cDc * cu - th0 * (3.0 * uu * cu + 6.0 * cDu + 3.0 * trD * cu);
+        F[q] = w6[shell_of(q)] * rho * (1.0 + cu / th0 + a2 / (2 * th0 * th0) + a3 / (6 * th0 * th0 * th0));
+    }
+}
+
+// magic numbers for q = (umulhi(n, m) + n) >> sh = n / d, valid for n < 2^31
+static inline void magic_div(unsigned d, unsigned &m, int &sh)
+{
+    int s = 0;
+    while ((1ull << s) < d) s++;
+    m = (unsigned)((((1ull << 32) * ((1ull << s) - d)) / d) + 1);
+    sh = s;
+}
+
+}  // namespace pgk

@@ -1,0 +1,192 @@
+"""Batched sweep (persistent kernel + graph replay + autotuner) on the GPU.
+
+Each batched case must equal the same case run alone through the single-grid
+path (the same device code in double precision: identical up to the few-ulp
+differences of the compiler's FMA contraction in the two kernels) and the FP64
+oracle (1e-12); convergence, divergence and the tuner are exercised on small
+cases.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.params import resolve
+from paper_2201_05280_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TH0 = oracle.THETA0
+
+
+def _cases():
+    import paper_2201_05280_amd as pgk
+    out = []
+    specs = [
+        # (L, bc, targets, faces)
+        (24, pgk.WALL, (0.05, 0.71, 0.8, 2.0), dict(u=((0, 0, 0), (0, 0.05, 0)), theta=(TH0, TH0 * 1.02))),
+        (37, pgk.WALL, (0.2, 0.9, 1.2, 3.0), dict(u=((0, -0.02, 0), (0, 0.03, 0.01)), theta=(TH0, TH0))),
+        (4, pgk.WALL, (0.02, 0.7, 0.6, 2.0), dict(u=((0, 0, 0), (0, 0.02, 0)), theta=(TH0, TH0))),
+        (64, pgk.DIRICHLET, (0.05, 0.71, 0.8, 2.0),
+         dict(rho=(1.02, 0.99), u=((0.03, 0, 0), (0.03, 0, 0)), theta=(TH0 * 1.01, TH0))),
+        (19, pgk.DIRICHLET, (0.1, 1.0, 1.0, 3.0),
+         dict(rho=(1.0, 1.05), u=((0.02, 0, 0), (0.019, 0, 0)), theta=(TH0, TH0 * 1.03))),
+    ]
+    for L, bc, tg, faces in specs:
+        p = resolve(*tg)
+        out.append(dict(L=L, bc=bc, p=p, faces=faces, vel_axis=1 if bc == pgk.WALL else 0))
+    return out
+
+
+def _fields(L, seed, bc):
+    f = inputs.random_smooth(L, 1, 1, seed=seed, amp_rho=0.01, amp_u=0.01, amp_th=0.01)
+    return f
+
+
+def _build(specs, variant=0):
+    import paper_2201_05280_amd as pgk
+    from paper_2201_05280_amd.batch import Batch, make_case
+    cases = []
+    for sp in specs:
+        p = sp["p"]
+        fc = sp["faces"]
+        cases.append(make_case(sp["L"], sp["bc"], (p["tau"], p["tau1"], p["b"], p["kr"], p["delta"]),
+                               rho=fc.get("rho", (1.0, 1.0)), u=fc["u"], theta=fc["theta"],
+                               vel_axis=sp["vel_axis"], variant=variant))
+    b = Batch(cases)
+    fields = [_fields(sp["L"], 10 + i, sp["bc"]) for i, sp in enumerate(specs)]
+    cat = {k: np.concatenate([f[k] for f in fields], axis=-1) for k in ("rho", "thT", "thR")}
+    cat["u"] = np.concatenate([f["u"] for f in fields], axis=1)
+    b.init(cat["rho"], cat["u"], cat["thT"], cat["thR"])
+    return b, fields
+
+
+def _single(sp, f, steps, variant=0):
+    import paper_2201_05280_amd as pgk
+    s = pgk.Solver(sp["L"], 1, 1, precision=pgk.FP64, variant=variant, bc_x=(sp["bc"], sp["bc"]))
+    p = sp["p"]
+    s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    fc = sp["faces"]
+    for side in (0, 1):
+        s.set_bc_x(side, fc.get("rho", (1.0, 1.0))[side], fc["u"][side], fc["theta"][side])
+    s.init(f["rho"], f["u"], f["thT"], f["thR"])
+    s.step(steps)
+    m = s.moments()
+    s.close()
+    return m
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_batched_cases_equal_single_grid_runs(variant):
+    specs = _cases()
+    b, fields = _build(specs, variant)
+    b.config(256, 20)
+    steps, resid, status = b.run(60, 0.0)
+    assert (steps == 60).all(), steps
+    assert (status == 3).all(), status                 # stopped at max_steps
+    bm = b.moments()
+    for c, sp in enumerate(specs):
+        sl = b.case_slice(c)
+        sm = _single(sp, fields[c], 60, variant)
+        for k in ("rho", "thT", "thR"):
+            err = np.abs(bm[k][sl] - sm[k]).max() / np.abs(sm[k]).max()
+            assert err <= 1e-13, (c, k, err)
+        err = np.abs(bm["u"][:, sl] - sm["u"]).max() / max(np.abs(sm["u"]).max(), 1e-2)
+        assert err <= 1e-13, (c, "u", err)
+    b.close()
+
+
+def test_batched_cases_match_oracle():
+    specs = _cases()
+    b, fields = _build(specs)
+    b.config(512, 25)
+    b.run(50, 0.0)
+    bm = b.moments()
+    for c, sp in enumerate(specs):
+        sl = b.case_slice(c)
+        o = oracle.Oracle(sp["L"], 1, 1)
+        p = sp["p"]
+        o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+        fc = sp["faces"]
+        for side in (0, 1):
+            o.set_bc_x(side, sp["bc"], fc.get("rho", (1.0, 1.0))[side], fc["u"][side], fc["theta"][side])
+        f = fields[c]
+        o.init(f["rho"], f["u"], f["thT"], f["thR"])
+        o.step(50)
+        om = o.moments()
+        for k in ("rho", "thT", "thR"):
+            err = np.abs(bm[k][sl] - om[k]).max() / np.abs(om[k]).max()
+            assert err < 1e-12, (c, k, err)
+        err = np.abs(bm["u"][:, sl] - om["u"]).max() / max(np.abs(om["u"]).max(), 1e-2)
+        assert err < 1e-12, (c, "u", err)
+    b.close()
+
+
+def test_couette_case_converges_to_linear_profile():
+    import paper_2201_05280_amd as pgk
+    from paper_2201_05280_amd.batch import Batch, make_case
+    L, U = 16, 0.03
+    p = resolve(0.5, 0.71, 0.8, 2.0)                 # large viscosity: fast diffusion
+    c = make_case(L, pgk.WALL, (p["tau"], p["tau1"], p["b"], p["kr"], p["delta"]),
+                  u=((0, 0, 0), (0, U, 0)), theta=(TH0, TH0), vel_axis=1)
+    b = Batch([c])
+    f = inputs.uniform(L, 1, 1)
+    b.init(f["rho"], f["u"], f["thT"], f["thR"])
+    b.config(256, 50)
+    steps, resid, status = b.run(200000, 1e-10)
+    assert status[0] == 1, (status, resid, steps)
+    assert resid[0] <= 1e-10
+    m = b.moments()
+    x = inputs.positions(L, 1, 1)[0]
+    uy = m["u"][1]
+    order = np.argsort(x)
+    assert np.all(np.diff(uy[order]) > 0)            # monotonic shear profile
+    # walls at x = -1/4 and L - 1/4: the profile is linear between slip values
+    fit = np.polyfit(x, uy, 1)
+    assert np.abs(np.polyval(fit, x) - uy).max() < 0.02 * U
+    mid = np.polyval(fit, (L - 0.5) / 2)
+    assert abs(mid - U / 2) < 0.02 * U
+    b.close()
+
+
+def test_divergence_is_flagged_per_case():
+    specs = _cases()[:3]
+    b, fields = _build(specs)
+    # plant a non-finite density in case 1 from the host (a single negative
+    # density is smoothed away by the streaming; a NaN cannot be)
+    sl = b.case_slice(1)
+    rho = np.concatenate([f["rho"] for f in fields])
+    rho[sl.start + 3] = np.nan
+    u = np.concatenate([f["u"] for f in fields], axis=1)
+    thT = np.concatenate([f["thT"] for f in fields])
+    thR = np.concatenate([f["thR"] for f in fields])
+    b.init(rho, u, thT, thR)
+    b.config(256, 10)
+    steps, resid, status = b.run(40, 0.0)
+    assert status[1] == 2, status
+    assert status[0] == 3 and status[2] == 3, status
+    assert steps[1] == 10 and steps[0] == 40
+    b.close()
+
+
+def test_autotuner_picks_and_caches(tmp_path, monkeypatch):
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("PGK_TUNE_CACHE", str(cache))
+    specs = _cases()
+    b, _ = _build(specs)
+    b.config(0, 0)
+    steps, resid, status = b.run(300, 0.0)
+    wg, K, ns = b.tuned()
+    assert wg in (256, 512) and K >= 2 and ns > 0
+    d = json.loads(cache.read_text())
+    assert len(d) == 1 and list(d.values())[0] == [wg, K]
+    assert (steps >= 300).all()
+    b.close()
+    # a second batch of the same shape reuses the cached choice
+    b2, _ = _build(specs)
+    b2.config(0, 0)
+    b2.run(40, 0.0)
+    assert b2.tuned()[:2] == (wg, K)
+    b2.close()

@@ -430,3 +430,23 @@ def test_thermal_mode_is_carried_by_a_uniform_flow():
     speedR = np.polyfit(t[50:], phR[50:], 1)[0] / k
     assert abs(speed / U - 1) < 0.02, speed
     assert abs(speedR / U - 1) < 0.02, speedR
+
+
+def test_subcycled_diffusion_is_stable_and_keeps_the_thermal_rate():
+    # nu = 0.5 on a 1D grid: D_R = 0.93 > 1/2, the single FTCS step is unstable;
+    # three sub-steps (ceil(2 * 1 * 0.9307 * 1.5)) restore stability
+    p = resolve(0.5, 0.71, 0.6, 2.0)
+    co = coefficients(**p)
+    nx = 64
+    k = 2 * np.pi / nx
+    o = oracle.Oracle(nx, 1, 1)
+    o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    assert o.substeps() == 3
+    f = inputs.temperature_wave(nx, 1, 1, eps=1e-4)
+    C = np.cos(k * inputs.positions(nx, 1, 1)[0])
+    d = p["delta"]
+    th, _ = _run_1d(f, p, nx, 400, lambda m: 2 * np.mean((3 * m["thT"] + d * m["thR"]) / (3 + d) * C))
+    assert np.isfinite(th).all()
+    t = np.arange(len(th))
+    rate = -np.polyfit(t[80:], np.log(th[80:]), 1)[0]
+    assert abs(rate / (co["alpha"] * k * k) - 1) < 0.03, rate

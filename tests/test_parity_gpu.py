@@ -174,3 +174,18 @@ def test_bitwise_determinism_fp64():
         s.close()
     for k in outs[0]:
         assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
+def test_subcycled_diffusion_paths(precision, bar):
+    # large viscosity: several FTCS sub-steps per step, both for a periodic
+    # grid (the unfused transport path) and for diffuse walls
+    import paper_2201_05280_amd as pgk
+    p = resolve(0.5, 0.71, 0.8, 2.0)
+    f = inputs.random_smooth(10, 6, 1, seed=21)
+    errs, _ = run_pair(10, 6, 1, f, p, 40, precision, checkpoints=[1, 40])
+    _assert_bar(errs, bar, "subcycled periodic")
+    th0 = oracle.THETA0
+    bc = [(pgk.WALL, 1.0, (0.0, 0.0, 0.0), th0), (pgk.WALL, 1.0, (0.0, 0.04, 0.0), th0 * 1.05)]
+    errs, _ = run_pair(20, 1, 1, inputs.uniform(20, 1, 1), p, 60, precision, bc=bc, checkpoints=[1, 60])
+    _assert_bar(errs, bar, "subcycled walls")
