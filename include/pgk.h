@@ -232,6 +232,38 @@ int pgk_batch_read_moments(pgk_batch *b, double *rho, double *u, double *theta_T
 const char *pgk_batch_last_error(const pgk_batch *b);
 void pgk_batch_destroy(pgk_batch *b);
 
+/* ------------------------------------------------------------------------
+ * Coordinate MLP of the learned warm start: 6 inputs (normalised x/L, Ma, Pr,
+ * mu_b/mu, log10 Kn, delta) -> 4 hidden layers of 128 with SiLU -> 4 outputs
+ * (normalised rho, u, theta_T, theta_R).  Weights and activations enter the
+ * products as bfloat16 (round to nearest even), products accumulate in FP32;
+ * FP32 master weights and Adam.  Parameters are one flat FP32 vector:
+ * W1[128][6], b1[128], W2[128][128], b2, W3, b3, W4, b4, W5[4][128], b5[4].
+ * Loss: mean squared error over points and outputs.  X is [n][6], Y [n][4],
+ * row-major FP32 device arrays.  One device buffer (pgk_mlp_bytes) holds the
+ * parameters, the Adam state and the activations of up to nmax points.
+ * ------------------------------------------------------------------------ */
+#define PGK_MLP_NPARAM 50948
+typedef struct pgk_mlp pgk_mlp;
+int pgk_mlp_bytes(int nmax, size_t *bytes);
+int pgk_mlp_create(void *stream, void *buf, size_t bytes, int nmax, pgk_mlp **out);
+/* theta: device vector of PGK_MLP_NPARAM floats; resets the Adam state */
+int pgk_mlp_set_params(pgk_mlp *m, const float *theta);
+int pgk_mlp_get_params(pgk_mlp *m, float *theta);
+/* inference of n points (any n, processed nmax at a time) */
+int pgk_mlp_forward(pgk_mlp *m, const float *X, float *Y, int n);
+/* mean loss (host, synchronises) and its gradient (device, may be NULL) on n <= nmax points */
+int pgk_mlp_loss_grad(pgk_mlp *m, const float *X, const float *Y, int n, float *grad, float *loss);
+/* one Adam update with the gradient of the last pgk_mlp_loss_grad */
+int pgk_mlp_adam_step(pgk_mlp *m, float lr, float beta1, float beta2, float eps);
+/* epochs of minibatch Adam (beta 0.9, 0.999, eps 1e-8) over n points in
+ * contiguous minibatches visited in a seeded random order; loss_per_epoch
+ * (host, may be NULL) receives the mean minibatch loss of each epoch */
+int pgk_mlp_train(pgk_mlp *m, const float *X, const float *Y, int64_t n, int batch, int epochs, float lr,
+                  uint64_t seed, float *loss_per_epoch);
+const char *pgk_mlp_last_error(const pgk_mlp *m);
+void pgk_mlp_destroy(pgk_mlp *m);
+
 /* Steps taken since the last pgk_init_fields. */
 int64_t pgk_steps_done(const pgk_ctx *ctx);
 

@@ -25,7 +25,10 @@ EXPORTS = ["pgk_resolve", "pgk_buffer_sizes", "pgk_create", "pgk_bind", "pgk_set
            "pgk_set_timing", "pgk_kernel_times", "pgk_steps_done", "pgk_last_error", "pgk_destroy",
            "pgk_batch_bytes", "pgk_batch_create", "pgk_batch_offsets", "pgk_batch_init", "pgk_batch_config",
            "pgk_batch_run", "pgk_batch_tuned", "pgk_batch_read_moments", "pgk_batch_last_error",
-           "pgk_batch_destroy"]
+           "pgk_batch_destroy", "pgk_mlp_bytes", "pgk_mlp_create", "pgk_mlp_set_params", "pgk_mlp_get_params",
+           "pgk_mlp_forward", "pgk_mlp_loss_grad", "pgk_mlp_adam_step", "pgk_mlp_train", "pgk_mlp_last_error",
+           "pgk_mlp_destroy"]
+MLP_NPARAM = 50948
 CASE_RUNNING, CASE_CONVERGED, CASE_DIVERGED, CASE_MAXSTEPS = 0, 1, 2, 3
 NKERNEL = 4
 KERNEL_NAMES = ["k_lb", "k_mc", "k_dif", "k_bc"]
@@ -110,9 +113,22 @@ def load():
     L.pgk_batch_last_error.restype = ctypes.c_char_p
     L.pgk_batch_destroy.argtypes = [vp]
     L.pgk_batch_destroy.restype = None
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.pgk_mlp_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(sz)]
+    L.pgk_mlp_create.argtypes = [vp, vp, sz, ctypes.c_int, ctypes.POINTER(vp)]
+    L.pgk_mlp_set_params.argtypes = [vp, vp]
+    L.pgk_mlp_get_params.argtypes = [vp, vp]
+    L.pgk_mlp_forward.argtypes = [vp, vp, vp, ctypes.c_int]
+    L.pgk_mlp_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int, vp, fp]
+    L.pgk_mlp_adam_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]
+    L.pgk_mlp_train.argtypes = [vp, vp, vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_uint64, fp]
+    L.pgk_mlp_last_error.argtypes = [vp]
+    L.pgk_mlp_last_error.restype = ctypes.c_char_p
+    L.pgk_mlp_destroy.argtypes = [vp]
+    L.pgk_mlp_destroy.restype = None
     for name in EXPORTS:
         if name not in ("pgk_steps_done", "pgk_last_error", "pgk_destroy", "pgk_batch_last_error",
-                        "pgk_batch_destroy"):
+                        "pgk_batch_destroy", "pgk_mlp_last_error", "pgk_mlp_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpgk.so")
-SOURCES = [os.path.join(HERE, "csrc", "pgk.hip"), os.path.join(HERE, "csrc", "batch.hip")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in ("pgk.hip", "batch.hip", "mlp.hip")]
 PROBE_LIB = os.path.join(HERE, "libpgk_probe.so")
 PROBE_SOURCES = [os.path.join(HERE, "csrc", "probe.hip")]
 
