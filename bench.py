@@ -121,6 +121,150 @@ def copy_probe(torch, nbytes=4 << 30, reps=10):
     return out
 
 
+def plain_case(case, tol, max_steps, time_cap, K=128):
+    """One case through the single-grid path (the plain, unbatched solver):
+    chunks of K steps with the one-step residual taken from two moment reads.
+    Stops at residual `tol`, `max_steps` or after `time_cap` seconds;
+    returns (steps, residual, seconds)."""
+    import numpy as np
+
+    import paper_2201_05280_amd as pgk
+    from paper_2201_05280_amd.inputs import THETA0
+    p = case["params"]
+    s = pgk.Solver(case["L"], 1, 1, precision=pgk.FP64, bc_x=(pgk.WALL, pgk.WALL))
+    s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    s.set_bc_x(0, 1.0, (0, 0, 0), THETA0)
+    s.set_bc_x(1, 1.0, (0, case["U"], 0), THETA0)
+    ns = 2 * case["L"]
+    s.init(np.ones(ns), np.zeros((3, ns)), np.full(ns, THETA0), np.full(ns, THETA0))
+    t0 = time.perf_counter()
+    steps, resid = 0, 1.0
+    while steps < max_steps and time.perf_counter() - t0 < time_cap:
+        s.step(K - 1)
+        a = s.moments()
+        s.step(1)
+        b = s.moments()
+        steps += K
+        resid = 0.0
+        for k, v in (("rho", None), ("u", 1), ("thT", None), ("thR", None)):
+            x0 = a[k] if v is None else a[k][v]
+            x1 = b[k] if v is None else b[k][v]
+            resid = max(resid, float(np.linalg.norm(x1 - x0) / max(np.linalg.norm(x1), 1e-300)))
+        if resid <= tol or not np.isfinite(resid):
+            break
+    dt = time.perf_counter() - t0
+    s.close()
+    return steps, resid, dt
+
+
+def sweep(args):
+    """Time to residual 1e-8 of a batch of Couette cases: plain (one case at a
+    time), batched cold, batched warm-started by the MLP."""
+    import numpy as np
+    import torch
+
+    from paper_2201_05280_amd import cases as C
+    from paper_2201_05280_amd.inputs import mlp_init
+    from paper_2201_05280_amd.batch import Batch
+    from paper_2201_05280_amd.mlp import MLP
+
+    S = 220105280
+    tol = 1e-8
+    kw = dict(L_range=(args.sweep_lmin, args.sweep_lmax), Kn_range=(args.sweep_knmin, args.sweep_knmax))
+    test, red_t = C.sweep_cases(args.sweep_n, S, **kw)
+    train, red_r = C.sweep_cases(args.sweep_train, S + 1, **kw)
+    out = {"metric": "sweep time-to-residual 1e-8 plain vs batched+MLP", "unit": "s", "tol": tol,
+           "cases": len(test), "train_cases": len(train), "infeasible_redraws": red_t + red_r,
+           "distribution": "Couette, L~U{%d..%d}, Ma_w~U[0.1,0.5], Kn~logU[%g,%g], Pr~U[0.67,1], "
+                           "mu_b/mu~U[0,2] (floor redraw), delta in {2,3}"
+                           % (args.sweep_lmin, args.sweep_lmax, args.sweep_knmin, args.sweep_knmax)}
+
+    def run_batch(cs, fields, label):
+        b = Batch(C.to_batch_cases(cs))
+        b.init(fields["rho"], fields["u"], fields["thT"], fields["thR"])
+        b.config(0, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, resid, status = b.run(args.sweep_max_steps, tol)
+        dt = time.perf_counter() - t0
+        m = b.moments()
+        wg, K, nsps = b.tuned()
+        b.close()
+        print("# %s: %.2f s, steps median %d max %d, converged %d/%d, config wg=%d K=%d"
+              % (label, dt, np.median(steps), steps.max(), (status == 1).sum(), len(cs), wg, K),
+              file=sys.stderr, flush=True)
+        return dict(time=dt, steps=steps, status=status, resid=resid, m=m, wg=wg, K=K, ns_per_site=nsps)
+
+    # training data: steady states of the training cases (cold batched runs);
+    # the first run also settles the autotuner's choice for this case mix
+    tr = run_batch(train, C.cold_fields(train), "train cold")
+    ok = np.repeat(tr["status"] == 1, [2 * c["L"] for c in train])
+    X = C.features(train)[ok]
+    Y = C.targets(train, tr["m"])[ok]
+    mlp = MLP(nmax=8192)
+    mlp.set_params(mlp_init(S))
+    t0 = time.perf_counter()
+    losses = mlp.train(X, Y, epochs=args.sweep_epochs, batch=2048, lr=2e-3, seed=S)
+    t_train = time.perf_counter() - t0
+    print("# mlp trained on %d points in %.1f s, loss %.3e -> %.3e" % (len(X), t_train, losses[0], losses[-1]),
+          file=sys.stderr, flush=True)
+
+    cold = run_batch(test, C.cold_fields(test), "held-out cold")
+    t0 = time.perf_counter()
+    y = mlp.forward(C.features(test)).cpu().numpy()
+    t_infer = time.perf_counter() - t0
+    warm = run_batch(test, C.fields_from_prediction(test, y), "held-out warm")
+    mlp.close()
+
+    # final match of warm and cold converged states, per case, against the
+    # bound 2 R / r_slow of a run stopped at residual R (r_slow ~ pi^2 nu / L^2)
+    both = (cold["status"] == 1) & (warm["status"] == 1)
+    worst, o = 0.0, 0
+    for c, ok_c in zip(test, both):
+        n = 2 * c["L"]
+        if ok_c:
+            sl = slice(o, o + n)
+            du = np.abs(warm["m"]["u"][1][sl] - cold["m"]["u"][1][sl]).max() / c["U"]
+            r_slow = math.pi ** 2 * c["nu"] / c["L"] ** 2
+            worst = max(worst, du / (2 * tol / r_slow))
+        o += n
+    # plain: a seeded subset of the held-out cases, one at a time through the
+    # single-grid path; a case stopped by the time cap is charged its measured
+    # time per step times the steps the batched run needed (same arithmetic,
+    # so the same step count: checked on the cases that finish)
+    idx = np.random.default_rng(S).choice(len(test), size=min(args.sweep_plain, len(test)), replace=False)
+    tp, n_full, step_match = 0.0, 0, True
+    for i in idx:
+        st, rs, dt = plain_case(test[i], tol, args.sweep_max_steps, args.sweep_plain_cap)
+        if rs <= tol:
+            n_full += 1
+            tp += dt
+            step_match &= abs(st - int(cold["steps"][i])) <= 128
+        else:
+            tp += dt / st * int(cold["steps"][i])
+        print("# plain case %d: L=%d steps %d (batched %d) %.2f s" % (i, test[i]["L"], st, cold["steps"][i], dt),
+              file=sys.stderr, flush=True)
+    plain_est = tp * len(test) / len(idx)   # unbiased for a uniform random subset
+    out.update({
+        "plain_subset_cases": len(idx), "plain_subset_time": round(tp, 2), "plain_subset_run_to_tol": n_full,
+        "plain_steps_match_batched": bool(step_match),
+        "plain_estimated_time": round(plain_est, 1),
+        "batched_cold_time": round(cold["time"], 2), "batched_warm_time": round(warm["time"] + t_infer, 2),
+        "mlp_inference_time": round(t_infer, 3), "mlp_train_time": round(t_train, 1),
+        "mlp_loss_first_last": [float(losses[0]), float(losses[-1])],
+        "steps_cold_median": int(np.median(cold["steps"])), "steps_warm_median": int(np.median(warm["steps"])),
+        "steps_cold_total": int(cold["steps"].sum()), "steps_warm_total": int(warm["steps"].sum()),
+        "converged_cold": int((cold["status"] == 1).sum()), "converged_warm": int((warm["status"] == 1).sum()),
+        "diverged_cold": int((cold["status"] == 2).sum()), "diverged_warm": int((warm["status"] == 2).sum()),
+        "warm_vs_cold_max_du_over_bound": round(worst, 3),
+        "batch_config": {"wg": cold["wg"], "K": cold["K"], "ns_per_site_update": round(cold["ns_per_site"], 4)},
+        "speedup_warm_vs_cold": round(cold["time"] / (warm["time"] + t_infer), 3),
+        "speedup_batched_cold_vs_plain": round(plain_est / cold["time"], 2),
+        "speedup_batched_warm_vs_plain": round(plain_est / (warm["time"] + t_infer), 2),
+    })
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +275,17 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sweep", action="store_true", help="run the batched sweep / warm-start experiment instead")
+    ap.add_argument("--sweep-n", type=int, default=256)
+    ap.add_argument("--sweep-train", type=int, default=512)
+    ap.add_argument("--sweep-lmin", type=int, default=128)
+    ap.add_argument("--sweep-lmax", type=int, default=512)
+    ap.add_argument("--sweep-knmin", type=float, default=1e-2)
+    ap.add_argument("--sweep-knmax", type=float, default=1e-1)
+    ap.add_argument("--sweep-max-steps", type=int, default=400000)
+    ap.add_argument("--sweep-epochs", type=int, default=40)
+    ap.add_argument("--sweep-plain", type=int, default=8)
+    ap.add_argument("--sweep-plain-cap", type=float, default=10.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain device copy (torch) as the achievable-bandwidth reference")
     args = ap.parse_args()
@@ -138,6 +293,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the z-slab decomposition is a design note); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.sweep:
+        sweep(args)
+        return
 
     import torch
 

@@ -49,16 +49,9 @@ def dsilu(z):
 
 
 def init(seed):
-    """He-style uniform initialisation (the same recipe the library's tests use)."""
-    rng = np.random.default_rng(seed)
-    parts = []
-    for s in SHAPES:
-        if len(s) == 2:
-            lim = np.sqrt(6.0 / s[1])
-            parts.append(rng.uniform(-lim, lim, s))
-        else:
-            parts.append(np.zeros(s))
-    return pack(parts).astype(np.float32)
+    """Seeded initial weights: the shared input generator (He uniform, zero biases)."""
+    from paper_2201_05280_amd.inputs import mlp_init
+    return mlp_init(seed)
 
 
 def forward(theta, X, bf16=False):

@@ -40,7 +40,12 @@ struct BatchArgs {
     double *popA, *popB, *thR, *that_, *tmc, *tmc2, *aux, *snap, *gh;
     long long max_steps;
     double tol;
+    int lds_sites;      // cases with ns <= lds_sites diffuse theta_R in LDS
 };
+
+// dynamic LDS of k_batch: theta ping-pong and the two face coefficients
+constexpr int LDS_ARRAYS = 4;
+constexpr int LDS_SITES_MAX = 2048;   // 64 KiB
 
 constexpr int GHOSTS_PER_CASE = 2 * NQ * NSLOT;   // ny = nz = 1
 
@@ -61,6 +66,87 @@ __device__ __forceinline__ void block_sum_n(double *val)
         val[c] = t;
     }
     __syncthreads();
+}
+
+// FTCS diffusion of a line (ny = nz = 1) in LDS.  The y and z neighbours of
+// a line are the site itself and contribute nothing, so the stencil is the
+// x pair: with the face conductances fixed within a step, one sub-step is
+//   CN:  t + c- (t[x-1] - t) + c+ (t[x+1] - t),  c+- = 2 (k_s + k_x+-1) / (2 rho delta nsub)
+//   LIT: the same with c+- = 2 k_s / (rho delta nsub)
+// (k = kfac rho theta_hat; a bounded face contributes its ghost value theta_w
+// with the ghost conductance of dif_site).  Site s = sub * nx + x.
+template <int VAR>
+__device__ __forceinline__ void dif_line_coef(int s, const double *__restrict__ aux, const Consts &k, double &cm,
+                                              double &cp)
+{
+    const int ns = k.ns, sub = s >= k.nx, x = s - sub * k.nx;
+    const double rho = aux[(size_t)3 * ns + s], ks = k.kfac * aux[(size_t)4 * ns + s];
+    const double fac = k.isub * 2.0 / (rho * k.delta);
+    double c[2];
+#pragma unroll
+    for (int d = 0; d < 2; d++) {
+        int xq = x + (d ? 1 : -1);
+        int side = xq < 0 ? 0 : (xq >= k.nx ? 1 : -1);
+        double kq;
+        if (side >= 0 && k.bc[side] != PGK_PERIODIC) {
+            double rg = k.bc[side] == PGK_WALL ? rho : k.rhobc[side];
+            kq = k.kfac * rg * k.thbc[side];
+        } else {
+            kq = k.kfac * aux[(size_t)4 * ns + sub * k.nx + wrapc(xq, k.nx)];
+        }
+        c[d] = VAR == PGK_CN ? fac * 0.5 * (ks + kq) : fac * ks;
+    }
+    cm = c[0];
+    cp = c[1];
+}
+
+__device__ __forceinline__ double dif_line(int s, const double *tin, const double *cm, const double *cp,
+                                           const Consts &k)
+{
+    const int sub = s >= k.nx, x = s - sub * k.nx;
+    const double t = tin[s];
+    double tm, tp;
+    if (x > 0) tm = tin[s - 1];
+    else tm = k.bc[0] != PGK_PERIODIC ? k.thbc[0] : tin[s + k.nx - 1];
+    if (x + 1 < k.nx) tp = tin[s + 1];
+    else tp = k.bc[1] != PGK_PERIODIC ? k.thbc[1] : tin[s + 1 - k.nx];
+    return t + cm[s] * (tm - t) + cp[s] * (tp - t);
+}
+
+// Ghost populations of both x faces of a line (ny = nz = 1), wavefront w
+// taking face w: the same quantities as bc_column, with the outgoing-mass sum
+// of a diffuse wall spread over the 64 lanes (lane l takes the candidates
+// (q, sub, xi) numbered l, l + 64, l + 128) and a butterfly reduction.  The
+// caller synchronises the work-group before the ghosts are read.
+__device__ __forceinline__ void bc_line(const double *__restrict__ src, double *__restrict__ gh, const Consts &k)
+{
+    const int side = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (side > 1 || k.bc[side] == PGK_PERIODIC) return;
+    double scale = 1.0;
+    if (k.bc[side] == PGK_WALL) {
+        double out = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            int idx = lane + 64 * j;                 // 160 candidates: q = 1..40, sub, xi
+            if (idx >= 4 * (NQ - 1)) break;
+            int q = 1 + (idx >> 2), sub = (idx >> 1) & 1, xi = idx & 1;
+            int cx = c2(q, 0);
+            if ((side == 0 && cx >= 0) || (side == 1 && cx <= 0)) continue;
+            if (xi == 1 && k.nx == 1) continue;
+            int x = side == 0 ? xi : k.nx - 1 - xi;
+            int dx = 2 * x + sub + cx;
+            bool crosses = side == 0 ? dx < 0 : dx > 2 * k.nx - 1;
+            if (crosses) out += src[(size_t)q * k.ns + sub * k.nx + x];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) out += __shfl_xor(out, o, 64);
+        scale = out / k.in_col[side];
+    }
+    if (lane < NQ) {
+        double val = scale * k.Fbc[side][lane];
+#pragma unroll
+        for (int slot = 0; slot < NSLOT; slot++) gh[(side * NQ + lane) * NSLOT + slot] = val;
+    }
 }
 
 template <int VAR, int NTH>
@@ -84,7 +170,7 @@ __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
     for (int j = 0; j < K; j++) {
         const double *src = cur ? pB : pA;
         double *dst = cur ? pA : pB;
-        if (steps > 0 && tid < 2) bc_column<double>(tid, 0, src, gh, k);
+        if (steps > 0) bc_line(src, gh, k);
         __syncthreads();
         for (int s = tid; s < ns; s += NTH) {
             double r;
@@ -93,7 +179,27 @@ __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
         __syncthreads();
         for (int s = tid; s < ns; s += NTH) mc_site<double, true>(s, that_, aux, tmc, k);
         __syncthreads();
-        {
+        if (ns <= a.lds_sites) {
+            extern __shared__ double lds[];
+            double *tin = lds, *tout = lds + a.lds_sites, *cm = lds + 2 * a.lds_sites, *cp = lds + 3 * a.lds_sites;
+            for (int s = tid; s < ns; s += NTH) {
+                tin[s] = tmc[s];
+                dif_line_coef<VAR>(s, aux, k, cm[s], cp[s]);
+            }
+            __syncthreads();
+            for (int it = 0; it + 1 < k.nsub; it++) {
+                for (int s = tid; s < ns; s += NTH) tout[s] = dif_line(s, tin, cm, cp, k);
+                __syncthreads();
+                double *t = tin;
+                tin = tout;
+                tout = t;
+            }
+            for (int s = tid; s < ns; s += NTH) {
+                double tdif = dif_line(s, tin, cm, cp, k), v = thR[s];
+                if (VAR == PGK_CN) thR[s] = tdif + (that_[s] - v);
+                else thR[s] = (tdif + k.X * v) * k.inv1X;
+            }
+        } else {
             double *tin = tmc, *tout = tmc2;
             for (int it = 0; it + 1 < k.nsub; it++) {
                 for (int s = tid; s < ns; s += NTH) dif_site<double, VAR, true, false>(s, tin, tout, that_, aux, thR, k);
@@ -110,7 +216,7 @@ __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
         if (j >= K - 2) {
             // moments of the new state: refresh the ghosts it pulls from
             const double *nsrc = cur ? pB : pA;
-            if (tid < 2) bc_column<double>(tid, 0, nsrc, gh, k);
+            bc_line(nsrc, gh, k);
             __syncthreads();
             double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
             for (int s = tid; s < ns; s += NTH) {
@@ -185,7 +291,7 @@ __global__ __launch_bounds__(NTH) void k_batch_moments(BatchArgs a, double *__re
     const long long off = bc.off;
     const double *src = (a.cur[c] ? a.popB : a.popA) + (size_t)NQ * off;
     double *gh = a.gh + (size_t)c * GHOSTS_PER_CASE;
-    if (a.steps[c] > 0 && threadIdx.x < 2) bc_column<double>(threadIdx.x, 0, src, gh, k);
+    if (a.steps[c] > 0) bc_line(src, gh, k);
     __syncthreads();
     for (int s = threadIdx.x; s < k.ns; s += NTH) {
         Mom m;
@@ -396,6 +502,9 @@ extern "C" int pgk_batch_create(const pgk_case *cases, int n, void *stream, void
     a.aux = (double *)(base + L.aux);
     a.snap = (double *)(base + L.snap);
     a.gh = (double *)(base + L.gh);
+    long long maxns = 0;
+    for (auto &c : b->host_cases) maxns = std::max<long long>(maxns, c.k.ns);
+    a.lds_sites = (int)std::min<long long>(maxns, LDS_SITES_MAX);
     // slots ordered by size, longest first (the cost model: work per step)
     std::vector<int> order(n);
     for (int i = 0; i < n; i++) order[i] = i;
@@ -448,12 +557,13 @@ static int chunk(pgk_batch *b, int wg, int K, int variant)
     if (it == b->graphs.end()) {
         hipGraph_t g;
         BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        const size_t lds = sizeof(double) * LDS_ARRAYS * b->args.lds_sites;
         if (variant == PGK_CN) {
-            if (wg == 256) hipLaunchKernelGGL((k_batch<PGK_CN, 256>), dim3(b->n), dim3(256), 0, b->stream, b->args, K);
-            else hipLaunchKernelGGL((k_batch<PGK_CN, 512>), dim3(b->n), dim3(512), 0, b->stream, b->args, K);
+            if (wg == 256) hipLaunchKernelGGL((k_batch<PGK_CN, 256>), dim3(b->n), dim3(256), lds, b->stream, b->args, K);
+            else hipLaunchKernelGGL((k_batch<PGK_CN, 512>), dim3(b->n), dim3(512), lds, b->stream, b->args, K);
         } else {
-            if (wg == 256) hipLaunchKernelGGL((k_batch<PGK_LIT, 256>), dim3(b->n), dim3(256), 0, b->stream, b->args, K);
-            else hipLaunchKernelGGL((k_batch<PGK_LIT, 512>), dim3(b->n), dim3(512), 0, b->stream, b->args, K);
+            if (wg == 256) hipLaunchKernelGGL((k_batch<PGK_LIT, 256>), dim3(b->n), dim3(256), lds, b->stream, b->args, K);
+            else hipLaunchKernelGGL((k_batch<PGK_LIT, 512>), dim3(b->n), dim3(512), lds, b->stream, b->args, K);
         }
         BHIP(b, hipStreamEndCapture(b->stream, &g));
         hipGraphExec_t ge;

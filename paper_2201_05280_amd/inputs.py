@@ -96,3 +96,21 @@ def random_smooth(nx, ny, nz, seed, amp_rho=0.02, amp_u=0.03, amp_th=0.03, modes
     f["thT"] = theta * (1.0 + field(amp_th))
     f["thR"] = theta * (1.0 + field(amp_th))
     return f
+
+
+MLP_SHAPES = [(128, 6), (128,), (128, 128), (128,), (128, 128), (128,), (128, 128), (128,), (4, 128), (4,)]
+
+
+def mlp_init(seed):
+    """Initial weights of the 6-128-128-128-128-4 coordinate MLP, flat in the
+    order W1, b1, ..., W5, b5 (row-major [out][in]): He uniform
+    U(-sqrt(6/fan_in), sqrt(6/fan_in)) for weights, zero biases; float32."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for s in MLP_SHAPES:
+        if len(s) == 2:
+            lim = np.sqrt(6.0 / s[1])
+            parts.append(rng.uniform(-lim, lim, s).ravel())
+        else:
+            parts.append(np.zeros(s[0]))
+    return np.concatenate(parts).astype(np.float32)
