@@ -162,8 +162,9 @@ int pgk_conserved(pgk_ctx *ctx, double out[5]);
  * pgk_step records an event before its first launch and after every launch.
  * pgk_kernel_times() waits for the stream, returns the summed milliseconds and
  * the launch counts of [0] the fused pull-collide kernel, [1] the MacCormack
- * advection, [2] the diffusion and second half relaxation, [3] the x ghost
- * fill, and clears the record.  Event handles are created on demand and kept
+ * advection (on a periodic grid with one diffusion sub-step: the single fused
+ * transport kernel, advection + diffusion + second half), [2] the diffusion
+ * and second half relaxation, [3] the x ghost fill, and clears the record.  Event handles are created on demand and kept
  * until pgk_destroy. */
 #define PGK_NKERNEL 4
 int pgk_set_timing(pgk_ctx *ctx, int enable);
