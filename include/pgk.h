@@ -63,6 +63,16 @@ extern "C" {
 
 /* discrete equilibrium (Sec. 5 leaves it open) */
 #define PGK_F3   0           /* third-order Hermite projection of the anisotropic Gaussian */
+#define PGK_E2   1           /* discrete quasi-equilibrium F_i = w_i exp(l . phi(c_i)) with
+                                phi = (1, c, cc): the H minimiser on the 41 velocities under
+                                the target's density, momentum and pressure tensor (Sec. 2,
+                                Sec. 3), found per site by damped Newton in double precision.
+                                It stays positive at Mach numbers where F3 turns negative, but
+                                a target beyond what a positive distribution on the lattice can
+                                carry has no solution: that site's populations become NaN.
+                                Diffuse walls re-emit F3 in either case; Dirichlet faces take
+                                E2 (pgk_set_bc_x returns PGK_EINFEASIBLE if the face state
+                                has none) */
 
 /* boundary kinds of the two x faces (y and z are periodic) */
 #define PGK_PERIODIC   0
@@ -83,7 +93,7 @@ typedef struct {
     int nx, ny, nz;          /* cells per axis, each >= 1 */
     int precision;           /* PGK_FP64 | PGK_FP32DEV */
     int variant;             /* PGK_CN | PGK_LIT */
-    int equilibrium;         /* PGK_F3 */
+    int equilibrium;         /* PGK_F3 | PGK_E2 */
     int bc_x[2];             /* kind of the low and high x faces */
 } pgk_grid;
 
@@ -135,7 +145,9 @@ int pgk_bind(pgk_ctx *ctx, void *const bufs[PGK_NBUF], const size_t bytes[PGK_NB
 int pgk_set_params(pgk_ctx *ctx, const pgk_params *p, pgk_resolved *out);
 
 /* Boundary data of x face `side` (0 low, 1 high): wall velocity and temperature
- * for PGK_WALL (rho ignored), ghost state for PGK_DIRICHLET. */
+ * for PGK_WALL (rho ignored), ghost state for PGK_DIRICHLET.  Every bounded
+ * face needs its state before pgk_init_fields (PGK_EINVAL otherwise); with
+ * PGK_E2, a Dirichlet state without an E2 equilibrium gives PGK_EINFEASIBLE. */
 int pgk_set_bc_x(pgk_ctx *ctx, int side, double rho, const double u[3], double theta);
 
 /* Initial state from device fields rho[ns], u[3][ns], theta_T[ns], theta_R[ns]:

@@ -16,6 +16,7 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EINFEASIBLE", -6: "ENO
 FP64, FP32DEV = 0, 1
 CN, LIT = 0, 1
 F3 = 0
+E2 = 1
 PERIODIC, WALL, DIRICHLET = 0, 1, 2
 NBUF = 4
 

@@ -11,6 +11,7 @@
 
 #include "pgk.h"
 #include "lattice.hpp"
+#include "e2.hpp"
 
 namespace pgk {
 
@@ -370,6 +371,58 @@ __device__ __forceinline__ void collide_store(S *v, const Eq<S> &e, const Consts
     }
 }
 
+// Collide toward the gain term of the E2 form and write the own site.  The
+// gain term is the rate-weighted mixture of the two targets, F =
+// wt1 F(lam_ES) + wt F(theta I) with wt1 = tau1/(tau+tau1), wt = tau/(tau+tau1)
+// (Sec. 4): for an equilibrium that is not linear in the covariance the two
+// terms do not merge into one.  l1, l2: multipliers of the two E2 targets,
+// computed in double; FP32 deviation storage takes F - w through expm1.
+template <typename S, int P = 0>
+__device__ __forceinline__ void collide_store_e2(S *v, const double *l1, const double *l2, const Consts &k,
+                                                 S *__restrict__ dst, int s)
+{
+    if constexpr (P < NPAIR) {
+        double e1, o1, e2, o2;
+        e2_parts<P>(l1, e1, o1);
+        e2_parts<P>(l2, e2, o2);
+        double w = k.w[Lattice::SHELL[P]];
+        if constexpr (sizeof(S) == 4) {
+            S tb = (S)(2.0 * k.beta);
+            S Fp = (S)(w * (k.wt1 * expm1(e1 + o1) + k.wt * expm1(e2 + o2)));
+            S Fm = (S)(w * (k.wt1 * expm1(e1 - o1) + k.wt * expm1(e2 - o2)));
+            __builtin_nontemporal_store(v[1 + P] + tb * (Fp - v[1 + P]), &dst[(size_t)(1 + P) * k.ns + s]);
+            __builtin_nontemporal_store(v[1 + NPAIR + P] + tb * (Fm - v[1 + NPAIR + P]),
+                                        &dst[(size_t)(1 + NPAIR + P) * k.ns + s]);
+        } else {
+            double omb = 1.0 - 2.0 * k.beta, tb = 2.0 * k.beta;
+            double Fp = w * (k.wt1 * exp(e1 + o1) + k.wt * exp(e2 + o2));
+            double Fm = w * (k.wt1 * exp(e1 - o1) + k.wt * exp(e2 - o2));
+            __builtin_nontemporal_store(omb * v[1 + P] + tb * Fp, &dst[(size_t)(1 + P) * k.ns + s]);
+            __builtin_nontemporal_store(omb * v[1 + NPAIR + P] + tb * Fm, &dst[(size_t)(1 + NPAIR + P) * k.ns + s]);
+        }
+        collide_store_e2<S, P + 1>(v, l1, l2, k, dst, s);
+    } else {
+        double w0 = k.w[0];
+        if constexpr (sizeof(S) == 4) {
+            S tb = (S)(2.0 * k.beta);
+            S F0 = (S)(w0 * (k.wt1 * expm1(l1[0]) + k.wt * expm1(l2[0])));
+            __builtin_nontemporal_store(v[0] + tb * (F0 - v[0]), &dst[s]);
+        } else {
+            double F0 = w0 * (k.wt1 * exp(l1[0]) + k.wt * exp(l2[0]));
+            __builtin_nontemporal_store((1.0 - 2.0 * k.beta) * v[0] + 2.0 * k.beta * F0, &dst[s]);
+        }
+    }
+}
+
+// E2 multipliers of density rho, velocity u, covariance lam; a target out of
+// the lattice's reach gives NaN multipliers, so the site's populations turn
+// NaN (never silently replaced by another equilibrium)
+__device__ __forceinline__ void e2_site(double rho, const double *u, const double *lam, const Consts &k, double *l)
+{
+    if (e2_solve(k.th0, k.w, rho, u, lam, l) < 0)
+        for (int i = 0; i < E2_NL; i++) l[i] = __builtin_nan("");
+}
+
 // block-wide sum of NV doubles; thread 0 of the block gets the result
 template <int NV>
 __device__ __forceinline__ void block_sum(double *val, double *out)
@@ -395,7 +448,7 @@ __device__ __forceinline__ void block_sum(double *val, double *out)
 // ---------------------------------------------------------------------------
 // fused pull - moments - solve - equilibrium - collide of site s; returns the
 // moments of g (time level n) and the stored theta_R in r_out
-template <typename S, typename A, int VAR, bool BOUNDED>
+template <typename S, typename A, int VAR, bool BOUNDED, int EQ = PGK_F3>
 __device__ __forceinline__ Mom lb_site(int s, const S *__restrict__ src, S *__restrict__ dst,
                                        const S *__restrict__ gh, double *__restrict__ thR,
                                        double *__restrict__ that_, A *__restrict__ aux, const Consts &k,
@@ -409,8 +462,21 @@ __device__ __forceinline__ Mom lb_site(int s, const S *__restrict__ src, S *__re
     double r = thR[s];
     Mom m = moments<S>(v, k);
     Solve so = site_solve(m, r, k);
-    Eq<S> e = make_eq<S>(so, k);
-    collide_store<S>(v, e, k, dst, s);
+    if constexpr (EQ == PGK_E2) {
+        // the two targets: lam_ES = T I + b sigma(f)/rho and theta I
+        double les[6], lmb[6], l1[E2_NL], l2[E2_NL];
+        double cb = k.bs / so.rho;
+        for (int i = 0; i < 6; i++) {
+            les[i] = (i < 3 ? so.T : 0.0) + cb * so.sg[i];
+            lmb[i] = i < 3 ? so.theta : 0.0;
+        }
+        e2_site(so.rho, so.u, les, k, l1);
+        e2_site(so.rho, so.u, lmb, k, l2);
+        collide_store_e2<S>(v, l1, l2, k, dst, s);
+    } else {
+        Eq<S> e = make_eq<S>(so, k);
+        collide_store<S>(v, e, k, dst, s);
+    }
     that_[s] = so.R;                                  // theta_R after step 1
     if (VAR == PGK_LIT) thR[s] = so.T;                // the printed second half needs theta_T
     aux[s] = (A)so.u[0];
@@ -569,7 +635,7 @@ __device__ __forceinline__ void bc_column(int side, int col, const S *__restrict
 // push F_i(rho, u, theta_T I) of site s to where the next pull reads it:
 // population i of site x is read from position x - c_i (a ghost slot when that
 // lies beyond a bounded face)
-template <typename S, bool BOUNDED>
+template <typename S, bool BOUNDED, int EQ = PGK_F3>
 __device__ __forceinline__ void init_site(int s, S *__restrict__ dst, S *__restrict__ gh, double *__restrict__ thR,
                                           const double *__restrict__ rho, const double *__restrict__ u,
                                           const double *__restrict__ thT, const double *__restrict__ thRin,
@@ -584,18 +650,27 @@ __device__ __forceinline__ void init_site(int s, S *__restrict__ dst, S *__restr
     so.u[2] = u[2 * ustride + s];
     for (int i = 0; i < 6; i++) so.lamF[i] = i < 3 ? thT[s] : 0.0;
     Eq<double> e = make_eq<double>(so, k);
+    double l[E2_NL];
+    if constexpr (EQ == PGK_E2) e2_site(so.rho, so.u, so.lamF, k, l);
     thR[s] = thRin[s];
     for (int q = 0; q < NQ; q++) {
         int cx = c2(q, 0), cy = c2(q, 1), cz = c2(q, 2);
         double hx = 0.5 * cx, hy = 0.5 * cy, hz = 0.5 * cz;
-        double cu = hx * e.u0 + hy * e.u1 + hz * e.u2;
-        double cDc = hx * hx * e.D0 + hy * hy * e.D1 + hz * hz * e.D2 + 2.0 * (hx * hy * e.D3 + hx * hz * e.D4 + hy * hz * e.D5);
-        double cDu = hx * e.Du0 + hy * e.Du1 + hz * e.Du2;
-        double even = (cu * cu + cDc) * e.k2 - e.k0;
-        double odd = cu * e.A1 + cu * cu * cu * e.k3 + cDc * cu * e.k4 - cDu * e.k5;
         double w = k.w[shell_of(q)];
-        double F = w * e.rho * (1.0 + even + odd);
-        S val = (S)(sizeof(S) == 4 ? w * (e.drho + e.rho * (even + odd)) : F);
+        S val;
+        if constexpr (EQ == PGK_E2) {
+            double ex = l[0] + hx * l[1] + hy * l[2] + hz * l[3] + hx * hx * l[4] + hy * hy * l[5] + hz * hz * l[6] +
+                        hx * hy * l[7] + hx * hz * l[8] + hy * hz * l[9];
+            val = (S)(sizeof(S) == 4 ? w * expm1(ex) : w * exp(ex));
+        } else {
+            double cu = hx * e.u0 + hy * e.u1 + hz * e.u2;
+            double cDc = hx * hx * e.D0 + hy * hy * e.D1 + hz * hz * e.D2 + 2.0 * (hx * hy * e.D3 + hx * hz * e.D4 + hy * hz * e.D5);
+            double cDu = hx * e.Du0 + hy * e.Du1 + hz * e.Du2;
+            double even = (cu * cu + cDc) * e.k2 - e.k0;
+            double odd = cu * e.A1 + cu * cu * cu * e.k3 + cDc * cu * e.k4 - cDu * e.k5;
+            double F = w * e.rho * (1.0 + even + odd);
+            val = (S)(sizeof(S) == 4 ? w * (e.drho + e.rho * (even + odd)) : F);
+        }
         // destination: position x - c_q
         int qx = 2 * x + sub - cx, qy = 2 * y + sub - cy, qz = 2 * z + sub - cz;
         int ssub = qx & 1;

@@ -1,0 +1,225 @@
+// e2.hpp -- the E2 equilibrium: the discrete quasi-equilibrium that
+// minimises the H function on the 41 velocities under fixed density,
+// momentum and pressure tensor (Sec. 2, quasi-equilibria; Sec. 3, the ES
+// target as a quasi-equilibrium).  On the lattice it has the exponential form
+//   F_i = w_i exp(l . phi_i),  phi_i = (1, c, cx^2, cy^2, cz^2, cxcy, cxcz, cycz),
+// with the ten multipliers l fixed by sum_i F_i phi_i = (rho, rho u, rho (uu + lam)).
+// The multipliers come from Newton's method on those ten equations, started
+// from the continuous Gaussian N(u, lam) / N(0, theta0 I) and damped so that
+// no exponent changes by more than 2 in one iteration; a Cholesky solve of the
+// (symmetric positive definite) Jacobian sum_i F_i phi_i phi_i^T gives the
+// step.  The same code runs on the host (face states) and in the kernels.
+//
+// The opposite velocities +-c of a pair share the even part of the exponent
+// and differ in the sign of the odd part (the three linear multipliers), so
+// every sum runs over the rest velocity and 20 pairs.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "lattice.hpp"
+
+namespace pgk {
+
+constexpr int E2_NL = 10;
+constexpr int E2_MAXIT = 100;
+
+// index of (k, l), k <= l, in the packed upper triangle of a 10 x 10 matrix
+__host__ __device__ constexpr int e2_ij(int k, int l)
+{
+    return k * E2_NL - k * (k - 1) / 2 + (l - k);
+}
+
+// basis values of pair representative P: phi[k] for k = 0..9
+template <int P>
+struct E2Phi {
+    static constexpr double cx = 0.5 * Lattice::REP2[P][0], cy = 0.5 * Lattice::REP2[P][1],
+                            cz = 0.5 * Lattice::REP2[P][2];
+    __host__ __device__ static constexpr double at(int k)
+    {
+        return k == 0 ? 1.0 : k == 1 ? cx : k == 2 ? cy : k == 3 ? cz : k == 4 ? cx * cx : k == 5 ? cy * cy
+             : k == 6 ? cz * cz : k == 7 ? cx * cy : k == 8 ? cx * cz : cy * cz;
+    }
+    // phi[k] is odd in c for k = 1..3
+    __host__ __device__ static constexpr bool odd(int k) { return k >= 1 && k <= 3; }
+};
+
+// even and odd parts of l . phi for pair P
+template <int P>
+__host__ __device__ __forceinline__ void e2_parts(const double *l, double &ev, double &od)
+{
+    using F = E2Phi<P>;
+    ev = l[0];
+    od = 0.0;
+    if (F::cx != 0.0) { od += F::cx * l[1]; ev += F::cx * F::cx * l[4]; }
+    if (F::cy != 0.0) { od += F::cy * l[2]; ev += F::cy * F::cy * l[5]; }
+    if (F::cz != 0.0) { od += F::cz * l[3]; ev += F::cz * F::cz * l[6]; }
+    if (F::cx * F::cy != 0.0) ev += F::cx * F::cy * l[7];
+    if (F::cx * F::cz != 0.0) ev += F::cx * F::cz * l[8];
+    if (F::cy * F::cz != 0.0) ev += F::cy * F::cz * l[9];
+}
+
+// moments and Jacobian contributions of pair P (F+ and F- of weight w)
+template <int P = 0>
+__host__ __device__ __forceinline__ void e2_accumulate(const double *l, const double *w6, double *mom, double *J)
+{
+    if constexpr (P < NPAIR) {
+        using F = E2Phi<P>;
+        double ev, od;
+        e2_parts<P>(l, ev, od);
+        double w = w6[Lattice::SHELL[P]];
+        double fp = w * exp(ev + od), fm = w * exp(ev - od);
+        double s = fp + fm, d = fp - fm;
+#pragma unroll
+        for (int k = 0; k < E2_NL; k++) {
+            double pk = F::at(k);
+            if (pk == 0.0) continue;
+            mom[k] += pk * (F::odd(k) ? d : s);
+#pragma unroll
+            for (int m = k; m < E2_NL; m++) {
+                double pm = F::at(m);
+                if (pm == 0.0) continue;
+                // phi_k phi_m is odd in c exactly when one of the two is
+                J[e2_ij(k, m)] += pk * pm * ((F::odd(k) != F::odd(m)) ? d : s);
+            }
+        }
+        e2_accumulate<P + 1>(l, w6, mom, J);
+    }
+}
+
+// largest |delta . phi_i| over the velocities (the damping measure)
+template <int P = 0>
+__host__ __device__ __forceinline__ double e2_maxchange(const double *dl, double acc)
+{
+    if constexpr (P < NPAIR) {
+        double ev, od;
+        e2_parts<P>(dl, ev, od);
+        double m = fabs(ev) + fabs(od);   // max(|ev + od|, |ev - od|)
+        return e2_maxchange<P + 1>(dl, m > acc ? m : acc);
+    } else {
+        return acc;
+    }
+}
+
+// In-place Cholesky solve of the packed SPD system J x = b; false if J is not
+// positive definite.
+__host__ __device__ __forceinline__ bool e2_cholesky_solve(double *J, double *b)
+{
+#pragma unroll
+    for (int j = 0; j < E2_NL; j++) {
+        double d = J[e2_ij(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; k++) d -= J[e2_ij(k, j)] * J[e2_ij(k, j)];
+        if (!(d > 0.0)) return false;
+        double r = sqrt(d);
+        J[e2_ij(j, j)] = r;
+        double ir = 1.0 / r;
+#pragma unroll
+        for (int i = j + 1; i < E2_NL; i++) {
+            double t = J[e2_ij(j, i)];
+#pragma unroll
+            for (int k = 0; k < j; k++) t -= J[e2_ij(k, j)] * J[e2_ij(k, i)];
+            J[e2_ij(j, i)] = t * ir;   // U[j][i] of J = U^T U
+        }
+    }
+    // U^T y = b
+#pragma unroll
+    for (int i = 0; i < E2_NL; i++) {
+        double t = b[i];
+#pragma unroll
+        for (int k = 0; k < i; k++) t -= J[e2_ij(k, i)] * b[k];
+        b[i] = t / J[e2_ij(i, i)];
+    }
+    // U x = y
+#pragma unroll
+    for (int i = E2_NL - 1; i >= 0; i--) {
+        double t = b[i];
+#pragma unroll
+        for (int k = i + 1; k < E2_NL; k++) t -= J[e2_ij(i, k)] * b[k];
+        b[i] = t / J[e2_ij(i, i)];
+    }
+    return true;
+}
+
+// Multipliers of the E2 equilibrium with density rho, velocity u and
+// covariance lam (xx yy zz xy xz yz).  Returns the Newton iteration count
+// (> 0), or -1 when the moments cannot be reached (covariance not positive
+// definite, Jacobian singular, no convergence in E2_MAXIT iterations); the
+// moments then lie outside what a positive distribution on the 41 velocities
+// can carry.
+__host__ __device__ __forceinline__ int e2_solve(double th0, const double *w6, double rho, const double *u,
+                                                 const double *lam, double *l)
+{
+    double tg[E2_NL];
+    tg[0] = rho;
+    tg[1] = rho * u[0];
+    tg[2] = rho * u[1];
+    tg[3] = rho * u[2];
+    tg[4] = rho * (u[0] * u[0] + lam[0]);
+    tg[5] = rho * (u[1] * u[1] + lam[1]);
+    tg[6] = rho * (u[2] * u[2] + lam[2]);
+    tg[7] = rho * (u[0] * u[1] + lam[3]);
+    tg[8] = rho * (u[0] * u[2] + lam[4]);
+    tg[9] = rho * (u[1] * u[2] + lam[5]);
+    // start: the continuous Gaussian over the reference Gaussian
+    double a = lam[0], b = lam[1], c = lam[2], d = lam[3], e = lam[4], f = lam[5];
+    double c00 = b * c - f * f, c01 = e * f - d * c, c02 = d * f - b * e;
+    double det = a * c00 + d * c01 + e * c02;
+    if (!(det > 0.0) || !(rho > 0.0)) return -1;
+    double id = 1.0 / det;
+    double i00 = c00 * id, i01 = c01 * id, i02 = c02 * id;
+    double i11 = (a * c - e * e) * id, i12 = (d * e - a * f) * id, i22 = (a * b - d * d) * id;
+    double v0 = i00 * u[0] + i01 * u[1] + i02 * u[2];
+    double v1 = i01 * u[0] + i11 * u[1] + i12 * u[2];
+    double v2 = i02 * u[0] + i12 * u[1] + i22 * u[2];
+    l[0] = log(rho) - 0.5 * log(det / (th0 * th0 * th0)) - 0.5 * (u[0] * v0 + u[1] * v1 + u[2] * v2);
+    l[1] = v0;
+    l[2] = v1;
+    l[3] = v2;
+    l[4] = -0.5 * (i00 - 1.0 / th0);
+    l[5] = -0.5 * (i11 - 1.0 / th0);
+    l[6] = -0.5 * (i22 - 1.0 / th0);
+    l[7] = -i01;
+    l[8] = -i02;
+    l[9] = -i12;
+    double scale = 0.0;
+#pragma unroll
+    for (int k = 0; k < E2_NL; k++) scale += fabs(tg[k]);
+    for (int it = 1; it <= E2_MAXIT; it++) {
+        double mom[E2_NL], J[E2_NL * (E2_NL + 1) / 2];
+#pragma unroll
+        for (int k = 0; k < E2_NL; k++) mom[k] = 0.0;
+#pragma unroll
+        for (int k = 0; k < E2_NL * (E2_NL + 1) / 2; k++) J[k] = 0.0;
+        double f0 = w6[0] * exp(l[0]);   // rest velocity: phi = (1, 0, ...)
+        mom[0] = f0;
+        J[0] = f0;
+        e2_accumulate(l, w6, mom, J);
+        double rhs[E2_NL], res = 0.0;
+#pragma unroll
+        for (int k = 0; k < E2_NL; k++) {
+            rhs[k] = tg[k] - mom[k];
+            res += fabs(rhs[k]);
+        }
+        if (res <= 1e-14 * scale) return it;
+        if (!e2_cholesky_solve(J, rhs)) return -1;
+        double maxd = e2_maxchange(rhs, fabs(rhs[0]));
+        double damp = maxd > 2.0 ? 2.0 / maxd : 1.0;
+#pragma unroll
+        for (int k = 0; k < E2_NL; k++) l[k] += damp * rhs[k];
+        if (!(fabs(l[0]) < 1e300)) return -1;   // NaN or overflow
+    }
+    return -1;
+}
+
+// F_q of the multipliers l (any q, host side)
+__host__ inline double e2_population(const double *l, const double *w6, int q)
+{
+    double cx = 0.5 * c2(q, 0), cy = 0.5 * c2(q, 1), cz = 0.5 * c2(q, 2);
+    double ex = l[0] + cx * l[1] + cy * l[2] + cz * l[3] + cx * cx * l[4] + cy * cy * l[5] + cz * cz * l[6] +
+                cx * cy * l[7] + cx * cz * l[8] + cy * cz * l[9];
+    return w6[shell_of(q)] * exp(ex);
+}
+
+}  // namespace pgk

@@ -30,7 +30,7 @@ namespace pgk {
 // ---------------------------------------------------------------------------
 // single-grid kernels: one thread per site
 // ---------------------------------------------------------------------------
-template <typename S, typename A, int VAR, bool BOUNDED, bool REDUCE>
+template <typename S, typename A, int VAR, bool BOUNDED, bool REDUCE, int EQ>
 __global__ __launch_bounds__(WG) void k_lb(const S *__restrict__ src, S *__restrict__ dst,
                                            const S *__restrict__ gh, double *__restrict__ thR,
                                            double *__restrict__ that_, A *__restrict__ aux,
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(WG) void k_lb(const S *__restrict__ src, S *__restr
     double red[5] = {0, 0, 0, 0, 0};
     if (s < k.ns) {
         double r;
-        Mom m = lb_site<S, A, VAR, BOUNDED>(s, src, dst, gh, thR, that_, aux, k, r);
+        Mom m = lb_site<S, A, VAR, BOUNDED, EQ>(s, src, dst, gh, thR, that_, aux, k, r);
         if (REDUCE) {
             red[0] = m.rho;
             red[1] = m.j[0];
@@ -275,14 +275,14 @@ __global__ void k_bc(const S *__restrict__ src, S *__restrict__ gh, Consts k)
     bc_column<S>(side, col - side * ncol, src, gh, k);
 }
 
-template <typename S, bool BOUNDED>
+template <typename S, bool BOUNDED, int EQ>
 __global__ __launch_bounds__(WG) void k_init(S *__restrict__ dst, S *__restrict__ gh, double *__restrict__ thR,
                                              const double *__restrict__ rho, const double *__restrict__ u,
                                              const double *__restrict__ thT, const double *__restrict__ thRin,
                                              Consts k)
 {
     int s = blockIdx.x * WG + threadIdx.x;
-    if (s < k.ns) init_site<S, BOUNDED>(s, dst, gh, thR, rho, u, thT, thRin, k, (size_t)k.ns);
+    if (s < k.ns) init_site<S, BOUNDED, EQ>(s, dst, gh, thR, rho, u, thT, thRin, k, (size_t)k.ns);
 }
 
 template <typename S, bool BOUNDED, bool REDUCE>
@@ -351,6 +351,7 @@ struct pgk_ctx {
     Consts k{};
     pgk_resolved res{};
     double bc_u[2][3]{};
+    bool bc_set[2] = {false, false};   // face state given by pgk_set_bc_x
     std::string err;
     // carved from the aux buffer
     double *that_ = nullptr, *tmc = nullptr, *tmc2 = nullptr, *partial = nullptr, *totals = nullptr;
@@ -402,7 +403,7 @@ static bool grid_ok(const pgk_grid *g)
     if ((long long)g->nx * g->ny * g->nz * 2 > (long long)INT_MAX) return false;  // site ids are int
     if (g->precision != PGK_FP64 && g->precision != PGK_FP32DEV) return false;
     if (g->variant != PGK_CN && g->variant != PGK_LIT) return false;
-    if (g->equilibrium != PGK_F3) return false;
+    if (g->equilibrium != PGK_F3 && g->equilibrium != PGK_E2) return false;
     for (int s = 0; s < 2; s++)
         if (g->bc_x[s] < PGK_PERIODIC || g->bc_x[s] > PGK_DIRICHLET) return false;
     if ((g->bc_x[0] == PGK_PERIODIC) != (g->bc_x[1] == PGK_PERIODIC)) return false;
@@ -532,15 +533,25 @@ extern "C" int pgk_bind(pgk_ctx *c, void *const bufs[PGK_NBUF], const size_t byt
     return PGK_OK;
 }
 
-static void fill_bc(pgk_ctx *c)
+// face equilibria (wall: F3 at unit density; Dirichlet: the grid's
+// equilibrium of the face state) and diffusion sub-steps; PGK_EINFEASIBLE if
+// a Dirichlet state has no E2 equilibrium
+static int fill_bc(pgk_ctx *c)
 {
     Consts &k = c->k;
     k.nsub = diffusion_substeps(k, c->res.kr);
     k.isub = 1.0 / k.nsub;
     for (int side = 0; side < 2; side++) {
-        if (k.bc[side] == PGK_PERIODIC) continue;
+        if (k.bc[side] == PGK_PERIODIC || !c->bc_set[side]) continue;
         double rho = k.bc[side] == PGK_WALL ? 1.0 : k.rhobc[side];
-        f3_host(k.th0, k.w, rho, c->bc_u[side], k.thbc[side], k.Fbc[side]);
+        if (k.bc[side] == PGK_DIRICHLET && c->g.equilibrium == PGK_E2) {
+            double th = k.thbc[side], lam[6] = {th, th, th, 0.0, 0.0, 0.0}, l[E2_NL];
+            if (e2_solve(k.th0, k.w, rho, c->bc_u[side], lam, l) < 0)
+                return fail(c, PGK_EINFEASIBLE, "the Dirichlet face state has no E2 equilibrium on the lattice");
+            for (int q = 0; q < NQ; q++) k.Fbc[side][q] = e2_population(l, k.w, q);
+        } else {
+            f3_host(k.th0, k.w, rho, c->bc_u[side], k.thbc[side], k.Fbc[side]);
+        }
         // mass re-emitted into one ghost column at unit density: every
         // population pulled from beyond the face, over both sublattices
         double in = 0.0;
@@ -553,6 +564,7 @@ static void fill_bc(pgk_ctx *c)
                 }
         k.in_col[side] = in;
     }
+    return PGK_OK;
 }
 
 extern "C" int pgk_set_params(pgk_ctx *c, const pgk_params *p, pgk_resolved *out)
@@ -600,8 +612,7 @@ extern "C" int pgk_set_params(pgk_ctx *c, const pgk_params *p, pgk_resolved *out
     c->res = r;
     if (out) *out = r;
     c->params_set = true;
-    fill_bc(c);
-    return PGK_OK;
+    return fill_bc(c);
 }
 
 extern "C" int pgk_set_bc_x(pgk_ctx *c, int side, double rho, const double u[3], double theta)
@@ -612,23 +623,23 @@ extern "C" int pgk_set_bc_x(pgk_ctx *c, int side, double rho, const double u[3],
     if (u && u[0] != 0.0 && c->k.bc[side] == PGK_WALL) return fail(c, PGK_EINVAL, "a wall cannot move normal to itself");
     c->k.rhobc[side] = rho;
     c->k.thbc[side] = theta;
+    c->bc_set[side] = true;
     for (int a = 0; a < 3; a++) c->bc_u[side][a] = u ? u[a] : 0.0;
-    if (c->params_set) fill_bc(c);
-    return PGK_OK;
+    return c->params_set ? fill_bc(c) : PGK_OK;
 }
 
 static bool bounded(const pgk_ctx *c) { return c->k.bc[0] != PGK_PERIODIC; }
 
-template <typename S>
+template <typename S, int EQ>
 static int init_t(pgk_ctx *c, const double *rho, const double *u, const double *thT, const double *thR)
 {
     dim3 grid(c->nblk), block(WG);
     S *dst = (S *)c->buf[c->cur];
     if (bounded(c))
-        hipLaunchKernelGGL((k_init<S, true>), grid, block, 0, c->stream, dst, (S *)c->gh,
+        hipLaunchKernelGGL((k_init<S, true, EQ>), grid, block, 0, c->stream, dst, (S *)c->gh,
                            (double *)c->buf[PGK_BUF_THETAR], rho, u, thT, thR, c->k);
     else
-        hipLaunchKernelGGL((k_init<S, false>), grid, block, 0, c->stream, dst, (S *)c->gh,
+        hipLaunchKernelGGL((k_init<S, false, EQ>), grid, block, 0, c->stream, dst, (S *)c->gh,
                            (double *)c->buf[PGK_BUF_THETAR], rho, u, thT, thR, c->k);
     HIPCHECK(c, hipGetLastError());
     return PGK_OK;
@@ -640,14 +651,20 @@ extern "C" int pgk_init_fields(pgk_ctx *c, const double *rho, const double *u, c
     if (!c->bound) return fail(c, PGK_ENOTBOUND, "buffers not bound");
     if (!c->params_set) return fail(c, PGK_EINVAL, "parameters not set");
     if (!rho || !u || !thT || !thR) return fail(c, PGK_EINVAL, "null field");
+    for (int side = 0; side < 2; side++)
+        if (c->k.bc[side] != PGK_PERIODIC && !c->bc_set[side])
+            return fail(c, PGK_EINVAL, "x face state not set (pgk_set_bc_x)");
     c->cur = 0;
     c->steps = 0;
-    int rc = c->g.precision == PGK_FP64 ? init_t<double>(c, rho, u, thT, thR) : init_t<float>(c, rho, u, thT, thR);
+    bool e2 = c->g.equilibrium == PGK_E2;
+    int rc = c->g.precision == PGK_FP64
+                 ? (e2 ? init_t<double, PGK_E2>(c, rho, u, thT, thR) : init_t<double, PGK_F3>(c, rho, u, thT, thR))
+                 : (e2 ? init_t<float, PGK_E2>(c, rho, u, thT, thR) : init_t<float, PGK_F3>(c, rho, u, thT, thR));
     if (rc == PGK_OK) c->initialised = true;
     return rc;
 }
 
-template <typename S, typename A, int VAR, bool BND>
+template <typename S, typename A, int VAR, bool BND, int EQ>
 static int step_t(pgk_ctx *c, int64_t n)
 {
     dim3 grid(c->nblk), block(WG);
@@ -659,7 +676,7 @@ static int step_t(pgk_ctx *c, int64_t n)
             hipLaunchKernelGGL((k_bc<S>), dim3(nbc), dim3(64), 0, c->stream, src, (S *)c->gh, c->k);
             mark(c, 3);
         }
-        hipLaunchKernelGGL((k_lb<S, A, VAR, BND, false>), grid, block, 0, c->stream, src, dst, (const S *)c->gh,
+        hipLaunchKernelGGL((k_lb<S, A, VAR, BND, false, EQ>), grid, block, 0, c->stream, src, dst, (const S *)c->gh,
                            (double *)c->buf[PGK_BUF_THETAR], c->that_, (A *)c->aux, c->partial, c->k);
         mark(c, 0);
         if (BND || c->k.nsub > 1) {
@@ -691,13 +708,13 @@ static int step_t(pgk_ctx *c, int64_t n)
     return PGK_OK;
 }
 
-template <typename S, typename A>
+template <typename S, typename A, int EQ>
 static int step_v(pgk_ctx *c, int64_t n)
 {
     bool b = bounded(c);
     if (c->g.variant == PGK_CN)
-        return b ? step_t<S, A, PGK_CN, true>(c, n) : step_t<S, A, PGK_CN, false>(c, n);
-    return b ? step_t<S, A, PGK_LIT, true>(c, n) : step_t<S, A, PGK_LIT, false>(c, n);
+        return b ? step_t<S, A, PGK_CN, true, EQ>(c, n) : step_t<S, A, PGK_CN, false, EQ>(c, n);
+    return b ? step_t<S, A, PGK_LIT, true, EQ>(c, n) : step_t<S, A, PGK_LIT, false, EQ>(c, n);
 }
 
 extern "C" int pgk_step(pgk_ctx *c, int64_t n)
@@ -705,7 +722,9 @@ extern "C" int pgk_step(pgk_ctx *c, int64_t n)
     if (!c || n < 0) return PGK_EINVAL;
     if (!c->initialised) return fail(c, PGK_EINVAL, "fields not initialised");
     if (n == 0) return PGK_OK;
-    return c->g.precision == PGK_FP64 ? step_v<double, double>(c, n) : step_v<float, float>(c, n);
+    if (c->g.equilibrium == PGK_E2)
+        return c->g.precision == PGK_FP64 ? step_v<double, double, PGK_E2>(c, n) : step_v<float, float, PGK_E2>(c, n);
+    return c->g.precision == PGK_FP64 ? step_v<double, double, PGK_F3>(c, n) : step_v<float, float, PGK_F3>(c, n);
 }
 
 template <typename S, bool REDUCE>

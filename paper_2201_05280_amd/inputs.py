@@ -114,3 +114,29 @@ def mlp_init(seed):
         else:
             parts.append(np.zeros(s[0]))
     return np.concatenate(parts).astype(np.float32)
+
+
+def rankine_hugoniot(Ma, gamma, theta1=THETA0, rho1=1.0):
+    """Upstream and downstream states (rho, u_x, theta) of a normal shock of an
+    ideal gas of heat-capacity ratio gamma, upstream Mach number Ma (flow along
+    +x, upstream at low x)."""
+    r = (gamma + 1) * Ma ** 2 / ((gamma - 1) * Ma ** 2 + 2)
+    p = 1 + 2 * gamma / (gamma + 1) * (Ma ** 2 - 1)
+    u1 = Ma * np.sqrt(gamma * theta1)
+    return (rho1, u1, theta1), (rho1 * r, u1 / r, theta1 * p / r)
+
+
+def shock_tube(L, Ma, gamma, theta1=THETA0, width=4.0, x0=None):
+    """1D line of L cells holding a tanh blend of the two Rankine-Hugoniot
+    states of `rankine_hugoniot`, centred at x0 (default L/2) with the given
+    width in cells; theta_R = theta_T."""
+    (r1, u1, t1), (r2, u2, t2) = rankine_hugoniot(Ma, gamma, theta1)
+    x = positions(L, 1, 1)[0]
+    x0 = L / 2 if x0 is None else x0
+    sm = 0.5 * (1 + np.tanh((x - x0) / width))
+    f = uniform(L, 1, 1)
+    f["rho"] = r1 + (r2 - r1) * sm
+    f["u"][0] = u1 + (u2 - u1) * sm
+    f["thT"] = t1 + (t2 - t1) * sm
+    f["thR"] = f["thT"].copy()
+    return f

@@ -9,7 +9,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import CN, FP64, PERIODIC
+from ._lib import CN, F3, FP64, PERIODIC
 
 
 def _torch():
@@ -23,11 +23,12 @@ class Solver:
     """One grid of nx*ny*nz bcc cells (2 sites per cell) on one GPU.
 
     precision: _lib.FP64 or _lib.FP32DEV; variant: _lib.CN or _lib.LIT;
-    bc_x: kinds of the low and high x faces (y and z are periodic).
+    equilibrium: _lib.F3 or _lib.E2; bc_x: kinds of the low and high x faces
+    (y and z are periodic).
     """
 
     def __init__(self, nx, ny, nz, precision=FP64, variant=CN, bc_x=(PERIODIC, PERIODIC),
-                 device=0, stream=None):
+                 device=0, stream=None, equilibrium=F3):
         torch = _torch()
         self.torch = torch
         self.L = _lib.load()
@@ -35,7 +36,7 @@ class Solver:
         self.ns = 2 * nx * ny * nz
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        g = _lib.Grid(nx, ny, nz, precision, variant, _lib.F3, (ctypes.c_int * 2)(*bc_x))
+        g = _lib.Grid(nx, ny, nz, precision, variant, equilibrium, (ctypes.c_int * 2)(*bc_x))
         sizes = (ctypes.c_size_t * _lib.NBUF)()
         self._check(self.L.pgk_buffer_sizes(ctypes.byref(g), sizes), None)
         h = ctypes.c_void_p()
