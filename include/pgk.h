@@ -131,6 +131,22 @@ typedef struct {
  * or below the floor 2 delta / (3 (3+delta)) or k_r would be negative.  Host only. */
 int pgk_resolve(const pgk_targets *t, pgk_resolved *out);
 
+/* The RD3Q41 velocity set (Sec. 5, table of velocities and weights) in the
+ * library's population order: 0 the rest velocity, 1 + p the representative
+ * c_p of opposite pair p (p = 0..19), 21 + p its negative.  c receives 41 x 3
+ * velocities in lattice units (half-integers included), w the 41 weights at
+ * reference temperature theta0 (0 = the printed value).  Host memory, host
+ * only. */
+int pgk_lattice(double theta0, double *c, double *w);
+
+/* Populations F[41] (library order) of the discrete equilibrium `equilibrium`
+ * (PGK_F3 or PGK_E2) with density rho, velocity u[3] and covariance lam[6]
+ * (xx yy zz xy xz yz), reference temperature theta0 (0 = printed).  The same
+ * host code fills the Dirichlet face ghosts.  Returns PGK_EINFEASIBLE when E2
+ * has no solution, PGK_EINVAL for rho <= 0 or an unknown kind.  Host memory,
+ * host only. */
+int pgk_equilibrium(int equilibrium, double theta0, double rho, const double *u, const double *lam, double *F);
+
 /* Bytes needed for each device buffer of this grid. */
 int pgk_buffer_sizes(const pgk_grid *g, size_t sizes[PGK_NBUF]);
 

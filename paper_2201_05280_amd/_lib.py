@@ -21,7 +21,7 @@ PERIODIC, WALL, DIRICHLET = 0, 1, 2
 NBUF = 4
 
 # every symbol include/pgk.h declares
-EXPORTS = ["pgk_resolve", "pgk_buffer_sizes", "pgk_create", "pgk_bind", "pgk_set_params",
+EXPORTS = ["pgk_resolve", "pgk_lattice", "pgk_equilibrium", "pgk_buffer_sizes", "pgk_create", "pgk_bind", "pgk_set_params",
            "pgk_set_bc_x", "pgk_init_fields", "pgk_step", "pgk_read_moments", "pgk_conserved",
            "pgk_set_timing", "pgk_kernel_times", "pgk_steps_done", "pgk_last_error", "pgk_destroy",
            "pgk_batch_bytes", "pgk_batch_create", "pgk_batch_offsets", "pgk_batch_init", "pgk_batch_config",
@@ -133,6 +133,34 @@ def load():
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
+
+
+def lattice(theta0=0.0):
+    """(c[41][3], w[41]) of the library's velocity order (host only)."""
+    import numpy as np
+    L = load()
+    c = np.zeros((41, 3))
+    w = np.zeros(41)
+    P = ctypes.POINTER(ctypes.c_double)
+    L.pgk_lattice(ctypes.c_double(theta0), c.ctypes.data_as(P), w.ctypes.data_as(P))
+    return c, w
+
+
+def equilibrium(kind, rho, u, lam6, theta0=0.0):
+    """Populations F[41] (library order) of the F3 or E2 equilibrium (host only);
+    raises ValueError when E2 has no solution."""
+    import numpy as np
+    L = load()
+    P = ctypes.POINTER(ctypes.c_double)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    lam = np.ascontiguousarray(lam6, dtype=np.float64)
+    F = np.zeros(41)
+    rc = L.pgk_equilibrium(int(kind), ctypes.c_double(theta0), ctypes.c_double(rho), u.ctypes.data_as(P),
+                           lam.ctypes.data_as(P), F.ctypes.data_as(P))
+    if rc != PGK_OK:
+        raise ValueError("no %s equilibrium for rho=%g u=%s lam=%s (%s)"
+                         % ("E2" if kind == E2 else "F3", rho, list(u), list(lam), ERRORS.get(rc, rc)))
+    return F
 
 
 def resolve(nu, Pr, mub_over_mu, delta, b=float("nan"), kr=float("nan"), theta0=0.0):

@@ -445,6 +445,58 @@ extern "C" int pgk_buffer_sizes(const pgk_grid *g, size_t sizes[PGK_NBUF])
     return PGK_OK;
 }
 
+// F3 with a general covariance: the third-order Hermite projection about
+// (0, theta0) of N(u, lam), D = lam - theta0 I (the device collide evaluates
+// the same polynomial in even/odd pairs)
+static void f3_host_lam(double th0, const double w6[6], double rho, const double u[3], const double lam[6],
+                        double F[NQ])
+{
+    double D[3][3] = {{lam[0] - th0, lam[3], lam[4]}, {lam[3], lam[1] - th0, lam[5]}, {lam[4], lam[5], lam[2] - th0}};
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double trD = D[0][0] + D[1][1] + D[2][2];
+    for (int q = 0; q < NQ; q++) {
+        double c[3] = {0.5 * c2(q, 0), 0.5 * c2(q, 1), 0.5 * c2(q, 2)};
+        double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2], cDc = 0.0, cDu = 0.0;
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                cDc += c[a] * D[a][b] * c[b];
+                cDu += c[a] * D[a][b] * u[b];
+            }
+        double a2 = cu * cu + cDc - th0 * (uu + trD);
+        double a3 = cu * cu * cu + 3.0 * cDc * cu - th0 * (3.0 * uu * cu + 6.0 * cDu + 3.0 * trD * cu);
+        F[q] = w6[shell_of(q)] * rho * (1.0 + cu / th0 + a2 / (2 * th0 * th0) + a3 / (6 * th0 * th0 * th0));
+    }
+}
+
+extern "C" int pgk_lattice(double theta0, double *c, double *w)
+{
+    if (!c || !w) return PGK_EINVAL;
+    double w6[6];
+    shell_weights(theta0 > 0 ? theta0 : THETA0_PRINTED, w6);
+    for (int q = 0; q < NQ; q++) {
+        for (int a = 0; a < 3; a++) c[3 * q + a] = 0.5 * c2(q, a);
+        w[q] = w6[shell_of(q)];
+    }
+    return PGK_OK;
+}
+
+extern "C" int pgk_equilibrium(int equilibrium, double theta0, double rho, const double *u, const double *lam,
+                               double *F)
+{
+    if (!u || !lam || !F || !(rho > 0)) return PGK_EINVAL;
+    double th0 = theta0 > 0 ? theta0 : THETA0_PRINTED, w6[6];
+    shell_weights(th0, w6);
+    if (equilibrium == PGK_F3) {
+        f3_host_lam(th0, w6, rho, u, lam, F);
+        return PGK_OK;
+    }
+    if (equilibrium != PGK_E2) return PGK_EINVAL;
+    double l[E2_NL];
+    if (e2_solve(th0, w6, rho, u, lam, l) < 0) return PGK_EINFEASIBLE;
+    for (int q = 0; q < NQ; q++) F[q] = e2_population(l, w6, q);
+    return PGK_OK;
+}
+
 extern "C" int pgk_resolve(const pgk_targets *t, pgk_resolved *out)
 {
     if (!t || !out) return PGK_EINVAL;
