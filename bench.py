@@ -171,6 +171,68 @@ def plain_case(case, tol, max_steps, time_cap, K=128):
     return steps, resid, dt
 
 
+def shock_summary(max_steps=60000):
+    """Normal-shock lines of 4096 cells between Dirichlet faces holding the
+    model's own jump states, E2 equilibrium, run until the one-step residual
+    stops falling (or reaches 1e-11): Mach 1.5 (upstream at the lattice
+    temperature) and Mach 3 (upstream theta 0.08), FP64 and FP32 storage."""
+    import numpy as np
+    import torch
+
+    import paper_2201_05280_amd as pgk
+    from paper_2201_05280_amd import inputs
+    from paper_2201_05280_amd.shock import discrete_rankine_hugoniot, profile_metrics, tanh_profile
+
+    L = 4096
+    x = inputs.positions(L, 1, 1)[0]
+
+    def resid(a, b):
+        r = 0.0
+        for k, v in (("rho", None), ("u", 0), ("thT", None), ("thR", None)):
+            x0 = a[k] if v is None else a[k][v]
+            x1 = b[k] if v is None else b[k][v]
+            r = max(r, float(np.linalg.norm(x1 - x0) / np.linalg.norm(x1)))
+        return r
+
+    out = {"cells": L, "sites": 2 * L, "equilibrium": "E2", "delta": 2.0, "Pr": 0.71, "mu_b/mu": 0.8,
+           "nu_upstream": "2 c_s (upstream mean free path nu sqrt(pi/(2 theta1)) = 2.97 cells)"}
+    for Ma, th1 in ((1.5, THETA0), (3.0, 0.08)):
+        up, down = discrete_rankine_hugoniot(Ma, 2.0, th1)
+        _, ideal = inputs.rankine_hugoniot(Ma, 1.4, th1)
+        nu = 2.0 * math.sqrt(1.4 * th1)
+        p = pgk.resolve(nu, 0.71, 0.8, 2.0)
+        lam1 = nu * math.sqrt(math.pi / (2 * th1))
+        case = {"theta1": th1, "upstream": [round(v, 6) for v in up], "downstream": [round(v, 6) for v in down],
+                "downstream_vs_ideal_gas_jump": [round(a / b - 1, 5) for a, b in zip(down, ideal)]}
+        for prec, name in ((pgk.FP64, "fp64"), (pgk.FP32DEV, "fp32dev")):
+            s = pgk.Solver(L, 1, 1, precision=prec, bc_x=(pgk.DIRICHLET, pgk.DIRICHLET), equilibrium=pgk.E2)
+            s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+            s.set_bc_x(0, up[0], (up[1], 0, 0), up[2])
+            s.set_bc_x(1, down[0], (down[1], 0, 0), down[2])
+            f = tanh_profile(L, up, down)
+            s.init(f["rho"], f["u"], f["thT"], f["thR"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            steps, hist = 0, []
+            while steps < max_steps:
+                s.step(4999)
+                a = s.moments()
+                s.step(1)
+                b = s.moments()
+                steps += 5000
+                hist.append(resid(a, b))
+                if hist[-1] < 1e-11 or (len(hist) > 3 and hist[-1] > 0.7 * hist[-4]):
+                    break
+            dt = time.perf_counter() - t0
+            s.close()
+            pos, thick = profile_metrics(x, b["rho"], up, down)
+            case[name] = {"steps": steps, "residual": float("%.3e" % hist[-1]), "seconds": round(dt, 2),
+                          "MLUPS": round(2 * L * steps / dt / 1e6, 1), "shock_position": round(pos, 4),
+                          "thickness_cells": round(thick, 3), "thickness_mean_free_paths": round(thick / lam1, 3)}
+        out["Ma%.1f" % Ma] = case
+    return out
+
+
 def sweep(args):
     """Time to residual 1e-8 of a batch of Couette cases: plain (one case at a
     time), batched cold, batched warm-started by the MLP."""
@@ -291,6 +353,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="run only the batched sweep / warm-start experiment")
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep experiment")
+    ap.add_argument("--no-shock", action="store_true", help="skip the normal-shock lines")
+    ap.add_argument("--shock", action="store_true", help="run only the normal-shock lines")
     ap.add_argument("--sweep-n", type=int, default=256)
     ap.add_argument("--sweep-train", type=int, default=512)
     ap.add_argument("--sweep-lmin", type=int, default=128)
@@ -310,6 +374,9 @@ def main():
         sys.exit(2)
     if args.sweep:
         print(json.dumps(sweep(args)), flush=True)
+        return
+    if args.shock:
+        print(json.dumps(shock_summary()), flush=True)
         return
 
     import torch
@@ -389,6 +456,8 @@ def main():
         out["copy_probe"] = copy_probe(torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)
+    if not args.no_shock:
+        out["shock"] = shock_summary()
     if not args.no_sweep:
         out["sweep"] = sweep(args)
     print(json.dumps(out), flush=True)
