@@ -326,6 +326,7 @@ def sweep(args):
         "plain_steps_match_batched": bool(step_match),
         "plain_estimated_time": round(plain_est, 1),
         "batched_cold_time": round(cold["time"], 2), "batched_warm_time": round(warm["time"] + t_infer, 2),
+        "batched_warm_plus_training_time": round(warm["time"] + t_infer + t_train, 2),
         "mlp_inference_time": round(t_infer, 3), "mlp_train_time": round(t_train, 1),
         "mlp_loss_first_last": [float(losses[0]), float(losses[-1])],
         "steps_cold_median": int(np.median(cold["steps"])), "steps_warm_median": int(np.median(warm["steps"])),

@@ -146,10 +146,9 @@ __global__ void k_loss(const float *__restrict__ yhat, const float *__restrict__
     if ((threadIdx.x & 63) == 0) atomicAdd(loss, l);
 }
 
-// last-layer gradients and dz4 = (dy W5) * dsilu(z4)
-__global__ void k_layer5_bwd(const float *__restrict__ dy, const uint16_t *__restrict__ a4,
-                             const float *__restrict__ z4, const uint16_t *__restrict__ wbf, int n, int npad,
-                             float *__restrict__ grad, float *__restrict__ dz4)
+// dz4 = (dy W5) * dsilu(z4)
+__global__ void k_layer5_bwd(const float *__restrict__ dy, const float *__restrict__ z4,
+                             const uint16_t *__restrict__ wbf, int npad, float *__restrict__ dz4)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < npad * H) {
@@ -158,18 +157,28 @@ __global__ void k_layer5_bwd(const float *__restrict__ dy, const uint16_t *__res
         for (int o = 0; o < NOUT; o++) da += dy[p * NOUT + o] * bf2f(wbf[OFF_W5 + o * H + k]);
         dz4[i] = da * dsilu(z4[i]);
     }
-    // weight gradient of layer 5: one thread per (o, k), loop over points
-    if (i < NOUT * H) {
-        int o = i / H, k = i - o * H;
-        float g = 0.f;
-        for (int p = 0; p < n; p++) g += dy[p * NOUT + o] * bf2f(a4[p * H + k]);
-        atomicAdd(&grad[OFF_W5 + i], g);
+}
+
+// Reductions over the points of a minibatch: work-group b takes points
+// [b GP, (b + 1) GP), thread k one hidden unit, and adds its partial sums to
+// the gradient (one atomic per value and work-group).
+constexpr int GP = 128;
+
+// last layer: dW5[o][k] = sum_p dy[p][o] a4[p][k], db5[o] = sum_p dy[p][o]
+__global__ __launch_bounds__(H) void k_layer5_wgrad(const float *__restrict__ dy, const uint16_t *__restrict__ a4,
+                                                    int n, float *__restrict__ grad)
+{
+    const int k = threadIdx.x, p0 = blockIdx.x * GP, p1 = min(n, p0 + GP);
+    float g[NOUT] = {0.f, 0.f, 0.f, 0.f}, gb = 0.f;
+    for (int p = p0; p < p1; p++) {
+        float a = bf2f(a4[(size_t)p * H + k]);
+#pragma unroll
+        for (int o = 0; o < NOUT; o++) g[o] += dy[p * NOUT + o] * a;
+        if (k < NOUT) gb += dy[p * NOUT + k];
     }
-    if (i < NOUT) {
-        float g = 0.f;
-        for (int p = 0; p < n; p++) g += dy[p * NOUT + i];
-        atomicAdd(&grad[OFF_B5 + i], g);
-    }
+#pragma unroll
+    for (int o = 0; o < NOUT; o++) atomicAdd(&grad[OFF_W5 + o * H + k], g[o]);
+    if (k < NOUT) atomicAdd(&grad[OFF_B5 + k], gb);
 }
 
 // bias gradient: column sums of dz[npad][H] (padding rows are zero)
@@ -185,16 +194,19 @@ __global__ void k_bias_grad(const float *__restrict__ dz, int npad, float *__res
     if (t == 0) atomicAdd(&gb[o], red[0] + red[1] + red[2] + red[3]);
 }
 
-// first-layer weight gradient: dz1^T X
-__global__ void k_layer1_wgrad(const float *__restrict__ dz1, const float *__restrict__ X, int n,
-                               float *__restrict__ grad)
+// first layer: dW1[o][j] = sum_p dz1[p][o] X[p][j]
+__global__ __launch_bounds__(H) void k_layer1_wgrad(const float *__restrict__ dz1, const float *__restrict__ X,
+                                                    int n, float *__restrict__ grad)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= H * NIN) return;
-    int o = i / NIN, k = i - o * NIN;
-    float g = 0.f;
-    for (int p = 0; p < n; p++) g += dz1[p * H + o] * X[p * NIN + k];
-    atomicAdd(&grad[OFF_W1 + i], g);
+    const int o = threadIdx.x, p0 = blockIdx.x * GP, p1 = min(n, p0 + GP);
+    float g[NIN] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int p = p0; p < p1; p++) {
+        float d = dz1[(size_t)p * H + o];
+#pragma unroll
+        for (int j = 0; j < NIN; j++) g[j] += d * X[p * NIN + j];
+    }
+#pragma unroll
+    for (int j = 0; j < NIN; j++) atomicAdd(&grad[OFF_W1 + o * NIN + j], g[j]);
 }
 
 __global__ void k_zero(float *__restrict__ a, int n)
@@ -367,8 +379,9 @@ static int loss_grad(pgk_mlp *m, const float *X, const float *Y, int n, float sc
                        m->master, m->yhat);
     hipLaunchKernelGGL(k_loss, dim3((np * NOUT + 255) / 256), dim3(256), 0, m->stream, m->yhat, Y, n, np, scale,
                        m->dy, m->loss);
-    hipLaunchKernelGGL(k_layer5_bwd, dim3((np * H + 255) / 256), dim3(256), 0, m->stream, m->dy, m->a[3], m->z[3],
-                       m->wbf, n, np, m->grad, m->dz);
+    hipLaunchKernelGGL(k_layer5_wgrad, dim3((n + GP - 1) / GP), dim3(H), 0, m->stream, m->dy, m->a[3], n, m->grad);
+    hipLaunchKernelGGL(k_layer5_bwd, dim3((np * H + 255) / 256), dim3(256), 0, m->stream, m->dy, m->z[3], m->wbf,
+                       np, m->dz);
     const int offW[3] = {OFF_W2, OFF_W3, OFF_W4}, offB[3] = {OFF_B2, OFF_B3, OFF_B4};
     float *dz = m->dz, *dzn = m->dz2;
     const int kchunk = 256;
@@ -388,7 +401,7 @@ static int loss_grad(pgk_mlp *m, const float *X, const float *Y, int n, float sc
         dzn = t;
     }
     hipLaunchKernelGGL(k_bias_grad, dim3(H), dim3(256), 0, m->stream, dz, np, m->grad + OFF_B1);
-    hipLaunchKernelGGL(k_layer1_wgrad, dim3((H * NIN + 255) / 256), dim3(256), 0, m->stream, dz, X, n, m->grad);
+    hipLaunchKernelGGL(k_layer1_wgrad, dim3((n + GP - 1) / GP), dim3(H), 0, m->stream, dz, X, n, m->grad);
     MHIP(m, hipGetLastError());
     return PGK_OK;
 }
