@@ -350,7 +350,7 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="cells per axis")
     ap.add_argument("--precision", choices=["fp32dev", "fp64"], default="fp32dev")
     ap.add_argument("--cpu-n", type=int, default=64)
-    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sweep", action="store_true", help="run only the batched sweep / warm-start experiment")
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep experiment")
