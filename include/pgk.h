@@ -227,6 +227,9 @@ typedef struct {
     double rho[2];           /* Dirichlet densities (ignored for walls) */
     double u[2][3];          /* face velocities (walls: tangential only) */
     double theta[2];         /* face temperatures */
+    int equilibrium;         /* PGK_F3 | PGK_E2 (a batch holding E2 cases runs with
+                                work-groups of 256; PGK_EINFEASIBLE if a Dirichlet face
+                                state has no E2 equilibrium) */
 } pgk_case;
 
 typedef struct pgk_batch pgk_batch;

@@ -61,7 +61,7 @@ class Resolved(ctypes.Structure):
 class Case(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int), ("bc", ctypes.c_int), ("vel_axis", ctypes.c_int), ("variant", ctypes.c_int),
                 ("p", Params), ("rho", ctypes.c_double * 2), ("u", (ctypes.c_double * 3) * 2),
-                ("theta", ctypes.c_double * 2)]
+                ("theta", ctypes.c_double * 2), ("equilibrium", ctypes.c_int)]
 
 
 _lib = None

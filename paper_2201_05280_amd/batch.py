@@ -8,6 +8,7 @@ HIP kernel.  A case is a dict:
   variant   CN or LIT
   params    (tau, tau1, b, kr, delta[, theta0])
   rho, u, theta   face data: pairs for the low and high x faces
+  equilibrium     F3 or E2
 """
 import ctypes
 
@@ -18,9 +19,10 @@ from ._lib import CN
 
 
 def make_case(L, bc, params, rho=(1.0, 1.0), u=((0, 0, 0), (0, 0, 0)), theta=(0.2948964908710633,) * 2,
-              vel_axis=1, variant=CN):
+              vel_axis=1, variant=CN, equilibrium=_lib.F3):
     c = _lib.Case()
     c.L, c.bc, c.vel_axis, c.variant = int(L), int(bc), int(vel_axis), int(variant)
+    c.equilibrium = int(equilibrium)
     p = list(params) + [0.0] * (6 - len(params))
     c.p = _lib.Params(*p)
     for s in range(2):

@@ -27,7 +27,7 @@ namespace pgk {
 struct BatchCase {
     Consts k;
     long long off;      // first site of the case
-    int vel_axis, variant;
+    int vel_axis, variant, eq;
 };
 
 struct BatchArgs {
@@ -149,7 +149,7 @@ __device__ __forceinline__ void bc_line(const double *__restrict__ src, double *
     }
 }
 
-template <int VAR, int NTH>
+template <int VAR, int NTH, bool E2CAP>
 __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
 {
     const int c = a.order[blockIdx.x];
@@ -172,9 +172,16 @@ __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
         double *dst = cur ? pA : pB;
         if (steps > 0) bc_line(src, gh, k);
         __syncthreads();
-        for (int s = tid; s < ns; s += NTH) {
-            double r;
-            lb_site<double, double, VAR, true>(s, src, dst, gh, thR, that_, aux, k, r);
+        if (E2CAP && bc.eq == PGK_E2) {
+            for (int s = tid; s < ns; s += NTH) {
+                double r;
+                lb_site<double, double, VAR, true, PGK_E2>(s, src, dst, gh, thR, that_, aux, k, r);
+            }
+        } else {
+            for (int s = tid; s < ns; s += NTH) {
+                double r;
+                lb_site<double, double, VAR, true, PGK_F3>(s, src, dst, gh, thR, that_, aux, k, r);
+            }
         }
         __syncthreads();
         for (int s = tid; s < ns; s += NTH) mc_site<double, true>(s, that_, aux, tmc, k);
@@ -269,9 +276,14 @@ __global__ __launch_bounds__(NTH) void k_batch_init(BatchArgs a, const double *_
     double *dst = a.popA + (size_t)NQ * off;
     double *gh = a.gh + (size_t)c * GHOSTS_PER_CASE;
     // the case's slices of the input fields; u is [3][ns_total]
-    for (int s = threadIdx.x; s < k.ns; s += NTH)
-        init_site<double, true>(s, dst, gh, a.thR + off, rho + off, u + off, thT + off, thRin + off, k,
-                                (size_t)ns_total);
+    for (int s = threadIdx.x; s < k.ns; s += NTH) {
+        if (bc.eq == PGK_E2)
+            init_site<double, true, PGK_E2>(s, dst, gh, a.thR + off, rho + off, u + off, thT + off, thRin + off, k,
+                                            (size_t)ns_total);
+        else
+            init_site<double, true, PGK_F3>(s, dst, gh, a.thR + off, rho + off, u + off, thT + off, thRin + off, k,
+                                            (size_t)ns_total);
+    }
     if (threadIdx.x == 0) {
         a.status[c] = PGK_CASE_RUNNING;
         a.steps[c] = 0;
@@ -316,6 +328,7 @@ struct pgk_batch {
     std::vector<BatchCase> host_cases;
     std::vector<long long> off;
     BatchArgs args{};
+    bool has_e2 = false;          // some case uses E2: the E2-capable kernel, work-groups of 256
     int wg = 0, K = 0;            // fixed config (0 = tune)
     int tuned_wg = 0, tuned_K = 0;
     double tuned_ns = 0.0;
@@ -382,6 +395,7 @@ static bool case_ok(const pgk_case &c)
     if (c.bc != PGK_WALL && c.bc != PGK_DIRICHLET) return false;
     if (c.vel_axis < 0 || c.vel_axis > 2) return false;
     if (c.variant != PGK_CN && c.variant != PGK_LIT) return false;
+    if (c.equilibrium != PGK_F3 && c.equilibrium != PGK_E2) return false;
     const pgk_params &p = c.p;
     if (!(p.tau > 0) || !(p.tau1 > 0) || !(p.delta > 0) || p.b < -0.5 || p.b > 1.0 || !(p.kr >= 0)) return false;
     for (int s = 0; s < 2; s++) {
@@ -404,10 +418,11 @@ extern "C" int pgk_batch_bytes(const pgk_case *cases, int n, size_t *bytes)
     return PGK_OK;
 }
 
-// model constants of one case, as pgk_set_params derives them for a grid
-static Consts case_consts(const pgk_case &cs)
+// model constants of one case, as pgk_set_params derives them for a grid;
+// false when a Dirichlet face state has no E2 equilibrium
+static bool case_consts(const pgk_case &cs, Consts &k)
 {
-    Consts k{};
+    k = Consts{};
     k.nx = cs.L; k.ny = 1; k.nz = 1; k.ns = 2 * cs.L;
     k.bc[0] = k.bc[1] = cs.bc;
     magic_div((unsigned)k.nx, k.mx, k.shx);
@@ -439,7 +454,13 @@ static Consts case_consts(const pgk_case &cs)
     for (int side = 0; side < 2; side++) {
         k.thbc[side] = cs.theta[side];
         k.rhobc[side] = cs.bc == PGK_WALL ? 1.0 : cs.rho[side];
-        f3_host(k.th0, k.w, k.rhobc[side], cs.u[side], k.thbc[side], k.Fbc[side]);
+        if (cs.bc == PGK_DIRICHLET && cs.equilibrium == PGK_E2) {
+            double th = k.thbc[side], lam[6] = {th, th, th, 0.0, 0.0, 0.0}, l[E2_NL];
+            if (e2_solve(k.th0, k.w, k.rhobc[side], cs.u[side], lam, l) < 0) return false;
+            for (int q = 0; q < NQ; q++) k.Fbc[side][q] = e2_population(l, k.w, q);
+        } else {
+            f3_host(k.th0, k.w, k.rhobc[side], cs.u[side], k.thbc[side], k.Fbc[side]);
+        }
         double in = 0.0;
         for (int q = 0; q < NQ; q++)
             for (int sub = 0; sub < 2; sub++)
@@ -451,7 +472,7 @@ static Consts case_consts(const pgk_case &cs)
     }
     k.nsub = diffusion_substeps(k, p.kr);
     k.isub = 1.0 / k.nsub;
-    return k;
+    return true;
 }
 
 extern "C" int pgk_batch_create(const pgk_case *cases, int n, void *stream, void *buf, size_t bytes, pgk_batch **out)
@@ -474,10 +495,15 @@ extern "C" int pgk_batch_create(const pgk_case *cases, int n, void *stream, void
     b->off.resize(n + 1);
     for (int i = 0; i < n; i++) {
         BatchCase bc{};
-        bc.k = case_consts(cases[i]);
+        if (!case_consts(cases[i], bc.k)) {
+            delete b;
+            return PGK_EINFEASIBLE;
+        }
         bc.off = o;
         bc.vel_axis = cases[i].vel_axis;
         bc.variant = cases[i].variant;
+        bc.eq = cases[i].equilibrium;
+        if (bc.eq == PGK_E2) b->has_e2 = true;
         b->host_cases.push_back(bc);
         b->off[i] = o;
         o += 2LL * cases[i].L;
@@ -545,6 +571,7 @@ extern "C" int pgk_batch_config(pgk_batch *b, int wg, int K)
 {
     if (!b) return PGK_EINVAL;
     if (!(wg == 0 && K == 0) && !((wg == 256 || wg == 512) && K >= 2)) return bfail(b, PGK_EINVAL, "bad config");
+    if (b->has_e2 && wg == 512) return bfail(b, PGK_EINVAL, "a batch with E2 cases runs with work-groups of 256");
     b->wg = wg;
     b->K = K;
     return PGK_OK;
@@ -558,12 +585,17 @@ static int chunk(pgk_batch *b, int wg, int K, int variant)
         hipGraph_t g;
         BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         const size_t lds = sizeof(double) * LDS_ARRAYS * b->args.lds_sites;
-        if (variant == PGK_CN) {
-            if (wg == 256) hipLaunchKernelGGL((k_batch<PGK_CN, 256>), dim3(b->n), dim3(256), lds, b->stream, b->args, K);
-            else hipLaunchKernelGGL((k_batch<PGK_CN, 512>), dim3(b->n), dim3(512), lds, b->stream, b->args, K);
+        dim3 grid(b->n);
+        if (b->has_e2) {
+            // the E2 Newton needs more registers than two wavefronts per SIMD leave
+            if (variant == PGK_CN) hipLaunchKernelGGL((k_batch<PGK_CN, 256, true>), grid, dim3(256), lds, b->stream, b->args, K);
+            else hipLaunchKernelGGL((k_batch<PGK_LIT, 256, true>), grid, dim3(256), lds, b->stream, b->args, K);
+        } else if (variant == PGK_CN) {
+            if (wg == 256) hipLaunchKernelGGL((k_batch<PGK_CN, 256, false>), grid, dim3(256), lds, b->stream, b->args, K);
+            else hipLaunchKernelGGL((k_batch<PGK_CN, 512, false>), grid, dim3(512), lds, b->stream, b->args, K);
         } else {
-            if (wg == 256) hipLaunchKernelGGL((k_batch<PGK_LIT, 256>), dim3(b->n), dim3(256), lds, b->stream, b->args, K);
-            else hipLaunchKernelGGL((k_batch<PGK_LIT, 512>), dim3(b->n), dim3(512), lds, b->stream, b->args, K);
+            if (wg == 256) hipLaunchKernelGGL((k_batch<PGK_LIT, 256, false>), grid, dim3(256), lds, b->stream, b->args, K);
+            else hipLaunchKernelGGL((k_batch<PGK_LIT, 512, false>), grid, dim3(512), lds, b->stream, b->args, K);
         }
         BHIP(b, hipStreamEndCapture(b->stream, &g));
         hipGraphExec_t ge;
@@ -643,7 +675,8 @@ static std::string tune_key(const pgk_batch *b)
     int nb = 0, lb = 0;
     while ((1 << nb) < b->n) nb++;
     while ((1LL << lb) < maxL) lb++;
-    snprintf(key, sizeof key, "%s/batch/n%d/L%d/v%d", prop.gcnArchName, nb, lb, b->host_cases[0].variant);
+    snprintf(key, sizeof key, "%s/batch/n%d/L%d/v%d/e%d", prop.gcnArchName, nb, lb, b->host_cases[0].variant,
+             b->has_e2 ? 1 : 0);
     for (char *p = key; *p; p++)
         if (*p == '"' || *p == ':') *p = '_';
     return key;
@@ -679,10 +712,12 @@ extern "C" int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_
             // time one chunk of every candidate on the live state
             const int cand[][2] = {{256, 32}, {512, 32}, {256, 128}, {512, 128}};
             double best = 1e300;
+            // (a batch holding E2 cases has one work-group size: only K is tuned)
             hipEvent_t e0, e1;
             BHIP(b, hipEventCreate(&e0));
             BHIP(b, hipEventCreate(&e1));
             for (auto &cd : cand) {
+                if (b->has_e2 && cd[0] != 256) continue;
                 long long act = running();
                 if (act == 0) break;
                 BHIP(b, hipEventRecord(e0, b->stream));

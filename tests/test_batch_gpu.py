@@ -196,3 +196,74 @@ def test_autotuner_picks_and_caches(tmp_path, monkeypatch):
     b2.run(40, 0.0)
     assert b2.tuned()[:2] == (wg, K)
     b2.close()
+
+
+def _shock_spec(Ma, L, delta, nu_cs=2.0):
+    import paper_2201_05280_amd as pgk
+    from paper_2201_05280_amd.shock import discrete_rankine_hugoniot
+    up, down = discrete_rankine_hugoniot(Ma, delta)
+    cs = np.sqrt((5 + delta) / (3 + delta) * TH0)
+    p = resolve(nu_cs * cs, 0.71, 0.8, delta)
+    return dict(L=L, bc=pgk.DIRICHLET, p=p, eq=pgk.E2, vel_axis=0,
+                faces=dict(rho=(up[0], down[0]), u=((up[1], 0, 0), (down[1], 0, 0)), theta=(up[2], down[2])),
+                up=up, down=down)
+
+
+def test_batched_e2_shocks_beside_f3_couette():
+    # one launch holding E2 shock lines and an F3 Couette layer: every case
+    # equals its single-grid run and the oracle
+    import paper_2201_05280_amd as pgk
+    from paper_2201_05280_amd.batch import Batch, make_case
+    from paper_2201_05280_amd.shock import tanh_profile
+    specs = [_shock_spec(1.5, 64, 2.0), _shock_spec(1.2, 40, 3.0, nu_cs=1.0), dict(_cases()[0], eq=pgk.F3)]
+    cases, fields = [], []
+    for i, sp in enumerate(specs):
+        p, fc = sp["p"], sp["faces"]
+        cases.append(make_case(sp["L"], sp["bc"], (p["tau"], p["tau1"], p["b"], p["kr"], p["delta"]),
+                               rho=fc.get("rho", (1.0, 1.0)), u=fc["u"], theta=fc["theta"], vel_axis=sp["vel_axis"],
+                               equilibrium=sp["eq"]))
+        fields.append(tanh_profile(sp["L"], sp["up"], sp["down"], width=3.0) if "up" in sp
+                      else _fields(sp["L"], 10 + i, sp["bc"]))
+    b = Batch(cases)
+    cat = {k: np.concatenate([f[k] for f in fields], axis=-1) for k in ("rho", "thT", "thR")}
+    cat["u"] = np.concatenate([f["u"] for f in fields], axis=1)
+    b.init(cat["rho"], cat["u"], cat["thT"], cat["thR"])
+    with pytest.raises(RuntimeError):
+        b.config(512, 25)                 # E2 batches run with work-groups of 256
+    b.config(256, 25)
+    steps, resid, status = b.run(50, 0.0)
+    assert (steps == 50).all() and (status == 3).all(), (steps, status)
+    bm = b.moments()
+    for c, sp in enumerate(specs):
+        sl = b.case_slice(c)
+        fc, p, f = sp["faces"], sp["p"], fields[c]
+        s = pgk.Solver(sp["L"], 1, 1, precision=pgk.FP64, bc_x=(sp["bc"], sp["bc"]), equilibrium=sp["eq"])
+        s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+        o = oracle.Oracle(sp["L"], 1, 1, equilibrium=oracle.E2 if sp["eq"] == pgk.E2 else oracle.F3)
+        o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+        for side in (0, 1):
+            s.set_bc_x(side, fc.get("rho", (1.0, 1.0))[side], fc["u"][side], fc["theta"][side])
+            o.set_bc_x(side, sp["bc"], fc.get("rho", (1.0, 1.0))[side], fc["u"][side], fc["theta"][side])
+        s.init(f["rho"], f["u"], f["thT"], f["thR"])
+        o.init(f["rho"], f["u"], f["thT"], f["thR"])
+        s.step(50)
+        o.step(50)
+        sm, om = s.moments(), o.moments()
+        s.close()
+        for ref, bar in ((sm, 1e-13), (om, 1e-12)):
+            for k in ("rho", "thT", "thR"):
+                err = np.abs(bm[k][sl] - ref[k]).max() / np.abs(ref[k]).max()
+                assert err <= bar, (c, k, err, bar)
+            err = np.abs(bm["u"][:, sl] - ref["u"]).max() / max(np.abs(ref["u"]).max(), 1e-2)
+            assert err <= bar, (c, "u", err, bar)
+    b.close()
+
+
+def test_batch_refuses_a_face_state_without_e2_equilibrium():
+    import paper_2201_05280_amd as pgk
+    from paper_2201_05280_amd.batch import Batch, make_case
+    p = resolve(0.05, 0.71, 0.8, 2.0)
+    c = make_case(16, pgk.DIRICHLET, (p["tau"], p["tau1"], p["b"], p["kr"], p["delta"]), rho=(1.0, 1.0),
+                  u=((0.4, 0, 0), (0.4, 0, 0)), theta=(0.05, 0.05), vel_axis=0, equilibrium=pgk.E2)
+    with pytest.raises(RuntimeError, match="EINFEASIBLE"):
+        Batch([c])
