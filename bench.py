@@ -10,8 +10,9 @@ Prints one JSON line.  MLUPS = 1e-6 x site updates per second (a cell holds
 two sites).  The roofline object is for the dominant kernel (the fused
 pull-collide kernel), timed live with HIP events on its own stream.
 
-The "sweep" object is the batched-sweep experiment: seeded 1D Couette cases
-run to residual 1e-8 cold in one persistent batched launch, warm-started
+The "sweep" object is the batched-sweep experiment: a seeded mix of 1D
+Couette layers and normal-shock lines run to residual 1e-8 cold in one
+persistent batched launch, warm-started
 from the coordinate MLP (trained on the steady states of a second seeded
 set), and one case at a time through the single-grid path (a seeded subset,
 scaled to the whole set).  `--sweep` runs it alone, `--no-sweep` skips it.
@@ -143,14 +144,24 @@ def plain_case(case, tol, max_steps, time_cap, K=128):
     import numpy as np
 
     import paper_2201_05280_amd as pgk
-    from paper_2201_05280_amd.inputs import THETA0
+    from paper_2201_05280_amd import cases as C
     p = case["params"]
-    s = pgk.Solver(case["L"], 1, 1, precision=pgk.FP64, bc_x=(pgk.WALL, pgk.WALL))
+    shock = case["kind"] == C.SHOCK
+    kind = pgk.DIRICHLET if shock else pgk.WALL
+    s = pgk.Solver(case["L"], 1, 1, precision=pgk.FP64, bc_x=(kind, kind),
+                   equilibrium=pgk.E2 if shock else pgk.F3)
     s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
-    s.set_bc_x(0, 1.0, (0, 0, 0), THETA0)
-    s.set_bc_x(1, 1.0, (0, case["U"], 0), THETA0)
-    ns = 2 * case["L"]
-    s.init(np.ones(ns), np.zeros((3, ns)), np.full(ns, THETA0), np.full(ns, THETA0))
+    if shock:
+        up, dn = case["up"], case["down"]
+        s.set_bc_x(0, up[0], (up[1], 0, 0), up[2])
+        s.set_bc_x(1, dn[0], (dn[1], 0, 0), dn[2])
+        axis = 0
+    else:
+        s.set_bc_x(0, 1.0, (0, 0, 0), THETA0)
+        s.set_bc_x(1, 1.0, (0, case["U"], 0), THETA0)
+        axis = 1
+    f = C.cold_fields([case])
+    s.init(f["rho"], f["u"], f["thT"], f["thR"])
     t0 = time.perf_counter()
     steps, resid = 0, 1.0
     while steps < max_steps and time.perf_counter() - t0 < time_cap:
@@ -160,7 +171,7 @@ def plain_case(case, tol, max_steps, time_cap, K=128):
         b = s.moments()
         steps += K
         resid = 0.0
-        for k, v in (("rho", None), ("u", 1), ("thT", None), ("thR", None)):
+        for k, v in (("rho", None), ("u", axis), ("thT", None), ("thR", None)):
             x0 = a[k] if v is None else a[k][v]
             x1 = b[k] if v is None else b[k][v]
             resid = max(resid, float(np.linalg.norm(x1 - x0) / max(np.linalg.norm(x1), 1e-300)))
@@ -234,42 +245,88 @@ def shock_summary(max_steps=60000):
 
 
 def sweep(args):
-    """Time to residual 1e-8 of a batch of Couette cases: plain (one case at a
-    time), batched cold, batched warm-started by the MLP."""
+    """Time to residual 1e-8 of a seeded mix of 1D cases (Couette layers and
+    normal-shock lines): plain (one case at a time), batched cold, batched
+    warm-started by the MLP."""
     import numpy as np
     import torch
 
     from paper_2201_05280_amd import cases as C
-    from paper_2201_05280_amd.inputs import mlp_init
     from paper_2201_05280_amd.batch import Batch
+    from paper_2201_05280_amd.inputs import mlp_init
     from paper_2201_05280_amd.mlp import MLP
+    from paper_2201_05280_amd.shock import profile_metrics
 
     S = 220105280
     tol = 1e-8
-    kw = dict(L_range=(args.sweep_lmin, args.sweep_lmax), Kn_range=(args.sweep_knmin, args.sweep_knmax))
+    kw = dict(L_range=(args.sweep_lmin, args.sweep_lmax), Kn_range=(args.sweep_knmin, args.sweep_knmax),
+              shock_fraction=args.sweep_shock_frac, shock_Ma_range=(1.1, 1.6), shock_Kn_range=(2e-3, 6e-3))
     test, red_t = C.sweep_cases(args.sweep_n, S, **kw)
     train, red_r = C.sweep_cases(args.sweep_train, S + 1, **kw)
+    is_shock = np.array([c["kind"] == C.SHOCK for c in test])
     out = {"metric": "sweep time-to-residual 1e-8 plain vs batched+MLP", "unit": "s", "tol": tol,
-           "cases": len(test), "train_cases": len(train), "infeasible_redraws": red_t + red_r,
-           "distribution": "Couette, L~U{%d..%d}, Ma_w~U[0.1,0.5], Kn~logU[%g,%g], Pr~U[0.67,1], "
-                           "mu_b/mu~U[0,2] (floor redraw), delta in {2,3}"
-                           % (args.sweep_lmin, args.sweep_lmax, args.sweep_knmin, args.sweep_knmax)}
+           "cases": len(test), "shock_cases": int(is_shock.sum()), "train_cases": len(train),
+           "infeasible_redraws": red_t + red_r,
+           "distribution": "L~U{%d..%d}, delta in {2,3}, Pr~U[0.67,1], mu_b/mu~U[0,2] (infeasible pairs redrawn); "
+                           "%.0f%% Couette (F3): Ma_w~U[0.1,0.5], Kn=nu/(c_s L)~logU[%g,%g]; "
+                           "%.0f%% normal shocks (E2): Ma~U[1.1,1.6], Kn=lambda1/L~logU[0.002,0.006]"
+                           % (args.sweep_lmin, args.sweep_lmax, 100 * (1 - args.sweep_shock_frac), args.sweep_knmin,
+                              args.sweep_knmax, 100 * args.sweep_shock_frac),
+           "stall_window_steps": args.sweep_stall}
 
     def run_batch(cs, fields, label):
-        b = Batch(C.to_batch_cases(cs))
-        b.init(fields["rho"], fields["u"], fields["thT"], fields["thR"])
-        b.config(0, 0)
+        """Run the cases to the tolerance: the Couette layers (F3, any
+        work-group size) and the shock lines (E2, work-groups of 256) as two
+        batches, each one persistent launch per chunk on its own stream, run
+        concurrently from two host threads; results in the order of cs."""
+        import threading
+        offs = np.concatenate([[0], np.cumsum([2 * c["L"] for c in cs])])
+        groups = [[i for i, c in enumerate(cs) if c["kind"] == k] for k in (C.COUETTE, C.SHOCK)]
+        groups = [g for g in groups if g]
+        res = [None] * len(groups)
+
+        wall = [0.0] * len(groups)
+
+        def worker(j, idx):
+            tw = time.perf_counter()
+            stream = torch.cuda.Stream()
+            sub = [cs[i] for i in idx]
+            sel = np.concatenate([np.arange(offs[i], offs[i + 1]) for i in idx])
+            b = Batch(C.to_batch_cases(sub), stream=stream)
+            b.init(fields["rho"][sel], fields["u"][:, sel], fields["thT"][sel], fields["thR"][sel])
+            b.config(0, 0)
+            b.stall(args.sweep_stall)
+            stream.synchronize()
+            steps, resid, status = b.run(args.sweep_max_steps, tol)
+            res[j] = (idx, sel, steps, resid, status, b.moments(), b.tuned())
+            b.close()
+            wall[j] = time.perf_counter() - tw
+
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        steps, resid, status = b.run(args.sweep_max_steps, tol)
+        th = [threading.Thread(target=worker, args=(j, g)) for j, g in enumerate(groups)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
         dt = time.perf_counter() - t0
-        m = b.moments()
-        wg, K, nsps = b.tuned()
-        b.close()
-        print("# %s: %.2f s, steps median %d max %d, converged %d/%d, config wg=%d K=%d"
-              % (label, dt, np.median(steps), steps.max(), (status == 1).sum(), len(cs), wg, K),
+        if any(r is None for r in res):
+            raise RuntimeError("a batch failed")
+        n, ns = len(cs), int(offs[-1])
+        steps, resid, status = np.zeros(n, dtype=np.int64), np.zeros(n), np.zeros(n, dtype=np.int64)
+        m = dict(rho=np.zeros(ns), u=np.zeros((3, ns)), thT=np.zeros(ns), thR=np.zeros(ns))
+        cfg = []
+        for (idx, sel, st, rs, stt, mm, tuned), w in zip(res, wall):
+            steps[idx], resid[idx], status[idx] = st, rs, stt
+            for k in ("rho", "thT", "thR"):
+                m[k][sel] = mm[k]
+            m["u"][:, sel] = mm["u"]
+            cfg.append({"kind": cs[idx[0]]["kind"], "cases": len(idx), "wg": tuned[0], "K": tuned[1],
+                        "ns_per_site_update": round(tuned[2], 4), "wall_s": round(w, 2)})
+        print("# %s: %.2f s, steps median %d max %d, status counts %s, configs %s"
+              % (label, dt, np.median(steps), steps.max(), np.bincount(status, minlength=5).tolist(), cfg),
               file=sys.stderr, flush=True)
-        return dict(time=dt, steps=steps, status=status, resid=resid, m=m, wg=wg, K=K, ns_per_site=nsps)
+        return dict(time=dt, steps=steps, status=status, resid=resid, m=m, cfg=cfg)
 
     # training data: steady states of the training cases (cold batched runs);
     # the first run also settles the autotuner's choice for this case mix
@@ -292,49 +349,79 @@ def sweep(args):
     warm = run_batch(test, C.fields_from_prediction(test, y), "held-out warm")
     mlp.close()
 
-    # final match of warm and cold converged states, per case, against the
-    # bound 2 R / r_slow of a run stopped at residual R (r_slow ~ pi^2 nu / L^2)
+    # final match of warm and cold converged states.  Couette: max |du|/U
+    # against the bound 2 R / r_slow of a run stopped at residual R
+    # (r_slow ~ pi^2 nu / L^2).  Shock: a shock between Dirichlet faces may
+    # settle anywhere, so the shift of its position is reported and the
+    # density profiles are compared with the positions aligned (max |drho| over
+    # the jump rho2 - rho1).
     both = (cold["status"] == 1) & (warm["status"] == 1)
-    worst, o = 0.0, 0
+    worst_c, worst_s, shift, o = 0.0, 0.0, 0.0, 0
+    from paper_2201_05280_amd.inputs import positions
     for c, ok_c in zip(test, both):
         n = 2 * c["L"]
         if ok_c:
             sl = slice(o, o + n)
-            du = np.abs(warm["m"]["u"][1][sl] - cold["m"]["u"][1][sl]).max() / c["U"]
-            r_slow = math.pi ** 2 * c["nu"] / c["L"] ** 2
-            worst = max(worst, du / (2 * tol / r_slow))
+            if c["kind"] == C.SHOCK:
+                # compare the profiles with the two shock positions aligned
+                dr = c["down"][0] - c["up"][0]
+                x = positions(c["L"], 1, 1)[0]
+                order = np.argsort(x)
+                xs, rw, rc_ = x[order], warm["m"]["rho"][sl][order], cold["m"]["rho"][sl][order]
+                pw = profile_metrics(x, warm["m"]["rho"][sl], c["up"], c["down"])[0]
+                pc = profile_metrics(x, cold["m"]["rho"][sl], c["up"], c["down"])[0]
+                d = pw - pc
+                inside = (xs + d >= xs[0]) & (xs + d <= xs[-1])
+                aligned = np.interp(xs[inside] + d, xs, rw)
+                worst_s = max(worst_s, float(np.abs(aligned - rc_[inside]).max() / dr))
+                shift = max(shift, abs(d))
+            else:
+                du = np.abs(warm["m"]["u"][1][sl] - cold["m"]["u"][1][sl]).max() / c["U"]
+                r_slow = math.pi ** 2 * c["nu"] / c["L"] ** 2
+                worst_c = max(worst_c, du / (2 * tol / r_slow))
         o += n
     # plain: a seeded subset of the held-out cases, one at a time through the
     # single-grid path; a case stopped by the time cap is charged its measured
-    # time per step times the steps the batched run needed (same arithmetic,
+    # time per step times the steps the batched run took (same arithmetic,
     # so the same step count: checked on the cases that finish)
     idx = np.random.default_rng(S).choice(len(test), size=min(args.sweep_plain, len(test)), replace=False)
     tp, n_full, step_match = 0.0, 0, True
     for i in idx:
-        st, rs, dt = plain_case(test[i], tol, args.sweep_max_steps, args.sweep_plain_cap)
-        if rs <= tol:
+        st, rs, dt = plain_case(test[i], tol, min(args.sweep_max_steps, int(cold["steps"][i])), args.sweep_plain_cap)
+        if rs <= tol or st >= int(cold["steps"][i]):
             n_full += 1
             tp += dt
             step_match &= abs(st - int(cold["steps"][i])) <= 128
         else:
             tp += dt / st * int(cold["steps"][i])
-        print("# plain case %d: L=%d steps %d (batched %d) %.2f s" % (i, test[i]["L"], st, cold["steps"][i], dt),
-              file=sys.stderr, flush=True)
+        print("# plain case %d (%s): L=%d steps %d (batched %d) %.2f s"
+              % (i, test[i]["kind"], test[i]["L"], st, cold["steps"][i], dt), file=sys.stderr, flush=True)
     plain_est = tp * len(test) / len(idx)   # unbiased for a uniform random subset
+
+    def counts(r, mask):
+        return {k: int(((r["status"] == v) & mask).sum()) for k, v in
+                (("converged", 1), ("diverged", 2), ("max_steps", 3), ("stalled", 4))}
+
     out.update({
-        "plain_subset_cases": len(idx), "plain_subset_time": round(tp, 2), "plain_subset_run_to_tol": n_full,
+        "plain_subset_cases": len(idx), "plain_subset_time": round(tp, 2), "plain_subset_run_to_end": n_full,
         "plain_steps_match_batched": bool(step_match),
         "plain_estimated_time": round(plain_est, 1),
         "batched_cold_time": round(cold["time"], 2), "batched_warm_time": round(warm["time"] + t_infer, 2),
         "batched_warm_plus_training_time": round(warm["time"] + t_infer + t_train, 2),
         "mlp_inference_time": round(t_infer, 3), "mlp_train_time": round(t_train, 1),
+        "mlp_train_points": int(len(X)),
         "mlp_loss_first_last": [float(losses[0]), float(losses[-1])],
-        "steps_cold_median": int(np.median(cold["steps"])), "steps_warm_median": int(np.median(warm["steps"])),
+        "couette": {"cold": counts(cold, ~is_shock), "warm": counts(warm, ~is_shock),
+                    "steps_cold_median": int(np.median(cold["steps"][~is_shock])) if (~is_shock).any() else None,
+                    "steps_warm_median": int(np.median(warm["steps"][~is_shock])) if (~is_shock).any() else None,
+                    "warm_vs_cold_max_du_over_bound": round(worst_c, 3)},
+        "shock": {"cold": counts(cold, is_shock), "warm": counts(warm, is_shock),
+                  "steps_cold_median": int(np.median(cold["steps"][is_shock])) if is_shock.any() else None,
+                  "steps_warm_median": int(np.median(warm["steps"][is_shock])) if is_shock.any() else None,
+                  "warm_vs_cold_max_drho_over_jump_aligned": round(worst_s, 6),
+                  "warm_vs_cold_max_shift_cells": round(shift, 4)},
         "steps_cold_total": int(cold["steps"].sum()), "steps_warm_total": int(warm["steps"].sum()),
-        "converged_cold": int((cold["status"] == 1).sum()), "converged_warm": int((warm["status"] == 1).sum()),
-        "diverged_cold": int((cold["status"] == 2).sum()), "diverged_warm": int((warm["status"] == 2).sum()),
-        "warm_vs_cold_max_du_over_bound": round(worst, 3),
-        "batch_config": {"wg": cold["wg"], "K": cold["K"], "ns_per_site_update": round(cold["ns_per_site"], 4)},
+        "batch_configs": cold["cfg"],
         "speedup_warm_vs_cold": round(cold["time"] / (warm["time"] + t_infer), 3),
         "speedup_batched_cold_vs_plain": round(plain_est / cold["time"], 2),
         "speedup_batched_warm_vs_plain": round(plain_est / (warm["time"] + t_infer), 2),
@@ -366,6 +453,8 @@ def main():
     ap.add_argument("--sweep-epochs", type=int, default=40)
     ap.add_argument("--sweep-plain", type=int, default=8)
     ap.add_argument("--sweep-plain-cap", type=float, default=10.0)
+    ap.add_argument("--sweep-shock-frac", type=float, default=0.5)
+    ap.add_argument("--sweep-stall", type=int, default=25600, help="steps without halving the residual")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain device copy (torch) as the achievable-bandwidth reference")
     args = ap.parse_args()

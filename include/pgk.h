@@ -217,6 +217,7 @@ int pgk_kernel_times(pgk_ctx *ctx, double ms[PGK_NKERNEL], int64_t launches[PGK_
 #define PGK_CASE_CONVERGED 1
 #define PGK_CASE_DIVERGED  2
 #define PGK_CASE_MAXSTEPS  3
+#define PGK_CASE_STALLED   4   /* residual stopped falling (see pgk_batch_stall) */
 
 typedef struct {
     int L;                   /* cells along x, 4 <= L <= 8192 */
@@ -254,6 +255,13 @@ int pgk_batch_config(pgk_batch *b, int wg, int K);
 /* Run until every case has stopped or max_steps per case.  Host arrays of n
  * entries receive the steps taken, the last residual and the status. */
 int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_t *steps, double *resid, int *status);
+
+/* Stall detection for pgk_batch_run: a running case whose residual has not
+ * fallen below half of its best value for `window` steps (counted in whole
+ * chunks) stops with PGK_CASE_STALLED (a structure that creeps instead of
+ * settling, such as a thin shock between two Dirichlet faces, holds its
+ * residual at a floor).  window = 0 (the default) turns it off. */
+int pgk_batch_stall(pgk_batch *b, int64_t window);
 
 /* Work-group size, K and measured nanoseconds per site update of the chosen config. */
 int pgk_batch_tuned(const pgk_batch *b, int *wg, int *K, double *ns_per_site_update);

@@ -25,12 +25,12 @@ EXPORTS = ["pgk_resolve", "pgk_lattice", "pgk_equilibrium", "pgk_buffer_sizes", 
            "pgk_set_bc_x", "pgk_init_fields", "pgk_step", "pgk_read_moments", "pgk_conserved",
            "pgk_set_timing", "pgk_kernel_times", "pgk_steps_done", "pgk_last_error", "pgk_destroy",
            "pgk_batch_bytes", "pgk_batch_create", "pgk_batch_offsets", "pgk_batch_init", "pgk_batch_config",
-           "pgk_batch_run", "pgk_batch_tuned", "pgk_batch_read_moments", "pgk_batch_last_error",
+           "pgk_batch_run", "pgk_batch_stall", "pgk_batch_tuned", "pgk_batch_read_moments", "pgk_batch_last_error",
            "pgk_batch_destroy", "pgk_mlp_bytes", "pgk_mlp_create", "pgk_mlp_set_params", "pgk_mlp_get_params",
            "pgk_mlp_forward", "pgk_mlp_loss_grad", "pgk_mlp_adam_step", "pgk_mlp_train", "pgk_mlp_last_error",
            "pgk_mlp_destroy"]
 MLP_NPARAM = 50948
-CASE_RUNNING, CASE_CONVERGED, CASE_DIVERGED, CASE_MAXSTEPS = 0, 1, 2, 3
+CASE_RUNNING, CASE_CONVERGED, CASE_DIVERGED, CASE_MAXSTEPS, CASE_STALLED = 0, 1, 2, 3, 4
 NKERNEL = 4
 KERNEL_NAMES = ["k_lb", "k_mc", "k_dif", "k_bc"]
 

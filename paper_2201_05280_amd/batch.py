@@ -87,6 +87,10 @@ class Batch:
     def config(self, wg=0, K=0):
         self._check(self.L.pgk_batch_config(self.h, wg, K))
 
+    def stall(self, window):
+        """Stop a case as STALLED after `window` steps without halving its best residual (0: off)."""
+        self._check(self.L.pgk_batch_stall(self.h, ctypes.c_int64(int(window))))
+
     def run(self, max_steps, tol):
         steps = (ctypes.c_int64 * self.n)()
         resid = (ctypes.c_double * self.n)()

@@ -1,5 +1,7 @@
 """Seeded 1D case generator for the batched sweep and the learned warm start.
 
+Two kinds of case: Couette layers (F3) and normal-shock lines (E2).
+
 Couette layers between two diffuse walls (Sec. 6 runs start-up and thermal
 Couette flows): the low wall at rest, the high wall moving tangentially (y)
 at Ma_w c_s, both at theta0.  Knudsen number Kn = nu/(c_s L) (the reading
@@ -10,9 +12,18 @@ mu_b/mu ~ U[mub range] redrawn together while it is out of the model's reach
 (mu_b/mu at or below 1.02 times the floor 2 delta/(3(3+delta)), or no
 feasible (b, k_r) for it).
 
-Network features (all O(1)): x/L, (Ma - 0.3)/0.2, (Pr - 0.835)/0.165,
-(mu_b/mu - 1), log10 Kn + 2, (delta - 2.5)/0.5; targets: (rho - 1)/U^2,
-u_y/U, (theta_T - theta0)/U^2, (theta_R - theta0)/U^2 with U the wall speed.
+Shock lines: upstream (rho 1, Ma c_s, theta0) at the low face, the model's
+own downstream state (equal equilibrium fluxes) at the high face, flow along
++x; Ma ~ U[shock Ma range], Kn = lambda1 / L with the upstream mean free path
+lambda1 = nu sqrt(pi / (2 theta0)), Kn ~ logU[shock Kn range]; same Pr,
+mu_b/mu and delta draws.  Their cold start is the tanh blend of the two
+states (width 4 cells) centred at L/2.
+
+Network features (all O(1)): x/L, 2 ln(Ma/0.3), (Pr - 0.835)/0.165,
+(mu_b/mu - 1), log10 Kn + 2, (delta - 2.5)/0.5.  Targets, Couette:
+(rho - 1)/U^2, u_y/U, (theta_T - theta0)/U^2, (theta_R - theta0)/U^2 with U the
+wall speed; shock: each field scaled to run from 0 upstream to 1 downstream,
+(phi - phi1)/(phi2 - phi1) for rho, u_x, theta_T, theta_R.
 """
 import math
 
@@ -22,22 +33,29 @@ from . import _lib
 from .inputs import THETA0, positions
 
 COUETTE = "couette"
+SHOCK = "shock"
 
 
 def sweep_cases(n, seed, L_range=(256, 1024), Ma_range=(0.1, 0.5), Kn_range=(3e-3, 3e-2),
-                Pr_range=(0.67, 1.0), mub_range=(0.0, 2.0), deltas=(2.0, 3.0)):
+                Pr_range=(0.67, 1.0), mub_range=(0.0, 2.0), deltas=(2.0, 3.0), shock_fraction=0.0,
+                shock_Ma_range=(1.1, 2.0), shock_Kn_range=(2e-3, 1e-2)):
+    """n seeded cases (a shock with probability shock_fraction) and the number
+    of infeasible (Pr, mu_b/mu) draws that were redrawn."""
+    from .shock import discrete_rankine_hugoniot
     rng = np.random.default_rng(seed)
     out = []
     redraws = 0
     for _ in range(n):
+        kind = SHOCK if rng.uniform() < shock_fraction else COUETTE
         L = int(rng.integers(L_range[0], L_range[1] + 1))
-        Ma = float(rng.uniform(*Ma_range))
-        Kn = float(10 ** rng.uniform(math.log10(Kn_range[0]), math.log10(Kn_range[1])))
+        ma_r, kn_r = (shock_Ma_range, shock_Kn_range) if kind == SHOCK else (Ma_range, Kn_range)
+        Ma = float(rng.uniform(*ma_r))
+        Kn = float(10 ** rng.uniform(math.log10(kn_r[0]), math.log10(kn_r[1])))
         delta = float(deltas[int(rng.integers(0, len(deltas)))])
         floor = 2 * delta / (3 * (3 + delta)) * 1.02
         gamma = (5 + delta) / (3 + delta)
         cs = math.sqrt(gamma * THETA0)
-        nu = Kn * cs * L
+        nu = Kn * cs * L if kind == COUETTE else Kn * L / math.sqrt(math.pi / (2 * THETA0))
         while True:
             # (Pr, mu_b/mu) pairs outside the model's reach (bulk viscosity at
             # or below the floor, or no b in [-1/2, 1) with k_r >= 0) are redrawn
@@ -50,8 +68,10 @@ def sweep_cases(n, seed, L_range=(256, 1024), Ma_range=(0.1, 0.5), Kn_range=(3e-
                 except ValueError:
                     pass
             redraws += 1
-        out.append(dict(kind=COUETTE, L=L, Ma=Ma, Kn=Kn, Pr=Pr, mub=mub, delta=delta, nu=nu,
-                        U=Ma * cs, params=p))
+        c = dict(kind=kind, L=L, Ma=Ma, Kn=Kn, Pr=Pr, mub=mub, delta=delta, nu=nu, U=Ma * cs, params=p)
+        if kind == SHOCK:
+            c["up"], c["down"] = discrete_rankine_hugoniot(Ma, delta)
+        out.append(c)
     return out, redraws
 
 
@@ -60,15 +80,29 @@ def to_batch_cases(cases, variant=0):
     res = []
     for c in cases:
         p = c["params"]
-        res.append(make_case(c["L"], _lib.WALL, (p["tau"], p["tau1"], p["b"], p["kr"], p["delta"]),
-                             u=((0, 0, 0), (0, c["U"], 0)), theta=(THETA0, THETA0), vel_axis=1, variant=variant))
+        pp = (p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+        if c["kind"] == SHOCK:
+            up, dn = c["up"], c["down"]
+            res.append(make_case(c["L"], _lib.DIRICHLET, pp, rho=(up[0], dn[0]), u=((up[1], 0, 0), (dn[1], 0, 0)),
+                                 theta=(up[2], dn[2]), vel_axis=0, variant=variant, equilibrium=_lib.E2))
+        else:
+            res.append(make_case(c["L"], _lib.WALL, pp, u=((0, 0, 0), (0, c["U"], 0)), theta=(THETA0, THETA0),
+                                 vel_axis=1, variant=variant))
     return res
 
 
 def cold_fields(cases):
-    """Uniform gas at rest at theta0 for every case, concatenated over sites."""
-    ns = sum(2 * c["L"] for c in cases)
-    return dict(rho=np.ones(ns), u=np.zeros((3, ns)), thT=np.full(ns, THETA0), thR=np.full(ns, THETA0))
+    """Cold starts concatenated over sites: Couette, uniform gas at rest at
+    theta0; shock, the tanh blend of its two states."""
+    from .shock import tanh_profile
+    parts = []
+    for c in cases:
+        if c["kind"] == SHOCK:
+            parts.append(tanh_profile(c["L"], c["up"], c["down"]))
+        else:
+            ns = 2 * c["L"]
+            parts.append(dict(rho=np.ones(ns), u=np.zeros((3, ns)), thT=np.full(ns, THETA0), thR=np.full(ns, THETA0)))
+    return {k: np.concatenate([f[k] for f in parts], axis=-1) for k in ("rho", "u", "thT", "thR")}
 
 
 def features(cases):
@@ -80,7 +114,7 @@ def features(cases):
         xl = (x + 0.25) / c["L"]
         f = np.empty((x.size, 6), dtype=np.float32)
         f[:, 0] = xl
-        f[:, 1] = (c["Ma"] - 0.3) / 0.2
+        f[:, 1] = 2.0 * math.log(c["Ma"] / 0.3)
         f[:, 2] = (c["Pr"] - 0.835) / 0.165
         f[:, 3] = c["mub"] - 1.0
         f[:, 4] = math.log10(c["Kn"]) + 2.0
@@ -97,10 +131,17 @@ def targets(cases, m):
         U = c["U"]
         sl = slice(o, o + ns)
         t = np.empty((ns, 4), dtype=np.float32)
-        t[:, 0] = (m["rho"][sl] - 1.0) / U ** 2
-        t[:, 1] = m["u"][1][sl] / U
-        t[:, 2] = (m["thT"][sl] - THETA0) / U ** 2
-        t[:, 3] = (m["thR"][sl] - THETA0) / U ** 2
+        if c["kind"] == SHOCK:
+            (r1, u1, t1), (r2, u2, t2) = c["up"], c["down"]
+            t[:, 0] = (m["rho"][sl] - r1) / (r2 - r1)
+            t[:, 1] = (m["u"][0][sl] - u1) / (u2 - u1)
+            t[:, 2] = (m["thT"][sl] - t1) / (t2 - t1)
+            t[:, 3] = (m["thR"][sl] - t1) / (t2 - t1)
+        else:
+            t[:, 0] = (m["rho"][sl] - 1.0) / U ** 2
+            t[:, 1] = m["u"][1][sl] / U
+            t[:, 2] = (m["thT"][sl] - THETA0) / U ** 2
+            t[:, 3] = (m["thR"][sl] - THETA0) / U ** 2
         out.append(t)
         o += ns
     return np.concatenate(out)
@@ -115,9 +156,16 @@ def fields_from_prediction(cases, y):
         n = 2 * c["L"]
         U = c["U"]
         sl = slice(o, o + n)
-        rho[sl] = 1.0 + U ** 2 * y[sl, 0]
-        u[1, sl] = U * y[sl, 1]
-        thT[sl] = THETA0 + U ** 2 * y[sl, 2]
-        thR[sl] = THETA0 + U ** 2 * y[sl, 3]
+        if c["kind"] == SHOCK:
+            (r1, u1, t1), (r2, u2, t2) = c["up"], c["down"]
+            rho[sl] = r1 + (r2 - r1) * y[sl, 0]
+            u[0, sl] = u1 + (u2 - u1) * y[sl, 1]
+            thT[sl] = t1 + (t2 - t1) * y[sl, 2]
+            thR[sl] = t1 + (t2 - t1) * y[sl, 3]
+        else:
+            rho[sl] = 1.0 + U ** 2 * y[sl, 0]
+            u[1, sl] = U * y[sl, 1]
+            thT[sl] = THETA0 + U ** 2 * y[sl, 2]
+            thR[sl] = THETA0 + U ** 2 * y[sl, 3]
         o += n
     return dict(rho=rho, u=u, thT=thT, thR=thR)

@@ -16,8 +16,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <sys/stat.h>
+#include <unistd.h>
 #include <vector>
 
 #include "device.hpp"
@@ -38,6 +40,7 @@ struct BatchArgs {
     int *cur;
     double *resid;
     double *popA, *popB, *thR, *that_, *tmc, *tmc2, *aux, *snap, *gh;
+    double *lmul;       // [2 E2_NL][2L] per case: E2 multipliers of the last step (E2 batches only)
     long long max_steps;
     double tol;
     int lds_sites;      // cases with ns <= lds_sites diffuse theta_R in LDS
@@ -173,9 +176,10 @@ __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
         if (steps > 0) bc_line(src, gh, k);
         __syncthreads();
         if (E2CAP && bc.eq == PGK_E2) {
+            double *lm = a.lmul + (size_t)2 * E2_NL * off;
             for (int s = tid; s < ns; s += NTH) {
                 double r;
-                lb_site<double, double, VAR, true, PGK_E2>(s, src, dst, gh, thR, that_, aux, k, r);
+                lb_site<double, double, VAR, true, PGK_E2>(s, src, dst, gh, thR, that_, aux, k, r, lm);
             }
         } else {
             for (int s = tid; s < ns; s += NTH) {
@@ -276,6 +280,11 @@ __global__ __launch_bounds__(NTH) void k_batch_init(BatchArgs a, const double *_
     double *dst = a.popA + (size_t)NQ * off;
     double *gh = a.gh + (size_t)c * GHOSTS_PER_CASE;
     // the case's slices of the input fields; u is [3][ns_total]
+    if (bc.eq == PGK_E2) {
+        // no previous multipliers: the first step starts Newton from the Gaussian
+        double *lm = a.lmul + (size_t)2 * E2_NL * off;
+        for (long long i = threadIdx.x; i < (long long)2 * E2_NL * k.ns; i += NTH) lm[i] = __builtin_nan("");
+    }
     for (int s = threadIdx.x; s < k.ns; s += NTH) {
         if (bc.eq == PGK_E2)
             init_site<double, true, PGK_E2>(s, dst, gh, a.thR + off, rho + off, u + off, thT + off, thRin + off, k,
@@ -329,6 +338,7 @@ struct pgk_batch {
     std::vector<long long> off;
     BatchArgs args{};
     bool has_e2 = false;          // some case uses E2: the E2-capable kernel, work-groups of 256
+    long long stall_window = 0;   // steps without halving the best residual before STALLED (0: off)
     int wg = 0, K = 0;            // fixed config (0 = tune)
     int tuned_wg = 0, tuned_K = 0;
     double tuned_ns = 0.0;
@@ -362,10 +372,10 @@ static int bfail(pgk_batch *b, int code, const std::string &m)
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BatchLayout {
-    size_t cases, order, status, steps, cur, resid, popA, popB, thR, that_, tmc, tmc2, aux, snap, gh, total;
+    size_t cases, order, status, steps, cur, resid, popA, popB, thR, that_, tmc, tmc2, aux, snap, gh, lmul, total;
 };
 
-static BatchLayout layout(int n, long long ns)
+static BatchLayout layout(int n, long long ns, bool e2)
 {
     BatchLayout L{};
     size_t o = 0;
@@ -385,6 +395,7 @@ static BatchLayout layout(int n, long long ns)
     L.aux = take(8ull * 5 * ns);
     L.snap = take(8ull * 4 * ns);
     L.gh = take(8ull * GHOSTS_PER_CASE * n);
+    L.lmul = e2 ? take(8ull * 2 * E2_NL * ns) : 0;
     L.total = o;
     return L;
 }
@@ -410,11 +421,13 @@ extern "C" int pgk_batch_bytes(const pgk_case *cases, int n, size_t *bytes)
 {
     if (!cases || n <= 0 || !bytes) return PGK_EINVAL;
     long long ns = 0;
+    bool e2 = false;
     for (int i = 0; i < n; i++) {
         if (!case_ok(cases[i])) return PGK_EINVAL;
         ns += 2LL * cases[i].L;
+        e2 = e2 || cases[i].equilibrium == PGK_E2;
     }
-    *bytes = layout(n, ns).total;
+    *bytes = layout(n, ns, e2).total;
     return PGK_OK;
 }
 
@@ -510,7 +523,7 @@ extern "C" int pgk_batch_create(const pgk_case *cases, int n, void *stream, void
     }
     b->off[n] = o;
     b->ns_total = o;
-    BatchLayout L = layout(n, o);
+    BatchLayout L = layout(n, o, b->has_e2);
     char *base = (char *)buf;
     BatchArgs &a = b->args;
     a.cases = (const BatchCase *)(base + L.cases);
@@ -528,6 +541,7 @@ extern "C" int pgk_batch_create(const pgk_case *cases, int n, void *stream, void
     a.aux = (double *)(base + L.aux);
     a.snap = (double *)(base + L.snap);
     a.gh = (double *)(base + L.gh);
+    a.lmul = b->has_e2 ? (double *)(base + L.lmul) : nullptr;
     long long maxns = 0;
     for (auto &c : b->host_cases) maxns = std::max<long long>(maxns, c.k.ns);
     a.lds_sites = (int)std::min<long long>(maxns, LDS_SITES_MAX);
@@ -647,12 +661,18 @@ static std::map<std::string, std::pair<int, int>> cache_load()
     return m;
 }
 
+// batches tuned from several host threads share the file: one lock per
+// process around load-modify-store, and a rename so that a reader never sees
+// a half-written file
+static std::mutex cache_mutex;
+
 static void cache_store(const std::map<std::string, std::pair<int, int>> &m)
 {
     std::string path = cache_path();
     size_t slash = path.rfind('/');
     if (slash != std::string::npos) (void)mkdir(path.substr(0, slash).c_str(), 0755);
-    FILE *f = fopen(path.c_str(), "w");
+    std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+    FILE *f = fopen(tmp.c_str(), "w");
     if (!f) return;
     fprintf(f, "{\n");
     size_t i = 0;
@@ -660,6 +680,7 @@ static void cache_store(const std::map<std::string, std::pair<int, int>> &m)
                               ++i < m.size() ? "," : "");
     fprintf(f, "}\n");
     fclose(f);
+    if (rename(tmp.c_str(), path.c_str()) != 0) (void)remove(tmp.c_str());
 }
 
 static std::string tune_key(const pgk_batch *b)
@@ -703,9 +724,15 @@ extern "C" int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_
     int wg = b->wg, K = b->K;
     if (wg == 0) {
         std::string key = tune_key(b);
-        auto cache = cache_load();
+        std::map<std::string, std::pair<int, int>> cache;
+        {
+            std::lock_guard<std::mutex> lock(cache_mutex);
+            cache = cache_load();
+        }
         auto hit = cache.find(key);
-        if (hit != cache.end()) {
+        bool usable = hit != cache.end() && (hit->second.first == 256 || (hit->second.first == 512 && !b->has_e2)) &&
+                      hit->second.second >= 2;
+        if (usable) {
             wg = hit->second.first;
             K = hit->second.second;
         } else {
@@ -736,6 +763,8 @@ extern "C" int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_
             (void)hipEventDestroy(e1);
             if (wg == 0) { wg = 256; K = 128; }
             b->tuned_ns = best;
+            std::lock_guard<std::mutex> lock(cache_mutex);
+            cache = cache_load();
             cache[key] = {wg, K};
             cache_store(cache);
         }
@@ -747,6 +776,8 @@ extern "C" int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_
     BHIP(b, hipEventCreate(&t0));
     BHIP(b, hipEventCreate(&t1));
     double site_updates = 0.0, ms_total = 0.0;
+    std::vector<double> best(b->n, 1e300);
+    std::vector<long long> since(b->n, 0);
     while (true) {
         long long act = running();
         if (act == 0) break;
@@ -760,6 +791,23 @@ extern "C" int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_
         BHIP(b, hipEventElapsedTime(&ms, t0, t1));
         ms_total += ms;
         site_updates += (double)act * K;
+        if (b->stall_window > 0) {
+            bool changed = false;
+            for (int i = 0; i < b->n; i++) {
+                if (b->h_status[i] != PGK_CASE_RUNNING) continue;
+                if (b->h_resid[i] < 0.5 * best[i]) {
+                    best[i] = b->h_resid[i];
+                    since[i] = 0;
+                } else if ((since[i] += K) >= b->stall_window) {
+                    b->h_status[i] = PGK_CASE_STALLED;
+                    changed = true;
+                }
+            }
+            // the kernel skips every case whose status is not RUNNING
+            if (changed)
+                BHIP(b, hipMemcpyAsync(b->args.status, b->h_status, sizeof(int) * b->n, hipMemcpyHostToDevice,
+                                       b->stream));
+        }
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
@@ -769,6 +817,13 @@ extern "C" int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_
         if (resid) resid[i] = b->h_resid[i];
         if (status) status[i] = b->h_status[i];
     }
+    return PGK_OK;
+}
+
+extern "C" int pgk_batch_stall(pgk_batch *b, int64_t window)
+{
+    if (!b || window < 0) return PGK_EINVAL;
+    b->stall_window = window;
     return PGK_OK;
 }
 

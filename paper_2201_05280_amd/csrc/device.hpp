@@ -423,6 +423,14 @@ __device__ __forceinline__ void e2_site(double rho, const double *u, const doubl
         for (int i = 0; i < E2_NL; i++) l[i] = __builtin_nan("");
 }
 
+// the same, Newton started from the multipliers in l when they are finite
+__device__ __forceinline__ void e2_site_from(double rho, const double *u, const double *lam, const Consts &k,
+                                             double *l)
+{
+    if (e2_solve_from(k.th0, k.w, rho, u, lam, l) < 0)
+        for (int i = 0; i < E2_NL; i++) l[i] = __builtin_nan("");
+}
+
 // block-wide sum of NV doubles; thread 0 of the block gets the result
 template <int NV>
 __device__ __forceinline__ void block_sum(double *val, double *out)
@@ -448,11 +456,13 @@ __device__ __forceinline__ void block_sum(double *val, double *out)
 // ---------------------------------------------------------------------------
 // fused pull - moments - solve - equilibrium - collide of site s; returns the
 // moments of g (time level n) and the stored theta_R in r_out
+// lmul (E2 only, may be null): per-site store [2 E2_NL][ns] of the two
+// multiplier sets of the last step; each Newton run starts from them
 template <typename S, typename A, int VAR, bool BOUNDED, int EQ = PGK_F3>
 __device__ __forceinline__ Mom lb_site(int s, const S *__restrict__ src, S *__restrict__ dst,
                                        const S *__restrict__ gh, double *__restrict__ thR,
                                        double *__restrict__ that_, A *__restrict__ aux, const Consts &k,
-                                       double &r_out)
+                                       double &r_out, double *__restrict__ lmul = nullptr)
 {
     int x, y, z, sub;
     decode(s, k, x, y, z, sub);
@@ -470,8 +480,21 @@ __device__ __forceinline__ Mom lb_site(int s, const S *__restrict__ src, S *__re
             les[i] = (i < 3 ? so.T : 0.0) + cb * so.sg[i];
             lmb[i] = i < 3 ? so.theta : 0.0;
         }
-        e2_site(so.rho, so.u, les, k, l1);
-        e2_site(so.rho, so.u, lmb, k, l2);
+        if (lmul) {
+            for (int i = 0; i < E2_NL; i++) {
+                l1[i] = lmul[(size_t)i * k.ns + s];
+                l2[i] = lmul[(size_t)(E2_NL + i) * k.ns + s];
+            }
+            e2_site_from(so.rho, so.u, les, k, l1);
+            e2_site_from(so.rho, so.u, lmb, k, l2);
+            for (int i = 0; i < E2_NL; i++) {
+                lmul[(size_t)i * k.ns + s] = l1[i];
+                lmul[(size_t)(E2_NL + i) * k.ns + s] = l2[i];
+            }
+        } else {
+            e2_site(so.rho, so.u, les, k, l1);
+            e2_site(so.rho, so.u, lmb, k, l2);
+        }
         collide_store_e2<S>(v, l1, l2, k, dst, s);
     } else {
         Eq<S> e = make_eq<S>(so, k);

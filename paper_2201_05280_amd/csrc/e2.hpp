@@ -142,16 +142,10 @@ __host__ __device__ __forceinline__ bool e2_cholesky_solve(double *J, double *b)
     return true;
 }
 
-// Multipliers of the E2 equilibrium with density rho, velocity u and
-// covariance lam (xx yy zz xy xz yz).  Returns the Newton iteration count
-// (> 0), or -1 when the moments cannot be reached (covariance not positive
-// definite, Jacobian singular, no convergence in E2_MAXIT iterations); the
-// moments then lie outside what a positive distribution on the 41 velocities
-// can carry.
-__host__ __device__ __forceinline__ int e2_solve(double th0, const double *w6, double rho, const double *u,
-                                                 const double *lam, double *l)
+// Moment targets (rho, rho u, rho (uu + lam)) of density rho, velocity u and
+// covariance lam (xx yy zz xy xz yz).
+__host__ __device__ __forceinline__ void e2_targets(double rho, const double *u, const double *lam, double *tg)
 {
-    double tg[E2_NL];
     tg[0] = rho;
     tg[1] = rho * u[0];
     tg[2] = rho * u[1];
@@ -162,11 +156,17 @@ __host__ __device__ __forceinline__ int e2_solve(double th0, const double *w6, d
     tg[7] = rho * (u[0] * u[1] + lam[3]);
     tg[8] = rho * (u[0] * u[2] + lam[4]);
     tg[9] = rho * (u[1] * u[2] + lam[5]);
-    // start: the continuous Gaussian over the reference Gaussian
+}
+
+// Newton start: the continuous Gaussian N(u, lam) over the reference
+// Gaussian N(0, theta0 I); false if lam is not positive definite
+__host__ __device__ __forceinline__ bool e2_gaussian_start(double th0, double rho, const double *u, const double *lam,
+                                                           double *l)
+{
     double a = lam[0], b = lam[1], c = lam[2], d = lam[3], e = lam[4], f = lam[5];
     double c00 = b * c - f * f, c01 = e * f - d * c, c02 = d * f - b * e;
     double det = a * c00 + d * c01 + e * c02;
-    if (!(det > 0.0) || !(rho > 0.0)) return -1;
+    if (!(det > 0.0) || !(rho > 0.0)) return false;
     double id = 1.0 / det;
     double i00 = c00 * id, i01 = c01 * id, i02 = c02 * id;
     double i11 = (a * c - e * e) * id, i12 = (d * e - a * f) * id, i22 = (a * b - d * d) * id;
@@ -183,6 +183,14 @@ __host__ __device__ __forceinline__ int e2_solve(double th0, const double *w6, d
     l[7] = -i01;
     l[8] = -i02;
     l[9] = -i12;
+    return true;
+}
+
+// Damped Newton from the multipliers in l toward the targets tg; returns the
+// iteration count (> 0) or -1 (Jacobian not positive definite, no
+// convergence in E2_MAXIT iterations, or a non-finite step).
+__host__ __device__ __forceinline__ int e2_newton(const double *w6, const double *tg, double *l)
+{
     double scale = 0.0;
 #pragma unroll
     for (int k = 0; k < E2_NL; k++) scale += fabs(tg[k]);
@@ -211,6 +219,40 @@ __host__ __device__ __forceinline__ int e2_solve(double th0, const double *w6, d
         if (!(fabs(l[0]) < 1e300)) return -1;   // NaN or overflow
     }
     return -1;
+}
+
+// Multipliers of the E2 equilibrium with density rho, velocity u and
+// covariance lam (xx yy zz xy xz yz), Newton started from the Gaussian.
+// Returns the Newton iteration count (> 0), or -1 when the moments cannot be
+// reached (covariance not positive definite, Jacobian singular, no
+// convergence); the moments then lie outside what a positive distribution on
+// the 41 velocities can carry.
+__host__ __device__ __forceinline__ int e2_solve(double th0, const double *w6, double rho, const double *u,
+                                                 const double *lam, double *l)
+{
+    double tg[E2_NL];
+    e2_targets(rho, u, lam, tg);
+    if (!e2_gaussian_start(th0, rho, u, lam, l)) return -1;
+    return e2_newton(w6, tg, l);
+}
+
+// The same, started from the multipliers already in l when they are finite
+// (a neighbouring state, e.g. the site's previous step), falling back to the
+// Gaussian start if that Newton run fails.
+__host__ __device__ __forceinline__ int e2_solve_from(double th0, const double *w6, double rho, const double *u,
+                                                      const double *lam, double *l)
+{
+    double tg[E2_NL];
+    e2_targets(rho, u, lam, tg);
+    bool warm = true;
+#pragma unroll
+    for (int k = 0; k < E2_NL; k++) warm = warm && fabs(l[k]) < 1e300;
+    if (warm) {
+        int it = e2_newton(w6, tg, l);
+        if (it > 0) return it;
+    }
+    if (!e2_gaussian_start(th0, rho, u, lam, l)) return -1;
+    return e2_newton(w6, tg, l);
 }
 
 // F_q of the multipliers l (any q, host side)

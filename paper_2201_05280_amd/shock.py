@@ -18,9 +18,14 @@ from . import _lib
 from .inputs import THETA0, positions, rankine_hugoniot, uniform
 
 
+_LATTICE = {}
+
+
 def equilibrium_fluxes(rho, u, theta, delta, kind=_lib.E2, theta0=0.0):
     """(mass, x momentum, energy) fluxes of the equilibrium at (rho, u e_x, theta)."""
-    c, _ = _lib.lattice(theta0)
+    if theta0 not in _LATTICE:
+        _LATTICE[theta0] = _lib.lattice(theta0)
+    c, _ = _LATTICE[theta0]
     F = _lib.equilibrium(kind, rho, (u, 0.0, 0.0), (theta, theta, theta, 0.0, 0.0, 0.0), theta0)
     cx, c2 = c[:, 0], (c ** 2).sum(1)
     return np.array([F @ cx, F @ cx ** 2, 0.5 * F @ (cx * c2) + 0.5 * delta * rho * u * theta])
