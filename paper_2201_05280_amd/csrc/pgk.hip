@@ -82,13 +82,20 @@ __global__ __launch_bounds__(WG) void k_dif(const double *__restrict__ tin, doub
 // fully relaxed theta_R at plane z-1.  Every value entering a stencil is
 // staged once per group; HBM sees each field about once.
 // ---------------------------------------------------------------------------
-constexpr int TX = 64, TY = 4, TZ = 32;
-constexpr int HX = TX + 4, HY = TY + 4;     // theta_hat plane (origin -2)
-constexpr int SX = TX + 3, SY = TY + 3;     // theta* and u plane (origin -2)
-constexpr int MX = TX + 2, MY = TY + 2;     // theta^mc and rho*theta plane (origin -1)
-constexpr int NH = (HX * HY + WG - 1) / WG; // staged points per thread
-constexpr int NS = (SX * SY + WG - 1) / WG;
-constexpr int NM = (MX * MY + WG - 1) / WG;
+#ifndef PGK_TR_TY
+#define PGK_TR_TY 8
+#endif
+#ifndef PGK_TR_TZ
+#define PGK_TR_TZ 64
+#endif
+constexpr int TX = 64, TY = PGK_TR_TY, TZ = PGK_TR_TZ;
+constexpr int TWG = TX * TY;                 // one output column per thread
+constexpr int HX = TX + 4, HY = TY + 4;      // theta_hat plane (origin -2)
+constexpr int SX = TX + 3, SY = TY + 3;      // theta* and u plane (origin -2)
+constexpr int MX = TX + 2, MY = TY + 2;      // theta^mc and rho*theta plane (origin -1)
+constexpr int NH = (HX * HY + TWG - 1) / TWG; // staged points per thread
+constexpr int NS = (SX * SY + TWG - 1) / TWG;
+constexpr int NM = (MX * MY + TWG - 1) / TWG;
 
 __device__ __forceinline__ int wrapn(int v, int n)
 {
@@ -97,7 +104,7 @@ __device__ __forceinline__ int wrapn(int v, int n)
 }
 
 template <typename A, int VAR>
-__global__ __launch_bounds__(WG) void k_tr(const double *__restrict__ that_, const A *__restrict__ aux,
+__global__ __launch_bounds__(TWG) void k_tr(const double *__restrict__ that_, const A *__restrict__ aux,
                                            double *__restrict__ thR, Consts k)
 {
     __shared__ double l_th[2][HY * HX];
@@ -131,19 +138,19 @@ __global__ __launch_bounds__(WG) void k_tr(const double *__restrict__ that_, con
     int oh[NH], os[NS], om[NM];
 #pragma unroll
     for (int j = 0; j < NH; j++) {
-        int i = min(tid + j * WG, HX * HY - 1);
+        int i = min(tid + j * TWG, HX * HY - 1);
         int ly = i / HX, lx = i - ly * HX;
         oh[j] = wrapn(y0 + ly - 2, k.ny) * k.nx + wrapn(x0 + lx - 2, k.nx);
     }
 #pragma unroll
     for (int j = 0; j < NS; j++) {
-        int i = min(tid + j * WG, SX * SY - 1);
+        int i = min(tid + j * TWG, SX * SY - 1);
         int ly = i / SX, lx = i - ly * SX;
         os[j] = wrapn(y0 + ly - 2, k.ny) * k.nx + wrapn(x0 + lx - 2, k.nx);
     }
 #pragma unroll
     for (int j = 0; j < NM; j++) {
-        int i = min(tid + j * WG, MX * MY - 1);
+        int i = min(tid + j * TWG, MX * MY - 1);
         int ly = i / MX, lx = i - ly * MX;
         om[j] = wrapn(y0 + ly - 1, k.ny) * k.nx + wrapn(x0 + lx - 1, k.nx);
     }
@@ -171,17 +178,17 @@ __global__ __launch_bounds__(WG) void k_tr(const double *__restrict__ that_, con
     auto stash = [&](int slot_th, int slot3) {
 #pragma unroll
         for (int j = 0; j < NH; j++)
-            if (tid + j * WG < HX * HY) l_th[slot_th][tid + j * WG] = r_th[j];
+            if (tid + j * TWG < HX * HY) l_th[slot_th][tid + j * TWG] = r_th[j];
 #pragma unroll
         for (int j = 0; j < NS; j++)
-            if (tid + j * WG < SX * SY) {
-                l_u[0][tid + j * WG] = r_u[0][j];
-                l_u[1][tid + j * WG] = r_u[1][j];
-                l_u[2][tid + j * WG] = r_u[2][j];
+            if (tid + j * TWG < SX * SY) {
+                l_u[0][tid + j * TWG] = r_u[0][j];
+                l_u[1][tid + j * TWG] = r_u[1][j];
+                l_u[2][tid + j * TWG] = r_u[2][j];
             }
 #pragma unroll
         for (int j = 0; j < NM; j++)
-            if (tid + j * WG < MX * MY) l_pt[slot3][tid + j * WG] = r_pt[j];
+            if (tid + j * TWG < MX * MY) l_pt[slot3][tid + j * TWG] = r_pt[j];
     };
 
     // prologue: theta_hat(z0-2) straight into its slot, then the data of plane z0-2
@@ -189,7 +196,7 @@ __global__ __launch_bounds__(WG) void k_tr(const double *__restrict__ that_, con
         int zt = zoff(z0 - 2);
 #pragma unroll
         for (int j = 0; j < NH; j++)
-            if (tid + j * WG < HX * HY) l_th[(z0 + 2) & 1][tid + j * WG] = that_[zt + oh[j]];
+            if (tid + j * TWG < HX * HY) l_th[(z0 + 2) & 1][tid + j * TWG] = that_[zt + oh[j]];
     }
     fetch(z0 - 1, z0 - 2);
     double o_rho = 0.0, o_v = 0.0, o_th = 0.0;
@@ -207,7 +214,7 @@ __global__ __launch_bounds__(WG) void k_tr(const double *__restrict__ that_, con
         }
         __syncthreads();
         // predictor theta*(zz) = th - sum_a u_a (th(+e_a) - th), region origin -2
-        for (int i = tid; i < SY * SX; i += WG) {
+        for (int i = tid; i < SY * SX; i += TWG) {
             int ly = i / SX, lx = i - ly * SX;
             int h = ly * HX + lx;
             double t = l_th[rz & 1][h];
@@ -219,7 +226,7 @@ __global__ __launch_bounds__(WG) void k_tr(const double *__restrict__ that_, con
         __syncthreads();
         // corrector theta^mc(zz) = 1/2 [th + th* - sum_a u_a (th* - th*(-e_a))], origin -1
         if (zz > z0 - 2) {
-            for (int i = tid; i < MY * MX; i += WG) {
+            for (int i = tid; i < MY * MX; i += TWG) {
                 int ly = i / MX, lx = i - ly * MX;
                 int sI = (ly + 1) * SX + lx + 1, hI = (ly + 1) * HX + lx + 1;
                 double ts = l_ts[rz & 1][sI];
@@ -749,7 +756,7 @@ static int step_t(pgk_ctx *c, int64_t n)
             mark(c, 2);
         } else {
             int ntile = ((c->k.nx + TX - 1) / TX) * ((c->k.ny + TY - 1) / TY) * ((c->k.nz + TZ - 1) / TZ) * 2;
-            hipLaunchKernelGGL((k_tr<A, VAR>), dim3(ntile), block, 0, c->stream, c->that_, (const A *)c->aux,
+            hipLaunchKernelGGL((k_tr<A, VAR>), dim3(ntile), dim3(TWG), 0, c->stream, c->that_, (const A *)c->aux,
                                (double *)c->buf[PGK_BUF_THETAR], c->k);
             mark(c, 1);
         }

@@ -267,3 +267,26 @@ def test_batch_refuses_a_face_state_without_e2_equilibrium():
                   u=((0.4, 0, 0), (0.4, 0, 0)), theta=(0.05, 0.05), vel_axis=0, equilibrium=pgk.E2)
     with pytest.raises(RuntimeError, match="EINFEASIBLE"):
         Batch([c])
+
+
+def test_stall_detection_stops_a_slow_case():
+    # a window shorter than the slow mode's halving time (~0.07 L^2/nu steps)
+    # stops the case as STALLED; with detection off the same case converges
+    import paper_2201_05280_amd as pgk
+    from paper_2201_05280_amd.batch import Batch, make_case
+    L, U = 48, 0.03
+    p = resolve(0.05, 0.71, 0.8, 2.0)
+    out = []
+    for window in (512, 0):
+        c = make_case(L, pgk.WALL, (p["tau"], p["tau1"], p["b"], p["kr"], p["delta"]),
+                      u=((0, 0, 0), (0, U, 0)), theta=(TH0, TH0), vel_axis=1)
+        b = Batch([c])
+        f = inputs.uniform(L, 1, 1)
+        b.init(f["rho"], f["u"], f["thT"], f["thR"])
+        b.config(256, 64)
+        b.stall(window)
+        out.append(b.run(400000, 1e-10))
+        b.close()
+    (s1, r1, st1), (s0, r0, st0) = out
+    assert st1[0] == 4 and r1[0] > 1e-10 and s1[0] < s0[0], (st1, r1, s1, s0)
+    assert st0[0] == 1 and r0[0] <= 1e-10, (st0, r0)
