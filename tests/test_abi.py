@@ -96,3 +96,51 @@ def test_null_arguments_are_errors_not_crashes():
     assert L.pgk_set_params(out, ctypes.byref(p), None) == -1
     L.pgk_destroy(out)
     assert not math.isnan(1.0)
+
+
+def _case(L=16, bc=None, eq=0):
+    c = _lib.Case()
+    c.L, c.bc, c.vel_axis, c.variant, c.equilibrium = L, _lib.WALL if bc is None else bc, 1, 0, eq
+    c.p = _lib.Params(1.0, 1.0, 0.0, 0.4, 2.0, 0.0)
+    for s in range(2):
+        c.rho[s] = 1.0
+        c.theta[s] = 0.2948964908710633
+    return c
+
+
+def test_batch_case_checks():
+    L = _lib.load()
+    nb = ctypes.c_size_t()
+    ok = (_lib.Case * 2)(_case(4), _case(8192))
+    assert L.pgk_batch_bytes(ok, 2, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert L.pgk_batch_bytes(ok, 0, ctypes.byref(nb)) == -1              # empty batch
+    for bad in (_case(3), _case(8193), _case(16, eq=7), _case(16, bc=_lib.PERIODIC)):
+        arr = (_lib.Case * 1)(bad)
+        assert L.pgk_batch_bytes(arr, 1, ctypes.byref(nb)) == -1
+    w = _case(16)
+    w.u[0][0] = 0.1                                                     # a wall cannot move normal to itself
+    assert L.pgk_batch_bytes((_lib.Case * 1)(w), 1, ctypes.byref(nb)) == -1
+    # E2 batches carry the per-site Newton multipliers: a larger buffer
+    n3, ne = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.pgk_batch_bytes((_lib.Case * 1)(_case(64)), 1, ctypes.byref(n3)) == 0
+    assert L.pgk_batch_bytes((_lib.Case * 1)(_case(64, eq=1)), 1, ctypes.byref(ne)) == 0
+    assert ne.value >= n3.value + 8 * 20 * 128
+
+
+def test_lattice_and_equilibrium_exports():
+    import numpy as np
+    c, w = _lib.lattice()
+    assert c.shape == (41, 3) and abs(w.sum() - 1) < 1e-15
+    assert np.allclose(np.abs(c[1:21]), np.abs(c[21:])) and np.allclose(c[1:21], -c[21:])
+    assert np.allclose(2 * c, np.round(2 * c))                          # half-integers included
+    F = _lib.equilibrium(_lib.F3, 1.0, (0, 0, 0), (0.2948964908710633,) * 3 + (0, 0, 0))
+    assert np.allclose(F, w, rtol=1e-14, atol=0)                         # at rest and theta0: the weights
+    Lb = _lib.load()
+    P = ctypes.POINTER(ctypes.c_double)
+    u = np.zeros(3)
+    lam = np.array([0.3, 0.3, 0.3, 0, 0, 0.])
+    out = np.zeros(41)
+    assert Lb.pgk_equilibrium(_lib.E2, ctypes.c_double(0), ctypes.c_double(-1.0), u.ctypes.data_as(P),
+                              lam.ctypes.data_as(P), out.ctypes.data_as(P)) == -1
+    assert Lb.pgk_equilibrium(9, ctypes.c_double(0), ctypes.c_double(1.0), u.ctypes.data_as(P),
+                              lam.ctypes.data_as(P), out.ctypes.data_as(P)) == -1

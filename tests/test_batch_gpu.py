@@ -290,3 +290,23 @@ def test_stall_detection_stops_a_slow_case():
     (s1, r1, st1), (s0, r0, st0) = out
     assert st1[0] == 4 and r1[0] > 1e-10 and s1[0] < s0[0], (st1, r1, s1, s0)
     assert st0[0] == 1 and r0[0] <= 1e-10, (st0, r0)
+
+
+def test_largest_case_equals_single_grid():
+    # L = 8192 cells (the largest line a batch takes) next to the smallest (4)
+    import paper_2201_05280_amd as pgk
+    specs = [dict(L=8192, bc=pgk.WALL, p=resolve(0.4, 0.8, 1.0, 2.0), vel_axis=1,
+                  faces=dict(u=((0, 0.0, 0), (0, 0.02, 0)), theta=(TH0, TH0 * 1.01))),
+             dict(_cases()[2])]
+    b, fields = _build(specs)
+    b.config(512, 10)
+    steps, resid, status = b.run(30, 0.0)
+    assert (steps == 30).all()
+    bm = b.moments()
+    for c, sp in enumerate(specs):
+        sl = b.case_slice(c)
+        sm = _single(sp, fields[c], 30)
+        for k in ("rho", "thT", "thR"):
+            err = np.abs(bm[k][sl] - sm[k]).max() / np.abs(sm[k]).max()
+            assert err <= 1e-13, (c, k, err)
+    b.close()
