@@ -272,7 +272,7 @@ def sweep(args):
                            "%.0f%% normal shocks (E2): Ma~U[1.1,1.6], Kn=lambda1/L~logU[0.002,0.006]"
                            % (args.sweep_lmin, args.sweep_lmax, 100 * (1 - args.sweep_shock_frac), args.sweep_knmin,
                               args.sweep_knmax, 100 * args.sweep_shock_frac),
-           "stall_window_steps": args.sweep_stall}
+           "stall_window_steps": {"couette": args.sweep_stall, "shock": args.sweep_stall_shock}}
 
     def run_batch(cs, fields, label):
         """Run the cases to the tolerance: the Couette layers (F3, any
@@ -295,7 +295,7 @@ def sweep(args):
             b = Batch(C.to_batch_cases(sub), stream=stream)
             b.init(fields["rho"][sel], fields["u"][:, sel], fields["thT"][sel], fields["thR"][sel])
             b.config(0, 0)
-            b.stall(args.sweep_stall)
+            b.stall(args.sweep_stall_shock if cs[idx[0]]["kind"] == C.SHOCK else args.sweep_stall)
             stream.synchronize()
             steps, resid, status = b.run(args.sweep_max_steps, tol)
             res[j] = (idx, sel, steps, resid, status, b.moments(), b.tuned())
@@ -454,7 +454,10 @@ def main():
     ap.add_argument("--sweep-plain", type=int, default=8)
     ap.add_argument("--sweep-plain-cap", type=float, default=10.0)
     ap.add_argument("--sweep-shock-frac", type=float, default=0.5)
-    ap.add_argument("--sweep-stall", type=int, default=25600, help="steps without halving the residual")
+    ap.add_argument("--sweep-stall", type=int, default=25600,
+                    help="Couette: steps without halving the residual before a case counts as stalled")
+    ap.add_argument("--sweep-stall-shock", type=int, default=6400,
+                    help="shock lines: the same window (a converging shock halves its residual every ~100 steps)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain device copy (torch) as the achievable-bandwidth reference")
     args = ap.parse_args()

@@ -116,6 +116,81 @@ __device__ __forceinline__ double dif_line(int s, const double *tin, const doubl
     return t + cm[s] * (tm - t) + cp[s] * (tp - t);
 }
 
+// The same sub-steps with the line in registers: wavefront `sub` holds the
+// sites of one sublattice chain, lane l the sites x = l + 64 j (j < DW_P), so
+// that the neighbours x -+ 1 come from lanes l -+ 1 (lane 63 / 0 of the next
+// j across the seam) by cross-lane moves, with no barrier between sub-steps.
+// Bounded faces only (both faces bounded, as every batched case is); the
+// arithmetic is that of dif_line.
+constexpr int DW_P = 8;   // lines of up to 512 cells
+
+// whole-wavefront rotations by one lane (DPP wave_ror:1 / wave_rol:1): lane i
+// receives the value of lane i - 1 / i + 1, modulo 64
+__device__ __forceinline__ double lane_prev(double v)
+{
+    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x13C, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x13C, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_next(double v)
+{
+    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x134, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x134, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// value of lane `l` of v in every lane
+__device__ __forceinline__ double lane_bcast(double v, int l)
+{
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+template <int VAR>
+__device__ __forceinline__ void dif_chain(int sub, const double *__restrict__ tmc, const double *__restrict__ aux,
+                                          const double *__restrict__ that_, double *__restrict__ thR, const Consts &k)
+{
+    const int lane = threadIdx.x & 63, L = k.nx;
+    double t[DW_P], cm[DW_P], cp[DW_P];
+#pragma unroll
+    for (int j = 0; j < DW_P; j++) {
+        int x = lane + 64 * j;
+        t[j] = cm[j] = cp[j] = 0.0;
+        if (x < L) {
+            int s = sub * L + x;
+            t[j] = tmc[s];
+            dif_line_coef<VAR>(s, aux, k, cm[j], cp[j]);
+        }
+    }
+    for (int it = 0; it < k.nsub; it++) {
+        double tn[DW_P];
+#pragma unroll
+        for (int j = 0; j < DW_P; j++) {
+            double a = lane_prev(t[j]);                                          // x - 1, lanes 1..63
+            double b = j > 0 ? lane_bcast(t[j - 1], 63) : k.thbc[0];             // x - 1, lane 0
+            double c = lane_next(t[j]);                                          // x + 1, lanes 0..62
+            double d = j + 1 < DW_P ? lane_bcast(t[j + 1], 0) : 0.0;             // x + 1, lane 63
+            double tm = lane == 0 ? b : a, tp = lane == 63 ? d : c;
+            if (lane + 64 * j == L - 1) tp = k.thbc[1];
+            tn[j] = t[j] + cm[j] * (tm - t[j]) + cp[j] * (tp - t[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < DW_P; j++) t[j] = tn[j];
+    }
+#pragma unroll
+    for (int j = 0; j < DW_P; j++) {
+        int x = lane + 64 * j;
+        if (x < L) {
+            int s = sub * L + x;
+            double v = thR[s];
+            if (VAR == PGK_CN) thR[s] = t[j] + (that_[s] - v);
+            else thR[s] = (t[j] + k.X * v) * k.inv1X;
+        }
+    }
+}
+
 // Ghost populations of both x faces of a line (ny = nz = 1), wavefront w
 // taking face w: the same quantities as bc_column, with the outgoing-mass sum
 // of a diffuse wall spread over the 64 lanes (lane l takes the candidates
@@ -190,7 +265,9 @@ __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
         __syncthreads();
         for (int s = tid; s < ns; s += NTH) mc_site<double, true>(s, that_, aux, tmc, k);
         __syncthreads();
-        if (ns <= a.lds_sites) {
+        if (k.nx <= 64 * DW_P) {
+            if (tid < 128) dif_chain<VAR>(tid >> 6, tmc, aux, that_, thR, k);
+        } else if (ns <= a.lds_sites) {
             extern __shared__ double lds[];
             double *tin = lds, *tout = lds + a.lds_sites, *cm = lds + 2 * a.lds_sites, *cp = lds + 3 * a.lds_sites;
             for (int s = tid; s < ns; s += NTH) {

@@ -3,8 +3,9 @@
 Each batched case must equal the same case run alone through the single-grid
 path (the same device code in double precision: identical up to the few-ulp
 differences of the compiler's FMA contraction in the two kernels) and the FP64
-oracle (1e-12).  The case mix covers both diffusion paths of the kernel (LDS
-for lines up to 2048 sites, global memory beyond) and sub-cycled diffusion;
+oracle (1e-12).  The case mix covers the three diffusion paths of the kernel
+(registers for lines up to 512 cells, LDS up to 2048 sites, global memory
+beyond) and sub-cycled diffusion;
 convergence, divergence and the tuner are exercised on small
 cases.
 """
@@ -37,6 +38,8 @@ def _cases():
          dict(rho=(1.0, 1.05), u=((0.02, 0, 0), (0.019, 0, 0)), theta=(TH0, TH0 * 1.03))),
         # several diffusion sub-steps per step, in LDS
         (40, pgk.WALL, (0.6, 0.71, 0.8, 2.0), dict(u=((0, 0, 0), (0, 0.04, 0)), theta=(TH0, TH0 * 1.05))),
+        # 700 cells: beyond the register-resident diffusion (512 cells), diffused in LDS
+        (700, pgk.WALL, (0.4, 0.8, 1.0, 3.0), dict(u=((0, 0.0, 0), (0, 0.02, 0)), theta=(TH0, TH0 * 1.02))),
         # 2060 sites: beyond the LDS diffusion path (2048 sites), diffused in global memory
         (1030, pgk.WALL, (0.3, 0.8, 1.0, 2.0), dict(u=((0, 0.01, 0), (0, 0.03, 0)), theta=(TH0 * 1.01, TH0))),
     ]
