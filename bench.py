@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 THETA0 = 0.2948964908710633
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS + % of HBM roofline (fused step); sweep time-to-residual 1e-8 plain vs batched+MLP"
-KERNEL_SOURCES = ("pgk.hip", "device.hpp", "lattice.hpp")
+KERNEL_SOURCES = ("pgk.hip", "device.hpp", "lattice.hpp", "e2.hpp")
 
 
 def algorithmic_bytes(precision):
