@@ -64,7 +64,21 @@ enum { EPI_FWD = 0, EPI_BWD = 1, EPI_WGRAD = 2 };
 //   EPI_FWD   z = C + bias[n] -> zout[m][n] (fp32), silu(z) -> aout[m][n] (bf16)
 //   EPI_BWD   dz = C * dsilu(zin[m][n]) -> zout[m][n] (fp32)
 //   EPI_WGRAD atomicAdd(C) into zout[m][n] (fp32)
-template <typename TA, int EPI>
+// four consecutive bf16 values (8-byte aligned) as one MFMA operand
+__device__ inline v4i16 load4_bf(const uint16_t *p)
+{
+    uint2 v = *reinterpret_cast<const uint2 *>(p);
+    v4i16 r;
+    r[0] = (short)(v.x & 0xFFFFu);
+    r[1] = (short)(v.x >> 16);
+    r[2] = (short)(v.y & 0xFFFFu);
+    r[3] = (short)(v.y >> 16);
+    return r;
+}
+
+// CONTIG: A and B are contiguous along k (ak = bk = 1, A in bf16): operands
+// come in 8-byte loads
+template <typename TA, int EPI, bool CONTIG = false>
 __global__ __launch_bounds__(256) void k_gemm(const TA *__restrict__ A, int am, int ak,
                                               const uint16_t *__restrict__ B, int bk, int bn, int K, int kchunk,
                                               const float *__restrict__ bias, const float *__restrict__ zin,
@@ -77,14 +91,36 @@ __global__ __launch_bounds__(256) void k_gemm(const TA *__restrict__ A, int am, 
     const int r = lane & 15, kq = (lane >> 4) * 4;
     v4f32 acc[4];
     for (int b = 0; b < 4; b++) acc[b] = v4f32{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = kb; k0 < ke; k0 += 16) {
-        v4i16 a;
-        for (int j = 0; j < 4; j++) a[j] = as_bf<TA>(A[(size_t)(m0 + r) * am + (size_t)(k0 + kq + j) * ak]);
-        for (int b = 0; b < 4; b++) {
-            v4i16 bb;
-            for (int j = 0; j < 4; j++) bb[j] = (short)B[(size_t)(k0 + kq + j) * bk + (size_t)(n0 + 16 * b + r) * bn];
-            acc[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[b], 0, 0, 0);
+    // K in blocks of four 16-deep MFMA steps: all loads of a block are issued
+    // before its products, so their latencies overlap
+    constexpr int KB = 4;
+    for (int k1 = kb; k1 < ke; k1 += 16 * KB) {
+        v4i16 a[KB], bb[KB][4];
+#pragma unroll
+        for (int s = 0; s < KB; s++) {
+            const int k0 = k1 + 16 * s;
+            const bool in = k0 < ke;
+            if constexpr (CONTIG) {
+                const uint16_t *Ab = reinterpret_cast<const uint16_t *>(A);
+                a[s] = in ? load4_bf(Ab + (size_t)(m0 + r) * am + k0 + kq) : v4i16{0, 0, 0, 0};
+#pragma unroll
+                for (int b = 0; b < 4; b++)
+                    bb[s][b] = in ? load4_bf(B + (size_t)(n0 + 16 * b + r) * bn + k0 + kq) : v4i16{0, 0, 0, 0};
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    a[s][j] = in ? as_bf<TA>(A[(size_t)(m0 + r) * am + (size_t)(k0 + kq + j) * ak]) : 0;
+#pragma unroll
+                for (int b = 0; b < 4; b++)
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        bb[s][b][j] = in ? (short)B[(size_t)(k0 + kq + j) * bk + (size_t)(n0 + 16 * b + r) * bn] : 0;
+            }
         }
+#pragma unroll
+        for (int s = 0; s < KB; s++)
+#pragma unroll
+            for (int b = 0; b < 4; b++) acc[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[s], bb[s][b], acc[b], 0, 0, 0);
     }
     // lane holds C[m0 + 4*(lane/16) + j][n0 + 16 b + lane%16]
     for (int b = 0; b < 4; b++)
@@ -162,7 +198,7 @@ __global__ void k_layer5_bwd(const float *__restrict__ dy, const float *__restri
 // Reductions over the points of a minibatch: work-group b takes points
 // [b GP, (b + 1) GP), thread k one hidden unit, and adds its partial sums to
 // the gradient (one atomic per value and work-group).
-constexpr int GP = 128;
+constexpr int GP = 32;
 
 // last layer: dW5[o][k] = sum_p dy[p][o] a4[p][k], db5[o] = sum_p dy[p][o]
 __global__ __launch_bounds__(H) void k_layer5_wgrad(const float *__restrict__ dy, const uint16_t *__restrict__ a4,
@@ -347,7 +383,7 @@ static int forward(pgk_mlp *m, const float *X, int n)
     const int offW[3] = {OFF_W2, OFF_W3, OFF_W4}, offB[3] = {OFF_B2, OFF_B3, OFF_B4};
     for (int l = 0; l < 3; l++) {
         // z_{l+1}[p][o] = sum_i a_l[p][i] W[o][i]: B(k=i, n=o) = W[o*H + i]
-        hipLaunchKernelGGL((k_gemm<uint16_t, EPI_FWD>), dim3(np / 64, H / 64, 1), dim3(256), 0, m->stream,
+        hipLaunchKernelGGL((k_gemm<uint16_t, EPI_FWD, true>), dim3(np / 64, H / 64, 1), dim3(256), 0, m->stream,
                            m->a[l], H, 1, m->wbf + offW[l], 1, H, H, H, m->master + offB[l], (const float *)nullptr,
                            m->z[l + 1], m->a[l + 1], H, np);
     }
