@@ -215,6 +215,7 @@ def shock_summary(max_steps=60000):
         lam1 = nu * math.sqrt(math.pi / (2 * th1))
         case = {"theta1": th1, "upstream": [round(v, 6) for v in up], "downstream": [round(v, 6) for v in down],
                 "downstream_vs_ideal_gas_jump": [round(a / b - 1, 5) for a, b in zip(down, ideal)]}
+        final = {}
         for prec, name in ((pgk.FP64, "fp64"), (pgk.FP32DEV, "fp32dev")):
             s = pgk.Solver(L, 1, 1, precision=prec, bc_x=(pgk.DIRICHLET, pgk.DIRICHLET), equilibrium=pgk.E2)
             s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
@@ -237,9 +238,26 @@ def shock_summary(max_steps=60000):
             dt = time.perf_counter() - t0
             s.close()
             pos, thick = profile_metrics(x, b["rho"], up, down)
+            final[name] = (pos, b)
             case[name] = {"steps": steps, "residual": float("%.3e" % hist[-1]), "seconds": round(dt, 2),
                           "MLUPS": round(2 * L * steps / dt / 1e6, 1), "shock_position": round(pos, 4),
                           "thickness_cells": round(thick, 3), "thickness_mean_free_paths": round(thick / lam1, 3)}
+        # FP32 storage against FP64 at steady state: the shock may settle at a
+        # slightly different place, so the profiles are compared with the two
+        # positions aligned, each field normalised by its jump
+        (p64, m64), (p32, m32) = final["fp64"], final["fp32dev"]
+        o = np.argsort(x)
+        xs = x[o]
+        d = p32 - p64
+        inside = (xs + d >= xs[0]) & (xs + d <= xs[-1])
+        err = {}
+        for k, v, j in (("rho", None, 0), ("u", 0, 1), ("thT", None, 2), ("thR", None, 2)):
+            a32 = (m32[k] if v is None else m32[k][v])[o]
+            a64 = (m64[k] if v is None else m64[k][v])[o]
+            diff = (np.interp(xs[inside] + d, xs, a32) - a64[inside]) / abs(down[j] - up[j])
+            err[k] = {"Linf": float("%.3e" % np.abs(diff).max()), "L2": float("%.3e" % np.sqrt((diff ** 2).mean()))}
+        case["fp32dev_vs_fp64_profile_error_aligned"] = err
+        case["fp32dev_vs_fp64_shift_cells"] = round(d, 4)
         out["Ma%.1f" % Ma] = case
     return out
 

@@ -450,3 +450,52 @@ def test_subcycled_diffusion_is_stable_and_keeps_the_thermal_rate():
     t = np.arange(len(th))
     rate = -np.polyfit(t[80:], np.log(th[80:]), 1)[0]
     assert abs(rate / (co["alpha"] * k * k) - 1) < 0.03, rate
+
+
+def _couette_oracle(L, nu, Pr, u_top, th_top):
+    p = resolve(nu, Pr, 0.8, 2.0)
+    o = oracle.Oracle(L, 1, 1)
+    o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    o.set_bc_x(0, oracle.WALL, 1.0, (0, 0, 0), TH0)
+    o.set_bc_x(1, oracle.WALL, 1.0, (0, u_top, 0), th_top)
+    f = inputs.uniform(L, 1, 1)
+    o.init(f["rho"], f["u"], f["thT"], f["thR"])
+    # walls a quarter cell outside the first and last sites: height L
+    y = (inputs.positions(L, 1, 1)[0] + 0.25) / L
+    return o, y
+
+
+def test_couette_start_up_follows_the_series_solution():
+    # Sec. 6: impulsively started plate, u/u_w = y/L - (2/pi) sum_k exp(-k^2 pi^2 nu t/L^2)
+    # sin(k pi (1 - y/L))/k; Kn = nu/(c_s L) = 3e-3, so slip stays near 1% of u_w
+    L, nu, U = 48, 0.1, 0.02
+    o, y = _couette_oracle(L, nu, 0.71, U, TH0)
+    k = np.arange(1, 400)[:, None]
+    done = 0
+    for ts in (0.05, 0.1, 0.3):
+        n = int(round(ts * L * L / nu))
+        o.step(n - done)
+        done = n
+        u = o.moments()["u"][1] / U
+        ua = y - 2 / np.pi * (np.exp(-k ** 2 * np.pi ** 2 * nu * n / L ** 2) / k * np.sin(k * np.pi * (1 - y))).sum(0)
+        assert np.abs(u - ua).max() < 0.02, (ts, np.abs(u - ua).max())
+
+
+@pytest.mark.parametrize("Pr,tol", [(0.71, 0.02), (2.0, 0.015)])
+def test_thermal_couette_profile_with_viscous_heating(Pr, tol):
+    # Sec. 6: steady (T - T0)/dT = y/H + (Pr Ec / 2)(y/H)(1 - y/H), Ec = U^2/(c_p dT),
+    # c_p = (5 + delta)/2; the heating term peaks at 1.6% (Pr 0.71) and 4.4% (Pr 2) of dT
+    # mid-channel, so at Pr 2 a scheme without it (or with half the conductivity) fails
+    L, nu, U, dT = 48, 0.1, 0.06, 0.02 * TH0
+    o, y = _couette_oracle(L, nu, Pr, U, TH0 + dT)
+    prev = None
+    for _ in range(40):
+        o.step(2000)
+        m = o.moments()
+        th = (3 * m["thT"] + 2 * m["thR"]) / 5
+        if prev is not None and np.abs(th - prev).max() < 1e-9:
+            break
+        prev = th
+    Ec = U ** 2 / (3.5 * dT)
+    ta = y + Pr * Ec / 2 * y * (1 - y)
+    assert np.abs((th - TH0) / dT - ta).max() < tol

@@ -1,6 +1,7 @@
 """Parity at the Taylor-Green workload's full size (256^3 cells, 33,554,432
 sites) in the launch configuration the benchmark times, against the FP64
-oracle run on the host for a few steps from the same seeded field."""
+oracle run on the host for 10 steps from the same seeded field; and at 64^3
+for the benchmark's 1000 steps."""
 import numpy as np
 import pytest
 
@@ -11,7 +12,7 @@ from paper_2201_05280_amd import inputs
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 N = 256
-STEPS = 2
+STEPS = 10
 
 
 @pytest.fixture(scope="module")
@@ -43,4 +44,35 @@ def test_taylor_green_256_full_grid(reference, precision, bar):
         den = max(np.abs(ref[k]).max(), 1e-2 if k == "u" else 0.0)
         err = float(np.abs(got[k] - ref[k]).max() / den)
         print("full-size parity precision=%d %s %.3e" % (precision, k, err), flush=True)
+        assert err <= bar, (k, err)
+
+
+@pytest.fixture(scope="module")
+def reference64():
+    n, steps = 64, 1000
+    U = 0.1 * np.sqrt(1.4 * oracle.THETA0)
+    nu = U * (n / (2 * np.pi)) / 1600.0
+    p = resolve(nu, 0.71, 0.6, 2.0)
+    f = inputs.taylor_green(n, U)
+    o = oracle.Oracle(n, n, n)
+    o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    o.init(f["rho"], f["u"], f["thT"], f["thR"])
+    o.step(steps)
+    return p, f, o.moments(), n, steps
+
+
+@pytest.mark.parametrize("precision,bar", [(1, 1e-5), (0, 1e-12)])
+def test_taylor_green_64_thousand_steps(reference64, precision, bar):
+    import paper_2201_05280_amd as pgk
+    p, f, ref, n, steps = reference64
+    s = pgk.Solver(n, n, n, precision=precision)
+    s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    s.init(f["rho"], f["u"], f["thT"], f["thR"])
+    s.step(steps)
+    got = s.moments()
+    s.close()
+    for k in ("rho", "u", "thT", "thR", "P"):
+        den = max(np.abs(ref[k]).max(), 1e-2 if k == "u" else 0.0)
+        err = float(np.abs(got[k] - ref[k]).max() / den)
+        print("64^3 x 1000 parity precision=%d %s %.3e" % (precision, k, err), flush=True)
         assert err <= bar, (k, err)
