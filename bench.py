@@ -67,9 +67,32 @@ def cpu_baseline(n_cpu, steps_cpu):
     o.step(steps_cpu)
     dt = time.perf_counter() - t0
     ns = 2 * n_cpu ** 3
-    return dict(value=ns * steps_cpu / dt / 1e6, unit="MLUPS", cores=oracle.threads(), kind="oracle",
-                sample="Taylor-Green %d^3 cells (%d sites, same Ma and Re), FP64 oracle, %d steps, %.1f s"
-                       % (n_cpu, ns, steps_cpu, dt))
+    out = dict(value=ns * steps_cpu / dt / 1e6, unit="MLUPS", cores=oracle.threads(), kind="oracle",
+               sample="Taylor-Green %d^3 cells (%d sites, same Ma and Re), FP64 oracle, %d steps, %.1f s"
+                      % (n_cpu, ns, steps_cpu, dt))
+    out["thread_sweep"] = cpu_thread_sweep(oracle.threads())
+    return out
+
+
+def cpu_thread_sweep(max_threads, n=32, steps=20):
+    """Oracle MLUPS on a small Taylor-Green sample (n^3 cells, `steps` steps)
+    with 1, 2, 4, ... threads up to max_threads, each in a child process with
+    OMP_NUM_THREADS set (the OpenMP team size is fixed at start-up)."""
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, %r); import bench, oracle; "
+            "from oracle.params import resolve; from paper_2201_05280_amd import inputs; "
+            "U, nu = bench.tgv_params(%d); p = resolve(nu, 0.71, 0.6, 2.0); o = oracle.Oracle(%d, %d, %d); "
+            "o.set_params(p['tau'], p['tau1'], p['b'], p['kr'], p['delta']); f = inputs.taylor_green(%d, U); "
+            "o.init(f['rho'], f['u'], f['thT'], f['thR']); o.step(1); t0 = time.perf_counter(); o.step(%d); "
+            "print(2 * %d ** 3 * %d / (time.perf_counter() - t0) / 1e6)") % (ROOT, n, n, n, n, n, steps, n, steps)
+    res, t = {}, 1
+    while t <= max_threads:
+        env = dict(os.environ, OMP_NUM_THREADS=str(t))
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        if r.returncode == 0:
+            res[str(t)] = round(float(r.stdout.strip().splitlines()[-1]), 2)
+        t *= 2
+    return {"sample": "Taylor-Green %d^3 cells, %d steps" % (n, steps), "MLUPS_by_threads": res}
 
 
 def kernel_source_sha():
