@@ -507,7 +507,7 @@ def main():
                     help="also time a plain device copy (torch) as the achievable-bandwidth reference")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the z-slab decomposition is a design note); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.sweep:
