@@ -124,9 +124,10 @@ def counter_traffic(n, precision):
     return float(vals["k_lb traffic_bytes_per_launch:"])
 
 
-def copy_probe(torch, nbytes=4 << 30, reps=10):
+def copy_probe(torch, nbytes=4 << 30, reps=10, quick=False):
     """Plain device copies of nbytes (n read + n written) timed with events:
-    the runtime's own copy and the project's float4 copy kernels."""
+    the runtime's own copy and the project's float4 copy kernels (quick: the
+    runtime copy and the fastest kernel only)."""
     import ctypes
     L = ctypes.CDLL(os.path.join(ROOT, "paper_2201_05280_amd", "libpgk_probe.so"))
     L.pgk_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
@@ -138,6 +139,8 @@ def copy_probe(torch, nbytes=4 << 30, reps=10):
     variants = [("runtime", None)] + [("float4_b%d" % nb, (0, nb)) for nb in (512, 1024, 2048)] + \
                [("float4_nt_b%d" % nb, (1, nb)) for nb in (1024,)] + [("float1", (2, 0))] + \
                [("float4_x%d" % u, (v, 0)) for u, v in ((4, 3), (8, 4), (16, 5))]
+    if quick:
+        variants = [("runtime", None), ("float4_x4", (3, 0))]
     for name, v in variants:
         def run():
             if v is None:
@@ -590,8 +593,17 @@ def main():
         "conservation_drift": drift,
     }
     s.close()
+    # the bandwidth a plain copy reaches on this device, beside the kernel's
+    cp = copy_probe(torch, reps=5, quick=not args.copy_probe)
+    best = max(v for k, v in cp.items() if k.endswith("_GBs"))
+    rf = out["roofline"]
+    rf["copy_reference_GBs"] = best
+    if rf["traffic"]:
+        actual = rf["traffic"] / (rf["avg_launch_ms"] * 1e-3) / 1e9
+        rf["actual_GBs_from_traffic"] = round(actual, 1)
+        rf["actual_over_copy_reference"] = round(actual / best, 4)
     if args.copy_probe:
-        out["copy_probe"] = copy_probe(torch)
+        out["copy_probe"] = cp
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)
     if not args.no_shock:
