@@ -86,16 +86,26 @@ class Solver:
         return t.contiguous()
 
     def init(self, rho, u, thT, thR):
+        """Initial state from host arrays: rho, theta_T, theta_R of ns sites and
+        u of [3][ns], site order [sub][z][y][x]."""
         ns = self.ns
         f = [self._dev(rho, (ns,)), self._dev(u, (3, ns)), self._dev(thT, (ns,)), self._dev(thR, (ns,))]
-        with self.torch.cuda.stream(self.stream):
-            self._check(self.L.pgk_init_fields(self.h, *[t.data_ptr() for t in f]))
+        # the copies ran on torch's current stream; the library works on self.stream
+        self.torch.cuda.current_stream(self.device).synchronize()
+        self._check(self.L.pgk_init_fields(self.h, *[t.data_ptr() for t in f]))
         self.stream.synchronize()
 
     def init_device(self, rho, u, thT, thR):
-        """Fields already on the device (float64 tensors)."""
+        """Fields already on the device: contiguous float64 tensors of ns (u: 3 x ns)
+        values, ready on this solver's stream; they must live until the call returns."""
+        ns = self.ns
+        for t, n in ((rho, ns), (u, 3 * ns), (thT, ns), (thR, ns)):
+            if (t.dtype != self.torch.float64 or not t.is_contiguous() or t.numel() != n
+                    or t.device != self.device):
+                raise ValueError("init_device needs contiguous float64 tensors of %d values on %s" % (n, self.device))
         self._check(self.L.pgk_init_fields(self.h, rho.data_ptr(), u.data_ptr(), thT.data_ptr(),
                                            thR.data_ptr()))
+        self.stream.synchronize()
 
     # ---- run -------------------------------------------------------------
     def step(self, n=1):
@@ -115,6 +125,8 @@ class Solver:
         return int(self.L.pgk_steps_done(self.h))
 
     def moments_device(self):
+        """f-moments as device tensors, written asynchronously on this solver's
+        stream (synchronise it before reading them elsewhere)."""
         torch, ns = self.torch, self.ns
         out = dict(rho=torch.empty(ns, dtype=torch.float64, device=self.device),
                    u=torch.empty(3, ns, dtype=torch.float64, device=self.device),
