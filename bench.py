@@ -382,7 +382,10 @@ def sweep(args):
     mlp = MLP(nmax=8192)
     mlp.set_params(mlp_init(S))
     t0 = time.perf_counter()
-    losses = mlp.train(X, Y, epochs=args.sweep_epochs, batch=2048, lr=2e-3, seed=S)
+    losses = []
+    for k, stage in enumerate(args.sweep_lr_schedule.split(",")):
+        lr, ep = stage.split(":")
+        losses += list(mlp.train(X, Y, epochs=int(ep), batch=2048, lr=float(lr), seed=S + k))
     t_train = time.perf_counter() - t0
     print("# mlp trained on %d points in %.1f s, loss %.3e -> %.3e" % (len(X), t_train, losses[0], losses[-1]),
           file=sys.stderr, flush=True)
@@ -458,7 +461,7 @@ def sweep(args):
         "batched_warm_plus_training_time": round(warm["time"] + t_infer + t_train, 2),
         "mlp_inference_time": round(t_infer, 3), "mlp_train_time": round(t_train, 1),
         "mlp_train_points": int(len(X)),
-        "mlp_loss_first_last": [float(losses[0]), float(losses[-1])],
+        "mlp_loss_first_last": [float(losses[0]), float(losses[-1])], "mlp_schedule": args.sweep_lr_schedule,
         "couette": {"cold": counts(cold, ~is_shock), "warm": counts(warm, ~is_shock),
                     "steps_cold_median": int(np.median(cold["steps"][~is_shock])) if (~is_shock).any() else None,
                     "steps_warm_median": int(np.median(warm["steps"][~is_shock])) if (~is_shock).any() else None,
@@ -498,7 +501,8 @@ def main():
     ap.add_argument("--sweep-knmin", type=float, default=1e-2)
     ap.add_argument("--sweep-knmax", type=float, default=1e-1)
     ap.add_argument("--sweep-max-steps", type=int, default=400000)
-    ap.add_argument("--sweep-epochs", type=int, default=40)
+    ap.add_argument("--sweep-lr-schedule", default="2e-3:40,5e-4:30,1.25e-4:30",
+                    help="MLP training stages lr:epochs[,lr:epochs...] (Adam state carried across stages)")
     ap.add_argument("--sweep-plain", type=int, default=8)
     ap.add_argument("--sweep-plain-cap", type=float, default=10.0)
     ap.add_argument("--sweep-shock-frac", type=float, default=0.5)
