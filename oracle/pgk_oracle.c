@@ -36,13 +36,18 @@
  *   - equilibrium F3: third-order Hermite projection about (0, theta0) of the
  *     anisotropic Gaussian; E2: discrete exponential quasi-equilibrium
  *     w_i exp(alpha + beta.c_i + c_i.G.c_i) matching rho, rho u and the
- *     pressure tensor;
+ *     pressure tensor (E2 is not linear in the covariance, so its gain term
+ *     mixes the ES and the Maxwellian E2 populations at their rates);
  *   - finite differences for E_R use the simple-cubic neighbours of the same
  *     sublattice (spacing 1);
  *   - kappa_R = k_r * 5 p tau / (2B) with the local p = rho theta; face values
  *     are arithmetic means.
  * Pins: see the oracle tests (lattice isotropy, Gaussian moments of F3 and
- * E2, exact conservation, CE decay rates, sound speed, Landau table).
+ * E2, exact conservation, CE decay rates, sound speed, Landau table, the
+ * Couette start-up series and the thermal Couette profile of Sec. 6).
+ * Parity unpinned: the interior profile of a normal shock (its end states,
+ * through the jump conditions, and its conservation are pinned; the shape
+ * between them has no reference outside this code).
  */
 #include <math.h>
 #include <stdlib.h>
