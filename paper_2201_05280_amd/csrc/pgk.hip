@@ -23,6 +23,8 @@
 #include <string>
 #include <vector>
 
+#include <type_traits>
+
 #include "device.hpp"
 
 namespace pgk {
@@ -159,53 +161,62 @@ __global__ __launch_bounds__(TWG) void k_tr(const double *__restrict__ that_, co
     const int oo = outv ? (y0 + lyo) * k.nx + (x0 + lxo) : 0;
     auto zoff = [&](int z) { return subo + wrapn(z, k.nz) * plane; };
 
-    // registers carrying the next plane's data
-    double r_th[NH];
-    A r_u[3][NS], r_pt[NM];
-    auto fetch = [&](int zth, int zu) {
+    // registers carrying the data of the next two iterations (slot = iteration
+    // parity, a compile-time index): each plane's loads have two planes of
+    // work to arrive in
+    double r_th[2][NH];
+    A r_u[2][3][NS], r_pt[2][NM];
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    // data of iteration j: theta_hat(j + 1), u(j), rho theta(j)
+    auto fetch = [&](auto slot, int zth, int zu) {
+        constexpr int S = decltype(slot)::value;
         int zt = zoff(zth), zuo = zoff(zu);
 #pragma unroll
-        for (int j = 0; j < NH; j++) r_th[j] = that_[zt + oh[j]];
+        for (int j = 0; j < NH; j++) r_th[S][j] = that_[zt + oh[j]];
 #pragma unroll
         for (int j = 0; j < NS; j++) {
-            r_u[0][j] = aux[zuo + os[j]];
-            r_u[1][j] = aux[(size_t)k.ns + zuo + os[j]];
-            r_u[2][j] = aux[(size_t)2 * k.ns + zuo + os[j]];
+            r_u[S][0][j] = aux[zuo + os[j]];
+            r_u[S][1][j] = aux[(size_t)k.ns + zuo + os[j]];
+            r_u[S][2][j] = aux[(size_t)2 * k.ns + zuo + os[j]];
         }
 #pragma unroll
-        for (int j = 0; j < NM; j++) r_pt[j] = aux[(size_t)4 * k.ns + zuo + om[j]];
+        for (int j = 0; j < NM; j++) r_pt[S][j] = aux[(size_t)4 * k.ns + zuo + om[j]];
     };
-    auto stash = [&](int slot_th, int slot3) {
+    auto stash = [&](auto slot, int slot_th, int slot3) {
+        constexpr int S = decltype(slot)::value;
 #pragma unroll
         for (int j = 0; j < NH; j++)
-            if (tid + j * TWG < HX * HY) l_th[slot_th][tid + j * TWG] = r_th[j];
+            if (tid + j * TWG < HX * HY) l_th[slot_th][tid + j * TWG] = r_th[S][j];
 #pragma unroll
         for (int j = 0; j < NS; j++)
             if (tid + j * TWG < SX * SY) {
-                l_u[0][tid + j * TWG] = r_u[0][j];
-                l_u[1][tid + j * TWG] = r_u[1][j];
-                l_u[2][tid + j * TWG] = r_u[2][j];
+                l_u[0][tid + j * TWG] = r_u[S][0][j];
+                l_u[1][tid + j * TWG] = r_u[S][1][j];
+                l_u[2][tid + j * TWG] = r_u[S][2][j];
             }
 #pragma unroll
         for (int j = 0; j < NM; j++)
-            if (tid + j * TWG < MX * MY) l_pt[slot3][tid + j * TWG] = r_pt[j];
+            if (tid + j * TWG < MX * MY) l_pt[slot3][tid + j * TWG] = r_pt[S][j];
     };
 
-    // prologue: theta_hat(z0-2) straight into its slot, then the data of plane z0-2
+    // prologue: theta_hat(z0-2) straight into its slot, then the data of
+    // iterations z0-2 and z0-1
     {
         int zt = zoff(z0 - 2);
 #pragma unroll
         for (int j = 0; j < NH; j++)
             if (tid + j * TWG < HX * HY) l_th[(z0 + 2) & 1][tid + j * TWG] = that_[zt + oh[j]];
     }
-    fetch(z0 - 1, z0 - 2);
-    double o_rho = 0.0, o_v = 0.0, o_th = 0.0;
+    fetch(I0{}, z0 - 1, z0 - 2);
+    fetch(I1{}, z0, z0 - 1);
 
-    for (int zz = z0 - 2; zz <= zend; zz++) {
+    auto iteration = [&](auto slot, int zz) {
         const int rz = zz + 4;                          // non-negative ring index
-        stash((rz + 1) & 1, rz % 3);                   // theta_hat(zz+1), u(zz), rho theta(zz)
-        if (zz < zend) fetch(zz + 2, zz + 1);          // in flight during this plane
+        stash(slot, (rz + 1) & 1, rz % 3);             // theta_hat(zz+1), u(zz), rho theta(zz)
+        if (zz + 2 <= zend) fetch(slot, zz + 3, zz + 2);   // iteration zz+2, in flight for two planes
         const int zo = zz - 1;                          // output plane of this iteration
+        double o_rho = 0.0, o_v = 0.0, o_th = 0.0;
         if (zz >= z0 + 1 && outv) {
             int g = zoff(zo) + oo;
             o_rho = (double)aux[(size_t)3 * k.ns + g];
@@ -262,6 +273,11 @@ __global__ __launch_bounds__(TWG) void k_tr(const double *__restrict__ that_, co
             }
         }
         __syncthreads();
+    };
+
+    for (int zz = z0 - 2; zz <= zend; zz += 2) {
+        iteration(I0{}, zz);
+        if (zz + 1 <= zend) iteration(I1{}, zz + 1);
     }
 }
 
