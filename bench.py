@@ -139,14 +139,17 @@ def copy_probe(torch, nbytes=4 << 30, reps=10, quick=False):
     variants = [("runtime", None)] + [("float4_b%d" % nb, (0, nb)) for nb in (512, 1024, 2048)] + \
                [("float4_nt_b%d" % nb, (1, nb)) for nb in (1024,)] + [("float1", (2, 0))] + \
                [("float4_x%d" % u, (v, 0)) for u, v in ((4, 3), (8, 4), (16, 5))]
+    # the population layout of the fused step: 41 streams of one float per site
+    variants.append(("soa41_streams", (6, 0)))
     if quick:
-        variants = [("runtime", None), ("float4_x4", (3, 0))]
+        variants = [("runtime", None), ("float4_x4", (3, 0)), ("soa41_streams", (6, 0))]
     for name, v in variants:
         def run():
             if v is None:
                 b.copy_(a)
             else:
-                rc = L.pgk_probe_copy(b.data_ptr(), a.data_ptr(), nbytes, v[0], v[1], stream)
+                nb = nbytes if v[0] != 6 else nbytes // (41 * 4) * (41 * 4)
+                rc = L.pgk_probe_copy(b.data_ptr(), a.data_ptr(), nb, v[0], v[1], stream)
                 assert rc == 0
         run()
         torch.cuda.synchronize()
@@ -157,7 +160,8 @@ def copy_probe(torch, nbytes=4 << 30, reps=10, quick=False):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        out[name + "_GBs"] = round(2 * nbytes / ms / 1e6, 1)
+        nb = nbytes if v is None or v[0] != 6 else nbytes // (41 * 4) * (41 * 4)
+        out[name + "_GBs"] = round(2 * nb / ms / 1e6, 1)
     del a, b
     return out
 
@@ -599,13 +603,15 @@ def main():
     s.close()
     # the bandwidth a plain copy reaches on this device, beside the kernel's
     cp = copy_probe(torch, reps=5, quick=not args.copy_probe)
-    best = max(v for k, v in cp.items() if k.endswith("_GBs"))
+    best = max(v for k, v in cp.items() if k.endswith("_GBs") and k != "soa41_streams_GBs")
     rf = out["roofline"]
     rf["copy_reference_GBs"] = best
+    rf["copy_soa41_streams_GBs"] = cp["soa41_streams_GBs"]
     if rf["traffic"]:
         actual = rf["traffic"] / (rf["avg_launch_ms"] * 1e-3) / 1e9
         rf["actual_GBs_from_traffic"] = round(actual, 1)
         rf["actual_over_copy_reference"] = round(actual / best, 4)
+        rf["actual_over_soa41_copy"] = round(actual / cp["soa41_streams_GBs"], 4)
     if args.copy_probe:
         out["copy_probe"] = cp
     if not args.no_cpu:

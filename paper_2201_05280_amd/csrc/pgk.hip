@@ -88,7 +88,7 @@ __global__ __launch_bounds__(WG) void k_dif(const double *__restrict__ tin, doub
 #define PGK_TR_TY 8
 #endif
 #ifndef PGK_TR_TZ
-#define PGK_TR_TZ 64
+#define PGK_TR_TZ 128
 #endif
 constexpr int TX = 64, TY = PGK_TR_TY, TZ = PGK_TR_TZ;
 constexpr int TWG = TX * TY;                 // one output column per thread

@@ -44,6 +44,20 @@ __global__ __launch_bounds__(256) void k_copyU(const float4 *__restrict__ src, f
         if (base + (size_t)j * 256 < n4) dst[base + (size_t)j * 256] = v[j];
 }
 
+// 41 structure-of-arrays streams (the population layout of the fused step):
+// thread i copies element i of each of 41 arrays of n floats, every value read
+// once and written once with a nontemporal store
+__global__ __launch_bounds__(256) void k_copy_soa41(const float *__restrict__ src, float *__restrict__ dst, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float v[41];
+#pragma unroll
+    for (int q = 0; q < 41; q++) v[q] = src[(size_t)q * n + i];
+#pragma unroll
+    for (int q = 0; q < 41; q++) __builtin_nontemporal_store(v[q], dst + (size_t)q * n + i);
+}
+
 extern "C" int pgk_probe_copy(void *dst, const void *src, size_t nbytes, int variant, int blocks, void *stream)
 {
     if (!dst || !src || (nbytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15)) return -1;
@@ -63,7 +77,13 @@ extern "C" int pgk_probe_copy(void *dst, const void *src, size_t nbytes, int var
     else if (variant == 5)
         hipLaunchKernelGGL(k_copyU<16>, dim3((unsigned)((n4 + 4095) / 4096)), dim3(256), 0, s, (const float4 *)src,
                            (float4 *)dst, n4);
-    else {
+    else if (variant == 6) {
+        // nbytes = 41 arrays of n floats
+        if (nbytes % (41 * 4)) return -1;
+        size_t n = nbytes / (41 * 4);
+        hipLaunchKernelGGL(k_copy_soa41, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const float *)src,
+                           (float *)dst, n);
+    } else {
         size_t n = nbytes / 4;
         hipLaunchKernelGGL(k_copy1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const float *)src,
                            (float *)dst, n);
