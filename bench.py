@@ -124,6 +124,12 @@ def counter_traffic(n, precision):
     return float(vals["k_lb traffic_bytes_per_launch:"])
 
 
+def soa41_bytes(nbytes):
+    """Largest size <= nbytes of 41 float arrays whose length is a multiple of
+    64 (every array starts on a 256-byte boundary, as the populations do)."""
+    return nbytes // (41 * 4 * 64) * (41 * 4 * 64)
+
+
 def copy_probe(torch, nbytes=4 << 30, reps=10, quick=False):
     """Plain device copies of nbytes (n read + n written) timed with events:
     the runtime's own copy and the project's float4 copy kernels (quick: the
@@ -148,7 +154,7 @@ def copy_probe(torch, nbytes=4 << 30, reps=10, quick=False):
             if v is None:
                 b.copy_(a)
             else:
-                nb = nbytes if v[0] != 6 else nbytes // (41 * 4) * (41 * 4)
+                nb = nbytes if v[0] != 6 else soa41_bytes(nbytes)
                 rc = L.pgk_probe_copy(b.data_ptr(), a.data_ptr(), nb, v[0], v[1], stream)
                 assert rc == 0
         run()
@@ -160,7 +166,7 @@ def copy_probe(torch, nbytes=4 << 30, reps=10, quick=False):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        nb = nbytes if v is None or v[0] != 6 else nbytes // (41 * 4) * (41 * 4)
+        nb = nbytes if v is None or v[0] != 6 else soa41_bytes(nbytes)
         out[name + "_GBs"] = round(2 * nb / ms / 1e6, 1)
     del a, b
     return out
