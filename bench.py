@@ -218,6 +218,43 @@ def plain_case(case, tol, max_steps, time_cap, K=128):
     return steps, resid, dt
 
 
+def shear_wave_summary(steps=2000):
+    """The 2D periodic shear wave, 64 x 64 x 1 cells, FP64 (nu 0.01, Pr 0.71,
+    mu_b/mu 0.6, delta 2, u_x = 0.01 sin(2 pi y / 64)): amplitude decay over
+    `steps` steps against exp(-nu k^2 t), and the drift of mass, momentum and
+    total energy."""
+    import numpy as np
+    import torch
+
+    import paper_2201_05280_amd as pgk
+    from paper_2201_05280_amd import inputs
+    n = 64
+    p = pgk.resolve(0.01, 0.71, 0.6, 2.0)
+    s = pgk.Solver(n, n, 1, precision=pgk.FP64)
+    s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    f = inputs.shear_wave(n, n, 1, amp=0.01)
+    s.init(f["rho"], f["u"], f["thT"], f["thR"])
+    y = inputs.positions(n, n, 1)[1]
+    mode = np.sin(2 * np.pi * y / n)
+    a0 = float(f["u"][0] @ mode / (mode @ mode))
+    c0 = s.conserved()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    m = s.moments()
+    c1 = s.conserved()
+    s.close()
+    a1 = float(m["u"][0] @ mode / (mode @ mode))
+    k = 2 * np.pi / n
+    ratio, expect = a1 / a0, math.exp(-p["nu"] * k * k * steps)
+    drift = [(c1[i] - c0[i]) / c0[0] for i in range(4)] + [(c1[4] - c0[4]) / c0[4]]
+    return {"cells": "64x64x1", "sites": 2 * n * n, "steps": steps, "amplitude_ratio": round(ratio, 6),
+            "exp_minus_nu_k2_t": round(expect, 6), "decay_rate_rel_err": round(math.log(ratio) / math.log(expect) - 1, 5),
+            "conservation_drift": drift, "MLUPS": round(2 * n * n * steps / dt / 1e6, 1)}
+
+
 def shock_summary(max_steps=60000):
     """Normal-shock lines of 4096 cells between Dirichlet faces holding the
     model's own jump states, E2 equilibrium, run until the one-step residual
@@ -622,6 +659,7 @@ def main():
         out["copy_probe"] = cp
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)
+    out["shear_wave"] = shear_wave_summary()
     if not args.no_shock:
         out["shock"] = shock_summary()
     if not args.no_sweep:
