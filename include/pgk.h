@@ -171,7 +171,14 @@ int pgk_set_bc_x(pgk_ctx *ctx, int side, double rho, const double u[3], double t
 int pgk_init_fields(pgk_ctx *ctx, const double *rho, const double *u,
                     const double *theta_T, const double *theta_R);
 
-/* Advance n time steps (asynchronous on the context stream). */
+/* Advance n time steps (asynchronous on the context stream; one step is
+ * Sec. 5: collide and stream g, then the four steps of the theta_Rot solver).
+ * From n >= 4 on, with timing off, two steps are recorded once as a HIP graph
+ * per starting buffer (on a private stream) and replayed n/2 times; the
+ * launches and results are those of stepping one by one, bit for bit.  The
+ * recorded pairs are dropped by pgk_bind, pgk_set_params and pgk_set_bc_x.
+ * Errors: PGK_EINVAL before pgk_init_fields, PGK_EDEVICE on a failed launch,
+ * capture or graph instantiation (message in pgk_last_error). */
 int pgk_step(pgk_ctx *ctx, int64_t n);
 
 /* Moments of the translational distribution f at the current time level

@@ -385,8 +385,22 @@ struct pgk_ctx {
     std::vector<hipEvent_t> events;   // pool
     std::vector<int> marks;           // kernel id of the interval ending at event i (-1: start)
     size_t nev = 0;
+    // replayed pairs of steps, one per starting buffer (invalid after a change
+    // of parameters, faces or buffers)
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipStream_t capture = nullptr;   // private stream the pair is recorded on (the null stream cannot be)
+    void drop_graphs()
+    {
+        for (auto &g : graph)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+    }
     ~pgk_ctx()
     {
+        drop_graphs();
+        if (capture) (void)hipStreamDestroy(capture);
         for (auto e : events) (void)hipEventDestroy(e);
     }
 };
@@ -605,6 +619,7 @@ extern "C" int pgk_bind(pgk_ctx *c, void *const bufs[PGK_NBUF], const size_t byt
     c->gh = (void *)(a + off[5]);
     c->bound = true;
     c->initialised = false;
+    c->drop_graphs();
     return PGK_OK;
 }
 
@@ -687,6 +702,7 @@ extern "C" int pgk_set_params(pgk_ctx *c, const pgk_params *p, pgk_resolved *out
     c->res = r;
     if (out) *out = r;
     c->params_set = true;
+    c->drop_graphs();
     return fill_bc(c);
 }
 
@@ -699,6 +715,7 @@ extern "C" int pgk_set_bc_x(pgk_ctx *c, int side, double rho, const double u[3],
     c->k.rhobc[side] = rho;
     c->k.thbc[side] = theta;
     c->bc_set[side] = true;
+    c->drop_graphs();
     for (int a = 0; a < 3; a++) c->bc_u[side][a] = u ? u[a] : 0.0;
     return c->params_set ? fill_bc(c) : PGK_OK;
 }
@@ -783,13 +800,21 @@ static int step_t(pgk_ctx *c, int64_t n)
     return PGK_OK;
 }
 
+using StepFn = int (*)(pgk_ctx *, int64_t);
+
 template <typename S, typename A, int EQ>
-static int step_v(pgk_ctx *c, int64_t n)
+static StepFn step_fn_v(const pgk_ctx *c)
 {
     bool b = bounded(c);
-    if (c->g.variant == PGK_CN)
-        return b ? step_t<S, A, PGK_CN, true, EQ>(c, n) : step_t<S, A, PGK_CN, false, EQ>(c, n);
-    return b ? step_t<S, A, PGK_LIT, true, EQ>(c, n) : step_t<S, A, PGK_LIT, false, EQ>(c, n);
+    if (c->g.variant == PGK_CN) return b ? &step_t<S, A, PGK_CN, true, EQ> : &step_t<S, A, PGK_CN, false, EQ>;
+    return b ? &step_t<S, A, PGK_LIT, true, EQ> : &step_t<S, A, PGK_LIT, false, EQ>;
+}
+
+static StepFn step_fn(const pgk_ctx *c)
+{
+    if (c->g.equilibrium == PGK_E2)
+        return c->g.precision == PGK_FP64 ? step_fn_v<double, double, PGK_E2>(c) : step_fn_v<float, float, PGK_E2>(c);
+    return c->g.precision == PGK_FP64 ? step_fn_v<double, double, PGK_F3>(c) : step_fn_v<float, float, PGK_F3>(c);
 }
 
 extern "C" int pgk_step(pgk_ctx *c, int64_t n)
@@ -797,9 +822,44 @@ extern "C" int pgk_step(pgk_ctx *c, int64_t n)
     if (!c || n < 0) return PGK_EINVAL;
     if (!c->initialised) return fail(c, PGK_EINVAL, "fields not initialised");
     if (n == 0) return PGK_OK;
-    if (c->g.equilibrium == PGK_E2)
-        return c->g.precision == PGK_FP64 ? step_v<double, double, PGK_E2>(c, n) : step_v<float, float, PGK_E2>(c, n);
-    return c->g.precision == PGK_FP64 ? step_v<double, double, PGK_F3>(c, n) : step_v<float, float, PGK_F3>(c, n);
+    StepFn f = step_fn(c);
+    // a few steps, or per-kernel timing (events between the launches): launch directly
+    if (c->timing || n < 4) return f(c, n);
+    int rc;
+    if (c->steps == 0) {   // the first step has no ghost refresh: not part of the replayed pair
+        rc = f(c, 1);
+        if (rc) return rc;
+        n--;
+    }
+    // a captured pair of steps returns the state to the buffer it started from
+    const int p = c->cur;
+    if (!c->graph[p]) {
+        if (!c->capture) HIPCHECK(c, hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+        const int cur0 = c->cur;
+        const int64_t steps0 = c->steps;
+        hipStream_t own = c->stream;
+        HIPCHECK(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+        c->stream = c->capture;
+        rc = f(c, 2);
+        c->stream = own;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->capture, &g);
+        c->cur = cur0;   // capturing launched nothing
+        c->steps = steps0;
+        if (rc || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc ? rc : fail(c, PGK_EDEVICE, std::string("step capture: ") + hipGetErrorString(e));
+        }
+        hipError_t ei = hipGraphInstantiate(&c->graph[p], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            c->graph[p] = nullptr;
+            return fail(c, PGK_EDEVICE, std::string("step graph: ") + hipGetErrorString(ei));
+        }
+    }
+    for (int64_t i = 0; i + 1 < n; i += 2) HIPCHECK(c, hipGraphLaunch(c->graph[p], c->stream));
+    c->steps += n / 2 * 2;
+    return (n & 1) ? f(c, 1) : PGK_OK;
 }
 
 template <typename S, bool REDUCE>
