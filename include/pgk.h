@@ -173,13 +173,19 @@ int pgk_init_fields(pgk_ctx *ctx, const double *rho, const double *u,
 
 /* Advance n time steps (asynchronous on the context stream; one step is
  * Sec. 5: collide and stream g, then the four steps of the theta_Rot solver).
- * From n >= 4 on, with timing off, two steps are recorded once as a HIP graph
- * per starting buffer (on a private stream) and replayed n/2 times; the
- * launches and results are those of stepping one by one, bit for bit.  The
- * recorded pairs are dropped by pgk_bind, pgk_set_params and pgk_set_bc_x.
+ * With graph steps K > 0 (pgk_set_graph_steps) and timing off, K steps are
+ * recorded once as a HIP graph per starting buffer (on a private stream) and
+ * replayed n/K times, the rest launched directly; the launches and results
+ * are those of stepping one by one, bit for bit.  The recorded chunks are
+ * dropped by pgk_bind, pgk_set_params, pgk_set_bc_x and a new K.
  * Errors: PGK_EINVAL before pgk_init_fields, PGK_EDEVICE on a failed launch,
  * capture or graph instantiation (message in pgk_last_error). */
 int pgk_step(pgk_ctx *ctx, int64_t n);
+
+/* Steps per replayed graph for pgk_step: 0 launches every kernel directly,
+ * an even K in [2, 4096] replays K-step graphs (default 32); PGK_EINVAL
+ * otherwise. */
+int pgk_set_graph_steps(pgk_ctx *ctx, int k);
 
 /* Moments of the translational distribution f at the current time level
  * (after the g -> f map of Sec. 5) into device arrays; any pointer may be

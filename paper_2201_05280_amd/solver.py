@@ -111,6 +111,10 @@ class Solver:
     def step(self, n=1):
         self._check(self.L.pgk_step(self.h, int(n)))
 
+    def set_graph_steps(self, k):
+        """Replay k-step HIP graphs in step() (k even); 0 launches directly."""
+        self._check(self.L.pgk_set_graph_steps(self.h, int(k)))
+
     def set_timing(self, enable=True):
         self._check(self.L.pgk_set_timing(self.h, 1 if enable else 0))
 

@@ -94,6 +94,11 @@ def test_null_arguments_are_errors_not_crashes():
     assert b"not initialised" in L.pgk_last_error(out)
     p = _lib.Params(-1.0, 1.0, 0.0, 0.0, 2.0, 0.0)
     assert L.pgk_set_params(out, ctypes.byref(p), None) == -1
+    # graph chunk lengths: 0 or even, at most 4096
+    assert L.pgk_set_graph_steps(None, 2) == -1
+    for k, rc in ((0, 0), (2, 0), (64, 0), (4096, 0), (3, -1), (-2, -1), (4098, -1)):
+        assert L.pgk_set_graph_steps(out, k) == rc, k
+    assert b"graph steps" in L.pgk_last_error(out)
     L.pgk_destroy(out)
     assert not math.isnan(1.0)
 

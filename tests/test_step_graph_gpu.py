@@ -1,12 +1,13 @@
-"""pgk_step's replayed pairs of steps against steps launched one by one (GPU only).
+"""pgk_step's replayed K-step graphs against steps launched one by one (GPU only).
 
-A call of four or more steps records two steps once per starting buffer and
-replays them; shorter calls and timed runs launch each kernel directly.  The
-two must give identical bits: the same kernels with the same arguments run in
-the same order.  The cases cover odd and even step counts, the untouched
-first step, diffuse walls and Dirichlet faces (the ghost refresh), the
-sub-cycled diffusion, FP32 storage, the E2 equilibrium, a parameter change
-between calls (the recorded pair must be rebuilt) and a caller's own stream.
+With K graph steps set, a call records K steps once per starting buffer and
+replays them, the rest launched directly; calls shorter than K and timed runs
+launch each kernel directly.  Both must give identical bits: the same kernels
+with the same arguments run in the same order.  The cases cover step counts
+below, at and above multiples of K, the untouched first step, diffuse walls
+and Dirichlet faces (the ghost refresh), the sub-cycled diffusion, FP32
+storage, the E2 equilibrium, a parameter change and a new K between calls
+(the recorded chunks must be rebuilt) and a caller's own stream.
 """
 import numpy as np
 import pytest
@@ -18,7 +19,7 @@ from paper_2201_05280_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def _pair(nx, ny, nz, f, p, precision=0, bc=None, equilibrium=0, stream=None):
+def _pair(nx, ny, nz, f, p, precision=0, bc=None, equilibrium=0, stream=None, K=2):
     import paper_2201_05280_amd as pgk
     kinds = (pgk.PERIODIC, pgk.PERIODIC) if bc is None else (bc[0][0], bc[1][0])
     out = []
@@ -31,6 +32,7 @@ def _pair(nx, ny, nz, f, p, precision=0, bc=None, equilibrium=0, stream=None):
                 s.set_bc_x(side, rho, u, th)
         s.init(f["rho"], f["u"], f["thT"], f["thR"])
         out.append(s)
+    out[0].set_graph_steps(K)
     return out
 
 
@@ -50,12 +52,12 @@ def _run(a, b, calls, label):
         _same(a, b, (label, n))
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_periodic_odd_and_even_calls(precision):
+@pytest.mark.parametrize("precision,K", [(0, 2), (1, 2), (0, 6), (1, 16)])
+def test_periodic_odd_and_even_calls(precision, K):
     f = inputs.random_smooth(12, 10, 6, seed=31)
     p = resolve(0.02, 0.71, 0.6, 2.0)
-    a, b = _pair(12, 10, 6, f, p, precision)
-    _run(a, b, [5, 8, 7, 3, 12], "periodic")
+    a, b = _pair(12, 10, 6, f, p, precision, K=K)
+    _run(a, b, [5, 8, 7, 3, 12, 2 * K + 1, K], "periodic")
     a.close(); b.close()
 
 
@@ -90,6 +92,10 @@ def test_parameter_change_rebuilds_the_pair():
     for s in (a, b):
         s.set_params(p2["tau"], p2["tau1"], p2["b"], p2["kr"], p2["delta"])
     _run(a, b, [6, 7], "after")
+    a.set_graph_steps(4)
+    _run(a, b, [9, 4], "new K")
+    a.set_graph_steps(0)
+    _run(a, b, [5], "direct")
     a.close(); b.close()
 
 
@@ -98,7 +104,8 @@ def test_callers_stream_and_timing():
     f = inputs.random_smooth(10, 6, 4, seed=33)
     p = resolve(0.02, 0.71, 0.6, 2.0)
     st = torch.cuda.Stream()
-    a, b = _pair(10, 6, 4, f, p, stream=st)
+    a, b = _pair(10, 6, 4, f, p, stream=st, K=4)
+    b.set_graph_steps(4)
     b.set_timing(True)   # timed runs launch kernel by kernel
     a.step(10)
     b.step(10)
