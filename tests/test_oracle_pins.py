@@ -499,3 +499,63 @@ def test_thermal_couette_profile_with_viscous_heating(Pr, tol):
     Ec = U ** 2 / (3.5 * dT)
     ta = y + Pr * Ec / 2 * y * (1 - y)
     assert np.abs((th - TH0) / dT - ta).max() < tol
+
+
+# ----------------------------------------------------------------------------
+# 3D Taylor-Green vortex (the benchmark flow at reduced size)
+# ----------------------------------------------------------------------------
+def _tgv(n, Re, steps):
+    U = 0.1 * np.sqrt(1.4 * TH0)
+    k = 2 * np.pi / n
+    p = resolve(U / (k * Re), 0.71, 0.6, 2.0)
+    o = oracle.Oracle(n, n, n)
+    o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    f = inputs.taylor_green(n, U)
+    o.init(f["rho"], f["u"], f["thT"], f["thR"])
+    ke = []
+    for st in range(steps + 1):
+        m = o.moments()
+        ke.append(0.5 * np.sum(m["rho"] * (m["u"] ** 2).sum(0)))
+        if st < steps:
+            o.step(1)
+    return np.array(ke), m, coefficients(**p), k, U
+
+
+def _swap_shift(a, n):
+    """a on sites [sub][z][y][x] -> a(P x + (n/2, 0, 0)), P swapping x and y:
+    out(x, y, z) = a(y + n/2, x, z) on both sublattices."""
+    a = a.reshape(2, n, n, n)
+    b = np.transpose(a, (0, 1, 3, 2))          # b[s][z][y][x] = a[s][z][x][y]
+    return np.roll(b, -(n // 2), axis=3).reshape(-1)   # out[s][z][y][x] = a[s][z][x][y + n/2]
+
+
+def test_taylor_green_energy_decay_starts_at_six_nu_k2():
+    # At t = 0 the vortex is divergence free and the advection term moves no
+    # energy, so d(KE)/dt = -nu <|grad u|^2> = -6 nu k^2 KE for this field.
+    # The fitted rate over the first 40 steps (after the 5-step start-up
+    # layer) approaches it as k -> 0.
+    errs = []
+    for n in (16, 24, 32):
+        ke, _, co, k, _ = _tgv(n, 50.0, 40)
+        t = np.arange(len(ke))
+        rate = -np.polyfit(t[5:], np.log(ke[5:]), 1)[0]
+        errs.append(abs(rate / (6 * co["nu"] * k * k) - 1))
+    assert errs[0] > errs[1] > errs[2], errs
+    assert errs[2] < 0.01, errs
+
+
+def test_taylor_green_keeps_its_swap_and_shift_symmetry():
+    # The initial field is invariant under x -> P x + (n/2, 0, 0) with P the
+    # x <-> y mirror (velocity components swapped by P).  P maps the bcc
+    # lattice, the velocity set, the forward and backward differences of the
+    # theta_R transport and the Laplacian onto themselves, so the discrete
+    # flow keeps the symmetry to round-off while w grows from zero.
+    n = 16
+    _, m, _, _, U = _tgv(n, 50.0, 40)
+    u, v, w = m["u"]
+    assert np.abs(w).max() > 0.05 * U
+    assert np.abs(_swap_shift(v, n) - u).max() < 1e-12 * U
+    assert np.abs(_swap_shift(u, n) - v).max() < 1e-12 * U
+    assert np.abs(_swap_shift(w, n) - w).max() < 1e-12 * U
+    for key in ("rho", "thT", "thR"):
+        assert np.abs(_swap_shift(m[key], n) - m[key]).max() < 1e-12 * np.abs(m[key]).max(), key
