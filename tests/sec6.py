@@ -1,0 +1,81 @@
+"""Measurements of the Sec. 6 validation flows, shared by the oracle pins and
+the GPU validation tests.
+
+Nothing here computes a step of the method: a `make(nx, ny, nz, p, fields)`
+callable returns an initialised runner (the oracle or the HIP solver) with
+`step(n)` and `moments()`, and these helpers read its moments, fit them and
+evaluate the closed-form solutions they are compared with.
+"""
+import numpy as np
+from scipy.integrate import quad
+from scipy.optimize import curve_fit
+from scipy.special import j0
+
+from oracle.params import coefficients, resolve
+from paper_2201_05280_amd import inputs
+
+THETA0 = inputs.THETA0
+
+
+def sound_speed(make, nx, delta, nu=0.002, Pr=0.71, mub_over_mu=1.0, periods=2.0, skip=20, eps=1e-4):
+    """Sound speed from a standing pressure wave p0 (1 + eps cos kx) on an
+    nx-cell periodic line (Sec. 6, first validation): the momentum projection
+    onto sin kx is fitted by A exp(-G t) sin(w t + phi) after `skip` steps,
+    and c_s = w / k.  Returns (c_s^2 / theta0, gamma of the resolved set)."""
+    p = resolve(nu, Pr, mub_over_mu, delta)
+    co = coefficients(**p)
+    f = inputs.density_wave(nx, 1, 1, eps=eps)
+    run = make(nx, 1, 1, p, f)
+    k = 2 * np.pi / nx
+    S = np.sin(k * inputs.positions(nx, 1, 1)[0])
+    steps = int(periods * nx / np.sqrt(co["gamma"] * THETA0))
+    j = []
+    for n in range(steps + 1):
+        m = run.moments()
+        j.append(2 * np.mean(m["rho"] * m["u"][0] * S))
+        if n < steps:
+            run.step(1)
+    j = np.array(j)
+    t = np.arange(len(j), dtype=np.float64)
+    w0 = k * np.sqrt(co["gamma"] * THETA0)
+
+    def model(t, A, G, w, ph):
+        return A * np.exp(-G * t) * np.sin(w * t + ph)
+
+    popt, _ = curve_fit(model, t[skip:], j[skip:], p0=[np.abs(j).max(), 1e-4, w0, 0.0], maxfev=20000)
+    return (popt[2] / k) ** 2 / THETA0, co["gamma"]
+
+
+def pulse_exact(r, t, eps, alpha, cs):
+    """Linear acoustics of p = p0 (1 + eps exp(-alpha r^2)) released from rest
+    in 2D: p'/p0 = eps/(2 alpha) int_0^inf exp(-xi^2/(4 alpha)) cos(cs xi t)
+    J0(xi r) xi dxi (the Hankel-transform solution the paper compares with)."""
+    def f(xi):
+        return np.exp(-xi * xi / (4 * alpha)) * np.cos(cs * xi * t) * j0(xi * r) * xi
+    v, _ = quad(f, 0.0, 12.0 * np.sqrt(alpha), limit=400)
+    return eps / (2 * alpha) * v
+
+
+def acoustic_pulse(make, n=256, nz=1, steps=80, nu=0.002, eps=1e-3):
+    """The axisymmetric pulse of Sec. 6 on [-1, 1]^2 = n x n cells (half-width
+    b = 0.1, alpha = ln 2 / b^2), carried by rho at theta0, z-invariant.
+    Returns (r, simulated p'/p0, exact p'/p0) along the centre line y = 0,
+    x >= 0 (corner sites), after `steps` steps."""
+    p = resolve(nu, 0.71, 0.6, 2.0)
+    co = coefficients(**p)
+    cs = np.sqrt(co["gamma"] * THETA0)
+    b = 0.1 * n / 2
+    alpha = np.log(2.0) / b ** 2
+    pos = inputs.positions(n, n, nz)
+    c = n / 2
+    f = inputs.uniform(n, n, nz)
+    f["rho"] = 1.0 + eps * np.exp(-alpha * ((pos[0] - c) ** 2 + (pos[1] - c) ** 2))
+    run = make(n, n, nz, p, f)
+    run.step(steps)
+    m = run.moments()
+    d = p["delta"]
+    theta = (3 * m["thT"] + d * m["thR"]) / (3 + d)
+    pp = m["rho"] * theta / THETA0 - 1.0
+    sel = (np.abs(pos[1] - c) < 1e-9) & (pos[0] >= c) & (np.abs(pos[2]) < 1e-9)
+    r = pos[0][sel] - c
+    return r, pp[sel], np.array([pulse_exact(x, steps, eps, alpha, cs) for x in r])

@@ -559,3 +559,48 @@ def test_taylor_green_keeps_its_swap_and_shift_symmetry():
     assert np.abs(_swap_shift(w, n) - w).max() < 1e-12 * U
     for key in ("rho", "thT", "thR"):
         assert np.abs(_swap_shift(m[key], n) - m[key]).max() < 1e-12 * np.abs(m[key]).max(), key
+
+
+# ----------------------------------------------------------------------------
+# Sec. 6 validation flows, measured the way the paper describes them
+# ----------------------------------------------------------------------------
+def _oracle_runner(nx, ny, nz, p, f):
+    o = oracle.Oracle(nx, ny, nz)
+    o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    o.init(f["rho"], f["u"], f["thT"], f["thR"])
+    return o
+
+
+def test_effective_delta_table_sound_speeds():
+    # every fluid of the effective-delta table on the paper's 128-cell line:
+    # gamma = c_s^2/theta0 within 2e-4 of (5+delta)/(3+delta) and equal to the
+    # printed value to its printed digits
+    from tests import sec6
+    for g, d, name in read_golden("effective_delta.txt"):
+        gam, gth = sec6.sound_speed(_oracle_runner, 128, float(d))
+        assert abs(gam / gth - 1) < 2e-4, (name, gam, gth)
+        digits = len(g.split(".")[1]) if "." in g else 0
+        assert abs(gam - float(g)) <= 0.5 * 10 ** (-digits) + 2e-4, (name, gam, g)
+
+
+def test_sound_speed_converges_at_second_order():
+    # air (delta 1.96): the c_s error falls by about 4 per doubling of the grid
+    from tests import sec6
+    errs = []
+    for n in (16, 32, 64, 128):
+        gam, gth = sec6.sound_speed(_oracle_runner, n, 1.96)
+        errs.append(abs(np.sqrt(gam / gth) - 1))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(3.5 < q < 5.5 for q in ratios), (errs, ratios)
+    assert errs[-1] < 5e-5, errs
+
+
+def test_acoustic_pulse_matches_the_bessel_solution():
+    # the axisymmetric pulse on 256 x 256 cells after 80 steps (the wave front
+    # at r ~ 0.45) against the linear-acoustics integral: 1.5% in L2 along the
+    # centre line, 1% of the peak pointwise
+    from tests import sec6
+    r, sim, ex = sec6.acoustic_pulse(_oracle_runner)
+    assert np.linalg.norm(sim - ex) / np.linalg.norm(ex) < 0.015
+    assert np.abs(sim - ex).max() < 0.01 * np.abs(ex).max()
+    assert 50 < r[np.argmax(ex)] < 64 and abs(r[np.argmax(sim)] - r[np.argmax(ex)]) <= 1
