@@ -3,8 +3,11 @@
 The same measurements as the oracle pins, with the same bars, on the GPU
 solver in FP64 and FP32 deviation storage: the sound speed of every fluid in
 the effective-delta table on the paper's 128-cell line, its second-order grid
-convergence for air, and the axisymmetric acoustic pulse on the paper's
-256 x 256 x 4 grid against the linear-acoustics (Bessel) integral.
+convergence for air, the axisymmetric acoustic pulse on the paper's
+256 x 256 x 4 grid against the linear-acoustics (Bessel) integral, and the
+two Couette flows between diffuse walls on 3D grids: the start-up of a shear
+flow against its series solution (on the paper's 64-by-128-by-8 grid, every
+column equal) and the steady thermal Couette profile with viscous heating.
 """
 import numpy as np
 import pytest
@@ -55,3 +58,68 @@ def test_acoustic_pulse_matches_the_bessel_solution(precision):
     assert l2 < 0.015
     assert np.abs(sim - ex).max() < 0.01 * np.abs(ex).max()
     assert abs(r[np.argmax(sim)] - r[np.argmax(ex)]) <= 1
+
+
+TH0 = sec6.THETA0
+
+
+def _couette(precision, L, nu, Pr, u_top, th_top, ny=128, nz=8):
+    # the paper's start-up grid: L cells between diffuse walls (x), 128 x 8 periodic
+    import paper_2201_05280_amd as pgk
+    from oracle.params import resolve
+    from paper_2201_05280_amd import inputs
+    p = resolve(nu, Pr, 0.8, 2.0)
+    s = pgk.Solver(L, ny, nz, precision=precision, bc_x=(pgk.WALL, pgk.WALL))
+    s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    s.set_bc_x(0, 1.0, (0, 0, 0), TH0)
+    s.set_bc_x(1, 1.0, (0, u_top, 0), th_top)
+    f = inputs.uniform(L, ny, nz)
+    s.init(f["rho"], f["u"], f["thT"], f["thR"])
+    # walls a quarter cell outside the first and last sites: height L
+    y = (inputs.positions(L, ny, nz)[0] + 0.25) / L
+    return s, y
+
+
+def _columns_equal(a, L, ny, nz):
+    # every (y, z) column holds the same profile
+    a = a.reshape(2, nz, ny, L)
+    return float(np.abs(a - a[:, :1, :1, :]).max())
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 0.02), (1, 0.02)])
+def test_couette_start_up_follows_the_series_solution(precision, bar):
+    L, nu, U = 64, 0.1, 0.02
+    s, y = _couette(precision, L, nu, 0.71, U, TH0)
+    k = np.arange(1, 400)[:, None]
+    done = 0
+    for ts in (0.05, 0.1, 0.3):
+        n = int(round(ts * L * L / nu))
+        s.step(n - done)
+        done = n
+        m = s.moments()
+        u = m["u"][1] / U
+        ua = y - 2 / np.pi * (np.exp(-k ** 2 * np.pi ** 2 * nu * n / L ** 2) / k * np.sin(k * np.pi * (1 - y))).sum(0)
+        print("start-up t*", ts, np.abs(u - ua).max())
+        assert np.abs(u - ua).max() < bar, (ts, np.abs(u - ua).max())
+        assert _columns_equal(m["u"][1], L, 128, 8) < 1e-12 * U
+    s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("Pr,tol", [(0.71, 0.02), (2.0, 0.015)])
+def test_thermal_couette_profile_with_viscous_heating(precision, Pr, tol):
+    L, nu, U, dT = 64, 0.1, 0.06, 0.02 * TH0
+    s, y = _couette(precision, L, nu, Pr, U, TH0 + dT, ny=8, nz=2)
+    prev = None
+    for _ in range(60):
+        s.step(4000)
+        m = s.moments()
+        th = (3 * m["thT"] + 2 * m["thR"]) / 5
+        if prev is not None and np.abs(th - prev).max() < 1e-9:
+            break
+        prev = th
+    Ec = U ** 2 / (3.5 * dT)
+    ta = y + Pr * Ec / 2 * y * (1 - y)
+    print("thermal Couette Pr", Pr, np.abs((th - TH0) / dT - ta).max())
+    assert np.abs((th - TH0) / dT - ta).max() < tol
+    s.close()
