@@ -84,7 +84,9 @@ extern "C" {
 #define PGK_BUF_POP1   1     /* 41*ns populations (pong) */
 #define PGK_BUF_THETAR 2     /* ns doubles: theta_R */
 #define PGK_BUF_AUX    3     /* per-site fields handed from the collision to the theta_R
-                                transport, reduction partials, wall densities */
+                                transport, reduction partials, wall densities; with
+                                PGK_E2 also each site's last Newton multipliers
+                                (2 x 10 doubles, the next step's starting point) */
 #define PGK_NBUF       4
 
 typedef struct pgk_ctx pgk_ctx;
@@ -223,8 +225,12 @@ int pgk_kernel_times(pgk_ctx *ctx, double ms[PGK_NKERNEL], int64_t launches[PGK_
  *              ||phi^n - phi^(n-1)||_2 / ||phi^n||_2   (one-step change)
  * and is frozen when it falls to `tol` (CONVERGED), when a density or a
  * temperature turns non-positive or non-finite (DIVERGED), or at max_steps.
- * Work-group size and K come from a built-in autotuner (timed first chunks,
- * cached as JSON in $PGK_TUNE_CACHE or ~/.cache/pgk_tune.json) unless set.
+ * Work-group size and K come from a built-in autotuner unless set: at the
+ * start of a run and again whenever the number of running cases has halved,
+ * one chunk of each candidate is timed on the live state (or the choice for
+ * that mix is read from the JSON cache, $PGK_TUNE_CACHE or
+ * ~/.cache/pgk_tune.json, keyed by the running case count and the longest
+ * running case).
  * ------------------------------------------------------------------------ */
 #define PGK_CASE_RUNNING   0
 #define PGK_CASE_CONVERGED 1
@@ -276,7 +282,8 @@ int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_t *steps, d
  * residual at a floor).  window = 0 (the default) turns it off. */
 int pgk_batch_stall(pgk_batch *b, int64_t window);
 
-/* Work-group size, K and measured nanoseconds per site update of the chosen config. */
+/* Work-group size and K last chosen, and nanoseconds per site update over
+ * the last run. */
 int pgk_batch_tuned(const pgk_batch *b, int *wg, int *K, double *ns_per_site_update);
 
 /* f-moments of every case into device arrays over all sites (NULL = skip). */

@@ -258,6 +258,7 @@ int pgko_feq_e2(double theta0, const double *w, const double *c, double rho,
     lm[9] = -Li[1][2];
     double scale = 0.0;
     for (int k = 0; k < 10; k++) scale += fabs(target[k]);
+    double last = 1e300;   /* largest exponent change of the last Newton step */
     for (int it = 1; it <= 100; it++) {
         double mom[10] = {0}, J[100] = {0};
         for (int i = 0; i < NQ; i++) {
@@ -274,7 +275,10 @@ int pgko_feq_e2(double theta0, const double *w, const double *c, double rho,
             rhs[k] = target[k] - mom[k];
             res += fabs(rhs[k]);
         }
-        if (res <= 1e-14 * scale) return it;
+        /* the equilibrium is fixed by its moments alone: stop at the round-off
+           floor (moments met and a last step too small to matter), so the
+           result does not depend on where the iteration started */
+        if (res <= 1e-14 * scale && last <= 1e-8) return it;
         if (spd_solve(10, J, rhs) != 0) return -1;
         /* damped step: limit the change of the exponent at any velocity */
         double maxd = 0.0;
@@ -283,6 +287,7 @@ int pgko_feq_e2(double theta0, const double *w, const double *c, double rho,
             for (int k = 0; k < 10; k++) d += rhs[k] * phi[i][k];
             if (fabs(d) > maxd) maxd = fabs(d);
         }
+        last = maxd;
         double damp = maxd > 2.0 ? 2.0 / maxd : 1.0;
         for (int k = 0; k < 10; k++) lm[k] += damp * rhs[k];
         if (!isfinite(lm[0])) return -1;

@@ -777,17 +777,102 @@ static std::string tune_key(const pgk_batch *b)
     (void)hipGetDevice(&dev);
     (void)hipGetDeviceProperties(&prop, dev);
     long long maxL = 0;
-    for (auto &c : b->host_cases) maxL = std::max<long long>(maxL, c.k.nx);
+    int nrun = 0;
+    for (int i = 0; i < b->n; i++)
+        if (b->h_status[i] == PGK_CASE_RUNNING) {
+            maxL = std::max<long long>(maxL, b->host_cases[i].k.nx);
+            nrun++;
+        }
     char key[256];
-    // arch, number of cases (log2 bucket), longest case (log2 bucket), variant
+    // arch, number of running cases (log2 bucket), longest running case (log2
+    // bucket), variant
     int nb = 0, lb = 0;
-    while ((1 << nb) < b->n) nb++;
+    while ((1 << nb) < nrun) nb++;
     while ((1LL << lb) < maxL) lb++;
     snprintf(key, sizeof key, "%s/batch/n%d/L%d/v%d/e%d", prop.gcnArchName, nb, lb, b->host_cases[0].variant,
              b->has_e2 ? 1 : 0);
     for (char *p = key; *p; p++)
         if (*p == '"' || *p == ':') *p = '_';
     return key;
+}
+
+static long long running_sites(const pgk_batch *b)
+{
+    long long act = 0;
+    for (int i = 0; i < b->n; i++)
+        if (b->h_status[i] == PGK_CASE_RUNNING) act += b->host_cases[i].k.ns;
+    return act;
+}
+
+static int running_cases(const pgk_batch *b)
+{
+    int n = 0;
+    for (int i = 0; i < b->n; i++) n += b->h_status[i] == PGK_CASE_RUNNING;
+    return n;
+}
+
+// Work-group size and chunk length for the cases still running: the cached
+// choice for this mix, else one chunk of every candidate timed on the live
+// state (the chunks advance the cases like any other) and the fastest per
+// site update cached.
+static int tune(pgk_batch *b, int variant, int &wg, int &K)
+{
+    std::string key = tune_key(b);
+    std::map<std::string, std::pair<int, int>> cache;
+    {
+        std::lock_guard<std::mutex> lock(cache_mutex);
+        cache = cache_load();
+    }
+    auto hit = cache.find(key);
+    bool usable = hit != cache.end() && (hit->second.first == 256 || (hit->second.first == 512 && !b->has_e2)) &&
+                  hit->second.second >= 2;
+    if (usable) {
+        wg = hit->second.first;
+        K = hit->second.second;
+        return PGK_OK;
+    }
+    const int cand[][2] = {{256, 32}, {512, 32}, {256, 128}, {512, 128}};
+    double best = 1e300;
+    int bw = 0, bk = 0, rc;
+    hipEvent_t e0, e1;
+    BHIP(b, hipEventCreate(&e0));
+    BHIP(b, hipEventCreate(&e1));
+    for (auto &cd : cand) {
+        // (a batch holding E2 cases has one work-group size: only K is tuned)
+        if (b->has_e2 && cd[0] != 256) continue;
+        if (running_sites(b) == 0) break;
+        // capture and instantiate outside the timed interval, and time the
+        // second of two chunks
+        hipGraphExec_t ge;
+        rc = chunk_graph(b, cd[0], cd[1], variant, &ge);
+        if (rc) return rc;
+        BHIP(b, hipGraphLaunch(ge, b->stream));
+        rc = readback(b);
+        if (rc) return rc;
+        long long act = running_sites(b);
+        if (act == 0) break;
+        BHIP(b, hipEventRecord(e0, b->stream));
+        BHIP(b, hipGraphLaunch(ge, b->stream));
+        BHIP(b, hipEventRecord(e1, b->stream));
+        BHIP(b, hipEventSynchronize(e1));
+        float ms = 0.f;
+        BHIP(b, hipEventElapsedTime(&ms, e0, e1));
+        double nsps = ms * 1e6 / ((double)act * cd[1]);
+        if (nsps < best) { best = nsps; bw = cd[0]; bk = cd[1]; }
+        rc = readback(b);
+        if (rc) return rc;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (bw == 0) return PGK_OK;   // every case stopped while timing: keep the last choice
+    wg = bw;
+    K = bk;
+    b->tuned_ns = best;
+    std::lock_guard<std::mutex> lock(cache_mutex);
+    cache = cache_load();
+    cache[key] = {wg, K};
+    cache_store(cache);
+    return PGK_OK;
 }
 
 extern "C" int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_t *steps, double *resid, int *status)
@@ -802,67 +887,17 @@ extern "C" int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_
     b->graphs.clear();
     int rc = readback(b);
     if (rc) return rc;
-    auto running = [&]() {
-        long long act = 0;
-        for (int i = 0; i < b->n; i++)
-            if (b->h_status[i] == PGK_CASE_RUNNING) act += b->host_cases[i].k.ns;
-        return act;
-    };
-    int wg = b->wg, K = b->K;
-    if (wg == 0) {
-        std::string key = tune_key(b);
-        std::map<std::string, std::pair<int, int>> cache;
-        {
-            std::lock_guard<std::mutex> lock(cache_mutex);
-            cache = cache_load();
-        }
-        auto hit = cache.find(key);
-        bool usable = hit != cache.end() && (hit->second.first == 256 || (hit->second.first == 512 && !b->has_e2)) &&
-                      hit->second.second >= 2;
-        if (usable) {
-            wg = hit->second.first;
-            K = hit->second.second;
-        } else {
-            // time one chunk of every candidate on the live state
-            const int cand[][2] = {{256, 32}, {512, 32}, {256, 128}, {512, 128}};
-            double best = 1e300;
-            // (a batch holding E2 cases has one work-group size: only K is tuned)
-            hipEvent_t e0, e1;
-            BHIP(b, hipEventCreate(&e0));
-            BHIP(b, hipEventCreate(&e1));
-            for (auto &cd : cand) {
-                if (b->has_e2 && cd[0] != 256) continue;
-                if (running() == 0) break;
-                // capture and instantiate outside the timed interval, and time
-                // the second of two chunks
-                hipGraphExec_t ge;
-                rc = chunk_graph(b, cd[0], cd[1], variant, &ge);
-                if (rc) return rc;
-                BHIP(b, hipGraphLaunch(ge, b->stream));
-                rc = readback(b);
-                if (rc) return rc;
-                long long act = running();
-                if (act == 0) break;
-                BHIP(b, hipEventRecord(e0, b->stream));
-                BHIP(b, hipGraphLaunch(ge, b->stream));
-                BHIP(b, hipEventRecord(e1, b->stream));
-                BHIP(b, hipEventSynchronize(e1));
-                float ms = 0.f;
-                BHIP(b, hipEventElapsedTime(&ms, e0, e1));
-                double nsps = ms * 1e6 / ((double)act * cd[1]);
-                if (nsps < best) { best = nsps; wg = cd[0]; K = cd[1]; }
-                rc = readback(b);
-                if (rc) return rc;
-            }
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            if (wg == 0) { wg = 256; K = 128; }
-            b->tuned_ns = best;
-            std::lock_guard<std::mutex> lock(cache_mutex);
-            cache = cache_load();
-            cache[key] = {wg, K};
-            cache_store(cache);
-        }
+    auto running = [&]() { return running_sites(b); };
+    // automatic choice: tuned at the start and again whenever the number of
+    // running cases has halved (the last, longest cases decide the wall time,
+    // and few work-groups favour other shapes than a full batch)
+    const bool autotune = b->wg == 0;
+    int wg = autotune ? 256 : b->wg, K = autotune ? 128 : b->K;
+    int tuned_at = 0;
+    if (autotune) {
+        tuned_at = running_cases(b);
+        rc = tune(b, variant, wg, K);
+        if (rc) return rc;
     }
     b->tuned_wg = wg;
     b->tuned_K = K;
@@ -876,6 +911,15 @@ extern "C" int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_
     while (true) {
         long long act = running();
         if (act == 0) break;
+        if (autotune && running_cases(b) * 2 <= tuned_at) {
+            tuned_at = running_cases(b);
+            rc = tune(b, variant, wg, K);
+            if (rc) return rc;
+            b->tuned_wg = wg;
+            b->tuned_K = K;
+            act = running();
+            if (act == 0) break;
+        }
         BHIP(b, hipEventRecord(t0, b->stream));
         rc = chunk(b, wg, K, variant);
         if (rc) return rc;

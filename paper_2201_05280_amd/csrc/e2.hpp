@@ -5,10 +5,13 @@
 //   F_i = w_i exp(l . phi_i),  phi_i = (1, c, cx^2, cy^2, cz^2, cxcy, cxcz, cycz),
 // with the ten multipliers l fixed by sum_i F_i phi_i = (rho, rho u, rho (uu + lam)).
 // The multipliers come from Newton's method on those ten equations, started
-// from the continuous Gaussian N(u, lam) / N(0, theta0 I) and damped so that
-// no exponent changes by more than 2 in one iteration; a Cholesky solve of the
-// (symmetric positive definite) Jacobian sum_i F_i phi_i phi_i^T gives the
-// step.  The same code runs on the host (face states) and in the kernels.
+// from the continuous Gaussian N(u, lam) / N(0, theta0 I) (or from a nearby
+// solution) and damped so that no exponent changes by more than 2 in one
+// iteration; a Cholesky solve of the (symmetric positive definite) Jacobian
+// sum_i F_i phi_i phi_i^T gives the step.  It stops once the moments are met
+// to 1e-14 and the last step moved no exponent by more than 1e-8, so that the
+// result is the constrained minimiser to round-off, not a function of the
+// starting point.  The same code runs on the host (face states) and in the kernels.
 //
 // The opposite velocities +-c of a pair share the even part of the exponent
 // and differ in the sign of the odd part (the three linear multipliers), so
@@ -194,6 +197,7 @@ __host__ __device__ __forceinline__ int e2_newton(const double *w6, const double
     double scale = 0.0;
 #pragma unroll
     for (int k = 0; k < E2_NL; k++) scale += fabs(tg[k]);
+    double last = 1e300;   // largest exponent change of the last step
     for (int it = 1; it <= E2_MAXIT; it++) {
         double mom[E2_NL], J[E2_NL * (E2_NL + 1) / 2];
 #pragma unroll
@@ -210,9 +214,13 @@ __host__ __device__ __forceinline__ int e2_newton(const double *w6, const double
             rhs[k] = tg[k] - mom[k];
             res += fabs(rhs[k]);
         }
-        if (res <= 1e-14 * scale) return it;
+        // converged: moments within 1e-14 and the last step so small that the
+        // next would change nothing (the multipliers then sit at the
+        // round-off floor whatever the starting point)
+        if (res <= 1e-14 * scale && last <= 1e-8) return it;
         if (!e2_cholesky_solve(J, rhs)) return -1;
         double maxd = e2_maxchange(rhs, fabs(rhs[0]));
+        last = maxd;
         double damp = maxd > 2.0 ? 2.0 / maxd : 1.0;
 #pragma unroll
         for (int k = 0; k < E2_NL; k++) l[k] += damp * rhs[k];

@@ -36,13 +36,13 @@ template <typename S, typename A, int VAR, bool BOUNDED, bool REDUCE, int EQ>
 __global__ __launch_bounds__(WG) void k_lb(const S *__restrict__ src, S *__restrict__ dst,
                                            const S *__restrict__ gh, double *__restrict__ thR,
                                            double *__restrict__ that_, A *__restrict__ aux,
-                                           double *__restrict__ partial, Consts k)
+                                           double *__restrict__ partial, double *__restrict__ lmul, Consts k)
 {
     int s = blockIdx.x * WG + threadIdx.x;
     double red[5] = {0, 0, 0, 0, 0};
     if (s < k.ns) {
         double r;
-        Mom m = lb_site<S, A, VAR, BOUNDED, EQ>(s, src, dst, gh, thR, that_, aux, k, r);
+        Mom m = lb_site<S, A, VAR, BOUNDED, EQ>(s, src, dst, gh, thR, that_, aux, k, r, lmul);
         if (REDUCE) {
             red[0] = m.rho;
             red[1] = m.j[0];
@@ -302,10 +302,15 @@ template <typename S, bool BOUNDED, int EQ>
 __global__ __launch_bounds__(WG) void k_init(S *__restrict__ dst, S *__restrict__ gh, double *__restrict__ thR,
                                              const double *__restrict__ rho, const double *__restrict__ u,
                                              const double *__restrict__ thT, const double *__restrict__ thRin,
-                                             Consts k)
+                                             double *__restrict__ lmul, Consts k)
 {
     int s = blockIdx.x * WG + threadIdx.x;
-    if (s < k.ns) init_site<S, BOUNDED, EQ>(s, dst, gh, thR, rho, u, thT, thRin, k, (size_t)k.ns);
+    if (s < k.ns) {
+        init_site<S, BOUNDED, EQ>(s, dst, gh, thR, rho, u, thT, thRin, k, (size_t)k.ns);
+        // no warm start yet: the first step's Newton runs start from the Gaussian
+        if (EQ == PGK_E2 && lmul)
+            for (int i = 0; i < 2 * E2_NL; i++) lmul[(size_t)i * k.ns + s] = __builtin_nan("");
+    }
 }
 
 template <typename S, bool BOUNDED, bool REDUCE>
@@ -379,6 +384,7 @@ struct pgk_ctx {
     // carved from the aux buffer
     double *that_ = nullptr, *tmc = nullptr, *tmc2 = nullptr, *partial = nullptr, *totals = nullptr;
     void *aux = nullptr, *gh = nullptr;
+    double *lmul = nullptr;       // E2 only: Newton warm starts
     int nblk = 0;
     // kernel timing
     bool timing = false;
@@ -457,7 +463,7 @@ static bool grid_ok(const pgk_grid *g)
 // ghosts [2][41][4][nz*ny] (population type), tmc2[ns] f64
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static void aux_layout(const pgk_grid *g, size_t off[8])
+static void aux_layout(const pgk_grid *g, size_t off[9])
 {
     size_t ns = 2ull * g->nx * g->ny * g->nz;
     size_t elt = g->precision == PGK_FP64 ? 8 : 4;
@@ -470,6 +476,8 @@ static void aux_layout(const pgk_grid *g, size_t off[8])
     off[5] = off[4] + align256(8 * 8);
     off[6] = off[5] + align256(2ull * NQ * NSLOT * g->ny * g->nz * elt);
     off[7] = off[6] + align256(ns * 8);
+    // E2: the two multiplier sets of each site's last equilibria, [2 * E2_NL][ns]
+    off[8] = off[7] + (g->equilibrium == PGK_E2 ? align256(2ull * E2_NL * ns * 8) : 0);
 }
 
 extern "C" int pgk_buffer_sizes(const pgk_grid *g, size_t sizes[PGK_NBUF])
@@ -477,12 +485,12 @@ extern "C" int pgk_buffer_sizes(const pgk_grid *g, size_t sizes[PGK_NBUF])
     if (!grid_ok(g) || !sizes) return PGK_EINVAL;
     size_t ns = 2ull * g->nx * g->ny * g->nz;
     size_t elt = g->precision == PGK_FP64 ? 8 : 4;
-    size_t off[8];
+    size_t off[9];
     aux_layout(g, off);
     sizes[PGK_BUF_POP0] = NQ * ns * elt;
     sizes[PGK_BUF_POP1] = NQ * ns * elt;
     sizes[PGK_BUF_THETAR] = ns * 8;
-    sizes[PGK_BUF_AUX] = off[7];
+    sizes[PGK_BUF_AUX] = off[8];
     return PGK_OK;
 }
 
@@ -611,9 +619,10 @@ extern "C" int pgk_bind(pgk_ctx *c, void *const bufs[PGK_NBUF], const size_t byt
         c->buf[i] = bufs[i];
         c->bytes[i] = bytes[i];
     }
-    size_t off[8];
+    size_t off[9];
     aux_layout(&c->g, off);
     char *a = (char *)bufs[PGK_BUF_AUX];
+    c->lmul = c->g.equilibrium == PGK_E2 ? (double *)(a + off[7]) : nullptr;
     c->tmc2 = (double *)(a + off[6]);
     c->that_ = (double *)(a + off[0]);
     c->tmc = (double *)(a + off[1]);
@@ -733,10 +742,10 @@ static int init_t(pgk_ctx *c, const double *rho, const double *u, const double *
     S *dst = (S *)c->buf[c->cur];
     if (bounded(c))
         hipLaunchKernelGGL((k_init<S, true, EQ>), grid, block, 0, c->stream, dst, (S *)c->gh,
-                           (double *)c->buf[PGK_BUF_THETAR], rho, u, thT, thR, c->k);
+                           (double *)c->buf[PGK_BUF_THETAR], rho, u, thT, thR, c->lmul, c->k);
     else
         hipLaunchKernelGGL((k_init<S, false, EQ>), grid, block, 0, c->stream, dst, (S *)c->gh,
-                           (double *)c->buf[PGK_BUF_THETAR], rho, u, thT, thR, c->k);
+                           (double *)c->buf[PGK_BUF_THETAR], rho, u, thT, thR, c->lmul, c->k);
     HIPCHECK(c, hipGetLastError());
     return PGK_OK;
 }
@@ -773,7 +782,7 @@ static int step_t(pgk_ctx *c, int64_t n)
             mark(c, 3);
         }
         hipLaunchKernelGGL((k_lb<S, A, VAR, BND, false, EQ>), grid, block, 0, c->stream, src, dst, (const S *)c->gh,
-                           (double *)c->buf[PGK_BUF_THETAR], c->that_, (A *)c->aux, c->partial, c->k);
+                           (double *)c->buf[PGK_BUF_THETAR], c->that_, (A *)c->aux, c->partial, c->lmul, c->k);
         mark(c, 0);
         if (BND || c->k.nsub > 1) {
             // MacCormack, then the diffusion in nsub FTCS sub-steps (ping-pong
