@@ -44,10 +44,13 @@
  *     are arithmetic means.
  * Pins: see the oracle tests (lattice isotropy, Gaussian moments of F3 and
  * E2, exact conservation, CE decay rates, sound speed, Landau table, the
- * Couette start-up series and the thermal Couette profile of Sec. 6).
- * Parity unpinned: the interior profile of a normal shock (its end states,
- * through the jump conditions, and its conservation are pinned; the shape
- * between them has no reference outside this code).
+ * Couette start-up series and the thermal Couette profile of Sec. 6, the
+ * effective-delta sound speeds, the acoustic pulse against the Bessel
+ * integral, weak shocks against the Navier-Stokes weak-shock thickness).
+ * Parity unpinned: the interior profile of a strong normal shock (its end
+ * states, through the jump conditions, and its conservation are pinned, and
+ * so is the thickness in the weak-shock limit; the shape of a strong shock
+ * has no reference outside this code).
  */
 #include <math.h>
 #include <stdlib.h>

@@ -79,3 +79,44 @@ def acoustic_pulse(make, n=256, nz=1, steps=80, nu=0.002, eps=1e-3):
     sel = (np.abs(pos[1] - c) < 1e-9) & (pos[0] >= c) & (np.abs(pos[2]) < 1e-9)
     r = pos[0][sel] - c
     return r, pp[sel], np.array([pulse_exact(x, steps, eps, alpha, cs) for x in r])
+
+
+def moving_weak_shock(make_line, Ma, nu=0.05, L=2048, steps=2000, gamma=1.4, Pr=0.71, mub_over_mu=0.8, delta=2.0):
+    """A weak normal shock running into gas at rest (lab frame, flow speeds
+    small against the lattice speeds): the ideal-gas Rankine-Hugoniot states,
+    joined by a tanh of width 4 cells at 15% of an L-cell line between
+    Dirichlet faces, run `steps` steps.  Returns the density thickness
+    (rho2 - rho1)/max|drho/dx|, the front speed over the last quarter of the
+    run, and their weak-shock (Taylor) values: 8 D/((gamma+1) du) with the
+    sound diffusivity D = nu (4/3 + mu_b/mu + (gamma-1)/Pr), and the
+    upstream speed u1 of the shock frame."""
+    p = resolve(nu, Pr, mub_over_mu, delta)
+    co = coefficients(**p)
+    (r1, u1, t1), (r2, u2, t2) = inputs.rankine_hugoniot(Ma, gamma)
+    U2 = u1 - u2   # downstream gas speed behind the shock; the upstream gas is at rest
+    x = inputs.positions(L, 1, 1)[0]
+    sm = 0.5 * (1 + np.tanh((x - 0.15 * L) / 4.0))
+    f = inputs.uniform(L, 1, 1)
+    f["rho"] = r2 + (r1 - r2) * sm
+    f["u"][0] = U2 * (1 - sm)
+    f["thT"] = t2 + (t1 - t2) * sm
+    f["thR"] = f["thT"].copy()
+    run = make_line(L, p, f, (r2, (U2, 0.0, 0.0), t2), (r1, (0.0, 0.0, 0.0), t1))
+    order = np.argsort(x)
+    xs = x[order]
+
+    def front():
+        rs = run.moments()["rho"][order]
+        mid = 0.5 * (r1 + r2)
+        i = np.where((rs[:-1] - mid) * (rs[1:] - mid) <= 0)[0][-1]
+        pos = xs[i] + (mid - rs[i]) / (rs[i + 1] - rs[i]) * (xs[i + 1] - xs[i])
+        return pos, rs
+
+    n1 = (3 * steps) // 4
+    run.step(n1)
+    p1, _ = front()
+    run.step(steps - n1)
+    p2, rs = front()
+    thick = (r2 - r1) / np.abs(np.diff(rs) / np.diff(xs)).max()
+    D = nu * (4.0 / 3.0 + co["lam_b"] + (co["gamma"] - 1.0) / co["Pr"])
+    return thick, (p2 - p1) / (steps - n1), 8.0 * D / ((gamma + 1.0) * (u1 - u2)), u1

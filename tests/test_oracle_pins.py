@@ -604,3 +604,36 @@ def test_acoustic_pulse_matches_the_bessel_solution():
     assert np.linalg.norm(sim - ex) / np.linalg.norm(ex) < 0.015
     assert np.abs(sim - ex).max() < 0.01 * np.abs(ex).max()
     assert 50 < r[np.argmax(ex)] < 64 and abs(r[np.argmax(sim)] - r[np.argmax(ex)]) <= 1
+
+
+def _oracle_line(equilibrium):
+    def make(L, p, f, left, right):
+        o = oracle.Oracle(L, 1, 1, equilibrium=equilibrium)
+        o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+        o.set_bc_x(0, oracle.DIRICHLET, *left)
+        o.set_bc_x(1, oracle.DIRICHLET, *right)
+        o.init(f["rho"], f["u"], f["thT"], f["thR"])
+        return o
+    return make
+
+
+@pytest.mark.parametrize("Ma,tol", [(1.05, 0.03), (1.1, 0.05)])
+def test_weak_shock_has_the_taylor_thickness_and_the_jump_speed(Ma, tol):
+    # Weak-shock limit of the Navier-Stokes-Fourier equations (Burgers): a tanh
+    # profile of density thickness 8 D/((gamma+1) du), D the sound diffusivity
+    # whose Landau damping the acoustic pin checks; the O(Ma-1) correction is
+    # +1.1% at Mach 1.05 and +3.1% at Mach 1.1.  The front runs at the upstream
+    # speed of the Rankine-Hugoniot shock frame.
+    from tests import sec6
+    thick, speed, taylor, u1 = sec6.moving_weak_shock(_oracle_line(oracle.F3), Ma)
+    assert abs(thick / taylor - 1) < tol, (thick, taylor)
+    assert abs(speed / u1 - 1) < 2e-3, (speed, u1)
+
+
+@pytest.mark.slow
+def test_weak_shock_e2_equilibrium():
+    # the same at Mach 1.05 with the E2 equilibrium
+    from tests import sec6
+    thick, speed, taylor, u1 = sec6.moving_weak_shock(_oracle_line(oracle.E2), 1.05)
+    assert abs(thick / taylor - 1) < 0.03, (thick, taylor)
+    assert abs(speed / u1 - 1) < 2e-3, (speed, u1)

@@ -7,7 +7,9 @@ convergence for air, the axisymmetric acoustic pulse on the paper's
 256 x 256 x 4 grid against the linear-acoustics (Bessel) integral, and the
 two Couette flows between diffuse walls on 3D grids: the start-up of a shear
 flow against its series solution (on the paper's 64-by-128-by-8 grid, every
-column equal) and the steady thermal Couette profile with viscous heating.
+column equal), the steady thermal Couette profile with viscous heating, and
+weak shocks running into gas at rest against the Navier-Stokes (Taylor)
+weak-shock thickness and the Rankine-Hugoniot shock speed.
 """
 import numpy as np
 import pytest
@@ -123,3 +125,27 @@ def test_thermal_couette_profile_with_viscous_heating(precision, Pr, tol):
     print("thermal Couette Pr", Pr, np.abs((th - TH0) / dT - ta).max())
     assert np.abs((th - TH0) / dT - ta).max() < tol
     s.close()
+
+
+def _gpu_line(precision, equilibrium):
+    def make(L, p, f, left, right):
+        import paper_2201_05280_amd as pgk
+        s = pgk.Solver(L, 1, 1, precision=precision, bc_x=(pgk.DIRICHLET, pgk.DIRICHLET), equilibrium=equilibrium)
+        s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+        s.set_bc_x(0, *left)
+        s.set_bc_x(1, *right)
+        s.init(f["rho"], f["u"], f["thT"], f["thR"])
+        return s
+    return make
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("equilibrium", [0, 1])
+@pytest.mark.parametrize("Ma,tol", [(1.05, 0.03), (1.1, 0.06)])
+def test_weak_shock_has_the_taylor_thickness_and_the_jump_speed(precision, equilibrium, Ma, tol):
+    # measured excess over the weak-shock thickness: F3 +1.1% / +3.1%, E2
+    # +1.8% / +5.0% at Mach 1.05 / 1.1 (the correction grows with Ma - 1)
+    thick, speed, taylor, u1 = sec6.moving_weak_shock(_gpu_line(precision, equilibrium), Ma)
+    print("weak shock", Ma, "eq", equilibrium, "thickness", thick, "Taylor", taylor, "speed", speed, u1)
+    assert abs(thick / taylor - 1) < tol, (thick, taylor)
+    assert abs(speed / u1 - 1) < 2e-3, (speed, u1)
