@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "pgk_oracle.c")
 
 PERIODIC, WALL, DIRICHLET = 0, 1, 2
 CN, LIT = 0, 1
-F3, E2 = 0, 1
+F3, E2, F4 = 0, 1, 2
 THETA0 = 0.2948964908710633  # lattice reference temperature, Table of weights
 
 _lib = None
@@ -59,6 +59,7 @@ def lib():
         L.pgko_lattice.argtypes = [ctypes.c_double, dp, dp]
         L.pgko_feq_f3.argtypes = [ctypes.c_double, dp, dp, ctypes.c_double, dp, dp, dp]
         L.pgko_feq_e2.argtypes = [ctypes.c_double, dp, dp, ctypes.c_double, dp, dp, dp]
+        L.pgko_feq_f4.argtypes = [ctypes.c_double, dp, dp, ctypes.c_double, dp, dp, dp]
         L.pgko_feq_e2.restype = ctypes.c_int
         L.pgko_collide_site.argtypes = [vp, dp, ctypes.c_double, dp, dp]
         L.pgko_get_state.argtypes = [vp, dp, dp]
@@ -92,6 +93,15 @@ def feq_f3(rho, u, lam6, theta0=THETA0):
     c, w = lattice(theta0)
     F = np.zeros(41)
     lib().pgko_feq_f3(theta0, _p(w), _p(c), float(rho), _p(np.ascontiguousarray(u, dtype=np.float64)),
+                      _p(np.ascontiguousarray(lam6, dtype=np.float64)), _p(F))
+    return F
+
+
+def feq_f4(rho, u, lam6, theta0=THETA0):
+    """F3 plus the contracted fourth-order Hermite terms (exact contracted fourth moment)."""
+    c, w = lattice(theta0)
+    F = np.zeros(41)
+    lib().pgko_feq_f4(theta0, _p(w), _p(c), float(rho), _p(np.ascontiguousarray(u, dtype=np.float64)),
                       _p(np.ascontiguousarray(lam6, dtype=np.float64)), _p(F))
     return F
 

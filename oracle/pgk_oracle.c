@@ -37,7 +37,10 @@
  *     anisotropic Gaussian; E2: discrete exponential quasi-equilibrium
  *     w_i exp(alpha + beta.c_i + c_i.G.c_i) matching rho, rho u and the
  *     pressure tensor (E2 is not linear in the covariance, so its gain term
- *     mixes the ES and the Maxwellian E2 populations at their rates);
+ *     mixes the ES and the Maxwellian E2 populations at their rates); F4:
+ *     F3 plus contracted fourth-order Hermite terms that make the contracted
+ *     fourth moment sum F c^2 c_a c_b Gaussian for every state (also
+ *     nonlinear in the covariance, mixed like E2);
  *   - finite differences for E_R use the simple-cubic neighbours of the same
  *     sublattice (spacing 1);
  *   - kappa_R = k_r * 5 p tau / (2B) with the local p = rho theta; face values
@@ -64,7 +67,7 @@
 
 enum { BC_PERIODIC = 0, BC_WALL = 1, BC_DIRICHLET = 2 };
 enum { VAR_CN = 0, VAR_LIT = 1 };
-enum { EQ_F3 = 0, EQ_E2 = 1 };
+enum { EQ_F3 = 0, EQ_E2 = 1, EQ_F4 = 2 };
 
 /* ------------------------------------------------------------------------ */
 /* RD3Q41 velocity set (Table "weights"): doubled integer coordinates so the  */
@@ -213,6 +216,96 @@ static double inv3(double m[3][3], double r[3][3])
     return det;
 }
 
+/* F4: F3 plus contracted fourth-order Hermite terms, so that besides the
+ * moments F3 carries (orders 0 to 3) the contracted fourth moment
+ *   R_ab = sum_i F_i c_i^2 c_ia c_ib
+ * equals that of the Gaussian N(u, lam) for every state.  The lattice's
+ * weights are built so that the contracted moments of the Gaussian hold up
+ * to the eighth order (Sec. 5, the weight and theta0 conditions), which is
+ * what such a term needs.  The correction is w_i sum_ab K_ab h_ab(c_i) with
+ *   h_ab(c) = c_a c_b (c^2 - 7 theta0) - delta_ab theta0 (c^2 - 5 theta0),
+ * the contracted fourth-order Hermite polynomial of the weight w: it is
+ * orthogonal to 1 and to c_e c_f under w (and even in c), so it leaves the
+ * moments of orders 0 to 3 unchanged.  K follows from the 6 x 6 linear system
+ *   sum_i w_i (sum_ab K_ab h_ab(c_i)) c_i^2 c_ie c_if = R^G_ef - R^F3_ef,
+ * with R^G from Isserlis' theorem and R^F3 summed over the 41 velocities. */
+static double f4_h(const double *ci, int a, int b, double t)
+{
+    double c2 = ci[0] * ci[0] + ci[1] * ci[1] + ci[2] * ci[2];
+    return ci[a] * ci[b] * (c2 - 7.0 * t) - (a == b ? t * (c2 - 5.0 * t) : 0.0);
+}
+
+/* Gauss-Jordan elimination with partial pivoting on an n x n system (n <= 6) */
+static int solve_general(int n, double *A, double *x)
+{
+    for (int col = 0; col < n; col++) {
+        int piv = col;
+        for (int r = col + 1; r < n; r++)
+            if (fabs(A[r * n + col]) > fabs(A[piv * n + col])) piv = r;
+        if (!(fabs(A[piv * n + col]) > 0.0)) return -1;
+        if (piv != col) {
+            for (int k = 0; k < n; k++) {
+                double t = A[col * n + k]; A[col * n + k] = A[piv * n + k]; A[piv * n + k] = t;
+            }
+            double t = x[col]; x[col] = x[piv]; x[piv] = t;
+        }
+        for (int r = 0; r < n; r++) {
+            if (r == col) continue;
+            double f = A[r * n + col] / A[col * n + col];
+            for (int k = col; k < n; k++) A[r * n + k] -= f * A[col * n + k];
+            x[r] -= f * x[col];
+        }
+    }
+    for (int r = 0; r < n; r++) x[r] /= A[r * n + r];
+    return 0;
+}
+
+void pgko_feq_f4(double theta0, const double *w, const double *c, double rho,
+                 const double *u, const double *lam6, double *F)
+{
+    static const int IA[6] = {0, 1, 2, 0, 0, 1}, IB[6] = {0, 1, 2, 1, 2, 2};
+    pgko_feq_f3(theta0, w, c, rho, u, lam6, F);
+    double L[3][3];
+    sym_from6(lam6, L);
+    /* Gaussian: E[c^2 c_a c_b] for c ~ N(u, L) (Isserlis) */
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double trL = L[0][0] + L[1][1] + L[2][2];
+    double Lu[3], LL[3][3];
+    for (int a = 0; a < 3; a++) {
+        Lu[a] = L[a][0] * u[0] + L[a][1] * u[1] + L[a][2] * u[2];
+        for (int b = 0; b < 3; b++) LL[a][b] = L[a][0] * L[0][b] + L[a][1] * L[1][b] + L[a][2] * L[2][b];
+    }
+    double rhs[6], A[36];
+    for (int e = 0; e < 6; e++) {
+        int a = IA[e], b = IB[e];
+        double RG = uu * u[a] * u[b] + uu * L[a][b] + 2.0 * (u[a] * Lu[b] + Lu[a] * u[b]) + trL * u[a] * u[b]
+                  + trL * L[a][b] + 2.0 * LL[a][b];
+        double RF = 0.0;
+        for (int i = 0; i < NQ; i++) {
+            const double *ci = c + 3 * i;
+            RF += F[i] * (ci[0] * ci[0] + ci[1] * ci[1] + ci[2] * ci[2]) * ci[a] * ci[b];
+        }
+        rhs[e] = rho * RG - RF;
+        /* column j: basis h_xx, h_yy, h_zz, h_xy + h_yx, h_xz + h_zx, h_yz + h_zy */
+        for (int j = 0; j < 6; j++) {
+            double m = 0.0;
+            for (int i = 0; i < NQ; i++) {
+                const double *ci = c + 3 * i;
+                double g = (j < 3 ? 1.0 : 2.0) * f4_h(ci, IA[j], IB[j], theta0);
+                m += w[i] * g * (ci[0] * ci[0] + ci[1] * ci[1] + ci[2] * ci[2]) * ci[a] * ci[b];
+            }
+            A[e * 6 + j] = m;
+        }
+    }
+    solve_general(6, A, rhs);   /* rhs -> K (xx yy zz xy xz yz) */
+    for (int i = 0; i < NQ; i++) {
+        const double *ci = c + 3 * i;
+        double corr = 0.0;
+        for (int j = 0; j < 6; j++) corr += (j < 3 ? 1.0 : 2.0) * rhs[j] * f4_h(ci, IA[j], IB[j], theta0);
+        F[i] += w[i] * corr;
+    }
+}
+
 /* E2: discrete quasi-equilibrium, the lattice analogue of the minimiser of
  * H under fixed rho, rho u and pressure tensor (Sec. 2, quasi-equilibrium):
  *   F_i = w_i exp(alpha + beta.c_i + c_i.G.c_i)
@@ -338,6 +431,7 @@ pgko *pgko_create(int nx, int ny, int nz, int variant, int equilibrium)
     pgko *o = (pgko *)calloc(1, sizeof(pgko));
     o->nx = nx; o->ny = ny; o->nz = nz;
     o->ns = 2 * nx * ny * nz;
+    if (equilibrium < EQ_F3 || equilibrium > EQ_F4) { free(o); return NULL; }
     o->variant = variant; o->eq = equilibrium;
     int shell[NQ];
     build_velocities(o->c2, shell);
@@ -417,7 +511,8 @@ static int equilibrium(const pgko *o, double rho, const double *u, const double 
         int it = pgko_feq_e2(o->th0, o->w, &o->c[0][0], rho, u, lam6, F);
         return it > 0 ? 0 : -1;
     }
-    pgko_feq_f3(o->th0, o->w, &o->c[0][0], rho, u, lam6, F);
+    if (o->eq == EQ_F4) pgko_feq_f4(o->th0, o->w, &o->c[0][0], rho, u, lam6, F);
+    else pgko_feq_f3(o->th0, o->w, &o->c[0][0], rho, u, lam6, F);
     return 0;
 }
 
@@ -536,6 +631,10 @@ static void dirichlet_equilibrium(const pgko *o, int side, double *Fd)
     double tmp[NQ];
     if (o->eq == EQ_E2 && pgko_feq_e2(o->th0, o->w, &o->c[0][0], o->bc_rho[side], o->bc_u[side], lam, tmp) > 0) {
         memcpy(Fd, tmp, sizeof(tmp));
+        return;
+    }
+    if (o->eq == EQ_F4) {
+        pgko_feq_f4(o->th0, o->w, &o->c[0][0], o->bc_rho[side], o->bc_u[side], lam, Fd);
         return;
     }
     pgko_feq_f3(o->th0, o->w, &o->c[0][0], o->bc_rho[side], o->bc_u[side], lam, Fd);

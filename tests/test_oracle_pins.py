@@ -637,3 +637,72 @@ def test_weak_shock_e2_equilibrium():
     thick, speed, taylor, u1 = sec6.moving_weak_shock(_oracle_line(oracle.E2), 1.05)
     assert abs(thick / taylor - 1) < 0.03, (thick, taylor)
     assert abs(speed / u1 - 1) < 2e-3, (speed, u1)
+
+
+# ----------------------------------------------------------------------------
+# F4: contracted fourth-order Hermite terms
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(5))
+def test_f4_keeps_the_f3_moments_and_makes_the_contracted_fourth_gaussian(seed):
+    rng = np.random.default_rng(300 + seed)
+    rho, u, L = _random_state(rng, du=0.12, dl=0.12)
+    F4 = oracle.feq_f4(rho, u, lam6(L))
+    F3 = oracle.feq_f3(rho, u, lam6(L))
+    c, _ = oracle.lattice()
+    c2 = (c ** 2).sum(1)
+    # orders 0 to 3 untouched
+    assert abs(F4.sum() - F3.sum()) < 1e-15
+    assert np.abs((F4 - F3) @ c).max() < 1e-15
+    assert np.abs(np.einsum("i,ia,ib->ab", F4 - F3, c, c)).max() < 1e-15
+    assert np.abs(np.einsum("i,ia,ib,ic->abc", F4 - F3, c, c, c)).max() < 1e-15
+    # sum F c^2 c_a c_b equals the Gaussian's (Isserlis); F3 misses it at O(D^2, u^2 D, u^4)
+    miss3 = 0.0
+    for a in range(3):
+        for b in range(3):
+            ref = rho * sum(gauss_moment((a, b, e, e), u, L) for e in range(3))
+            assert abs((F4 * c2 * c[:, a] * c[:, b]).sum() - ref) < 1e-15
+            miss3 = max(miss3, abs((F3 * c2 * c[:, a] * c[:, b]).sum() - ref))
+    assert miss3 > 1e-4
+
+
+def test_f4_equals_f3_at_the_reference_state():
+    # at u = 0, lam = theta0 I the Gaussian's contracted fourth moment is the weights' own
+    c, w = oracle.lattice()
+    F = oracle.feq_f4(1.1, np.zeros(3), lam6(TH0 * np.eye(3)))
+    assert np.allclose(F, 1.1 * w, rtol=0, atol=1e-15)
+
+
+def _thermal_rate(ratio, equilibrium):
+    th = ratio * TH0
+    p = resolve(0.01, 0.71, 0.6, 2.0)
+    co = coefficients(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"], theta0=th)
+    nx = 64
+    k = 2 * np.pi / nx
+    x = inputs.positions(nx, 1, 1)[0]
+    f = inputs.temperature_wave(nx, 1, 1, eps=1e-4, theta=th)
+    f["rho"] = 1.0 / (1.0 + 1e-4 * np.cos(k * x))      # uniform pressure about the mean state
+    o = oracle.Oracle(nx, 1, 1, equilibrium=equilibrium)
+    o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    o.init(f["rho"], f["u"], f["thT"], f["thR"])
+    C = np.cos(k * x)
+    d = p["delta"]
+    out = []
+    for n in range(2001):
+        m = o.moments()
+        out.append(2 * np.mean((3 * m["thT"] + d * m["thR"]) / (3 + d) * C))
+        if n < 2000:
+            o.step(1)
+    t = np.arange(len(out))
+    rate = -np.polyfit(t[300:], np.log(np.abs(out[300:])), 1)[0]
+    return rate / (co["alpha"] * k * k)
+
+
+@pytest.mark.parametrize("ratio", [0.8, 1.2, 1.4])
+def test_f4_conducts_heat_at_kappa_over_rho_cp_off_theta0(ratio):
+    # Chapman-Enskog: the heat flux follows the temperature derivative of the
+    # equilibrium's contracted fourth moment.  F3 carries it at theta0 only
+    # (its R grows like theta0 theta instead of theta^2), so a thermal wave about
+    # a mean temperature theta decays at about theta0/theta times alpha k^2;
+    # with F4 it decays at alpha(theta) k^2
+    assert abs(_thermal_rate(ratio, oracle.F4) - 1) < 0.01
+    assert abs(_thermal_rate(ratio, oracle.F3) - 1) > 0.1
