@@ -73,6 +73,17 @@ extern "C" {
                                 Diffuse walls re-emit F3 in either case; Dirichlet faces take
                                 E2 (pgk_set_bc_x returns PGK_EINFEASIBLE if the face state
                                 has none) */
+#define PGK_F4   2           /* F3 plus the contracted fourth-order Hermite terms
+                                w_i sum_ab K_ab h_ab(c_i), h_ab(c) = c_a c_b (c^2 - 7 theta0)
+                                - delta_ab theta0 (c^2 - 5 theta0): moments of orders 0 to 3
+                                as F3, and the contracted fourth moment sum F c^2 c_a c_b
+                                of the Gaussian N(u, lam) for every state (the lattice's
+                                weights satisfy the contracted moment conditions this needs,
+                                Sec. 5), so heat conducts at kappa/(rho c_p) at any
+                                temperature, not only near theta0.  Not linear in lam: the
+                                gain term mixes F4(lam_ES) and F4(theta I) at their rates.
+                                Walls re-emit F3, Dirichlet faces take F4.  Single grid only
+                                (not in the batched sweep) */
 
 /* boundary kinds of the two x faces (y and z are periodic) */
 #define PGK_PERIODIC   0
@@ -95,7 +106,7 @@ typedef struct {
     int nx, ny, nz;          /* cells per axis, each >= 1 */
     int precision;           /* PGK_FP64 | PGK_FP32DEV */
     int variant;             /* PGK_CN | PGK_LIT */
-    int equilibrium;         /* PGK_F3 | PGK_E2 */
+    int equilibrium;         /* PGK_F3 | PGK_E2 | PGK_F4 */
     int bc_x[2];             /* kind of the low and high x faces */
 } pgk_grid;
 
@@ -142,7 +153,7 @@ int pgk_resolve(const pgk_targets *t, pgk_resolved *out);
 int pgk_lattice(double theta0, double *c, double *w);
 
 /* Populations F[41] (library order) of the discrete equilibrium `equilibrium`
- * (PGK_F3 or PGK_E2) with density rho, velocity u[3] and covariance lam[6]
+ * (PGK_F3, PGK_E2 or PGK_F4) with density rho, velocity u[3] and covariance lam[6]
  * (xx yy zz xy xz yz), reference temperature theta0 (0 = printed).  The same
  * host code fills the Dirichlet face ghosts.  Returns PGK_EINFEASIBLE when E2
  * has no solution, PGK_EINVAL for rho <= 0 or an unknown kind.  Host memory,

@@ -17,6 +17,7 @@ FP64, FP32DEV = 0, 1
 CN, LIT = 0, 1
 F3 = 0
 E2 = 1
+F4 = 2
 PERIODIC, WALL, DIRICHLET = 0, 1, 2
 NBUF = 4
 
@@ -148,8 +149,8 @@ def lattice(theta0=0.0):
 
 
 def equilibrium(kind, rho, u, lam6, theta0=0.0):
-    """Populations F[41] (library order) of the F3 or E2 equilibrium (host only);
-    raises ValueError when E2 has no solution."""
+    """Populations F[41] (library order) of the F3, E2 or F4 equilibrium (host
+    only); raises ValueError when E2 has no solution."""
     import numpy as np
     L = load()
     P = ctypes.POINTER(ctypes.c_double)
@@ -160,7 +161,7 @@ def equilibrium(kind, rho, u, lam6, theta0=0.0):
                            lam.ctypes.data_as(P), F.ctypes.data_as(P))
     if rc != PGK_OK:
         raise ValueError("no %s equilibrium for rho=%g u=%s lam=%s (%s)"
-                         % ("E2" if kind == E2 else "F3", rho, list(u), list(lam), ERRORS.get(rc, rc)))
+                         % ({E2: "E2", F4: "F4"}.get(kind, "F3"), rho, list(u), list(lam), ERRORS.get(rc, rc)))
     return F
 
 

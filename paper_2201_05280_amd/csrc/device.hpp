@@ -38,7 +38,32 @@ struct Consts {
     double it, i2t, ih2, i6t3, i2t3, it2;  // 1/t, 1/(2t), 1/(2t^2), 1/(6t^3), 1/(2t^3), 1/t^2 with t = theta0
     int nsub;                     // FTCS sub-steps of the theta_R diffusion per step
     double isub;                  // 1/nsub
+    double f4inv[36];             // F4: inverse of the lattice map K -> contracted fourth moment
 };
+
+// F4 coefficients K (xx yy zz xy xz yz) of the target (rho, u, lam): the
+// contracted fourth moment of the Gaussian N(u, lam) less that of F3,
+//   rho [tr E E + 2 E E - 2 u^2 u u],  E = u u + lam - theta0 I,
+// mapped through the inverse lattice matrix (the correction's own moment).
+__host__ __device__ __forceinline__ void f4_coeffs(const double *inv, double th0, double rho, const double *u,
+                                                   const double *lam, double *K)
+{
+    double E[6] = {u[0] * u[0] + lam[0] - th0, u[1] * u[1] + lam[1] - th0, u[2] * u[2] + lam[2] - th0,
+                   u[0] * u[1] + lam[3],       u[0] * u[2] + lam[4],       u[1] * u[2] + lam[5]};
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double tr = E[0] + E[1] + E[2];
+    double EE[6] = {E[0] * E[0] + E[3] * E[3] + E[4] * E[4], E[3] * E[3] + E[1] * E[1] + E[5] * E[5],
+                    E[4] * E[4] + E[5] * E[5] + E[2] * E[2], E[0] * E[3] + E[3] * E[1] + E[4] * E[5],
+                    E[0] * E[4] + E[3] * E[5] + E[4] * E[2], E[3] * E[4] + E[1] * E[5] + E[5] * E[2]};
+    double uiuj[6] = {u[0] * u[0], u[1] * u[1], u[2] * u[2], u[0] * u[1], u[0] * u[2], u[1] * u[2]};
+    double d[6];
+    for (int i = 0; i < 6; i++) d[i] = rho * (tr * E[i] + 2.0 * EE[i] - 2.0 * uu * uiuj[i]);
+    for (int i = 0; i < 6; i++) {
+        double t = 0.0;
+        for (int j = 0; j < 6; j++) t += inv[i * 6 + j] * d[j];
+        K[i] = t;
+    }
+}
 
 // Sub-steps that keep the explicit (FTCS) diffusion of theta_R stable: it
 // needs 2 dim D_R dt <= dx^2, D_R = 2 kappa_R/(rho delta) = 5 k_r theta tau/(B delta),
@@ -297,7 +322,20 @@ struct Eq {
     R k5;               // 1/theta0^2
     R rho, drho;        // rho, rho - 1
     R omb, tb;          // 1 - 2 beta, 2 beta
+    // F4 only: correction w [cKc (c^2 - 7 theta0) - q1 c^2 + q0]
+    R K0, K1, K2, K3, K4, K5;
+    R t7, q1, q0;       // 7 theta0, theta0 tr K, 5 theta0^2 tr K
 };
+
+template <typename R>
+__device__ __forceinline__ void set_f4(Eq<R> &e, const double *K, const Consts &k)
+{
+    double trK = K[0] + K[1] + K[2];
+    e.K0 = (R)K[0]; e.K1 = (R)K[1]; e.K2 = (R)K[2]; e.K3 = (R)K[3]; e.K4 = (R)K[4]; e.K5 = (R)K[5];
+    e.t7 = (R)(7.0 * k.th0);
+    e.q1 = (R)(k.th0 * trK);
+    e.q0 = (R)(5.0 * k.th0 * k.th0 * trK);
+}
 
 template <typename R>
 __device__ __forceinline__ Eq<R> make_eq(const Solve &s, const Consts &k)
@@ -327,7 +365,8 @@ __device__ __forceinline__ Eq<R> make_eq(const Solve &s, const Consts &k)
 }
 
 // Collide the pair (+c_P, -c_P) and the rest population, write the own site.
-template <typename S, int P = 0>
+// F4: the even correction of the contracted fourth-order terms is added.
+template <typename S, bool F4 = false, int P = 0>
 __device__ __forceinline__ void collide_store(S *v, const Eq<S> &e, const Consts &k, S *__restrict__ dst, int s)
 {
     if constexpr (P < NPAIR) {
@@ -339,6 +378,13 @@ __device__ __forceinline__ void collide_store(S *v, const Eq<S> &e, const Consts
         S cDu = hx * e.Du0 + hy * e.Du1 + hz * e.Du2;
         S even = (cu * cu + cDc) * e.k2 - e.k0;
         S odd = cu * e.A1 + cu * cu * cu * e.k3 + cDc * cu * e.k4 - cDu * e.k5;
+        S corr = (S)0;
+        if constexpr (F4) {
+            constexpr S cc = hx * hx + hy * hy + hz * hz;
+            S cKc = hx * hx * e.K0 + hy * hy * e.K1 + hz * hz * e.K2
+                  + (S)2 * (hx * hy * e.K3 + hx * hz * e.K4 + hy * hz * e.K5);
+            corr = cKc * (cc - e.t7) - e.q1 * cc + e.q0;
+        }
         if constexpr (sizeof(S) == 4) {
             // deviation form: F - w = w [(rho - 1) + rho (even +- odd)], with w
             // carried as hi + lo floats so the rounding of w adds no bias to the
@@ -346,6 +392,10 @@ __device__ __forceinline__ void collide_store(S *v, const Eq<S> &e, const Consts
             // the collision whatever the rounding of 2 beta
             S wh = k.whi[Lattice::SHELL[P]], wl = k.wlo[Lattice::SHELL[P]];
             S Xp = e.drho + e.rho * (even + odd), Xm = e.drho + e.rho * (even - odd);
+            if constexpr (F4) {
+                Xp += corr;
+                Xm += corr;
+            }
             S Fp = wh * Xp + wl * Xp, Fm = wh * Xm + wl * Xm;
             // the next read of these values is a step away: stream them past the caches
             __builtin_nontemporal_store(v[1 + P] + e.tb * (Fp - v[1 + P]), &dst[(size_t)(1 + P) * k.ns + s]);
@@ -353,20 +403,30 @@ __device__ __forceinline__ void collide_store(S *v, const Eq<S> &e, const Consts
                                         &dst[(size_t)(1 + NPAIR + P) * k.ns + s]);
         } else {
             S w = (S)k.w[Lattice::SHELL[P]];
-            S Fp = w * e.rho * ((S)1 + even + odd);
-            S Fm = w * e.rho * ((S)1 + even - odd);
+            S Fp, Fm;
+            if constexpr (F4) {
+                Fp = w * (e.rho * ((S)1 + even + odd) + corr);
+                Fm = w * (e.rho * ((S)1 + even - odd) + corr);
+            } else {
+                Fp = w * e.rho * ((S)1 + even + odd);
+                Fm = w * e.rho * ((S)1 + even - odd);
+            }
             __builtin_nontemporal_store(e.omb * v[1 + P] + e.tb * Fp, &dst[(size_t)(1 + P) * k.ns + s]);
             __builtin_nontemporal_store(e.omb * v[1 + NPAIR + P] + e.tb * Fm, &dst[(size_t)(1 + NPAIR + P) * k.ns + s]);
         }
-        collide_store<S, P + 1>(v, e, k, dst, s);
+        collide_store<S, F4, P + 1>(v, e, k, dst, s);
     } else {
         if constexpr (sizeof(S) == 4) {
             S X0 = e.drho - e.rho * e.k0;
+            if constexpr (F4) X0 += e.q0;
             S F0 = k.whi[0] * X0 + k.wlo[0] * X0;
             __builtin_nontemporal_store(v[0] + e.tb * (F0 - v[0]), &dst[s]);
         } else {
             S w0 = (S)k.w[0];
-            __builtin_nontemporal_store(e.omb * v[0] + e.tb * (w0 * e.rho * ((S)1 - e.k0)), &dst[s]);
+            S F0;
+            if constexpr (F4) F0 = w0 * (e.rho * ((S)1 - e.k0) + e.q0);
+            else F0 = w0 * e.rho * ((S)1 - e.k0);
+            __builtin_nontemporal_store(e.omb * v[0] + e.tb * F0, &dst[s]);
         }
     }
 }
@@ -496,6 +556,21 @@ __device__ __forceinline__ Mom lb_site(int s, const S *__restrict__ src, S *__re
             e2_site(so.rho, so.u, lmb, k, l2);
         }
         collide_store_e2<S>(v, l1, l2, k, dst, s);
+    } else if constexpr (EQ == PGK_F4) {
+        // the F3 part is linear in the covariance (lam_F); the fourth-order
+        // coefficients mix those of the two targets at their rates
+        double les[6], lmb[6], K1[6], K2[6], K[6];
+        double cb = k.bs / so.rho;
+        for (int i = 0; i < 6; i++) {
+            les[i] = (i < 3 ? so.T : 0.0) + cb * so.sg[i];
+            lmb[i] = i < 3 ? so.theta : 0.0;
+        }
+        f4_coeffs(k.f4inv, k.th0, so.rho, so.u, les, K1);
+        f4_coeffs(k.f4inv, k.th0, so.rho, so.u, lmb, K2);
+        for (int i = 0; i < 6; i++) K[i] = k.wt1 * K1[i] + k.wt * K2[i];
+        Eq<S> e = make_eq<S>(so, k);
+        set_f4(e, K, k);
+        collide_store<S, true>(v, e, k, dst, s);
     } else {
         Eq<S> e = make_eq<S>(so, k);
         collide_store<S>(v, e, k, dst, s);
@@ -673,8 +748,10 @@ __device__ __forceinline__ void init_site(int s, S *__restrict__ dst, S *__restr
     so.u[2] = u[2 * ustride + s];
     for (int i = 0; i < 6; i++) so.lamF[i] = i < 3 ? thT[s] : 0.0;
     Eq<double> e = make_eq<double>(so, k);
-    double l[E2_NL];
+    double l[E2_NL], K[6] = {0, 0, 0, 0, 0, 0};
     if constexpr (EQ == PGK_E2) e2_site(so.rho, so.u, so.lamF, k, l);
+    if constexpr (EQ == PGK_F4) f4_coeffs(k.f4inv, k.th0, so.rho, so.u, so.lamF, K);
+    double trK = K[0] + K[1] + K[2];
     thR[s] = thRin[s];
     for (int q = 0; q < NQ; q++) {
         int cx = c2(q, 0), cy = c2(q, 1), cz = c2(q, 2);
@@ -691,8 +768,22 @@ __device__ __forceinline__ void init_site(int s, S *__restrict__ dst, S *__restr
             double cDu = hx * e.Du0 + hy * e.Du1 + hz * e.Du2;
             double even = (cu * cu + cDc) * e.k2 - e.k0;
             double odd = cu * e.A1 + cu * cu * cu * e.k3 + cDc * cu * e.k4 - cDu * e.k5;
-            double F = w * e.rho * (1.0 + even + odd);
-            val = (S)(sizeof(S) == 4 ? w * (e.drho + e.rho * (even + odd)) : F);
+            double corr = 0.0;
+            if constexpr (EQ == PGK_F4) {
+                double cc = hx * hx + hy * hy + hz * hz;
+                double cKc = hx * hx * K[0] + hy * hy * K[1] + hz * hz * K[2] +
+                             2.0 * (hx * hy * K[3] + hx * hz * K[4] + hy * hz * K[5]);
+                corr = cKc * (cc - 7.0 * k.th0) - k.th0 * trK * (cc - 5.0 * k.th0);
+            }
+            double F, X;
+            if constexpr (EQ == PGK_F4) {
+                F = w * (e.rho * (1.0 + even + odd) + corr);
+                X = w * (e.drho + e.rho * (even + odd) + corr);
+            } else {
+                F = w * e.rho * (1.0 + even + odd);
+                X = w * (e.drho + e.rho * (even + odd));
+            }
+            val = (S)(sizeof(S) == 4 ? X : F);
         }
         // destination: position x - c_q
         int qx = 2 * x + sub - cx, qy = 2 * y + sub - cy, qz = 2 * z + sub - cz;

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include <type_traits>
+#include <utility>
 
 #include "device.hpp"
 
@@ -450,7 +451,7 @@ static bool grid_ok(const pgk_grid *g)
     if ((long long)g->nx * g->ny * g->nz * 2 > (long long)INT_MAX) return false;  // site ids are int
     if (g->precision != PGK_FP64 && g->precision != PGK_FP32DEV) return false;
     if (g->variant != PGK_CN && g->variant != PGK_LIT) return false;
-    if (g->equilibrium != PGK_F3 && g->equilibrium != PGK_E2) return false;
+    if (g->equilibrium != PGK_F3 && g->equilibrium != PGK_E2 && g->equilibrium != PGK_F4) return false;
     for (int s = 0; s < 2; s++)
         if (g->bc_x[s] < PGK_PERIODIC || g->bc_x[s] > PGK_DIRICHLET) return false;
     if ((g->bc_x[0] == PGK_PERIODIC) != (g->bc_x[1] == PGK_PERIODIC)) return false;
@@ -517,6 +518,69 @@ static void f3_host_lam(double th0, const double w6[6], double rho, const double
     }
 }
 
+// F4 correction basis at velocity c: h_xx, h_yy, h_zz, then h_ab + h_ba for
+// xy, xz, yz, with h_ab(c) = c_a c_b (c^2 - 7 theta0) - delta_ab theta0 (c^2 - 5 theta0)
+static double f4_basis(int j, const double c[3], double th0)
+{
+    static const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+    double cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+    double h = c[ia[j]] * c[ib[j]] * (cc - 7.0 * th0) - (ia[j] == ib[j] ? th0 * (cc - 5.0 * th0) : 0.0);
+    return j < 3 ? h : 2.0 * h;
+}
+
+// Inverse of the 6 x 6 lattice matrix M[e][j] = sum_q w_q basis_j(c_q) c_q^2 c_qa c_qb
+// (e = ab in xx yy zz xy xz yz order): maps the wanted change of the
+// contracted fourth moment to the correction coefficients K.  False if singular.
+static bool f4_matrix(double th0, const double w6[6], double inv[36])
+{
+    static const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+    double M[6][12];
+    for (int e = 0; e < 6; e++) {
+        for (int j = 0; j < 6; j++) {
+            double m = 0.0;
+            for (int q = 0; q < NQ; q++) {
+                double c[3] = {0.5 * c2(q, 0), 0.5 * c2(q, 1), 0.5 * c2(q, 2)};
+                double cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+                m += w6[shell_of(q)] * f4_basis(j, c, th0) * cc * c[ia[e]] * c[ib[e]];
+            }
+            M[e][j] = m;
+            M[e][6 + j] = e == j ? 1.0 : 0.0;
+        }
+    }
+    for (int col = 0; col < 6; col++) {   // Gauss-Jordan with partial pivoting
+        int piv = col;
+        for (int r = col + 1; r < 6; r++)
+            if (std::fabs(M[r][col]) > std::fabs(M[piv][col])) piv = r;
+        if (!(std::fabs(M[piv][col]) > 1e-300)) return false;
+        if (piv != col)
+            for (int t = 0; t < 12; t++) std::swap(M[col][t], M[piv][t]);
+        double d = 1.0 / M[col][col];
+        for (int t = 0; t < 12; t++) M[col][t] *= d;
+        for (int r = 0; r < 6; r++) {
+            if (r == col) continue;
+            double f = M[r][col];
+            for (int t = 0; t < 12; t++) M[r][t] -= f * M[col][t];
+        }
+    }
+    for (int e = 0; e < 6; e++)
+        for (int j = 0; j < 6; j++) inv[e * 6 + j] = M[e][6 + j];
+    return true;
+}
+
+// F4 on the host: F3 plus the correction of the target (rho, u, lam)
+static void f4_host_lam(double th0, const double w6[6], const double inv[36], double rho, const double u[3],
+                        const double lam[6], double F[NQ])
+{
+    f3_host_lam(th0, w6, rho, u, lam, F);
+    double K[6];
+    f4_coeffs(inv, th0, rho, u, lam, K);
+    for (int q = 0; q < NQ; q++) {
+        double c[3] = {0.5 * c2(q, 0), 0.5 * c2(q, 1), 0.5 * c2(q, 2)}, corr = 0.0;
+        for (int j = 0; j < 6; j++) corr += K[j] * f4_basis(j, c, th0);
+        F[q] += w6[shell_of(q)] * corr;
+    }
+}
+
 extern "C" int pgk_lattice(double theta0, double *c, double *w)
 {
     if (!c || !w) return PGK_EINVAL;
@@ -537,6 +601,12 @@ extern "C" int pgk_equilibrium(int equilibrium, double theta0, double rho, const
     shell_weights(th0, w6);
     if (equilibrium == PGK_F3) {
         f3_host_lam(th0, w6, rho, u, lam, F);
+        return PGK_OK;
+    }
+    if (equilibrium == PGK_F4) {
+        double inv[36];
+        if (!f4_matrix(th0, w6, inv)) return PGK_EINVAL;
+        f4_host_lam(th0, w6, inv, rho, u, lam, F);
         return PGK_OK;
     }
     if (equilibrium != PGK_E2) return PGK_EINVAL;
@@ -652,6 +722,9 @@ static int fill_bc(pgk_ctx *c)
             if (e2_solve(k.th0, k.w, rho, c->bc_u[side], lam, l) < 0)
                 return fail(c, PGK_EINFEASIBLE, "the Dirichlet face state has no E2 equilibrium on the lattice");
             for (int q = 0; q < NQ; q++) k.Fbc[side][q] = e2_population(l, k.w, q);
+        } else if (k.bc[side] == PGK_DIRICHLET && c->g.equilibrium == PGK_F4) {
+            double th = k.thbc[side], lam[6] = {th, th, th, 0.0, 0.0, 0.0};
+            f4_host_lam(k.th0, k.w, k.f4inv, rho, c->bc_u[side], lam, k.Fbc[side]);
         } else {
             f3_host(k.th0, k.w, rho, c->bc_u[side], k.thbc[side], k.Fbc[side]);
         }
@@ -682,6 +755,7 @@ extern "C" int pgk_set_params(pgk_ctx *c, const pgk_params *p, pgk_resolved *out
         k.whi[i] = (float)k.w[i];
         k.wlo[i] = (float)(k.w[i] - (double)k.whi[i]);
     }
+    if (!f4_matrix(k.th0, k.w, k.f4inv)) return fail(c, PGK_EINVAL, "F4 lattice matrix is singular");
     k.tau = p->tau; k.tau1 = p->tau1; k.b = p->b; k.delta = p->delta;
     double taus = p->tau * p->tau1 / (p->tau + p->tau1);
     double B = 1.0 + p->tau / p->tau1;
@@ -761,10 +835,15 @@ extern "C" int pgk_init_fields(pgk_ctx *c, const double *rho, const double *u, c
             return fail(c, PGK_EINVAL, "x face state not set (pgk_set_bc_x)");
     c->cur = 0;
     c->steps = 0;
-    bool e2 = c->g.equilibrium == PGK_E2;
-    int rc = c->g.precision == PGK_FP64
-                 ? (e2 ? init_t<double, PGK_E2>(c, rho, u, thT, thR) : init_t<double, PGK_F3>(c, rho, u, thT, thR))
-                 : (e2 ? init_t<float, PGK_E2>(c, rho, u, thT, thR) : init_t<float, PGK_F3>(c, rho, u, thT, thR));
+    int eq = c->g.equilibrium, rc;
+    if (c->g.precision == PGK_FP64)
+        rc = eq == PGK_E2 ? init_t<double, PGK_E2>(c, rho, u, thT, thR)
+           : eq == PGK_F4 ? init_t<double, PGK_F4>(c, rho, u, thT, thR)
+                          : init_t<double, PGK_F3>(c, rho, u, thT, thR);
+    else
+        rc = eq == PGK_E2 ? init_t<float, PGK_E2>(c, rho, u, thT, thR)
+           : eq == PGK_F4 ? init_t<float, PGK_F4>(c, rho, u, thT, thR)
+                          : init_t<float, PGK_F3>(c, rho, u, thT, thR);
     if (rc == PGK_OK) c->initialised = true;
     return rc;
 }
@@ -827,6 +906,8 @@ static StepFn step_fn(const pgk_ctx *c)
 {
     if (c->g.equilibrium == PGK_E2)
         return c->g.precision == PGK_FP64 ? step_fn_v<double, double, PGK_E2>(c) : step_fn_v<float, float, PGK_E2>(c);
+    if (c->g.equilibrium == PGK_F4)
+        return c->g.precision == PGK_FP64 ? step_fn_v<double, double, PGK_F4>(c) : step_fn_v<float, float, PGK_F4>(c);
     return c->g.precision == PGK_FP64 ? step_fn_v<double, double, PGK_F3>(c) : step_fn_v<float, float, PGK_F3>(c);
 }
 

@@ -32,6 +32,9 @@ def test_library_equilibria_equal_the_oracles(seed):
         F3o = oracle.feq_f3(rho, u, lam)
         F3 = _lib.equilibrium(_lib.F3, rho, u, lam)
         assert np.abs(F3 - F3o[idx]).max() <= 1e-13 * np.abs(F3o).max()
+        F4o = oracle.feq_f4(rho, u, lam)
+        F4 = _lib.equilibrium(_lib.F4, rho, u, lam)
+        assert np.abs(F4 - F4o[idx]).max() <= 1e-13 * np.abs(F4o).max()
 
 
 def test_e2_refuses_a_state_off_the_lattice():

@@ -1,0 +1,98 @@
+"""The F4 equilibrium on the HIP path (GPU only): parity with the oracle's F4
+element by element on the moments (FP64 1e-12, FP32 deviation storage 1e-5)
+on periodic 3D fields, between diffuse walls and between Dirichlet faces, and
+heat conduction at alpha(theta) k^2 for a thermal wave about 1.3 theta0 (where
+F3 is about 20% off)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.params import coefficients, resolve
+from paper_2201_05280_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FLOOR = dict(rho=0.0, u=1e-2, thT=0.0, thR=0.0, P=0.0)
+
+
+def _pair(nx, ny, nz, f, p, precision, bc=None):
+    import paper_2201_05280_amd as pgk
+    kinds = (pgk.PERIODIC, pgk.PERIODIC) if bc is None else (bc[0][0], bc[1][0])
+    s = pgk.Solver(nx, ny, nz, precision=precision, bc_x=kinds, equilibrium=pgk.F4)
+    o = oracle.Oracle(nx, ny, nz, equilibrium=oracle.F4)
+    for r in (s, o):
+        r.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    if bc is not None:
+        for side in (0, 1):
+            kind, rho, u, th = bc[side]
+            s.set_bc_x(side, rho, u, th)
+            o.set_bc_x(side, kind, rho, u, th)
+    for r in (s, o):
+        r.init(f["rho"], f["u"], f["thT"], f["thR"])
+    return s, o
+
+
+def _check(s, o, checkpoints, bar, label):
+    done = 0
+    for n in checkpoints:
+        s.step(n - done)
+        o.step(n - done)
+        done = n
+        g, r = s.moments(), o.moments()
+        for k in FLOOR:
+            err = np.abs(g[k] - r[k]).max() / max(np.abs(r[k]).max(), FLOOR[k])
+            assert err <= bar, (label, n, k, err)
+    s.close()
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
+def test_f4_random_fields_match_the_oracle(precision, bar):
+    f = inputs.random_smooth(9, 7, 5, seed=41, amp_th=0.15)
+    p = resolve(0.02, 0.71, 0.6, 2.0)
+    s, o = _pair(9, 7, 5, f, p, precision)
+    _check(s, o, [1, 7, 60], bar, "random")
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
+def test_f4_walls_and_dirichlet_faces_match_the_oracle(precision, bar):
+    import paper_2201_05280_amd as pgk
+    th0 = oracle.THETA0
+    p = resolve(0.05, 0.71, 0.8, 2.0)
+    bc = [(pgk.WALL, 1.0, (0.0, 0.0, 0.0), 0.8 * th0), (pgk.WALL, 1.0, (0.0, 0.05, 0.0), 1.3 * th0)]
+    s, o = _pair(24, 1, 1, inputs.uniform(24, 1, 1), p, precision, bc=bc)
+    _check(s, o, [1, 2, 30, 300], bar, "walls")
+    bc = [(pgk.DIRICHLET, 1.02, (0.03, 0.0, 0.0), 1.25 * th0), (pgk.DIRICHLET, 0.99, (0.03, 0.0, 0.0), 0.85 * th0)]
+    s, o = _pair(32, 1, 1, inputs.uniform(32, 1, 1, u=(0.03, 0, 0)), p, precision, bc=bc)
+    _check(s, o, [1, 2, 200], bar, "dirichlet")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_f4_conducts_heat_at_kappa_over_rho_cp_off_theta0(precision):
+    import paper_2201_05280_amd as pgk
+    th = 1.3 * oracle.THETA0
+    p = resolve(0.01, 0.71, 0.6, 2.0)
+    co = coefficients(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"], theta0=th)
+    nx = 64
+    k = 2 * np.pi / nx
+    x = inputs.positions(nx, 1, 1)[0]
+    f = inputs.temperature_wave(nx, 1, 1, eps=1e-4, theta=th)
+    f["rho"] = 1.0 / (1.0 + 1e-4 * np.cos(k * x))
+    rates = {}
+    for eq in (pgk.F4, pgk.F3):
+        s = pgk.Solver(nx, 1, 1, precision=precision, equilibrium=eq)
+        s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+        s.init(f["rho"], f["u"], f["thT"], f["thR"])
+        C = np.cos(k * x)
+        d = p["delta"]
+        out = []
+        for n in range(2001):
+            m = s.moments()
+            out.append(2 * np.mean((3 * m["thT"] + d * m["thR"]) / (3 + d) * C))
+            if n < 2000:
+                s.step(1)
+        s.close()
+        t = np.arange(len(out))
+        rates[eq] = -np.polyfit(t[300:], np.log(np.abs(out[300:])), 1)[0] / (co["alpha"] * k * k)
+    print("thermal rate / alpha k^2 at 1.3 theta0:", rates)
+    assert abs(rates[pgk.F4] - 1) < 0.01
+    assert abs(rates[pgk.F3] - 1) > 0.1
