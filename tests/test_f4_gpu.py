@@ -96,3 +96,37 @@ def test_f4_conducts_heat_at_kappa_over_rho_cp_off_theta0(precision):
     print("thermal rate / alpha k^2 at 1.3 theta0:", rates)
     assert abs(rates[pgk.F4] - 1) < 0.01
     assert abs(rates[pgk.F3] - 1) > 0.1
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_f4_conduction_between_walls_is_linear(precision):
+    # steady conduction across 64 cells between walls at 0.8 and 1.3 theta0
+    # (a 64 x 4 x 2 grid, every column alike): the interior profile is a line
+    # with F4 and bends with F3
+    import paper_2201_05280_amd as pgk
+    th0 = oracle.THETA0
+    L = 64
+    p = resolve(0.1, 0.71, 0.8, 2.0)
+    curv = {}
+    for eq in (pgk.F4, pgk.F3):
+        s = pgk.Solver(L, 4, 2, precision=precision, bc_x=(pgk.WALL, pgk.WALL), equilibrium=eq)
+        s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+        s.set_bc_x(0, 1.0, (0, 0, 0), 0.8 * th0)
+        s.set_bc_x(1, 1.0, (0, 0, 0), 1.3 * th0)
+        f = inputs.uniform(L, 4, 2)
+        s.init(f["rho"], f["u"], f["thT"], f["thR"])
+        y = (inputs.positions(L, 4, 2)[0] + 0.25) / L
+        prev = None
+        for _ in range(60):
+            s.step(4000)
+            m = s.moments()
+            t = (3 * m["thT"] + 2 * m["thR"]) / 5
+            if prev is not None and np.abs(t - prev).max() < 1e-9:
+                break
+            prev = t
+        s.close()
+        sel = (y > 0.15) & (y < 0.85)
+        curv[eq] = np.polyfit(y[sel], t[sel], 2)[0] / (0.5 * th0)
+    print("conduction curvature / dT:", curv)
+    assert abs(curv[pgk.F4]) < 0.02
+    assert abs(curv[pgk.F3]) > 0.1

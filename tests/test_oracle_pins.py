@@ -706,3 +706,36 @@ def test_f4_conducts_heat_at_kappa_over_rho_cp_off_theta0(ratio):
     # with F4 it decays at alpha(theta) k^2
     assert abs(_thermal_rate(ratio, oracle.F4) - 1) < 0.01
     assert abs(_thermal_rate(ratio, oracle.F3) - 1) > 0.1
+
+
+def _conduction_curvature(equilibrium):
+    # steady conduction between diffuse walls at 0.8 and 1.3 theta0, no flow
+    L = 48
+    p = resolve(0.1, 0.71, 0.8, 2.0)
+    o = oracle.Oracle(L, 1, 1, equilibrium=equilibrium)
+    o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    tl, th = 0.8 * TH0, 1.3 * TH0
+    o.set_bc_x(0, oracle.WALL, 1.0, (0, 0, 0), tl)
+    o.set_bc_x(1, oracle.WALL, 1.0, (0, 0, 0), th)
+    f = inputs.uniform(L, 1, 1)
+    o.init(f["rho"], f["u"], f["thT"], f["thR"])
+    y = (inputs.positions(L, 1, 1)[0] + 0.25) / L
+    prev = None
+    for _ in range(60):
+        o.step(2000)
+        m = o.moments()
+        t = (3 * m["thT"] + 2 * m["thR"]) / 5
+        if prev is not None and np.abs(t - prev).max() < 1e-10:
+            break
+        prev = t
+    sel = (y > 0.15) & (y < 0.85)     # away from the Knudsen layers
+    return np.polyfit(y[sel], t[sel], 2)[0] / (th - tl)
+
+
+def test_f4_conduction_between_walls_at_different_temperatures_is_linear():
+    # Fourier: with no flow the pressure is uniform, kappa = 5 p tau (1 + k_r)/(2B)
+    # is uniform with it, and the steady temperature is linear across the gap
+    # whatever the wall temperatures.  F3's conductivity scales like theta0/theta,
+    # which bends the profile (curvature 0.30 of the temperature difference here)
+    assert abs(_conduction_curvature(oracle.F4)) < 0.02
+    assert abs(_conduction_curvature(oracle.F3)) > 0.1
