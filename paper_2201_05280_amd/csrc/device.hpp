@@ -586,6 +586,50 @@ __device__ __forceinline__ Mom lb_site(int s, const S *__restrict__ src, S *__re
     return m;
 }
 
+// E2 with the two Newton solves of site s on a pair of adjacent lanes (r = 0:
+// the lam_ES target, r = 1: theta I).  Both lanes pull the site and solve its
+// temperatures; each runs one Newton solve from its multipliers of the last
+// step (lmul, [2 E2_NL][ns], never null here); the pair swaps the results and
+// lane 0 collides, writes the site and hands the fields to the transport.
+// The arithmetic per site is that of lb_site<..., PGK_E2>.
+template <typename S, typename A, int VAR, bool BOUNDED>
+__device__ __forceinline__ void lb_site_e2pair(int s, int r, const S *__restrict__ src, S *__restrict__ dst,
+                                               const S *__restrict__ gh, double *__restrict__ thR,
+                                               double *__restrict__ that_, A *__restrict__ aux, const Consts &k,
+                                               double *__restrict__ lmul)
+{
+    int x, y, z, sub;
+    decode(s, k, x, y, z, sub);
+    S v[NQ];
+    if constexpr (BOUNDED) load_all<S, true>(src, gh, x, y, z, sub, k, v);
+    else load_periodic<S>(src, pull_map(x, y, z, sub, k), k.ns, v);
+    Mom m = moments<S>(v, k);
+    Solve so = site_solve(m, thR[s], k);
+    double lam[6], l[E2_NL];
+    double cb = k.bs / so.rho;
+    for (int i = 0; i < 6; i++)
+        lam[i] = r == 0 ? (i < 3 ? so.T : 0.0) + cb * so.sg[i] : (i < 3 ? so.theta : 0.0);
+    double *lm = lmul + (size_t)r * E2_NL * k.ns + s;
+    for (int i = 0; i < E2_NL; i++) l[i] = lm[(size_t)i * k.ns];
+    e2_site_from(so.rho, so.u, lam, k, l);
+    for (int i = 0; i < E2_NL; i++) lm[(size_t)i * k.ns] = l[i];
+    double l1[E2_NL], l2[E2_NL];
+    for (int i = 0; i < E2_NL; i++) {
+        double o = __shfl_xor(l[i], 1);
+        l1[i] = r == 0 ? l[i] : o;
+        l2[i] = r == 0 ? o : l[i];
+    }
+    if (r != 0) return;
+    collide_store_e2<S>(v, l1, l2, k, dst, s);
+    that_[s] = so.R;
+    if (VAR == PGK_LIT) thR[s] = so.T;
+    aux[s] = (A)so.u[0];
+    aux[(size_t)k.ns + s] = (A)so.u[1];
+    aux[(size_t)2 * k.ns + s] = (A)so.u[2];
+    aux[(size_t)3 * k.ns + s] = (A)so.rho;
+    aux[(size_t)4 * k.ns + s] = (A)(so.rho * so.theta);
+}
+
 // ---------------------------------------------------------------------------
 // theta_R transport
 // ---------------------------------------------------------------------------

@@ -55,6 +55,18 @@ __global__ __launch_bounds__(WG) void k_lb(const S *__restrict__ src, S *__restr
     if (REDUCE) block_sum<5>(red, partial + (size_t)blockIdx.x * 5);
 }
 
+// E2 grids: two lanes per site, one Newton solve each (lb_site_e2pair)
+template <typename S, typename A, int VAR, bool BOUNDED>
+__global__ __launch_bounds__(WG) void k_lb_e2(const S *__restrict__ src, S *__restrict__ dst,
+                                              const S *__restrict__ gh, double *__restrict__ thR,
+                                              double *__restrict__ that_, A *__restrict__ aux,
+                                              double *__restrict__ lmul, Consts k)
+{
+    const int t = blockIdx.x * WG + threadIdx.x;
+    const int s = t >> 1;   // both lanes of a pair see the same s, so they branch alike
+    if (s < k.ns) lb_site_e2pair<S, A, VAR, BOUNDED>(s, t & 1, src, dst, gh, thR, that_, aux, k, lmul);
+}
+
 template <typename A, bool BOUNDED>
 __global__ __launch_bounds__(WG) void k_mc(const double *__restrict__ that_, const A *__restrict__ aux,
                                            double *__restrict__ tmc, Consts k)
@@ -860,8 +872,14 @@ static int step_t(pgk_ctx *c, int64_t n)
             hipLaunchKernelGGL((k_bc<S>), dim3(nbc), dim3(64), 0, c->stream, src, (S *)c->gh, c->k);
             mark(c, 3);
         }
-        hipLaunchKernelGGL((k_lb<S, A, VAR, BND, false, EQ>), grid, block, 0, c->stream, src, dst, (const S *)c->gh,
-                           (double *)c->buf[PGK_BUF_THETAR], c->that_, (A *)c->aux, c->partial, c->lmul, c->k);
+        if constexpr (EQ == PGK_E2)
+            hipLaunchKernelGGL((k_lb_e2<S, A, VAR, BND>), dim3(2 * c->nblk), block, 0, c->stream, src, dst,
+                               (const S *)c->gh, (double *)c->buf[PGK_BUF_THETAR], c->that_, (A *)c->aux, c->lmul,
+                               c->k);
+        else
+            hipLaunchKernelGGL((k_lb<S, A, VAR, BND, false, EQ>), grid, block, 0, c->stream, src, dst,
+                               (const S *)c->gh, (double *)c->buf[PGK_BUF_THETAR], c->that_, (A *)c->aux,
+                               c->partial, c->lmul, c->k);
         mark(c, 0);
         if (BND || c->k.nsub > 1) {
             // MacCormack, then the diffusion in nsub FTCS sub-steps (ping-pong
