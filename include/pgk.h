@@ -176,7 +176,11 @@ int pgk_set_params(pgk_ctx *ctx, const pgk_params *p, pgk_resolved *out);
 /* Boundary data of x face `side` (0 low, 1 high): wall velocity and temperature
  * for PGK_WALL (rho ignored), ghost state for PGK_DIRICHLET.  Every bounded
  * face needs its state before pgk_init_fields (PGK_EINVAL otherwise); with
- * PGK_E2, a Dirichlet state without an E2 equilibrium gives PGK_EINFEASIBLE. */
+ * PGK_E2, a Dirichlet state without an E2 equilibrium gives PGK_EINFEASIBLE.
+ * Between steps, a new state acts as in a push scheme: the pull of the next
+ * step still reads what the face in force during the last collision sends
+ * (the library fills those ghosts first), the step after reads the new state.
+ * Dirichlet ghosts are filled once per state, wall ghosts every step. */
 int pgk_set_bc_x(pgk_ctx *ctx, int side, double rho, const double u[3], double theta);
 
 /* Initial state from device fields rho[ns], u[3][ns], theta_T[ns], theta_R[ns]:

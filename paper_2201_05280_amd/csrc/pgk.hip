@@ -393,6 +393,10 @@ struct pgk_ctx {
     pgk_resolved res{};
     double bc_u[2][3]{};
     bool bc_set[2] = {false, false};   // face state given by pgk_set_bc_x
+    // x ghosts: ghosts_ok = they hold what the next pull needs (filled from the
+    // face states in force when the stored populations were collided, as the
+    // streaming of that step would); face_changed = a face state changed since
+    bool ghosts_ok = false, face_changed = false;
     std::string err;
     // carved from the aux buffer
     double *that_ = nullptr, *tmc = nullptr, *tmc2 = nullptr, *partial = nullptr, *totals = nullptr;
@@ -714,9 +718,12 @@ extern "C" int pgk_bind(pgk_ctx *c, void *const bufs[PGK_NBUF], const size_t byt
     c->gh = (void *)(a + off[5]);
     c->bound = true;
     c->initialised = false;
+    c->ghosts_ok = c->face_changed = false;
     c->drop_graphs();
     return PGK_OK;
 }
+
+static int settle_ghosts(pgk_ctx *c);
 
 // face equilibria (wall: F3 at unit density; Dirichlet: the grid's
 // equilibrium of the face state) and diffusion sub-steps; PGK_EINFEASIBLE if
@@ -760,6 +767,9 @@ extern "C" int pgk_set_params(pgk_ctx *c, const pgk_params *p, pgk_resolved *out
     if (!c || !p) return PGK_EINVAL;
     if (!(p->tau > 0) || !(p->tau1 > 0) || !(p->delta >= 0) || p->b < -0.5 || p->b > 1.0 || !(p->kr >= 0))
         return fail(c, PGK_EINVAL, "parameters out of range");
+    int rc0 = settle_ghosts(c);   // the pending pull keeps the old face equilibria
+    if (rc0) return rc0;
+    c->face_changed = true;
     Consts &k = c->k;
     k.th0 = p->theta0 > 0 ? p->theta0 : THETA0_PRINTED;
     shell_weights(k.th0, k.w);
@@ -811,6 +821,9 @@ extern "C" int pgk_set_bc_x(pgk_ctx *c, int side, double rho, const double u[3],
     if (c->k.bc[side] == PGK_PERIODIC) return fail(c, PGK_EINVAL, "face is periodic");
     if (c->k.bc[side] == PGK_DIRICHLET && !(rho > 0)) return fail(c, PGK_EINVAL, "Dirichlet density must be positive");
     if (u && u[0] != 0.0 && c->k.bc[side] == PGK_WALL) return fail(c, PGK_EINVAL, "a wall cannot move normal to itself");
+    int rc0 = settle_ghosts(c);   // the pending pull keeps the old face state
+    if (rc0) return rc0;
+    c->face_changed = true;
     c->k.rhobc[side] = rho;
     c->k.thbc[side] = theta;
     c->bc_set[side] = true;
@@ -820,6 +833,23 @@ extern "C" int pgk_set_bc_x(pgk_ctx *c, int side, double rho, const double u[3],
 }
 
 static bool bounded(const pgk_ctx *c) { return c->k.bc[0] != PGK_PERIODIC; }
+
+// Fill the x ghosts the next pull reads, if they are not filled yet, from the
+// face states in force now (before a change of those states takes effect).
+static int settle_ghosts(pgk_ctx *c)
+{
+    if (!c->initialised || c->steps == 0 || !bounded(c) || c->ghosts_ok) return PGK_OK;
+    int nbc = (2 * c->k.ny * c->k.nz + 63) / 64;
+    if (c->g.precision == PGK_FP64)
+        hipLaunchKernelGGL((k_bc<double>), dim3(nbc), dim3(64), 0, c->stream, (const double *)c->buf[c->cur],
+                           (double *)c->gh, c->k);
+    else
+        hipLaunchKernelGGL((k_bc<float>), dim3(nbc), dim3(64), 0, c->stream, (const float *)c->buf[c->cur],
+                           (float *)c->gh, c->k);
+    HIPCHECK(c, hipGetLastError());
+    c->ghosts_ok = true;
+    return PGK_OK;
+}
 
 template <typename S, int EQ>
 static int init_t(pgk_ctx *c, const double *rho, const double *u, const double *thT, const double *thR)
@@ -847,6 +877,10 @@ extern "C" int pgk_init_fields(pgk_ctx *c, const double *rho, const double *u, c
             return fail(c, PGK_EINVAL, "x face state not set (pgk_set_bc_x)");
     c->cur = 0;
     c->steps = 0;
+    // the initialisation pushes what the first pull reads; from the second
+    // step on the ghosts come from the face states
+    c->ghosts_ok = true;
+    c->face_changed = true;
     int eq = c->g.equilibrium, rc;
     if (c->g.precision == PGK_FP64)
         rc = eq == PGK_E2 ? init_t<double, PGK_E2>(c, rho, u, thT, thR)
@@ -868,9 +902,10 @@ static int step_t(pgk_ctx *c, int64_t n)
     for (int64_t it = 0; it < n; it++) {
         S *src = (S *)c->buf[c->cur], *dst = (S *)c->buf[1 - c->cur];
         mark(c, -1);
-        if (BND && c->steps > 0) {
+        if (BND && !c->ghosts_ok) {
             hipLaunchKernelGGL((k_bc<S>), dim3(nbc), dim3(64), 0, c->stream, src, (S *)c->gh, c->k);
             mark(c, 3);
+            c->ghosts_ok = true;
         }
         if constexpr (EQ == PGK_E2)
             hipLaunchKernelGGL((k_lb_e2<S, A, VAR, BND>), dim3(2 * c->nblk), block, 0, c->stream, src, dst,
@@ -905,6 +940,10 @@ static int step_t(pgk_ctx *c, int64_t n)
         }
         c->cur = 1 - c->cur;
         c->steps++;
+        // a wall re-emits what the last collision sent into it: new ghosts
+        // every step; Dirichlet ghosts stay until a face state changes
+        if (BND && (c->k.bc[0] == PGK_WALL || c->k.bc[1] == PGK_WALL || c->face_changed)) c->ghosts_ok = false;
+        c->face_changed = false;
     }
     HIPCHECK(c, hipGetLastError());
     return PGK_OK;
@@ -945,12 +984,22 @@ extern "C" int pgk_step(pgk_ctx *c, int64_t n)
         if (rc) return rc;
         n--;
     }
+    // a replay starts from filled ghosts; the chunk keeps them filled (with
+    // walls it refreshes them before every step, its first included)
+    rc = settle_ghosts(c);
+    if (rc) return rc;
+    const bool walls = c->k.bc[0] == PGK_WALL || c->k.bc[1] == PGK_WALL;
     // a chunk of an even number of steps returns the state to the buffer it started from
     const int p = c->cur;
     if (!c->graph[p]) {
         if (!c->capture) HIPCHECK(c, hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
         const int cur0 = c->cur;
         const int64_t steps0 = c->steps;
+        const bool ok0 = c->ghosts_ok, changed0 = c->face_changed;
+        // every replay must begin like the recorded one: with walls each step
+        // refreshes the ghosts, so the chunk records that refresh from its
+        // first step on (a repeat of a settled fill writes the same values)
+        if (walls) c->ghosts_ok = false;
         hipStream_t own = c->stream;
         HIPCHECK(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
         c->stream = c->capture;
@@ -961,18 +1010,26 @@ extern "C" int pgk_step(pgk_ctx *c, int64_t n)
         c->cur = cur0;   // capturing launched nothing
         c->steps = steps0;
         if (rc || e != hipSuccess) {
+            c->ghosts_ok = ok0;
+            c->face_changed = changed0;
             if (g) (void)hipGraphDestroy(g);
             return rc ? rc : fail(c, PGK_EDEVICE, std::string("step capture: ") + hipGetErrorString(e));
         }
         hipError_t ei = hipGraphInstantiate(&c->graph[p], g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (ei != hipSuccess) {
+            c->ghosts_ok = ok0;
+            c->face_changed = changed0;
             c->graph[p] = nullptr;
             return fail(c, PGK_EDEVICE, std::string("step graph: ") + hipGetErrorString(ei));
         }
     }
     for (int64_t i = 0; i + K <= n; i += K) HIPCHECK(c, hipGraphLaunch(c->graph[p], c->stream));
     c->steps += n / K * K;
+    // after a chunk: a wall's ghosts wait for the last collision, Dirichlet
+    // ghosts hold the face states
+    if (bounded(c)) c->ghosts_ok = !walls;
+    c->face_changed = false;
     return (n % K) ? f(c, n % K) : PGK_OK;
 }
 
@@ -981,11 +1038,9 @@ static int moments_t(pgk_ctx *c, double *rho, double *u, double *thT, double *th
 {
     dim3 grid(c->nblk), block(WG);
     const S *src = (const S *)c->buf[c->cur];
-    // ghosts for the current pull: after a step they must be refreshed first
-    if (bounded(c) && c->steps > 0) {
-        int nbc = (2 * c->k.ny * c->k.nz + 63) / 64;
-        hipLaunchKernelGGL((k_bc<S>), dim3(nbc), dim3(64), 0, c->stream, src, (S *)c->gh, c->k);
-    }
+    // ghosts for the current pull
+    int rc0 = settle_ghosts(c);
+    if (rc0) return rc0;
     if (bounded(c))
         hipLaunchKernelGGL((k_moments<S, true, REDUCE>), grid, block, 0, c->stream, src, (const S *)c->gh,
                            (const double *)c->buf[PGK_BUF_THETAR], rho, u, thT, thR, P, c->partial, c->k);

@@ -189,3 +189,34 @@ def test_subcycled_diffusion_paths(precision, bar):
     bc = [(pgk.WALL, 1.0, (0.0, 0.0, 0.0), th0), (pgk.WALL, 1.0, (0.0, 0.04, 0.0), th0 * 1.05)]
     errs, _ = run_pair(20, 1, 1, inputs.uniform(20, 1, 1), p, 60, precision, bc=bc, checkpoints=[1, 60])
     _assert_bar(errs, bar, "subcycled walls")
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
+def test_dirichlet_face_state_changed_mid_run(precision, bar):
+    # Dirichlet ghosts are written once per face state: a new state given
+    # between calls must reach the next step (graph-replayed and direct)
+    import paper_2201_05280_amd as pgk
+    th0 = oracle.THETA0
+    bc = [(pgk.DIRICHLET, 1.02, (0.03, 0.0, 0.0), th0 * 1.01), (pgk.DIRICHLET, 0.99, (0.03, 0.0, 0.0), th0)]
+    f = inputs.uniform(32, 1, 1, u=(0.03, 0, 0))
+    p = resolve(0.05, 0.71, 0.8, 2.0)
+    s = _solver(32, 1, 1, precision=precision, bc_x=(pgk.DIRICHLET, pgk.DIRICHLET))
+    o = oracle.Oracle(32, 1, 1)
+    for r in (s, o):
+        r.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    for side in (0, 1):
+        kind, rho, u, th = bc[side]
+        s.set_bc_x(side, rho, u, th)
+        o.set_bc_x(side, kind, rho, u, th)
+    s.init(f["rho"], f["u"], f["thT"], f["thR"])
+    o.init(f["rho"], f["u"], f["thT"], f["thR"])
+    errs = []
+    for n, new in ((70, (1.05, (0.0, 0.0, 0.0), th0 * 1.1)), (3, (0.97, (0.05, 0.0, 0.0), th0 * 0.95)), (40, None)):
+        s.step(n)
+        o.step(n)
+        errs.append(rel_err(s.moments(), o.moments()))
+        if new is not None:
+            s.set_bc_x(0, *new)
+            o.set_bc_x(0, oracle.DIRICHLET, *new)
+    s.close()
+    _assert_bar(errs, bar, "dirichlet change")

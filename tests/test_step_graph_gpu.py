@@ -111,3 +111,27 @@ def test_callers_stream_and_timing():
     b.step(10)
     _same(a, b, "stream")
     a.close(); b.close()
+
+
+@pytest.mark.parametrize("kind", ["wall", "dirichlet"])
+def test_face_changes_and_reinitialisation_between_calls(kind):
+    # the ghost bookkeeping across replays: face states changed between calls
+    # (the pending pull keeps the old state), moments read in between, and a
+    # second initialisation of the same grid
+    import paper_2201_05280_amd as pgk
+    th0 = oracle.THETA0
+    K = pgk.WALL if kind == "wall" else pgk.DIRICHLET
+    bc = [(K, 1.0, (0.0, 0.0, 0.0) if kind == "wall" else (0.03, 0.0, 0.0), th0),
+          (K, 1.0, (0.0, 0.04, 0.0) if kind == "wall" else (0.03, 0.0, 0.0), th0 * 1.05)]
+    p = resolve(0.05, 0.71, 0.8, 2.0)
+    f = inputs.uniform(24, 2, 1, u=(0.0, 0, 0) if kind == "wall" else (0.03, 0, 0))
+    a, b = _pair(24, 2, 1, f, p, 0, bc=bc, K=4)
+    _run(a, b, [9, 5], "start")
+    new = (1.0, (0.0, -0.03, 0.0), th0 * 0.9) if kind == "wall" else (1.04, (0.0, 0.0, 0.0), th0 * 1.1)
+    for s in (a, b):
+        s.set_bc_x(0, *new)
+    _run(a, b, [1, 8, 13], "changed")
+    for s in (a, b):
+        s.init(f["rho"], f["u"], f["thT"], f["thR"])
+    _run(a, b, [12, 3], "again")
+    a.close(); b.close()
