@@ -777,7 +777,8 @@ extern "C" int pgk_set_params(pgk_ctx *c, const pgk_params *p, pgk_resolved *out
         k.whi[i] = (float)k.w[i];
         k.wlo[i] = (float)(k.w[i] - (double)k.whi[i]);
     }
-    if (!f4_matrix(k.th0, k.w, k.f4inv)) return fail(c, PGK_EINVAL, "F4 lattice matrix is singular");
+    if (c->g.equilibrium == PGK_F4 && !f4_matrix(k.th0, k.w, k.f4inv))
+        return fail(c, PGK_EINVAL, "the F4 lattice matrix is singular at this theta0");
     k.tau = p->tau; k.tau1 = p->tau1; k.b = p->b; k.delta = p->delta;
     double taus = p->tau * p->tau1 / (p->tau + p->tau1);
     double B = 1.0 + p->tau / p->tau1;
