@@ -120,3 +120,37 @@ def moving_weak_shock(make_line, Ma, nu=0.05, L=2048, steps=2000, gamma=1.4, Pr=
     thick = (r2 - r1) / np.abs(np.diff(rs) / np.diff(xs)).max()
     D = nu * (4.0 / 3.0 + co["lam_b"] + (co["gamma"] - 1.0) / co["Pr"])
     return thick, (p2 - p1) / (steps - n1), 8.0 * D / ((gamma + 1.0) * (u1 - u2)), u1
+
+
+def landau_pulse(make, Pr, L=400, Kn=1e-3, sigma0=6.0, eps=1e-3):
+    """The Landau-number runs of Sec. 6 (Table "La vs Pr") in one dimension:
+    tau = 3 tau1/5 and k_r = 0 (so b = 1.6 - 2.24/Pr and mu_b/mu =
+    224/(225 Pr)), Kn = nu/(c_s L) on an L-cell periodic line holding a
+    Gaussian density pulse (width sigma0 cells, amplitude eps) at rest.  The
+    pulse splits into two sound pulses; in linear acoustics with sound
+    attenuation k^2 D/2 a Gaussian pulse keeps its shape and its variance
+    grows by D t, D = La c_s L.  Returns the Landau number from the growth of
+    the pressure-weighted variance of the right-running pulse between 0.1 and
+    0.3 acoustic times t_a = L/c_s, and the pulse speed."""
+    cs = np.sqrt(1.4 * THETA0)
+    p = resolve(Kn * cs * L, Pr, 224.0 / (225.0 * Pr), 2.0, b=1.6 - 1.6 * 1.4 / Pr)
+    x = inputs.positions(L, 1, 1)[0]
+    c = L / 2
+    f = inputs.uniform(L, 1, 1)
+    f["rho"] = 1.0 + eps * np.exp(-0.5 * ((x - c) / sigma0) ** 2)
+    run = make(L, 1, 1, p, f)
+    ta = L / cs
+    out, done = [], 0
+    for frac in (0.1, 0.3):
+        n = int(frac * ta)
+        run.step(n - done)
+        done = n
+        m = run.moments()
+        d = p["delta"]
+        pp = m["rho"] * (3 * m["thT"] + d * m["thR"]) / (3 + d) - THETA0
+        sel = x > c + 0.25 * cs * n
+        w, xs = pp[sel], x[sel]
+        mu = (w * xs).sum() / w.sum()
+        out.append((n, mu, (w * (xs - mu) ** 2).sum() / w.sum()))
+    (n1, m1, v1), (n2, m2, v2) = out
+    return (v2 - v1) / (n2 - n1) / (cs * L), (m2 - m1) / (n2 - n1)

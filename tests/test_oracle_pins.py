@@ -739,3 +739,16 @@ def test_f4_conduction_between_walls_at_different_temperatures_is_linear():
     # which bends the profile (curvature 0.30 of the temperature difference here)
     assert abs(_conduction_curvature(oracle.F4)) < 0.02
     assert abs(_conduction_curvature(oracle.F3)) > 0.1
+
+
+def test_landau_numbers_of_the_table_from_pulse_spreading():
+    # Sec. 6, Table "La vs Pr": the rows reachable with b <= 1 (Pr 1.4, b = 0;
+    # Pr 2, b = 0.48), measured from the spreading of a sound pulse
+    from tests import sec6
+    for Pr, La in read_golden("landau_table.txt"):
+        Pr, La = float(Pr), float(La)
+        if 1.6 - 1.6 * 1.4 / Pr > 1.0:
+            continue
+        la, speed = sec6.landau_pulse(_oracle_runner, Pr)
+        assert abs(la / La - 1) < 0.01, (Pr, la, La)
+        assert abs(speed / np.sqrt(1.4 * TH0) - 1) < 1e-3

@@ -149,3 +149,15 @@ def test_weak_shock_has_the_taylor_thickness_and_the_jump_speed(precision, equil
     print("weak shock", Ma, "eq", equilibrium, "thickness", thick, "Taylor", taylor, "speed", speed, u1)
     assert abs(thick / taylor - 1) < tol, (thick, taylor)
     assert abs(speed / u1 - 1) < 2e-3, (speed, u1)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_landau_numbers_of_the_table_from_pulse_spreading(precision):
+    for Pr, La in read_golden("landau_table.txt"):
+        Pr, La = float(Pr), float(La)
+        if 1.6 - 1.6 * 1.4 / Pr > 1.0:
+            continue   # b > 1: outside the ES range
+        la, speed = sec6.landau_pulse(_runner(precision), Pr)
+        print("Pr", Pr, "La", la, "printed", La)
+        assert abs(la / La - 1) < 0.01, (Pr, la, La)
+        assert abs(speed / np.sqrt(1.4 * TH0) - 1) < 1e-3
