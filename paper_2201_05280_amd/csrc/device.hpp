@@ -731,12 +731,15 @@ __device__ __forceinline__ void dif_site(int s, const double *__restrict__ tin, 
     }
 }
 
-// ghost populations of x face `side`, column col (diffuse wall: density of the
-// re-emitted populations from zero net mass flux through the face in the last
-// collision; Dirichlet: the equilibrium of the ghost state)
+// Ghost populations of x face `side`, column col, by one wavefront (lane
+// 0..63).  Diffuse wall: the density of the re-emitted populations comes from
+// zero net mass flux through the face in the last collision, the outgoing sum
+// spread over the lanes (lane l takes the candidates (q, sub, xi) numbered
+// l, l + 64, l + 128) and reduced by a butterfly; Dirichlet: the equilibrium
+// of the ghost state.  Lanes 0..40 write population q = lane.
 template <typename S>
-__device__ __forceinline__ void bc_column(int side, int col, const S *__restrict__ src, S *__restrict__ gh,
-                                          const Consts &k)
+__device__ __forceinline__ void bc_column(int side, int col, int lane, const S *__restrict__ src,
+                                          S *__restrict__ gh, const Consts &k)
 {
     int ncol = k.ny * k.nz;
     if (k.bc[side] == PGK_PERIODIC) return;
@@ -744,33 +747,33 @@ __device__ __forceinline__ void bc_column(int side, int col, const S *__restrict
     double scale = 1.0;
     if (k.bc[side] == PGK_WALL) {
         double out = 0.0;
-        for (int q = 1; q < NQ; q++) {
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            int idx = lane + 64 * j;                 // 160 candidates: q = 1..40, sub, xi
+            if (idx >= 4 * (NQ - 1)) break;
+            int q = 1 + (idx >> 2), sub = (idx >> 1) & 1, xi = idx & 1;
             int cx = c2(q, 0), cy = c2(q, 1), cz = c2(q, 2);
             if ((side == 0 && cx >= 0) || (side == 1 && cx <= 0)) continue;
-            for (int sub = 0; sub < 2; sub++)
-                for (int xi = 0; xi < 2; xi++) {
-                    int x = side == 0 ? xi : k.nx - 1 - xi;
-                    if (x < 0 || x >= k.nx) continue;
-                    if (xi == 1 && k.nx == 1) continue;
-                    int dx = 2 * x + sub + cx;
-                    bool crosses = side == 0 ? dx < 0 : dx > 2 * k.nx - 1;
-                    if (!crosses) continue;
-                    // ghost column of the destination: floor((2y + sub + cy)/2) = y + floor((sub + cy)/2)
-                    int ky = (sub + cy) >= 0 ? (sub + cy) / 2 : -((-(sub + cy) + 1) / 2);
-                    int kz = (sub + cz) >= 0 ? (sub + cz) / 2 : -((-(sub + cz) + 1) / 2);
-                    int y = wrapc(gy - ky, k.ny), z = wrapc(gz - kz, k.nz);
-                    if (k.ny == 1) y = 0;
-                    if (k.nz == 1) z = 0;
-                    int s = ((sub * k.nz + z) * k.ny + y) * k.nx + x;
-                    out += (double)src[(size_t)q * k.ns + s] + (sizeof(S) == 4 ? k.w[shell_of(q)] : 0.0);
-                }
+            if (xi == 1 && k.nx == 1) continue;
+            int x = side == 0 ? xi : k.nx - 1 - xi;
+            int dx = 2 * x + sub + cx;
+            bool crosses = side == 0 ? dx < 0 : dx > 2 * k.nx - 1;
+            if (!crosses) continue;
+            // ghost column of the destination: floor((2y + sub + cy)/2) = y + floor((sub + cy)/2)
+            int ky = (sub + cy) >= 0 ? (sub + cy) / 2 : -((-(sub + cy) + 1) / 2);
+            int kz = (sub + cz) >= 0 ? (sub + cz) / 2 : -((-(sub + cz) + 1) / 2);
+            int y = k.ny == 1 ? 0 : wrapc(gy - ky, k.ny), z = k.nz == 1 ? 0 : wrapc(gz - kz, k.nz);
+            int s = ((sub * k.nz + z) * k.ny + y) * k.nx + x;
+            out += (double)src[(size_t)q * k.ns + s] + (sizeof(S) == 4 ? k.w[shell_of(q)] : 0.0);
         }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) out += __shfl_xor(out, o, 64);
         scale = out / k.in_col[side];
     }
-    for (int q = 0; q < NQ; q++) {
-        double val = scale * k.Fbc[side][q] - (sizeof(S) == 4 ? k.w[shell_of(q)] : 0.0);
-        for (int slot = 0; slot < NSLOT; slot++)
-            gh[((side * NQ + q) * NSLOT + slot) * ncol + col] = (S)val;
+    if (lane < NQ) {
+        double val = scale * k.Fbc[side][lane] - (sizeof(S) == 4 ? k.w[shell_of(lane)] : 0.0);
+#pragma unroll
+        for (int slot = 0; slot < NSLOT; slot++) gh[((side * NQ + lane) * NSLOT + slot) * ncol + col] = (S)val;
     }
 }
 

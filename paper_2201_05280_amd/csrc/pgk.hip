@@ -84,6 +84,33 @@ __global__ __launch_bounds__(WG) void k_dif(const double *__restrict__ tin, doub
     if (s < k.ns) dif_site<A, VAR, BOUNDED, FINAL>(s, tin, tout, that_, aux, thR, k);
 }
 
+// The theta_R transport of a small grid (at most TR_SMALL sites) in one
+// work-group: MacCormack into LDS, then every FTCS sub-step ping-ponging in
+// LDS with a work-group barrier between them, the last one with the second
+// half of the relaxation.  One launch instead of 1 + n_sub; the per-site
+// arithmetic is that of k_mc and k_dif, so the results are the same bits.
+constexpr int TR_SMALL = 4096, TR_SMALL_WG = 1024;
+
+template <typename A, int VAR, bool BOUNDED>
+__global__ __launch_bounds__(TR_SMALL_WG) void k_tr_small(const double *__restrict__ that_,
+                                                          const A *__restrict__ aux, double *__restrict__ thR,
+                                                          Consts k)
+{
+    extern __shared__ double lds[];
+    double *tin = lds, *tout = lds + k.ns;
+    for (int s = threadIdx.x; s < k.ns; s += TR_SMALL_WG) mc_site<A, BOUNDED>(s, that_, aux, tin, k);
+    __syncthreads();
+    for (int it = 0; it + 1 < k.nsub; it++) {
+        for (int s = threadIdx.x; s < k.ns; s += TR_SMALL_WG)
+            dif_site<A, VAR, BOUNDED, false>(s, tin, tout, that_, aux, thR, k);
+        __syncthreads();
+        double *t = tin;
+        tin = tout;
+        tout = t;
+    }
+    for (int s = threadIdx.x; s < k.ns; s += TR_SMALL_WG) dif_site<A, VAR, BOUNDED, true>(s, tin, tout, that_, aux, thR, k);
+}
+
 // ---------------------------------------------------------------------------
 // k_tr: fused theta_R transport on periodic grids (steps 2-4 in one pass).
 // A work-group owns a TX x TY tile of one sublattice and marches through TZ
@@ -302,13 +329,12 @@ __global__ __launch_bounds__(TWG) void k_tr(const double *__restrict__ that_, co
 // the last collision (zero net mass flux per column); Dirichlet: equilibrium.
 // One thread per (side, ghost column).
 template <typename S>
-__global__ void k_bc(const S *__restrict__ src, S *__restrict__ gh, Consts k)
+__global__ __launch_bounds__(64) void k_bc(const S *__restrict__ src, S *__restrict__ gh, Consts k)
 {
-    int col = blockIdx.x * blockDim.x + threadIdx.x;
+    // one wavefront per (face, ghost column): 2 ny nz work-groups of 64
     int ncol = k.ny * k.nz;
-    if (col >= 2 * ncol) return;
-    int side = col / ncol;
-    bc_column<S>(side, col - side * ncol, src, gh, k);
+    int side = blockIdx.x / ncol;
+    bc_column<S>(side, blockIdx.x - side * ncol, threadIdx.x, src, gh, k);
 }
 
 template <typename S, bool BOUNDED, int EQ>
@@ -840,7 +866,7 @@ static bool bounded(const pgk_ctx *c) { return c->k.bc[0] != PGK_PERIODIC; }
 static int settle_ghosts(pgk_ctx *c)
 {
     if (!c->initialised || c->steps == 0 || !bounded(c) || c->ghosts_ok) return PGK_OK;
-    int nbc = (2 * c->k.ny * c->k.nz + 63) / 64;
+    int nbc = 2 * c->k.ny * c->k.nz;   // one wavefront per face column
     if (c->g.precision == PGK_FP64)
         hipLaunchKernelGGL((k_bc<double>), dim3(nbc), dim3(64), 0, c->stream, (const double *)c->buf[c->cur],
                            (double *)c->gh, c->k);
@@ -899,7 +925,7 @@ template <typename S, typename A, int VAR, bool BND, int EQ>
 static int step_t(pgk_ctx *c, int64_t n)
 {
     dim3 grid(c->nblk), block(WG);
-    int nbc = (2 * c->k.ny * c->k.nz + 63) / 64;
+    int nbc = 2 * c->k.ny * c->k.nz;   // one wavefront per face column
     for (int64_t it = 0; it < n; it++) {
         S *src = (S *)c->buf[c->cur], *dst = (S *)c->buf[1 - c->cur];
         mark(c, -1);
@@ -917,7 +943,11 @@ static int step_t(pgk_ctx *c, int64_t n)
                                (const S *)c->gh, (double *)c->buf[PGK_BUF_THETAR], c->that_, (A *)c->aux,
                                c->partial, c->lmul, c->k);
         mark(c, 0);
-        if (BND || c->k.nsub > 1) {
+        if ((BND || c->k.nsub > 1) && c->k.ns <= TR_SMALL) {
+            hipLaunchKernelGGL((k_tr_small<A, VAR, BND>), dim3(1), dim3(TR_SMALL_WG), sizeof(double) * 2 * c->k.ns,
+                               c->stream, c->that_, (const A *)c->aux, (double *)c->buf[PGK_BUF_THETAR], c->k);
+            mark(c, 2);
+        } else if (BND || c->k.nsub > 1) {
             // MacCormack, then the diffusion in nsub FTCS sub-steps (ping-pong
             // between two scratch fields), the last one with the second half
             hipLaunchKernelGGL((k_mc<A, BND>), grid, block, 0, c->stream, c->that_, (const A *)c->aux, c->tmc, c->k);
