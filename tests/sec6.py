@@ -154,3 +154,45 @@ def landau_pulse(make, Pr, L=400, Kn=1e-3, sigma0=6.0, eps=1e-3):
         out.append((n, mu, (w * (xs - mu) ** 2).sum() / w.sum()))
     (n1, m1, v1), (n2, m2, v2) = out
     return (v2 - v1) / (n2 - n1) / (cs * L), (m2 - m1) / (n2 - n1)
+
+
+def linear_symbol(p, N=64, m=1, h=1e-6):
+    """The one-step operator of the oracle linearised about the resting gas at
+    theta0, on an N-cell periodic line, at the wavenumber k = 2 pi m/N: the
+    84 x 84 matrix (41 populations and theta_R on both sublattices) from
+    central differences of single-site perturbations and the translation
+    invariance of the scheme (each site's response carries exp(-i k dx)).
+    Returns (eigenvalues, k)."""
+    import oracle
+    o = oracle.Oracle(N, 1, 1)
+    o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    f = inputs.uniform(N, 1, 1)
+    o.init(f["rho"], f["u"], f["thT"], f["thR"])
+    g0, e0 = o.get_state()
+    x = inputs.positions(N, 1, 1)[0]
+    k = 2 * np.pi * m / N
+    comps = [(q, sub) for sub in range(2) for q in range(42)]
+    M = np.zeros((84, 84), dtype=complex)
+
+    def step_from(g, e):
+        o.set_state(g, e)
+        o.step(1)
+        return o.get_state()
+
+    for j, (qj, subj) in enumerate(comps):
+        s0 = subj * N
+        out = []
+        for sgn in (1.0, -1.0):
+            g, e = g0.copy(), e0.copy()
+            if qj < 41:
+                g[qj, s0] += sgn * h
+            else:
+                e[s0] += sgn * h
+            out.append(step_from(g, e))
+        dg = (out[0][0] - out[1][0]) / (2 * h)
+        de = (out[0][1] - out[1][1]) / (2 * h)
+        for i, (qi, subi) in enumerate(comps):
+            sl = slice(subi * N, subi * N + N)
+            resp = dg[qi, sl] if qi < 41 else de[sl]
+            M[i, j] = (resp * np.exp(-1j * k * (x[sl] - x[s0]))).sum()
+    return np.linalg.eigvals(M), k

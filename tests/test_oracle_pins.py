@@ -752,3 +752,43 @@ def test_landau_numbers_of_the_table_from_pulse_spreading():
         la, speed = sec6.landau_pulse(_oracle_runner, Pr)
         assert abs(la / La - 1) < 0.01, (Pr, la, La)
         assert abs(speed / np.sqrt(1.4 * TH0) - 1) < 1e-3
+
+
+def test_linearised_scheme_rates_match_chapman_enskog():
+    # eigenvalues of the oracle's one-step operator linearised at rest, at
+    # k = 2 pi/64 (numpy eig): the slow modes are the shear pair (nu k^2), the
+    # sound pair (Landau damping, c_s k) and the thermal mode (alpha k^2),
+    # each within 0.2% of its Chapman-Enskog value; every other mode decays
+    # at least a hundred times faster than sound
+    from tests import sec6
+    p = resolve(0.01, 0.71, 0.6, 2.0)
+    co = coefficients(**p)
+    lam, k = sec6.linear_symbol(p)
+    rate, omega = -np.log(np.abs(lam)), np.angle(lam)
+    order = np.argsort(rate)
+    shear, sound, thermal = order[:2], order[2:4], order[4]
+    G = k * k / 2 * (4 / 3 * co["nu"] + co["nu_b"] + (co["gamma"] - 1) * co["alpha"])
+    assert np.allclose(rate[shear] / (co["nu"] * k * k), 1, atol=2e-3), rate[shear]
+    assert np.abs(omega[shear]).max() < 1e-9
+    assert np.allclose(rate[sound] / G, 1, atol=2e-3), rate[sound]
+    assert np.allclose(np.abs(omega[sound]) / (co["cs"] * k), 1, atol=2e-4), omega[sound]
+    assert abs(rate[thermal] / (co["alpha"] * k * k) - 1) < 2e-3 and abs(omega[thermal]) < 1e-9
+    assert rate[order[5]] > 3 * rate[thermal]
+    assert rate[order[6]] > 100 * G
+
+
+def test_small_shear_wave_decays_at_the_linear_eigenvalue():
+    # a shear wave is an exact solution of the nonlinear equations (u.grad u
+    # = 0), so the nonlinear oracle must decay at the linear operator's rate
+    # (not only at the Chapman-Enskog nu k^2)
+    from tests import sec6
+    p = resolve(0.01, 0.71, 0.6, 2.0)
+    lam, k = sec6.linear_symbol(p)
+    r_lin = np.sort(-np.log(np.abs(lam)))[0]
+    nx = 64
+    f = inputs.shear_wave(nx, 1, 1, amp=0.01, axis_u=1, axis_k=0)
+    S = np.sin(k * inputs.positions(nx, 1, 1)[0])
+    amp, _ = _run_1d(f, p, nx, 1500, lambda m: 2 * np.mean(m["u"][1] * S))
+    t = np.arange(len(amp))
+    rate = -np.polyfit(t[200:], np.log(amp[200:]), 1)[0]
+    assert abs(rate / r_lin - 1) < 2e-5, (rate, r_lin)

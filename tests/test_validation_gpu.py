@@ -161,3 +161,31 @@ def test_landau_numbers_of_the_table_from_pulse_spreading(precision):
         print("Pr", Pr, "La", la, "printed", La)
         assert abs(la / La - 1) < 0.01, (Pr, la, La)
         assert abs(speed / np.sqrt(1.4 * TH0) - 1) < 1e-3
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 2e-5), (1, 2e-4)])
+def test_shear_wave_64x64_decays_at_the_linear_eigenvalue(precision, tol):
+    # the 2D shear-wave workload (64 x 64, the wave along y) between steps 500
+    # and 2000 against the decay rate of the oracle's linearised one-step
+    # operator at k = 2 pi/64 (by the x <-> y symmetry of the lattice the same
+    # for a wave along x); a shear wave is an exact nonlinear solution
+    import paper_2201_05280_amd as pgk
+    from oracle.params import resolve
+    from paper_2201_05280_amd import inputs
+    p = resolve(0.01, 0.71, 0.6, 2.0)
+    lam, k = sec6.linear_symbol(p)
+    r_lin = np.sort(-np.log(np.abs(lam)))[0]
+    n = 64
+    s = pgk.Solver(n, n, 1, precision=precision)
+    s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    f = inputs.shear_wave(n, n, 1, amp=0.01)
+    s.init(f["rho"], f["u"], f["thT"], f["thR"])
+    mode = np.sin(k * inputs.positions(n, n, 1)[1])
+    amps = []
+    for steps in (500, 1500):
+        s.step(steps)
+        amps.append(float(s.moments()["u"][0] @ mode / (mode @ mode)))
+    s.close()
+    rate = -np.log(amps[1] / amps[0]) / 1500
+    print("shear rate", rate, "linear", r_lin, rate / r_lin - 1)
+    assert abs(rate / r_lin - 1) < tol
