@@ -33,26 +33,23 @@ namespace pgk {
 // ---------------------------------------------------------------------------
 // single-grid kernels: one thread per site
 // ---------------------------------------------------------------------------
-template <typename S, typename A, int VAR, bool BOUNDED, bool REDUCE, int EQ>
-__global__ __launch_bounds__(WG) void k_lb(const S *__restrict__ src, S *__restrict__ dst,
-                                           const S *__restrict__ gh, double *__restrict__ thR,
-                                           double *__restrict__ that_, A *__restrict__ aux,
-                                           double *__restrict__ partial, double *__restrict__ lmul, Consts k)
+// Work-group size of the fused kernel: 1024 for FP32 storage, where against
+// 256 a step of the 256^3 benchmark grid takes 1.5% less (fewer, longer-lived
+// groups) and the kernel fits the 128 registers this allows without spilling;
+// 256 for FP64 storage and for F4 with faces, which would spill at 128.
+template <typename S, bool BOUNDED, int EQ>
+constexpr int lb_wg() { return sizeof(S) == 4 && (EQ == PGK_F3 || !BOUNDED) ? 1024 : WG; }
+
+template <typename S, typename A, int VAR, bool BOUNDED, int EQ, int NT>
+__global__ __launch_bounds__(NT) void k_lb(const S *__restrict__ src, S *__restrict__ dst, const S *__restrict__ gh,
+                                           double *__restrict__ thR, double *__restrict__ that_, A *__restrict__ aux,
+                                           double *__restrict__ lmul, Consts k)
 {
-    int s = blockIdx.x * WG + threadIdx.x;
-    double red[5] = {0, 0, 0, 0, 0};
+    int s = blockIdx.x * NT + threadIdx.x;
     if (s < k.ns) {
         double r;
-        Mom m = lb_site<S, A, VAR, BOUNDED, EQ>(s, src, dst, gh, thR, that_, aux, k, r, lmul);
-        if (REDUCE) {
-            red[0] = m.rho;
-            red[1] = m.j[0];
-            red[2] = m.j[1];
-            red[3] = m.j[2];
-            red[4] = 0.5 * (m.P[0] + m.P[1] + m.P[2]) + 0.5 * k.delta * m.rho * r;
-        }
+        lb_site<S, A, VAR, BOUNDED, EQ>(s, src, dst, gh, thR, that_, aux, k, r, lmul);
     }
-    if (REDUCE) block_sum<5>(red, partial + (size_t)blockIdx.x * 5);
 }
 
 // E2 grids: two lanes per site, one Newton solve each (lb_site_e2pair)
@@ -934,14 +931,16 @@ static int step_t(pgk_ctx *c, int64_t n)
             mark(c, 3);
             c->ghosts_ok = true;
         }
-        if constexpr (EQ == PGK_E2)
+        if constexpr (EQ == PGK_E2) {
             hipLaunchKernelGGL((k_lb_e2<S, A, VAR, BND>), dim3(2 * c->nblk), block, 0, c->stream, src, dst,
                                (const S *)c->gh, (double *)c->buf[PGK_BUF_THETAR], c->that_, (A *)c->aux, c->lmul,
                                c->k);
-        else
-            hipLaunchKernelGGL((k_lb<S, A, VAR, BND, false, EQ>), grid, block, 0, c->stream, src, dst,
-                               (const S *)c->gh, (double *)c->buf[PGK_BUF_THETAR], c->that_, (A *)c->aux,
-                               c->partial, c->lmul, c->k);
+        } else {
+            constexpr int nt = lb_wg<S, BND, EQ>();
+            hipLaunchKernelGGL((k_lb<S, A, VAR, BND, EQ, nt>), dim3((c->k.ns + nt - 1) / nt), dim3(nt), 0, c->stream,
+                               src, dst, (const S *)c->gh, (double *)c->buf[PGK_BUF_THETAR], c->that_, (A *)c->aux,
+                               c->lmul, c->k);
+        }
         mark(c, 0);
         if ((BND || c->k.nsub > 1) && c->k.ns <= TR_SMALL) {
             hipLaunchKernelGGL((k_tr_small<A, VAR, BND>), dim3(1), dim3(TR_SMALL_WG), sizeof(double) * 2 * c->k.ns,
