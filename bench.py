@@ -511,6 +511,7 @@ def sweep(args):
         "mlp_inference_time": round(t_infer, 3), "mlp_train_time": round(t_train, 1),
         "mlp_train_points": int(len(X)),
         "mlp_loss_first_last": [float(losses[0]), float(losses[-1])], "mlp_schedule": args.sweep_lr_schedule,
+        "mlp_loss_curve_every_5_epochs": [float("%.4g" % v) for v in losses[::5]],
         "couette": {"cold": counts(cold, ~is_shock), "warm": counts(warm, ~is_shock),
                     "steps_cold_median": int(np.median(cold["steps"][~is_shock])) if (~is_shock).any() else None,
                     "steps_warm_median": int(np.median(warm["steps"][~is_shock])) if (~is_shock).any() else None,
