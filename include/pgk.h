@@ -344,6 +344,24 @@ void pgk_mlp_destroy(pgk_mlp *m);
 /* Steps taken since the last pgk_init_fields. */
 int64_t pgk_steps_done(const pgk_ctx *ctx);
 
+/* Checkpoints.  Between steps the state of a grid is the content of its four
+ * bound buffers plus this clock: the steps taken, which population buffer
+ * holds the state, and whether the x ghosts hold what the next pull reads
+ * (and a face state changed since).  A caller that copies the buffers out
+ * (after synchronising the stream) with pgk_get_clock, and later back into a
+ * grid of the same shape, precision, equilibrium, parameters and faces
+ * followed by pgk_set_clock, continues bit for bit.  pgk_get_clock needs an
+ * initialised grid; pgk_set_clock needs bound buffers, parameters and face
+ * states, and marks the grid initialised (PGK_EINVAL for a bad clock). */
+typedef struct {
+    int64_t steps;
+    int cur;                 /* 0: PGK_BUF_POP0 holds the state, 1: PGK_BUF_POP1 */
+    int ghosts_ok;
+    int face_changed;
+} pgk_clock;
+int pgk_get_clock(const pgk_ctx *ctx, pgk_clock *out);
+int pgk_set_clock(pgk_ctx *ctx, const pgk_clock *in);
+
 /* Message of the last failed call on this context (never NULL). */
 const char *pgk_last_error(const pgk_ctx *ctx);
 

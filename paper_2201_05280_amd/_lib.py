@@ -24,7 +24,7 @@ NBUF = 4
 # every symbol include/pgk.h declares
 EXPORTS = ["pgk_resolve", "pgk_lattice", "pgk_equilibrium", "pgk_buffer_sizes", "pgk_create", "pgk_bind", "pgk_set_params",
            "pgk_set_bc_x", "pgk_init_fields", "pgk_step", "pgk_read_moments", "pgk_conserved",
-           "pgk_set_graph_steps", "pgk_set_timing", "pgk_kernel_times", "pgk_steps_done", "pgk_last_error", "pgk_destroy",
+           "pgk_set_graph_steps", "pgk_set_timing", "pgk_kernel_times", "pgk_get_clock", "pgk_set_clock", "pgk_steps_done", "pgk_last_error", "pgk_destroy",
            "pgk_batch_bytes", "pgk_batch_create", "pgk_batch_offsets", "pgk_batch_init", "pgk_batch_config",
            "pgk_batch_run", "pgk_batch_stall", "pgk_batch_tuned", "pgk_batch_read_moments", "pgk_batch_last_error",
            "pgk_batch_destroy", "pgk_mlp_bytes", "pgk_mlp_create", "pgk_mlp_set_params", "pgk_mlp_get_params",
@@ -40,6 +40,11 @@ class Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("precision", ctypes.c_int), ("variant", ctypes.c_int), ("equilibrium", ctypes.c_int),
                 ("bc_x", ctypes.c_int * 2)]
+
+
+class Clock(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("cur", ctypes.c_int), ("ghosts_ok", ctypes.c_int),
+                ("face_changed", ctypes.c_int)]
 
 
 class Params(ctypes.Structure):
@@ -97,6 +102,8 @@ def load():
     L.pgk_set_graph_steps.argtypes = [vp, ctypes.c_int]
     L.pgk_set_timing.argtypes = [vp, ctypes.c_int]
     L.pgk_kernel_times.argtypes = [vp, ctypes.c_double * NKERNEL, ctypes.c_int64 * NKERNEL]
+    L.pgk_get_clock.argtypes = [vp, ctypes.POINTER(Clock)]
+    L.pgk_set_clock.argtypes = [vp, ctypes.POINTER(Clock)]
     L.pgk_steps_done.argtypes = [vp]
     L.pgk_steps_done.restype = i64
     L.pgk_last_error.argtypes = [vp]

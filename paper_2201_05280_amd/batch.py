@@ -114,5 +114,22 @@ class Batch:
         self.stream.synchronize()
         return {k: v.cpu().numpy() for k, v in out.items()}
 
+    def checkpoint(self):
+        """A copy of the batch buffer: every case's populations, theta_R, step
+        count, residual and status live there, so restore() of it continues
+        bit for bit under a fixed config (an autotuned run may choose other
+        chunk lengths after a resume; stall windows restart)."""
+        self.stream.synchronize()
+        b = self.buf.clone()
+        self.torch.cuda.current_stream(self.device).synchronize()
+        return b
+
+    def restore(self, ckpt):
+        if ckpt.numel() != self.buf.numel():
+            raise ValueError("checkpoint of a different batch")
+        self.stream.synchronize()
+        self.buf.copy_(ckpt)
+        self.torch.cuda.current_stream(self.device).synchronize()
+
     def case_slice(self, c):
         return slice(int(self.off[c]), int(self.off[c + 1]))

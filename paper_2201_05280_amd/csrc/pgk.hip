@@ -1139,6 +1139,34 @@ extern "C" int pgk_kernel_times(pgk_ctx *c, double ms[PGK_NKERNEL], int64_t laun
 
 extern "C" int64_t pgk_steps_done(const pgk_ctx *c) { return c ? c->steps : -1; }
 
+extern "C" int pgk_get_clock(const pgk_ctx *c, pgk_clock *out)
+{
+    if (!c || !out) return PGK_EINVAL;
+    if (!c->initialised) return PGK_EINVAL;
+    out->steps = c->steps;
+    out->cur = c->cur;
+    out->ghosts_ok = c->ghosts_ok ? 1 : 0;
+    out->face_changed = c->face_changed ? 1 : 0;
+    return PGK_OK;
+}
+
+extern "C" int pgk_set_clock(pgk_ctx *c, const pgk_clock *in)
+{
+    if (!c || !in) return PGK_EINVAL;
+    if (!c->bound) return fail(c, PGK_ENOTBOUND, "buffers not bound");
+    if (!c->params_set) return fail(c, PGK_EINVAL, "parameters not set");
+    for (int side = 0; side < 2; side++)
+        if (c->k.bc[side] != PGK_PERIODIC && !c->bc_set[side])
+            return fail(c, PGK_EINVAL, "x face state not set (pgk_set_bc_x)");
+    if (in->steps < 0 || (in->cur != 0 && in->cur != 1)) return fail(c, PGK_EINVAL, "bad clock");
+    c->steps = in->steps;
+    c->cur = in->cur;
+    c->ghosts_ok = in->ghosts_ok != 0;
+    c->face_changed = in->face_changed != 0;
+    c->initialised = true;
+    return PGK_OK;
+}
+
 extern "C" const char *pgk_last_error(const pgk_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 extern "C" void pgk_destroy(pgk_ctx *c) { delete c; }

@@ -128,6 +128,44 @@ class Solver:
     def steps_done(self):
         return int(self.L.pgk_steps_done(self.h))
 
+    # ---- checkpoints -------------------------------------------------------
+    def checkpoint(self):
+        """The grid's state between steps: copies of the four bound buffers and
+        the step clock (pgk_get_clock).  restore() of it continues bit for bit."""
+        c = _lib.Clock()
+        self._check(self.L.pgk_get_clock(self.h, ctypes.byref(c)))
+        self.stream.synchronize()
+        bufs = [b.clone() for b in self.bufs]
+        self.torch.cuda.current_stream(self.device).synchronize()
+        return {"buffers": bufs, "clock": (int(c.steps), int(c.cur), int(c.ghosts_ok), int(c.face_changed))}
+
+    def restore(self, ckpt):
+        """Back to a checkpoint of a grid of the same shape, precision and
+        equilibrium (parameters and face states are the caller's to set, as
+        they were when the checkpoint was taken)."""
+        bufs = [self.torch.as_tensor(b) for b in ckpt["buffers"]]
+        if len(bufs) != len(self.bufs) or any(a.numel() != b.numel() for a, b in zip(bufs, self.bufs)):
+            raise ValueError("checkpoint of a different grid")
+        self.stream.synchronize()
+        for dst, src in zip(self.bufs, bufs):
+            dst.copy_(src.to(self.device))
+        self.torch.cuda.current_stream(self.device).synchronize()
+        c = _lib.Clock(*ckpt["clock"])
+        self._check(self.L.pgk_set_clock(self.h, ctypes.byref(c)))
+
+    def save(self, path):
+        """Write a checkpoint to `path` (numpy .npz, no pickled objects)."""
+        ck = self.checkpoint()
+        arrays = {"buf%d" % i: b.cpu().numpy() for i, b in enumerate(ck["buffers"])}
+        np.savez(path, clock=np.array(ck["clock"], dtype=np.int64), **arrays)
+
+    def load(self, path):
+        """Restore a checkpoint written by save()."""
+        with np.load(path, allow_pickle=False) as d:
+            ck = {"buffers": [d["buf%d" % i] for i in range(len(self.bufs))],
+                  "clock": tuple(int(v) for v in d["clock"])}
+        self.restore(ck)
+
     def moments_device(self):
         """f-moments as device tensors, written asynchronously on this solver's
         stream (synchronise it before reading them elsewhere)."""

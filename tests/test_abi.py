@@ -99,6 +99,12 @@ def test_null_arguments_are_errors_not_crashes():
     for k, rc in ((0, 0), (2, 0), (64, 0), (4096, 0), (3, -1), (-2, -1), (4098, -1)):
         assert L.pgk_set_graph_steps(out, k) == rc, k
     assert b"graph steps" in L.pgk_last_error(out)
+    # clocks: none before initialisation, none set on unbound buffers
+    clk = _lib.Clock()
+    assert L.pgk_get_clock(out, ctypes.byref(clk)) == -1
+    assert L.pgk_get_clock(None, ctypes.byref(clk)) == -1
+    assert L.pgk_set_clock(out, ctypes.byref(_lib.Clock(5, 0, 1, 0))) == -6
+    assert L.pgk_set_clock(out, None) == -1
     L.pgk_destroy(out)
     assert not math.isnan(1.0)
 
