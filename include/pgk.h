@@ -112,8 +112,10 @@ typedef struct {
 
 /* The model parameters of Sec. 4: relaxation times tau (ES-BGK part) and tau1
  * (BGK part and rotational relaxation), ES parameter b, k_r = kappa_R/kappa_T,
- * rotational degrees of freedom delta, lattice reference temperature theta0
- * (0 selects the printed value 0.2948964908710633). */
+ * rotational degrees of freedom delta (> 0: the rotational energy equation
+ * divides by it; a monatomic gas is approached with a small delta, as in the
+ * paper's table of fluids), lattice reference temperature theta0 (0 selects
+ * the printed value 0.2948964908710633). */
 typedef struct {
     double tau, tau1, b, kr, delta, theta0;
 } pgk_params;
@@ -141,7 +143,8 @@ typedef struct {
  * b is NaN: start from k_r = delta/5 (or the fixed kr), solve b from Pr, clamp b
  * to the ES range [-1/2, 1] (Sec. 2), then tau1/tau from the viscosity ratio,
  * k_r from Pr and tau from nu.  Returns PGK_EINFEASIBLE when mub_over_mu is at
- * or below the floor 2 delta / (3 (3+delta)) or k_r would be negative.  Host only. */
+ * or below the floor 2 delta / (3 (3+delta)) or k_r would be negative,
+ * PGK_EINVAL for delta <= 0 or non-positive targets.  Host only. */
 int pgk_resolve(const pgk_targets *t, pgk_resolved *out);
 
 /* The RD3Q41 velocity set (Sec. 5, table of velocities and weights) in the
@@ -170,7 +173,7 @@ int pgk_create(const pgk_grid *g, void *stream, pgk_ctx **out);
 int pgk_bind(pgk_ctx *ctx, void *const bufs[PGK_NBUF], const size_t bytes[PGK_NBUF]);
 
 /* Set the resolved parameters; `out` (may be NULL) receives the derived constants.
- * Returns PGK_EINVAL for tau, tau1 <= 0, delta < 0 or b outside [-1/2, 1]. */
+ * Returns PGK_EINVAL for tau, tau1 <= 0, delta <= 0 or b outside [-1/2, 1]. */
 int pgk_set_params(pgk_ctx *ctx, const pgk_params *p, pgk_resolved *out);
 
 /* Boundary data of x face `side` (0 low, 1 high): wall velocity and temperature

@@ -476,7 +476,7 @@ int pgko_threads(void)
 int pgko_set_params(pgko *o, double tau, double tau1, double b, double kr,
                     double delta, double theta0)
 {
-    if (!(tau > 0) || !(tau1 > 0) || !(delta >= 0) || !(theta0 > 0)) return -1;
+    if (!(tau > 0) || !(tau1 > 0) || !(delta > 0) || !(theta0 > 0)) return -1;
     o->tau = tau; o->tau1 = tau1; o->b = b; o->kr = kr; o->delta = delta; o->th0 = theta0;
     o->taus = tau * tau1 / (tau + tau1);                   /* 1/tau* = 1/tau + 1/tau1 */
     o->beta = 1.0 / (2.0 * o->taus + 1.0);                 /* beta* = dt/(2 tau* + dt) */

@@ -660,7 +660,7 @@ extern "C" int pgk_resolve(const pgk_targets *t, pgk_resolved *out)
     if (!t || !out) return PGK_EINVAL;
     double th0 = t->theta0 > 0 ? t->theta0 : THETA0_PRINTED;
     double d = t->delta, nu = t->nu, Pr = t->Pr, lb = t->mub_over_mu;
-    if (!(d >= 0) || !(nu > 0) || !(Pr > 0) || !(lb > 0)) return PGK_EINVAL;
+    if (!(d > 0) || !(nu > 0) || !(Pr > 0) || !(lb > 0)) return PGK_EINVAL;
     double cd = 2.0 * d / (3.0 * (3.0 + d));
     double b = t->b;
     if (std::isnan(b)) {
@@ -788,7 +788,7 @@ static int fill_bc(pgk_ctx *c)
 extern "C" int pgk_set_params(pgk_ctx *c, const pgk_params *p, pgk_resolved *out)
 {
     if (!c || !p) return PGK_EINVAL;
-    if (!(p->tau > 0) || !(p->tau1 > 0) || !(p->delta >= 0) || p->b < -0.5 || p->b > 1.0 || !(p->kr >= 0))
+    if (!(p->tau > 0) || !(p->tau1 > 0) || !(p->delta > 0) || p->b < -0.5 || p->b > 1.0 || !(p->kr >= 0))
         return fail(c, PGK_EINVAL, "parameters out of range");
     int rc0 = settle_ghosts(c);   // the pending pull keeps the old face equilibria
     if (rc0) return rc0;

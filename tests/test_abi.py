@@ -63,6 +63,8 @@ def test_resolver_rejects_infeasible():
         _lib.resolve(0.01, 0.71, 0.2, 2.0)       # below the floor 4/15
     with pytest.raises(ValueError):
         _lib.resolve(-1.0, 0.71, 0.6, 2.0)
+    with pytest.raises(ValueError):
+        _lib.resolve(0.01, 0.71, 0.6, 0.0)       # no rotational degrees of freedom
 
 
 def test_buffer_sizes_and_bad_grids():
@@ -93,6 +95,9 @@ def test_null_arguments_are_errors_not_crashes():
     assert L.pgk_step(out, 1) == -1
     assert b"not initialised" in L.pgk_last_error(out)
     p = _lib.Params(-1.0, 1.0, 0.0, 0.0, 2.0, 0.0)
+    assert L.pgk_set_params(out, ctypes.byref(p), None) == -1
+    # no rotational degrees of freedom: the rotational energy equation is void
+    p = _lib.Params(1.0, 1.0, 0.0, 0.0, 0.0, 0.0)
     assert L.pgk_set_params(out, ctypes.byref(p), None) == -1
     # graph chunk lengths: 0 or even, at most 4096
     assert L.pgk_set_graph_steps(None, 2) == -1
