@@ -220,3 +220,20 @@ def test_dirichlet_face_state_changed_mid_run(precision, bar):
             o.set_bc_x(0, oracle.DIRICHLET, *new)
     s.close()
     _assert_bar(errs, bar, "dirichlet change")
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
+@pytest.mark.parametrize("nx", [2, 3])
+def test_thinnest_bounded_grids(precision, bar, nx):
+    # the fewest cells between two faces: populations with |c_x| = 2 reach
+    # past the opposite face's first cell, every pull near a face reads ghosts
+    import paper_2201_05280_amd as pgk
+    th0 = oracle.THETA0
+    p = resolve(0.05, 0.71, 0.8, 2.0)
+    walls = [(pgk.WALL, 1.0, (0.0, 0.0, 0.0), th0), (pgk.WALL, 1.0, (0.0, 0.03, 0.0), th0 * 1.05)]
+    errs, _ = run_pair(nx, 3, 2, inputs.uniform(nx, 3, 2), p, 50, precision, bc=walls, checkpoints=[1, 2, 50])
+    _assert_bar(errs, bar, ("walls", nx))
+    dirichlet = [(pgk.DIRICHLET, 1.01, (0.02, 0.0, 0.0), th0), (pgk.DIRICHLET, 0.99, (0.02, 0.0, 0.0), th0 * 0.98)]
+    errs, _ = run_pair(nx, 1, 1, inputs.uniform(nx, 1, 1, u=(0.02, 0, 0)), p, 50, precision, bc=dirichlet,
+                       checkpoints=[1, 2, 50])
+    _assert_bar(errs, bar, ("dirichlet", nx))
