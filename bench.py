@@ -428,13 +428,13 @@ def sweep(args):
     ok = np.repeat(tr["status"] == 1, [2 * c["L"] for c in train])
     X = C.features(train)[ok]
     Y = C.targets(train, tr["m"])[ok]
-    mlp = MLP(nmax=8192)
+    mlp = MLP(nmax=max(8192, args.sweep_mlp_batch))
     mlp.set_params(mlp_init(S))
     t0 = time.perf_counter()
     losses = []
     for k, stage in enumerate(args.sweep_lr_schedule.split(",")):
         lr, ep = stage.split(":")
-        losses += list(mlp.train(X, Y, epochs=int(ep), batch=2048, lr=float(lr), seed=S + k))
+        losses += list(mlp.train(X, Y, epochs=int(ep), batch=args.sweep_mlp_batch, lr=float(lr), seed=S + k))
     t_train = time.perf_counter() - t0
     print("# mlp trained on %d points in %.1f s, loss %.3e -> %.3e" % (len(X), t_train, losses[0], losses[-1]),
           file=sys.stderr, flush=True)
@@ -511,6 +511,7 @@ def sweep(args):
         "mlp_inference_time": round(t_infer, 3), "mlp_train_time": round(t_train, 1),
         "mlp_train_points": int(len(X)),
         "mlp_loss_first_last": [float(losses[0]), float(losses[-1])], "mlp_schedule": args.sweep_lr_schedule,
+        "mlp_minibatch": args.sweep_mlp_batch,
         "mlp_loss_curve_every_5_epochs": [float("%.4g" % v) for v in losses[::5]],
         "couette": {"cold": counts(cold, ~is_shock), "warm": counts(warm, ~is_shock),
                     "steps_cold_median": int(np.median(cold["steps"][~is_shock])) if (~is_shock).any() else None,
@@ -553,6 +554,7 @@ def main():
     ap.add_argument("--sweep-knmin", type=float, default=1e-2)
     ap.add_argument("--sweep-knmax", type=float, default=1e-1)
     ap.add_argument("--sweep-max-steps", type=int, default=400000)
+    ap.add_argument("--sweep-mlp-batch", type=int, default=2048, help="MLP training minibatch")
     ap.add_argument("--sweep-lr-schedule", default="2e-3:40,5e-4:30,1.25e-4:30",
                     help="MLP training stages lr:epochs[,lr:epochs...] (Adam state carried across stages)")
     ap.add_argument("--sweep-plain", type=int, default=8)
