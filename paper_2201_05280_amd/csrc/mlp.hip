@@ -483,12 +483,13 @@ extern "C" int pgk_mlp_train(pgk_mlp *m, const float *X, const float *Y, int64_t
             int64_t t = order[i]; order[i] = order[j]; order[j] = t;
         }
         hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, m->stream, m->loss, 1);
+        // the gradient accumulator starts at zero; every Adam step clears it again
+        if (e == 0) hipLaunchKernelGGL(k_zero, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->grad, NPARAM);
         for (int64_t i = 0; i < nb; i++) {
             int64_t b0 = order[i] * batch;
             int c = (int)(n - b0 < batch ? n - b0 : batch);
             // gradients of the mean loss over this minibatch; the loss sum is
             // scaled so that one epoch reports the mean over all points
-            hipLaunchKernelGGL(k_zero, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->grad, NPARAM);
             int rc = loss_grad(m, X + b0 * NIN, Y + b0 * NOUT, c, 1.0f / (4.0f * c));
             if (rc) return rc;
             rc = pgk_mlp_adam_step(m, lr, 0.9f, 0.999f, 1e-8f);
