@@ -172,11 +172,13 @@ def copy_probe(torch, nbytes=4 << 30, reps=10, quick=False):
     return out
 
 
-def plain_case(case, tol, max_steps, time_cap, K=128):
-    """One case through the single-grid path (the plain, unbatched solver):
-    chunks of K steps with the one-step residual taken from two moment reads.
-    Stops at residual `tol`, `max_steps` or after `time_cap` seconds;
-    returns (steps, residual, seconds)."""
+def single_grid_run(case, fields, tol, max_steps, time_cap=1e30, K=128, stream=None, stall=0):
+    """One 1D case through the single-grid path: chunks of K steps, the
+    one-step residual taken from two moment reads at the end of each chunk
+    (the batched kernel's rule).  Stops at residual `tol` (status 1), a
+    non-finite residual (2), `max_steps` or `time_cap` seconds (3), or when the
+    residual has not halved within `stall` steps (4, 0 = off).  Returns
+    (steps, residual, status, moments, seconds)."""
     import numpy as np
 
     import paper_2201_05280_amd as pgk
@@ -185,7 +187,7 @@ def plain_case(case, tol, max_steps, time_cap, K=128):
     shock = case["kind"] == C.SHOCK
     kind = pgk.DIRICHLET if shock else pgk.WALL
     s = pgk.Solver(case["L"], 1, 1, precision=pgk.FP64, bc_x=(kind, kind),
-                   equilibrium=pgk.E2 if shock else pgk.F3)
+                   equilibrium=pgk.E2 if shock else pgk.F3, stream=stream)
     s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
     if shock:
         up, dn = case["up"], case["down"]
@@ -196,10 +198,9 @@ def plain_case(case, tol, max_steps, time_cap, K=128):
         s.set_bc_x(0, 1.0, (0, 0, 0), THETA0)
         s.set_bc_x(1, 1.0, (0, case["U"], 0), THETA0)
         axis = 1
-    f = C.cold_fields([case])
-    s.init(f["rho"], f["u"], f["thT"], f["thR"])
+    s.init(fields["rho"], fields["u"], fields["thT"], fields["thR"])
     t0 = time.perf_counter()
-    steps, resid = 0, 1.0
+    steps, resid, status, best, since, b = 0, 1.0, 3, 1e300, 0, None
     while steps < max_steps and time.perf_counter() - t0 < time_cap:
         s.step(K - 1)
         a = s.moments()
@@ -211,10 +212,27 @@ def plain_case(case, tol, max_steps, time_cap, K=128):
             x0 = a[k] if v is None else a[k][v]
             x1 = b[k] if v is None else b[k][v]
             resid = max(resid, float(np.linalg.norm(x1 - x0) / max(np.linalg.norm(x1), 1e-300)))
-        if resid <= tol or not np.isfinite(resid):
+        if not np.isfinite(resid):
+            status = 2
+            break
+        if resid <= tol:
+            status = 1
+            break
+        if resid < 0.5 * best:
+            best, since = resid, 0
+        elif stall and (since := since + K) >= stall:
+            status = 4
             break
     dt = time.perf_counter() - t0
     s.close()
+    return steps, resid, status, b, dt
+
+
+def plain_case(case, tol, max_steps, time_cap, K=128):
+    """One case from its cold start through the single-grid path (the plain,
+    unbatched solver); returns (steps, residual, seconds)."""
+    from paper_2201_05280_amd import cases as C
+    steps, resid, _, _, dt = single_grid_run(case, C.cold_fields([case]), tol, max_steps, time_cap, K)
     return steps, resid, dt
 
 
@@ -417,6 +435,7 @@ def sweep(args):
             m["u"][:, sel] = mm["u"]
             cfg.append({"kind": cs[idx[0]]["kind"], "cases": len(idx), "wg": tuned[0], "K": tuned[1],
                         "ns_per_site_update": round(tuned[2], 4), "wall_s": round(w, 2)})
+
         print("# %s: %.2f s, steps median %d max %d, status counts %s, configs %s"
               % (label, dt, np.median(steps), steps.max(), np.bincount(status, minlength=5).tolist(), cfg),
               file=sys.stderr, flush=True)
