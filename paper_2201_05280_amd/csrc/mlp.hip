@@ -420,7 +420,7 @@ static int loss_grad(pgk_mlp *m, const float *X, const float *Y, int n, float sc
                        np, m->dz);
     const int offW[3] = {OFF_W2, OFF_W3, OFF_W4}, offB[3] = {OFF_B2, OFF_B3, OFF_B4};
     float *dz = m->dz, *dzn = m->dz2;
-    const int kchunk = 256;
+    const int kchunk = 128;   // split-K depth of the weight gradients (128: 10% faster per minibatch than 256)
     for (int l = 2; l >= 0; l--) {
         // layer l+2 (0-based hidden index l+1): weights W_{l+2}, input a_l, output dz (of z_{l+1})
         hipLaunchKernelGGL(k_bias_grad, dim3(H), dim3(256), 0, m->stream, dz, np, m->grad + offB[l]);
