@@ -142,9 +142,13 @@ typedef struct {
 /* Parameter map (Sec. 4, shear and bulk viscosity, Prandtl number).  Rule when
  * b is NaN: start from k_r = delta/5 (or the fixed kr), solve b from Pr, clamp b
  * to the ES range [-1/2, 1] (Sec. 2), then tau1/tau from the viscosity ratio,
- * k_r from Pr and tau from nu.  Returns PGK_EINFEASIBLE when mub_over_mu is at
- * or below the floor 2 delta / (3 (3+delta)) or k_r would be negative,
- * PGK_EINVAL for delta <= 0 or non-positive targets.  Host only. */
+ * k_r from Pr and tau from nu.  An explicit b may also lie above 1, up to
+ * B = 1 + tau/tau1 (positive shear viscosity), as the Landau-number runs of
+ * Sec. 6 at Pr 5 and 10 need; b = 1 exactly leaves tau1/tau undetermined.
+ * Returns PGK_EINFEASIBLE when no positive tau1/tau meets mub_over_mu (for
+ * b < 1: mub_over_mu at or below the floor 2 delta / (3 (3+delta)); for b > 1:
+ * above it), when b is 1, below -1/2 or at or above B, or k_r would be
+ * negative; PGK_EINVAL for delta <= 0 or non-positive targets.  Host only. */
 int pgk_resolve(const pgk_targets *t, pgk_resolved *out);
 
 /* The RD3Q41 velocity set (Sec. 5, table of velocities and weights) in the
@@ -173,7 +177,12 @@ int pgk_create(const pgk_grid *g, void *stream, pgk_ctx **out);
 int pgk_bind(pgk_ctx *ctx, void *const bufs[PGK_NBUF], const size_t bytes[PGK_NBUF]);
 
 /* Set the resolved parameters; `out` (may be NULL) receives the derived constants.
- * Returns PGK_EINVAL for tau, tau1 <= 0, delta <= 0 or b outside [-1/2, 1]. */
+ * Returns PGK_EINVAL for tau, tau1 <= 0, delta <= 0, kr < 0, b < -1/2 or
+ * b >= 1 + tau/tau1 (zero or negative shear viscosity).  b in (1, 1 + tau/tau1)
+ * lies beyond the ES range of Sec. 2, where the covariance T I + b sigma/rho can
+ * lose positive definiteness far from equilibrium: accepted for PGK_F3 and
+ * PGK_F4 (polynomial targets, as the Landau-number runs of Sec. 6 use it) and
+ * refused with PGK_EINVAL on a PGK_E2 grid. */
 int pgk_set_params(pgk_ctx *ctx, const pgk_params *p, pgk_resolved *out);
 
 /* Boundary data of x face `side` (0 low, 1 high): wall velocity and temperature

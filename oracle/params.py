@@ -38,7 +38,11 @@ def resolve(nu, Pr, lam_b, delta, theta0=THETA0, b=None, kr=None):
 
     The map has one free direction.  Rule: start from k_r = delta/5; solve b
     from Pr; clamp b to the ES range [-1/2, 1]; then tau1/tau from eta_b/eta,
-    k_r from Pr, tau from nu.  An explicit b (or k_r) replaces that step.
+    k_r from Pr, tau from nu.  An explicit b (or k_r) replaces that step.  An
+    explicit b may exceed 1 (Sec. 6 runs its Landau-number table at Pr 5 and
+    10 with tau = 3 tau1/5 and k_r = 0, which needs b = 1.152 and 1.376); it
+    must stay below B = 1 + tau/tau1, where the shear viscosity p tau/(B - b)
+    is positive.
     """
     cd = 2.0 * delta / (3.0 * (3.0 + delta))
     if b is None:
@@ -53,13 +57,17 @@ def resolve(nu, Pr, lam_b, delta, theta0=THETA0, b=None, kr=None):
         B = 1.0 + 1.0 / r
         b = B * (1.0 - 1.0 / P)
         b = min(max(b, -0.5), 1.0)
-    if b < 1.0:
-        r = (lam_b / cd - 1.0) / (1.0 - b)  # tau1/tau from lam_b = cd (1 + (1-b) tau1/tau)
-        if not r > 0:
-            raise ValueError("infeasible: eta_b/eta below the floor 2 delta/(3(3+delta))")
-    else:
+    if b == 1.0:
         raise ValueError("b = 1 needs an explicit tau1")
+    if b < -0.5:
+        raise ValueError("b below the ES range")
+    r = (lam_b / cd - 1.0) / (1.0 - b)      # tau1/tau from lam_b = cd (1 + (1-b) tau1/tau)
+    if not r > 0:
+        raise ValueError("infeasible: no positive tau1/tau gives this eta_b/eta "
+                         "(b < 1 needs it above 2 delta/(3(3+delta)), b > 1 below)")
     B = 1.0 + 1.0 / r
+    if not b < B:
+        raise ValueError("infeasible: b >= 1 + tau/tau1 (no positive shear viscosity)")
     kr_new = (B / (B - b)) * (1.0 + delta / 5.0) / Pr - 1.0
     if kr_new < -1e-12:
         raise ValueError("infeasible: k_r < 0")

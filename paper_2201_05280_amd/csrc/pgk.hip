@@ -672,10 +672,13 @@ extern "C" int pgk_resolve(const pgk_targets *t, pgk_resolved *out)
         b = B * (1.0 - 1.0 / P);
         b = std::fmin(std::fmax(b, -0.5), 1.0);
     }
-    if (!(b < 1.0) || b < -0.5) return PGK_EINFEASIBLE;
+    // b = 1 leaves tau1/tau free; an explicit b > 1 (the Landau-number runs of
+    // Sec. 6 at Pr 5 and 10) pairs with a viscosity ratio below the floor
+    if (!(b != 1.0) || b < -0.5) return PGK_EINFEASIBLE;
     double r = (lb / cd - 1.0) / (1.0 - b);              // eta_b/eta = cd (1 + (1-b) tau1/tau)
     if (!(r > 0)) return PGK_EINFEASIBLE;
     double B = 1.0 + 1.0 / r;
+    if (!(b < B)) return PGK_EINFEASIBLE;                // shear viscosity p tau/(B - b) > 0
     double kr = (B / (B - b)) * (1.0 + d / 5.0) / Pr - 1.0;
     if (kr < -1e-12) return PGK_EINFEASIBLE;
     kr = std::fmax(kr, 0.0);
@@ -788,8 +791,13 @@ static int fill_bc(pgk_ctx *c)
 extern "C" int pgk_set_params(pgk_ctx *c, const pgk_params *p, pgk_resolved *out)
 {
     if (!c || !p) return PGK_EINVAL;
-    if (!(p->tau > 0) || !(p->tau1 > 0) || !(p->delta > 0) || p->b < -0.5 || p->b > 1.0 || !(p->kr >= 0))
+    if (!(p->tau > 0) || !(p->tau1 > 0) || !(p->delta > 0) || !(p->b >= -0.5) || !(p->kr >= 0) ||
+        !(p->b < 1.0 + p->tau / p->tau1))
         return fail(c, PGK_EINVAL, "parameters out of range");
+    // beyond b = 1 the ES covariance can lose positive definiteness (Sec. 2); the
+    // polynomial targets stay defined, the exponential E2 target does not
+    if (p->b > 1.0 && c->g.equilibrium == PGK_E2)
+        return fail(c, PGK_EINVAL, "b > 1 needs a polynomial equilibrium (F3 or F4)");
     int rc0 = settle_ghosts(c);   // the pending pull keeps the old face equilibria
     if (rc0) return rc0;
     c->face_changed = true;

@@ -45,12 +45,8 @@ def test_resolver_landau_table_case():
         Pr, La = float(Pr), float(La)
         lb = 224.0 / (225.0 * Pr)
         # fix b so that tau/tau1 = 0.6: B = 1.6, b = B - 1.4 B / Pr
+        # (b = 1.152 and 1.376 at Pr 5 and 10: beyond the ES range, below B)
         b = 1.6 - 1.6 * 1.4 / Pr
-        if b > 1.0:
-            # the printed cases Pr = 5, 10 need b > 1, outside the ES range
-            with pytest.raises(ValueError):
-                _lib.resolve(0.01, Pr, lb, 2.0, b=b)
-            continue
         r = _lib.resolve(0.01, Pr, lb, 2.0, b=b)
         assert abs(r["tau"] / r["tau1"] - 0.6) < 1e-12
         assert abs(r["kr"]) < 1e-12
@@ -160,3 +156,18 @@ def test_lattice_and_equilibrium_exports():
                               lam.ctypes.data_as(P), out.ctypes.data_as(P)) == -1
     assert Lb.pgk_equilibrium(9, ctypes.c_double(0), ctypes.c_double(1.0), u.ctypes.data_as(P),
                               lam.ctypes.data_as(P), out.ctypes.data_as(P)) == -1
+
+
+def test_resolver_b_above_one_bounds():
+    # b = 1 leaves tau1/tau free; for b > 1 the viscosity ratio must lie below
+    # the b < 1 floor 4/15 (delta = 2); b < B = 1 + tau/tau1 then follows
+    for b, lb in ((1.0, 0.2), (1.2, 0.6), (-0.6, 0.6)):
+        with pytest.raises(ValueError):
+            _lib.resolve(0.01, 5.0, lb, 2.0, b=b)
+    # tau1/tau = 1.25, B = 1.8, B/(B - b) = 3: Pr 3 with k_r = 0.4
+    r = _lib.resolve(0.01, 3.0, 0.2, 2.0, b=1.2)
+    assert abs(r["tau1"] / r["tau"] - 1.25) < 1e-12 and abs(r["kr"] - 0.4) < 1e-12
+    assert abs(r["nu"] - 0.01) < 1e-15 and abs(r["mub_over_mu"] - 0.2) < 1e-14
+    assert abs(r["Pr"] - 3.0) < 1e-12
+    with pytest.raises(ValueError):
+        _lib.resolve(0.01, 5.0, 0.2, 2.0, b=1.2)   # k_r would be -0.16

@@ -741,14 +741,30 @@ def test_f4_conduction_between_walls_at_different_temperatures_is_linear():
     assert abs(_conduction_curvature(oracle.F3)) > 0.1
 
 
+def test_resolver_takes_an_explicit_b_above_one_up_to_B():
+    # the Landau-table settings (tau = 3 tau1/5, k_r = 0) at Pr 5 and 10 need
+    # b > 1 with eta_b/eta = 224/(225 Pr) below the b < 1 floor 4/15 (with
+    # eta_b/eta > 0, b < B then holds by itself: B - b = (b - 1) lam_b/(cd - lam_b))
+    for Pr, bb in ((5.0, 1.152), (10.0, 1.376)):
+        p = resolve(0.01, Pr, 224.0 / (225.0 * Pr), 2.0, b=1.6 - 2.24 / Pr)
+        assert abs(p["b"] - bb) < 1e-12
+        assert abs(p["tau"] / p["tau1"] - 0.6) < 1e-12 and abs(p["kr"]) < 1e-12
+        co = coefficients(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+        assert abs(co["nu"] - 0.01) < 1e-15 and abs(co["Pr"] - Pr) < 1e-12
+    with pytest.raises(ValueError):
+        resolve(0.01, 5.0, 0.2, 2.0, b=1.0)          # tau1/tau undetermined
+    with pytest.raises(ValueError):
+        resolve(0.01, 5.0, 0.6, 2.0, b=1.2)          # above the floor: tau1/tau < 0
+    with pytest.raises(ValueError):
+        resolve(0.01, 1.0, 0.6, 2.0, b=-0.6)
+
+
 def test_landau_numbers_of_the_table_from_pulse_spreading():
-    # Sec. 6, Table "La vs Pr": the rows reachable with b <= 1 (Pr 1.4, b = 0;
-    # Pr 2, b = 0.48), measured from the spreading of a sound pulse
+    # Sec. 6, Table "La vs Pr", every row (b = 0, 0.48, 1.152, 1.376 for Pr
+    # 1.4, 2, 5, 10), measured from the spreading of a sound pulse
     from tests import sec6
     for Pr, La in read_golden("landau_table.txt"):
         Pr, La = float(Pr), float(La)
-        if 1.6 - 1.6 * 1.4 / Pr > 1.0:
-            continue
         la, speed = sec6.landau_pulse(_oracle_runner, Pr)
         assert abs(la / La - 1) < 0.01, (Pr, la, La)
         assert abs(speed / np.sqrt(1.4 * TH0) - 1) < 1e-3

@@ -155,12 +155,30 @@ def test_weak_shock_has_the_taylor_thickness_and_the_jump_speed(precision, equil
 def test_landau_numbers_of_the_table_from_pulse_spreading(precision):
     for Pr, La in read_golden("landau_table.txt"):
         Pr, La = float(Pr), float(La)
-        if 1.6 - 1.6 * 1.4 / Pr > 1.0:
-            continue   # b > 1: outside the ES range
         la, speed = sec6.landau_pulse(_runner(precision), Pr)
         print("Pr", Pr, "La", la, "printed", La)
         assert abs(la / La - 1) < 0.01, (Pr, la, La)
         assert abs(speed / np.sqrt(1.4 * TH0) - 1) < 1e-3
+
+
+def test_set_params_bounds_on_b():
+    # b in (1, 1 + tau/tau1) is taken on F3 and F4 grids and refused on E2
+    # grids; b at or above 1 + tau/tau1 (no positive shear viscosity) and
+    # below -1/2 everywhere
+    import paper_2201_05280_amd as pgk
+    for eq in (pgk.F3, pgk.F4, pgk.E2):
+        s = pgk.Solver(8, 1, 1, precision=pgk.FP64, equilibrium=eq)
+        s.set_params(0.3, 0.5, 1.0, 0.0, 2.0)
+        if eq == pgk.E2:
+            with pytest.raises(RuntimeError):
+                s.set_params(0.3, 0.5, 1.3, 0.0, 2.0)
+        else:
+            r = s.set_params(0.3, 0.5, 1.5, 0.0, 2.0)
+            assert abs(r["Pr"] - 1.4 * 1.6 / 0.1) < 1e-9
+        for b in (1.6, 2.0, -0.51):
+            with pytest.raises(RuntimeError):
+                s.set_params(0.3, 0.5, b, 0.0, 2.0)
+        s.close()
 
 
 @pytest.mark.parametrize("precision,tol", [(0, 2e-5), (1, 2e-4)])
