@@ -248,17 +248,22 @@ __global__ __launch_bounds__(TWG) void k_tr(const double *__restrict__ that_, co
     fetch(I0{}, z0 - 1, z0 - 2);
     fetch(I1{}, z0, z0 - 1);
 
+    // theta_hat of this thread's column at the previous plane, taken from the
+    // LDS ring while it still holds that plane (the output plane lags by one)
+    double th_prev = 0.0;
+    const int hc = (lyo + 2) * HX + lxo + 2;
+
     auto iteration = [&](auto slot, int zz) {
         const int rz = zz + 4;                          // non-negative ring index
         stash(slot, (rz + 1) & 1, rz % 3);             // theta_hat(zz+1), u(zz), rho theta(zz)
         if (zz + 2 <= zend) fetch(slot, zz + 3, zz + 2);   // iteration zz+2, in flight for two planes
         const int zo = zz - 1;                          // output plane of this iteration
-        double o_rho = 0.0, o_v = 0.0, o_th = 0.0;
+        double o_rho = 0.0, o_v = 0.0;
+        const double o_th = th_prev;                    // theta_hat(zo)
         if (zz >= z0 + 1 && outv) {
             int g = zoff(zo) + oo;
             o_rho = (double)aux[(size_t)3 * k.ns + g];
             o_v = thR[g];
-            o_th = that_[g];
         }
         __syncthreads();
         // predictor theta*(zz) = th - sum_a u_a (th(+e_a) - th), region origin -2
@@ -309,6 +314,7 @@ __global__ __launch_bounds__(TWG) void k_tr(const double *__restrict__ that_, co
                 thR[g] = (t + DR * lap + k.X * o_v) * k.inv1X;
             }
         }
+        th_prev = l_th[rz & 1][hc];                     // theta_hat(zz), the next output plane
         __syncthreads();
     };
 
