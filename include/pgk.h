@@ -234,9 +234,11 @@ int pgk_conserved(pgk_ctx *ctx, double out[5]);
  * the launch counts of [0] the fused pull-collide kernel, [1] the MacCormack
  * advection (on a periodic grid with one diffusion sub-step: the single fused
  * transport kernel, advection + diffusion + second half), [2] the diffusion
- * and second half relaxation (on a grid of at most 4096 sites otherwise
- * bounded or sub-cycled: the whole transport in one work-group), [3] the x
- * ghost fill, and clears the record.  Event handles are created on demand and
+ * and second half relaxation (on a bounded or sub-cycled grid of at most 4096
+ * sites: the whole transport in one work-group; on such a line, ny = nz = 1,
+ * of more than 4096 sites with at most 63 sub-steps: the whole transport in
+ * one launch of 1024-cell work-groups), [3] the x ghost fill, and clears the
+ * record.  Event handles are created on demand and
  * kept until pgk_destroy. */
 #define PGK_NKERNEL 4
 int pgk_set_timing(pgk_ctx *ctx, int enable);

@@ -108,6 +108,119 @@ __global__ __launch_bounds__(TR_SMALL_WG) void k_tr_small(const double *__restri
     for (int s = threadIdx.x; s < k.ns; s += TR_SMALL_WG) dif_site<A, VAR, BOUNDED, true>(s, tin, tout, that_, aux, thR, k);
 }
 
+// The theta_R transport of a line (ny = nz = 1) longer than TR_SMALL sites,
+// bounded or sub-cycled, in one launch.  Along a line the transport is two
+// independent 1D problems, one per sublattice.  A work-group owns TL_C cells of
+// one sublattice and stages them with a halo of H = nsub + 1 cells on each
+// side (theta_hat, u_x, rho, kfac rho theta); MacCormack and every FTCS
+// sub-step then run in LDS, the valid window shrinking by one cell per stage,
+// so the halo cells are recomputed by both neighbours and no work-group waits
+// for another.  The y and z terms of the stencils of mc_site / dif_site vanish
+// on a line (their neighbours are the site itself and add exact zeros), and
+// the x terms are evaluated in the same order: the same bits as k_mc + k_dif.
+constexpr int TL_C = 1024, TL_WG = 1024, TL_HMAX = 64, TL_L = TL_C + 2 * TL_HMAX;
+
+template <typename A, int VAR, bool BOUNDED>
+__global__ __launch_bounds__(TL_WG) void k_tr_line(const double *__restrict__ that_, const A *__restrict__ aux,
+                                                   double *__restrict__ thR, Consts k)
+{
+    __shared__ double l_th[TL_L], l_u[TL_L], l_rho[TL_L], l_ks[TL_L], l_a[TL_L], l_b[TL_L];
+    const int nx = k.nx, nchunk = (nx + TL_C - 1) / TL_C;
+    const int sub = blockIdx.x / nchunk, x0 = (blockIdx.x - sub * nchunk) * TL_C;
+    const int H = k.nsub + 1, nout = min(TL_C, nx - x0), Lw = nout + 2 * H;   // Lw <= TL_L (host check)
+    const int base = sub * nx, tid = threadIdx.x;
+    // window cell i is the line's cell x0 - H + i (wrapped on a periodic line);
+    // on a bounded line the cells beyond a face hold nothing and are never read
+    auto cell = [&](int i, bool &in) {
+        int x = x0 - H + i;
+        if (BOUNDED) {
+            in = x >= 0 && x < nx;
+            return x;
+        }
+        in = true;
+        x %= nx;
+        return x < 0 ? x + nx : x;
+    };
+    for (int i = tid; i < Lw; i += TL_WG) {
+        bool in;
+        int x = cell(i, in);
+        if (in) {
+            int s = base + x;
+            l_th[i] = that_[s];
+            l_u[i] = (double)aux[s];
+            l_rho[i] = (double)aux[(size_t)3 * k.ns + s];
+            l_ks[i] = k.kfac * (double)aux[(size_t)4 * k.ns + s];
+        }
+    }
+    __syncthreads();
+    // predictor theta* on [0, Lw-1)
+    for (int i = tid; i < Lw - 1; i += TL_WG) {
+        bool in;
+        int x = cell(i, in);
+        if (!in) continue;
+        double t = l_th[i];
+        double tp = (BOUNDED && x + 1 >= nx) ? k.thbc[1] : l_th[i + 1];
+        double adv = 0.0;
+        adv += l_u[i] * (tp - t);
+        l_a[i] = t - adv;
+    }
+    __syncthreads();
+    // corrector theta^mc on [1, Lw-1)
+    for (int i = tid + 1; i < Lw - 1; i += TL_WG) {
+        bool in;
+        int x = cell(i, in);
+        if (!in) continue;
+        double ts = l_a[i];
+        double tm = (BOUNDED && x - 1 < 0) ? k.thbc[0] : l_a[i - 1];
+        double adv = 0.0;
+        adv += l_u[i] * (ts - tm);
+        l_b[i] = 0.5 * (l_th[i] + ts - adv);
+    }
+    __syncthreads();
+    double *tin = l_b, *tout = l_a;
+    for (int j = 1; j <= k.nsub; j++) {
+        const bool last = j == k.nsub;
+        for (int i = tid + 1 + j; i < Lw - 1 - j; i += TL_WG) {   // the last stage covers exactly the outputs
+            bool in;
+            int x = cell(i, in);
+            if (!in) continue;
+            double rho = l_rho[i], ks = l_ks[i], t = tin[i];
+            double flux = 0.0, lap = 0.0;
+#pragma unroll
+            for (int dir = -1; dir <= 1; dir += 2) {
+                double tq, kq;
+                bool face = BOUNDED && (dir < 0 ? x - 1 < 0 : x + 1 >= nx);
+                if (face) {
+                    bool hi = dir > 0;
+                    tq = hi ? k.thbc[1] : k.thbc[0];
+                    bool wall = (hi ? k.bc[1] : k.bc[0]) == PGK_WALL;
+                    double rg = wall ? rho : (hi ? k.rhobc[1] : k.rhobc[0]);
+                    kq = k.kfac * rg * tq;
+                } else {
+                    tq = tin[i + dir];
+                    kq = l_ks[i + dir];
+                }
+                flux += 0.5 * (ks + kq) * (tq - t);
+                lap += tq - t;
+            }
+            double tdif = VAR == PGK_CN ? t + k.isub * 2.0 * flux / (rho * k.delta)
+                                        : t + k.isub * 2.0 * ks / (rho * k.delta) * lap;
+            if (!last) {
+                tout[i] = tdif;
+            } else {
+                int s = base + x;
+                double v = thR[s];
+                if (VAR == PGK_CN) thR[s] = tdif + (l_th[i] - v);
+                else thR[s] = (tdif + k.X * v) * k.inv1X;
+            }
+        }
+        __syncthreads();
+        double *t = tin;
+        tin = tout;
+        tout = t;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_tr: fused theta_R transport on periodic grids (steps 2-4 in one pass).
 // A work-group owns a TX x TY tile of one sublattice and marches through TZ
@@ -956,7 +1069,13 @@ static int step_t(pgk_ctx *c, int64_t n)
                                c->lmul, c->k);
         }
         mark(c, 0);
-        if ((BND || c->k.nsub > 1) && c->k.ns <= TR_SMALL) {
+        if ((BND || c->k.nsub > 1) && c->k.ns > TR_SMALL && c->k.ny == 1 && c->k.nz == 1 &&
+            c->k.nsub + 1 <= TL_HMAX) {
+            int nchunk = (c->k.nx + TL_C - 1) / TL_C;
+            hipLaunchKernelGGL((k_tr_line<A, VAR, BND>), dim3(2 * nchunk), dim3(TL_WG), 0, c->stream, c->that_,
+                               (const A *)c->aux, (double *)c->buf[PGK_BUF_THETAR], c->k);
+            mark(c, 2);
+        } else if ((BND || c->k.nsub > 1) && c->k.ns <= TR_SMALL) {
             hipLaunchKernelGGL((k_tr_small<A, VAR, BND>), dim3(1), dim3(TR_SMALL_WG), sizeof(double) * 2 * c->k.ns,
                                c->stream, c->that_, (const A *)c->aux, (double *)c->buf[PGK_BUF_THETAR], c->k);
             mark(c, 2);

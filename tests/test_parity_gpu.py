@@ -192,6 +192,30 @@ def test_subcycled_diffusion_paths(precision, bar):
 
 
 @pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
+@pytest.mark.parametrize("nx", [2049, 2100])
+def test_long_lines_transport_in_one_launch(precision, bar, nx):
+    # lines of more than 4096 sites, bounded or sub-cycled: the theta_R
+    # transport runs in work-groups of 1024 cells with a halo of nsub + 1
+    # (2049 cells: a last chunk of one cell; 2100: of 52); walls with a
+    # temperature step, Dirichlet faces with inflow, and a periodic line, each
+    # with 1, 3 and 11 diffusion sub-steps
+    import paper_2201_05280_amd as pgk
+    th0 = oracle.THETA0
+    f = inputs.random_smooth(nx, 1, 1, seed=nx, amp_u=0.02, amp_th=0.05)
+    for nu, steps in ((0.05, 12), (0.5, 12), (2.0, 8)):
+        p = resolve(nu, 0.71, 0.8, 2.0)
+        bc = [(pgk.WALL, 1.0, (0.0, 0.0, 0.0), 0.95 * th0), (pgk.WALL, 1.0, (0.0, 0.03, 0.0), 1.05 * th0)]
+        errs, _ = run_pair(nx, 1, 1, f, p, steps, precision, bc=bc, checkpoints=[1, 2, steps])
+        _assert_bar(errs, bar, ("walls", nu))
+        bc = [(pgk.DIRICHLET, 1.01, (0.02, 0.0, 0.0), 1.02 * th0), (pgk.DIRICHLET, 0.99, (0.02, 0.0, 0.0), th0)]
+        errs, _ = run_pair(nx, 1, 1, f, p, steps, precision, bc=bc, checkpoints=[1, steps])
+        _assert_bar(errs, bar, ("dirichlet", nu))
+        if nu > 0.1:
+            errs, _ = run_pair(nx, 1, 1, f, p, steps, precision, checkpoints=[1, steps])
+            _assert_bar(errs, bar, ("periodic", nu))
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
 def test_dirichlet_face_state_changed_mid_run(precision, bar):
     # Dirichlet ghosts are written once per face state: a new state given
     # between calls must reach the next step (graph-replayed and direct)
