@@ -290,7 +290,10 @@ int pgk_batch_bytes(const pgk_case *cases, int n, size_t *bytes);
 
 /* Create a batch on `stream` over the caller's device buffer `buf` (256-byte
  * aligned, at least pgk_batch_bytes).  Case c owns sites [off_c, off_c + 2 L_c)
- * of every per-site field; pgk_batch_offsets() returns off_0..off_n. */
+ * of every per-site field; pgk_batch_offsets() returns off_0..off_n.  A case
+ * must keep b within the ES range [-1/2, 1] of Sec. 2 (a batch may hold E2
+ * cases, whose target needs a definite covariance), besides 4 <= L <= 8192
+ * and positive tau, tau1, delta and face temperatures: PGK_EINVAL otherwise. */
 int pgk_batch_create(const pgk_case *cases, int n, void *stream, void *buf, size_t bytes, pgk_batch **out);
 int pgk_batch_offsets(const pgk_batch *b, int64_t *off);
 

@@ -132,6 +132,10 @@ def test_batch_case_checks():
     w = _case(16)
     w.u[0][0] = 0.1                                                     # a wall cannot move normal to itself
     assert L.pgk_batch_bytes((_lib.Case * 1)(w), 1, ctypes.byref(nb)) == -1
+    for bb, rc in ((1.0, 0), (-0.5, 0), (1.2, -1), (-0.6, -1)):         # batched cases keep b in [-1/2, 1]
+        w = _case(16)
+        w.p.b = bb
+        assert L.pgk_batch_bytes((_lib.Case * 1)(w), 1, ctypes.byref(nb)) == rc, bb
     # E2 batches carry the per-site Newton multipliers: a larger buffer
     n3, ne = ctypes.c_size_t(), ctypes.c_size_t()
     assert L.pgk_batch_bytes((_lib.Case * 1)(_case(64)), 1, ctypes.byref(n3)) == 0
