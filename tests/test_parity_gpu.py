@@ -213,6 +213,15 @@ def test_long_lines_transport_in_one_launch(precision, bar, nx):
         if nu > 0.1:
             errs, _ = run_pair(nx, 1, 1, f, p, steps, precision, checkpoints=[1, steps])
             _assert_bar(errs, bar, ("periodic", nu))
+    # the printed (LIT) variant on the same path, and 78 sub-steps: beyond the
+    # halo the work-groups hold, so the transport falls back to 1 + n_sub launches
+    p = resolve(0.5, 0.71, 0.8, 2.0)
+    bc = [(pgk.WALL, 1.0, (0.0, 0.0, 0.0), 0.95 * th0), (pgk.WALL, 1.0, (0.0, 0.03, 0.0), 1.05 * th0)]
+    errs, _ = run_pair(nx, 1, 1, f, p, 10, precision, variant=1, bc=bc, checkpoints=[1, 10])
+    _assert_bar(errs, bar, "walls, printed variant")
+    p = resolve(15.0, 0.71, 0.8, 2.0)
+    errs, _ = run_pair(nx, 1, 1, f, p, 4, precision, checkpoints=[1, 4])
+    _assert_bar(errs, bar, "periodic, 78 sub-steps")
 
 
 @pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
