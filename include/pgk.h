@@ -228,6 +228,20 @@ int pgk_read_moments(pgk_ctx *ctx, double *rho, double *u, double *theta_T,
  * the context stream; `out` is host memory. */
 int pgk_conserved(pgk_ctx *ctx, double out[5]);
 
+/* The theta_R transport (Sec. 5, steps 2-4) by its plain reference kernels on
+ * every grid (on != 0): one MacCormack launch and n_sub diffusion launches
+ * that read and write global memory only, instead of the LDS kernels chosen by
+ * grid shape (the fused periodic kernel, the one-work-group kernel of small
+ * grids, the line kernel with its halo).  The one-work-group kernel runs the
+ * reference kernels' per-site code, so its results are the same bits; the
+ * fused periodic and line kernels evaluate the same formulas in the same
+ * order, with fused multiply-adds that the compiler may round differently, and
+ * agree to round-off.  The switch checks the LDS kernels (a
+ * missing barrier or a halo indexing slip shows as a difference) and costs
+ * speed only.  Takes effect at the next pgk_step; recorded step graphs are
+ * dropped.  Off by default. */
+int pgk_set_transport_reference(pgk_ctx *ctx, int on);
+
 /* Per-kernel timing with HIP events on the context stream.  While enabled,
  * pgk_step records an event before its first launch and after every launch.
  * pgk_kernel_times() waits for the stream, returns the summed milliseconds and

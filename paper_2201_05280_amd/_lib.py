@@ -24,7 +24,7 @@ NBUF = 4
 # every symbol include/pgk.h declares
 EXPORTS = ["pgk_resolve", "pgk_lattice", "pgk_equilibrium", "pgk_buffer_sizes", "pgk_create", "pgk_bind", "pgk_set_params",
            "pgk_set_bc_x", "pgk_init_fields", "pgk_step", "pgk_read_moments", "pgk_conserved",
-           "pgk_set_graph_steps", "pgk_set_timing", "pgk_kernel_times", "pgk_get_clock", "pgk_set_clock", "pgk_steps_done", "pgk_last_error", "pgk_destroy",
+           "pgk_set_graph_steps", "pgk_set_transport_reference", "pgk_set_timing", "pgk_kernel_times", "pgk_get_clock", "pgk_set_clock", "pgk_steps_done", "pgk_last_error", "pgk_destroy",
            "pgk_batch_bytes", "pgk_batch_create", "pgk_batch_offsets", "pgk_batch_init", "pgk_batch_config",
            "pgk_batch_run", "pgk_batch_stall", "pgk_batch_tuned", "pgk_batch_read_moments", "pgk_batch_last_error",
            "pgk_batch_destroy", "pgk_mlp_bytes", "pgk_mlp_create", "pgk_mlp_set_params", "pgk_mlp_get_params",
@@ -100,6 +100,7 @@ def load():
     L.pgk_read_moments.argtypes = [vp, vp, vp, vp, vp, vp]
     L.pgk_conserved.argtypes = [vp, dp]
     L.pgk_set_graph_steps.argtypes = [vp, ctypes.c_int]
+    L.pgk_set_transport_reference.argtypes = [vp, ctypes.c_int]
     L.pgk_set_timing.argtypes = [vp, ctypes.c_int]
     L.pgk_kernel_times.argtypes = [vp, ctypes.c_double * NKERNEL, ctypes.c_int64 * NKERNEL]
     L.pgk_get_clock.argtypes = [vp, ctypes.POINTER(Clock)]

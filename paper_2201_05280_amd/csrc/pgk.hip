@@ -117,7 +117,9 @@ __global__ __launch_bounds__(TR_SMALL_WG) void k_tr_small(const double *__restri
 // so the halo cells are recomputed by both neighbours and no work-group waits
 // for another.  The y and z terms of the stencils of mc_site / dif_site vanish
 // on a line (their neighbours are the site itself and add exact zeros), and
-// the x terms are evaluated in the same order: the same bits as k_mc + k_dif.
+// the x terms are evaluated in the same order; the compiler's fused
+// multiply-adds may still round differently, so the results agree with
+// k_mc + k_dif to round-off (a last bit here and there), not bit for bit.
 constexpr int TL_C = 1024, TL_WG = 1024, TL_HMAX = 64, TL_L = TL_C + 2 * TL_HMAX;
 
 template <typename A, int VAR, bool BOUNDED>
@@ -556,6 +558,7 @@ struct pgk_ctx {
     // grid of a few thousand sites and are neutral on large grids; 2 steps
     // per graph are slower than direct launches.
     int graph_steps = 32;
+    bool transport_ref = false;   // theta_R transport by k_mc + k_dif on every grid
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipStream_t capture = nullptr;   // private stream the pair is recorded on (the null stream cannot be)
     void drop_graphs()
@@ -1069,17 +1072,17 @@ static int step_t(pgk_ctx *c, int64_t n)
                                c->lmul, c->k);
         }
         mark(c, 0);
-        if ((BND || c->k.nsub > 1) && c->k.ns > TR_SMALL && c->k.ny == 1 && c->k.nz == 1 &&
+        if (!c->transport_ref && (BND || c->k.nsub > 1) && c->k.ns > TR_SMALL && c->k.ny == 1 && c->k.nz == 1 &&
             c->k.nsub + 1 <= TL_HMAX) {
             int nchunk = (c->k.nx + TL_C - 1) / TL_C;
             hipLaunchKernelGGL((k_tr_line<A, VAR, BND>), dim3(2 * nchunk), dim3(TL_WG), 0, c->stream, c->that_,
                                (const A *)c->aux, (double *)c->buf[PGK_BUF_THETAR], c->k);
             mark(c, 2);
-        } else if ((BND || c->k.nsub > 1) && c->k.ns <= TR_SMALL) {
+        } else if (!c->transport_ref && (BND || c->k.nsub > 1) && c->k.ns <= TR_SMALL) {
             hipLaunchKernelGGL((k_tr_small<A, VAR, BND>), dim3(1), dim3(TR_SMALL_WG), sizeof(double) * 2 * c->k.ns,
                                c->stream, c->that_, (const A *)c->aux, (double *)c->buf[PGK_BUF_THETAR], c->k);
             mark(c, 2);
-        } else if (BND || c->k.nsub > 1) {
+        } else if (c->transport_ref || BND || c->k.nsub > 1) {
             // MacCormack, then the diffusion in nsub FTCS sub-steps (ping-pong
             // between two scratch fields), the last one with the second half
             hipLaunchKernelGGL((k_mc<A, BND>), grid, block, 0, c->stream, c->that_, (const A *)c->aux, c->tmc, c->k);
@@ -1242,6 +1245,14 @@ extern "C" int pgk_set_graph_steps(pgk_ctx *c, int k)
     if (k < 0 || (k & 1) || k > 4096) return fail(c, PGK_EINVAL, "graph steps must be 0 or even and at most 4096");
     if (k != c->graph_steps) c->drop_graphs();
     c->graph_steps = k;
+    return PGK_OK;
+}
+
+extern "C" int pgk_set_transport_reference(pgk_ctx *c, int on)
+{
+    if (!c) return PGK_EINVAL;
+    if ((on != 0) != c->transport_ref) c->drop_graphs();
+    c->transport_ref = on != 0;
     return PGK_OK;
 }
 

@@ -115,6 +115,11 @@ class Solver:
         """Replay k-step HIP graphs in step() (k even); 0 launches directly."""
         self._check(self.L.pgk_set_graph_steps(self.h, int(k)))
 
+    def set_transport_reference(self, on=True):
+        """theta_R transport by the plain global-memory kernels on every grid
+        (same bits as the LDS kernels, slower): a check of the LDS kernels."""
+        self._check(self.L.pgk_set_transport_reference(self.h, 1 if on else 0))
+
     def set_timing(self, enable=True):
         self._check(self.L.pgk_set_timing(self.h, 1 if enable else 0))
 

@@ -100,6 +100,9 @@ def test_null_arguments_are_errors_not_crashes():
     for k, rc in ((0, 0), (2, 0), (64, 0), (4096, 0), (3, -1), (-2, -1), (4098, -1)):
         assert L.pgk_set_graph_steps(out, k) == rc, k
     assert b"graph steps" in L.pgk_last_error(out)
+    # the reference transport switch
+    assert L.pgk_set_transport_reference(None, 1) == -1
+    assert L.pgk_set_transport_reference(out, 1) == 0 and L.pgk_set_transport_reference(out, 0) == 0
     # clocks: none before initialisation, none set on unbound buffers
     clk = _lib.Clock()
     assert L.pgk_get_clock(out, ctypes.byref(clk)) == -1
