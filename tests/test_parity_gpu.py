@@ -176,6 +176,29 @@ def test_bitwise_determinism_fp64():
         assert np.array_equal(outs[0][k], outs[1][k]), k
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_bitwise_determinism_e2_shock_line(precision):
+    # a 2100-cell E2 line between Dirichlet faces (warm-started Newton
+    # multipliers, the one-launch line transport), run twice from the same
+    # state: the same bits in FP64 and in FP32 storage
+    import paper_2201_05280_amd as pgk
+    th0 = oracle.THETA0
+    p = resolve(0.3, 0.71, 0.8, 2.0)
+    f = inputs.uniform(2100, 1, 1, u=(0.2, 0, 0))
+    outs = []
+    for _ in range(2):
+        s = _solver(2100, 1, 1, precision=precision, bc_x=(pgk.DIRICHLET, pgk.DIRICHLET), equilibrium=pgk.E2)
+        s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+        s.set_bc_x(0, 1.0, (0.2, 0.0, 0.0), th0)
+        s.set_bc_x(1, 1.05, (0.19, 0.0, 0.0), 1.02 * th0)
+        s.init(f["rho"], f["u"], f["thT"], f["thR"])
+        s.step(300)
+        outs.append(s.moments())
+        s.close()
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), (precision, k)
+
+
 @pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 1e-5)])
 def test_subcycled_diffusion_paths(precision, bar):
     # large viscosity: several FTCS sub-steps per step, both for a periodic
