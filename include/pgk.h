@@ -248,10 +248,10 @@ int pgk_set_transport_reference(pgk_ctx *ctx, int on);
  * the launch counts of [0] the fused pull-collide kernel, [1] the MacCormack
  * advection (on a periodic grid with one diffusion sub-step: the single fused
  * transport kernel, advection + diffusion + second half), [2] the diffusion
- * and second half relaxation (on a bounded or sub-cycled grid of at most 4096
- * sites: the whole transport in one work-group; on such a line, ny = nz = 1,
- * of more than 4096 sites with at most 63 sub-steps: the whole transport in
- * one launch of 1024-cell work-groups), [3] the x ghost fill, and clears the
+ * and second half relaxation (on a bounded or sub-cycled line, ny = nz = 1,
+ * with at most 63 sub-steps: the whole transport in one launch of 1024-cell
+ * work-groups; on another bounded or sub-cycled grid of at most 4096 sites:
+ * the whole transport in one work-group), [3] the x ghost fill, and clears the
  * record.  Event handles are created on demand and
  * kept until pgk_destroy. */
 #define PGK_NKERNEL 4

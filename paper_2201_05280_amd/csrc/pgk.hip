@@ -81,8 +81,8 @@ __global__ __launch_bounds__(WG) void k_dif(const double *__restrict__ tin, doub
     if (s < k.ns) dif_site<A, VAR, BOUNDED, FINAL>(s, tin, tout, that_, aux, thR, k);
 }
 
-// The theta_R transport of a small grid (at most TR_SMALL sites) in one
-// work-group: MacCormack into LDS, then every FTCS sub-step ping-ponging in
+// The theta_R transport of a small grid (at most TR_SMALL sites; lines take
+// k_tr_line) in one work-group: MacCormack into LDS, then every FTCS sub-step ping-ponging in
 // LDS with a work-group barrier between them, the last one with the second
 // half of the relaxation.  One launch instead of 1 + n_sub; the per-site
 // arithmetic is that of k_mc and k_dif, so the results are the same bits.
@@ -108,8 +108,10 @@ __global__ __launch_bounds__(TR_SMALL_WG) void k_tr_small(const double *__restri
     for (int s = threadIdx.x; s < k.ns; s += TR_SMALL_WG) dif_site<A, VAR, BOUNDED, true>(s, tin, tout, that_, aux, thR, k);
 }
 
-// The theta_R transport of a line (ny = nz = 1) longer than TR_SMALL sites,
-// bounded or sub-cycled, in one launch.  Along a line the transport is two
+// The theta_R transport of a line (ny = nz = 1), bounded or sub-cycled, in one
+// launch (any length; at most TL_HMAX - 1 sub-steps).  Unlike the one-work-group
+// kernel it keeps every field of a sub-step in LDS, which also makes it the
+// faster of the two on short lines.  Along a line the transport is two
 // independent 1D problems, one per sublattice.  A work-group owns TL_C cells of
 // one sublattice and stages them with a halo of H = nsub + 1 cells on each
 // side (theta_hat, u_x, rho, kfac rho theta); MacCormack and every FTCS
@@ -1072,7 +1074,7 @@ static int step_t(pgk_ctx *c, int64_t n)
                                c->lmul, c->k);
         }
         mark(c, 0);
-        if (!c->transport_ref && (BND || c->k.nsub > 1) && c->k.ns > TR_SMALL && c->k.ny == 1 && c->k.nz == 1 &&
+        if (!c->transport_ref && (BND || c->k.nsub > 1) && c->k.ny == 1 && c->k.nz == 1 &&
             c->k.nsub + 1 <= TL_HMAX) {
             int nchunk = (c->k.nx + TL_C - 1) / TL_C;
             hipLaunchKernelGGL((k_tr_line<A, VAR, BND>), dim3(2 * nchunk), dim3(TL_WG), 0, c->stream, c->that_,

@@ -46,7 +46,7 @@ def _cases():
     return [
         ("fused periodic, ragged tiles", (70, 20, 9), low, None, False),
         ("fused periodic, three z-chunks", (16, 9, 260), low, None, False),
-        ("one work-group, walls", (24, 1, 1), low, walls, True),
+        ("line, walls, 24 cells", (24, 1, 1), low, walls, False),
         ("one work-group, walls, 3D columns", (6, 5, 3), high, walls, True),
         ("one work-group, periodic sub-cycled", (10, 6, 1), high, None, True),
         ("line, walls, 3 sub-steps", (2100, 1, 1), high, walls, False),
