@@ -474,6 +474,46 @@ __device__ __forceinline__ void collide_store_e2(S *v, const double *l1, const d
     }
 }
 
+// The same collide spread over the two lanes of a site pair (both hold v, l1
+// and l2): lane r stores the member +c (r = 0) or -c (r = 1) of every opposite
+// pair, lane 0 also the rest velocity.  e + sg o with sg = +-1 is e + o or
+// e - o exactly, so every population is the same bits as in collide_store_e2,
+// with half the exponentials per lane.
+template <typename S, int P = 0>
+__device__ __forceinline__ void collide_store_e2_lane(const S *v, const double *l1, const double *l2,
+                                                      const Consts &k, S *__restrict__ dst, int s, int r)
+{
+    if constexpr (P < NPAIR) {
+        double e1, o1, e2, o2;
+        e2_parts<P>(l1, e1, o1);
+        e2_parts<P>(l2, e2, o2);
+        double w = k.w[Lattice::SHELL[P]];
+        const double sg = r ? -1.0 : 1.0;
+        const size_t q = r ? 1 + NPAIR + P : 1 + P;
+        const S vq = r ? v[1 + NPAIR + P] : v[1 + P];
+        if constexpr (sizeof(S) == 4) {
+            S tb = (S)(2.0 * k.beta);
+            S F = (S)(w * (k.wt1 * expm1(e1 + sg * o1) + k.wt * expm1(e2 + sg * o2)));
+            __builtin_nontemporal_store(vq + tb * (F - vq), &dst[q * k.ns + s]);
+        } else {
+            double omb = 1.0 - 2.0 * k.beta, tb = 2.0 * k.beta;
+            double F = w * (k.wt1 * exp(e1 + sg * o1) + k.wt * exp(e2 + sg * o2));
+            __builtin_nontemporal_store(omb * vq + tb * F, &dst[q * k.ns + s]);
+        }
+        collide_store_e2_lane<S, P + 1>(v, l1, l2, k, dst, s, r);
+    } else if (r == 0) {
+        double w0 = k.w[0];
+        if constexpr (sizeof(S) == 4) {
+            S tb = (S)(2.0 * k.beta);
+            S F0 = (S)(w0 * (k.wt1 * expm1(l1[0]) + k.wt * expm1(l2[0])));
+            __builtin_nontemporal_store(v[0] + tb * (F0 - v[0]), &dst[s]);
+        } else {
+            double F0 = w0 * (k.wt1 * exp(l1[0]) + k.wt * exp(l2[0]));
+            __builtin_nontemporal_store((1.0 - 2.0 * k.beta) * v[0] + 2.0 * k.beta * F0, &dst[s]);
+        }
+    }
+}
+
 // E2 multipliers of density rho, velocity u, covariance lam; a target out of
 // the lattice's reach gives NaN multipliers, so the site's populations turn
 // NaN (never silently replaced by another equilibrium)
@@ -589,8 +629,9 @@ __device__ __forceinline__ Mom lb_site(int s, const S *__restrict__ src, S *__re
 // E2 with the two Newton solves of site s on a pair of adjacent lanes (r = 0:
 // the lam_ES target, r = 1: theta I).  Both lanes pull the site and solve its
 // temperatures; each runs one Newton solve from its multipliers of the last
-// step (lmul, [2 E2_NL][ns], never null here); the pair swaps the results and
-// lane 0 collides, writes the site and hands the fields to the transport.
+// step (lmul, [2 E2_NL][ns], never null here); the pair swaps the results,
+// collides with each lane storing one member of every opposite pair, and lane
+// 0 hands the fields to the transport.
 // The arithmetic per site is that of lb_site<..., PGK_E2>.
 template <typename S, typename A, int VAR, bool BOUNDED>
 __device__ __forceinline__ void lb_site_e2pair(int s, int r, const S *__restrict__ src, S *__restrict__ dst,
@@ -619,8 +660,8 @@ __device__ __forceinline__ void lb_site_e2pair(int s, int r, const S *__restrict
         l1[i] = r == 0 ? l[i] : o;
         l2[i] = r == 0 ? o : l[i];
     }
+    collide_store_e2_lane<S>(v, l1, l2, k, dst, s, r);
     if (r != 0) return;
-    collide_store_e2<S>(v, l1, l2, k, dst, s);
     that_[s] = so.R;
     if (VAR == PGK_LIT) thR[s] = so.T;
     aux[s] = (A)so.u[0];
