@@ -366,10 +366,27 @@ int pgk_mlp_loss_grad(pgk_mlp *m, const float *X, const float *Y, int n, float *
 int pgk_mlp_adam_step(pgk_mlp *m, float lr, float beta1, float beta2, float eps);
 /* epochs of minibatch Adam (beta 0.9, 0.999, eps 1e-8) over n points in
  * contiguous minibatches visited in a seeded random order; loss_per_epoch
- * (host, may be NULL) receives the mean minibatch loss of each epoch */
+ * (host, may be NULL) receives each epoch's loss, the squared errors met
+ * during the epoch summed over all n points and divided by 4 n (every point
+ * counts once, whatever the size of the last minibatch) */
 int pgk_mlp_train(pgk_mlp *m, const float *X, const float *Y, int64_t n, int batch, int epochs, float lr,
                   uint64_t seed, float *loss_per_epoch);
+/* The whole trainable state: FP32 master weights, their bfloat16 copies (the
+ * values the products use), the Adam moments m and v (device arrays of
+ * PGK_MLP_NPARAM values, any may be NULL) and the Adam step count t (host).
+ * pgk_mlp_set_state restores master, m, v and t (the bf16 copies are rounded
+ * from master, the gradient accumulator is cleared), so that training resumes
+ * bit for bit.  Asynchronous on the MLP stream. */
+int pgk_mlp_get_state(pgk_mlp *m, float *master, uint16_t *wbf, float *adam_m, float *adam_v, int64_t *t);
+int pgk_mlp_set_state(pgk_mlp *m, const float *master, const float *adam_m, const float *adam_v, int64_t t);
+/* The same state in a file at `path`: an 8-byte tag "PGKMLP1", the parameter
+ * count and t as int64, then master, m and v as FP32 (host byte order).
+ * pgk_mlp_load refuses a file of another tag or parameter count (PGK_EINVAL,
+ * message in pgk_mlp_last_error).  Both synchronise the MLP stream. */
+int pgk_mlp_save(pgk_mlp *m, const char *path);
+int pgk_mlp_load(pgk_mlp *m, const char *path);
 const char *pgk_mlp_last_error(const pgk_mlp *m);
+
 void pgk_mlp_destroy(pgk_mlp *m);
 
 /* Steps taken since the last pgk_init_fields. */

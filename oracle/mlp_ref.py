@@ -91,3 +91,23 @@ def loss_and_grad(theta, X, Y, bf16=False):
             da = r(dz) @ r(W[2 * li])
         g[2 * li + 1] = dz.sum(0)
     return loss, pack(g)
+
+
+def adam(theta, grads, lr, beta1=0.9, beta2=0.999, eps=1e-8, m=None, v=None, t=0):
+    """Adam (Kingma & Ba, "Adam: a method for stochastic optimization", ICLR
+    2015, Algorithm 1) in double precision, one update per gradient of
+    `grads` in order: first and second moment estimates m, v, their bias
+    corrections by 1 - beta^t, and the step lr * mhat / (sqrt(vhat) + eps).
+    Returns (theta, m, v, t) after the last update."""
+    th = np.asarray(theta, dtype=np.float64).copy()
+    m = np.zeros_like(th) if m is None else np.asarray(m, dtype=np.float64).copy()
+    v = np.zeros_like(th) if v is None else np.asarray(v, dtype=np.float64).copy()
+    for g in grads:
+        g = np.asarray(g, dtype=np.float64)
+        t += 1
+        m = beta1 * m + (1.0 - beta1) * g
+        v = beta2 * v + (1.0 - beta2) * g * g
+        mhat = m / (1.0 - beta1 ** t)
+        vhat = v / (1.0 - beta2 ** t)
+        th = th - lr * mhat / (np.sqrt(vhat) + eps)
+    return th, m, v, t

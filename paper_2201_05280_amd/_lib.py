@@ -28,8 +28,8 @@ EXPORTS = ["pgk_resolve", "pgk_lattice", "pgk_equilibrium", "pgk_buffer_sizes", 
            "pgk_batch_bytes", "pgk_batch_create", "pgk_batch_offsets", "pgk_batch_init", "pgk_batch_config",
            "pgk_batch_run", "pgk_batch_stall", "pgk_batch_tuned", "pgk_batch_read_moments", "pgk_batch_last_error",
            "pgk_batch_destroy", "pgk_mlp_bytes", "pgk_mlp_create", "pgk_mlp_set_params", "pgk_mlp_get_params",
-           "pgk_mlp_forward", "pgk_mlp_loss_grad", "pgk_mlp_adam_step", "pgk_mlp_train", "pgk_mlp_last_error",
-           "pgk_mlp_destroy"]
+           "pgk_mlp_forward", "pgk_mlp_loss_grad", "pgk_mlp_adam_step", "pgk_mlp_train", "pgk_mlp_get_state",
+           "pgk_mlp_set_state", "pgk_mlp_save", "pgk_mlp_load", "pgk_mlp_last_error", "pgk_mlp_destroy"]
 MLP_NPARAM = 50948
 CASE_RUNNING, CASE_CONVERGED, CASE_DIVERGED, CASE_MAXSTEPS, CASE_STALLED = 0, 1, 2, 3, 4
 NKERNEL = 4
@@ -133,6 +133,10 @@ def load():
     L.pgk_mlp_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int, vp, fp]
     L.pgk_mlp_adam_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]
     L.pgk_mlp_train.argtypes = [vp, vp, vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_uint64, fp]
+    L.pgk_mlp_get_state.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(i64)]
+    L.pgk_mlp_set_state.argtypes = [vp, vp, vp, vp, i64]
+    L.pgk_mlp_save.argtypes = [vp, ctypes.c_char_p]
+    L.pgk_mlp_load.argtypes = [vp, ctypes.c_char_p]
     L.pgk_mlp_last_error.argtypes = [vp]
     L.pgk_mlp_last_error.restype = ctypes.c_char_p
     L.pgk_mlp_destroy.argtypes = [vp]

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -167,8 +168,10 @@ __global__ void k_layer5(const uint16_t *__restrict__ a4, int n, const uint16_t 
 }
 
 // dy = 2 (yhat - y)/(4 N) (zero on padding rows) and the loss sum
+// dy = 2 (yhat - Y) scale (gradient of the minibatch's mean loss); the
+// squared errors are summed into *loss with weight lscale
 __global__ void k_loss(const float *__restrict__ yhat, const float *__restrict__ Y, int n, int npad, float scale,
-                       float *__restrict__ dy, float *__restrict__ loss)
+                       float lscale, float *__restrict__ dy, float *__restrict__ loss)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     float l = 0.f;
@@ -176,7 +179,7 @@ __global__ void k_loss(const float *__restrict__ yhat, const float *__restrict__
         int p = i / NOUT;
         float d = p < n ? yhat[i] - Y[i] : 0.f;
         dy[i] = 2.f * d * scale;
-        l = d * d * scale;
+        l = d * d * lscale;
     }
     for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
     if ((threadIdx.x & 63) == 0) atomicAdd(loss, l);
@@ -278,6 +281,15 @@ __global__ void k_set_params(const float *__restrict__ theta, float *__restrict_
     grad[i] = 0.f;
     m[i] = 0.f;
     v[i] = 0.f;
+}
+
+// bf16 copies of the master weights and a cleared gradient after a load
+__global__ void k_refresh(const float *__restrict__ master, uint16_t *__restrict__ wbf, float *__restrict__ grad)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPARAM) return;
+    wbf[i] = f2bf(master[i]);
+    grad[i] = 0.f;
 }
 
 }  // namespace pgk_mlp_dev
@@ -405,8 +417,9 @@ extern "C" int pgk_mlp_forward(pgk_mlp *m, const float *X, float *Y, int n)
     return PGK_OK;
 }
 
-// loss and gradient of one minibatch (n <= nmax) into m->grad (accumulated)
-static int loss_grad(pgk_mlp *m, const float *X, const float *Y, int n, float scale)
+// loss and gradient of one minibatch (n <= nmax) into m->grad (accumulated);
+// the squared errors enter m->loss with weight lscale
+static int loss_grad(pgk_mlp *m, const float *X, const float *Y, int n, float scale, float lscale)
 {
     int np = (n + 63) / 64 * 64;
     int rc = forward(m, X, n);
@@ -414,7 +427,7 @@ static int loss_grad(pgk_mlp *m, const float *X, const float *Y, int n, float sc
     hipLaunchKernelGGL(k_layer5, dim3((n * NOUT + 255) / 256), dim3(256), 0, m->stream, m->a[3], n, m->wbf,
                        m->master, m->yhat);
     hipLaunchKernelGGL(k_loss, dim3((np * NOUT + 255) / 256), dim3(256), 0, m->stream, m->yhat, Y, n, np, scale,
-                       m->dy, m->loss);
+                       lscale, m->dy, m->loss);
     hipLaunchKernelGGL(k_layer5_wgrad, dim3((n + GP - 1) / GP), dim3(H), 0, m->stream, m->dy, m->a[3], n, m->grad);
     hipLaunchKernelGGL(k_layer5_bwd, dim3((np * H + 255) / 256), dim3(256), 0, m->stream, m->dy, m->z[3], m->wbf,
                        np, m->dz);
@@ -447,7 +460,7 @@ extern "C" int pgk_mlp_loss_grad(pgk_mlp *m, const float *X, const float *Y, int
     if (!m || !X || !Y || n < 1 || n > m->nmax) return PGK_EINVAL;
     hipLaunchKernelGGL(k_zero, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->grad, NPARAM);
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, m->stream, m->loss, 1);
-    int rc = loss_grad(m, X, Y, n, 1.0f / (4.0f * n));
+    int rc = loss_grad(m, X, Y, n, 1.0f / (4.0f * n), 1.0f / (4.0f * n));
     if (rc) return rc;
     if (grad) MHIP(m, hipMemcpyAsync(grad, m->grad, 4ull * NPARAM, hipMemcpyDeviceToDevice, m->stream));
     if (loss) {
@@ -488,9 +501,10 @@ extern "C" int pgk_mlp_train(pgk_mlp *m, const float *X, const float *Y, int64_t
         for (int64_t i = 0; i < nb; i++) {
             int64_t b0 = order[i] * batch;
             int c = (int)(n - b0 < batch ? n - b0 : batch);
-            // gradients of the mean loss over this minibatch; the loss sum is
-            // scaled so that one epoch reports the mean over all points
-            int rc = loss_grad(m, X + b0 * NIN, Y + b0 * NOUT, c, 1.0f / (4.0f * c));
+            // gradients of the mean loss over this minibatch; the squared
+            // errors are weighted 1/(4 n), so that the epoch's sum is the mean
+            // over all n points (a last, partial minibatch counts by its size)
+            int rc = loss_grad(m, X + b0 * NIN, Y + b0 * NOUT, c, 1.0f / (4.0f * c), 1.0f / (4.0f * (float)n));
             if (rc) return rc;
             rc = pgk_mlp_adam_step(m, lr, 0.9f, 0.999f, 1e-8f);
             if (rc) return rc;
@@ -499,9 +513,76 @@ extern "C" int pgk_mlp_train(pgk_mlp *m, const float *X, const float *Y, int64_t
             float l;
             MHIP(m, hipMemcpyAsync(&l, m->loss, 4, hipMemcpyDeviceToHost, m->stream));
             MHIP(m, hipStreamSynchronize(m->stream));
-            loss_per_epoch[e] = l / (float)nb;
+            loss_per_epoch[e] = l;
         }
     }
+    return PGK_OK;
+}
+
+extern "C" int pgk_mlp_get_state(pgk_mlp *m, float *master, uint16_t *wbf, float *adam_m, float *adam_v,
+                                 int64_t *t)
+{
+    if (!m) return PGK_EINVAL;
+    if (master) MHIP(m, hipMemcpyAsync(master, m->master, 4ull * NPARAM, hipMemcpyDeviceToDevice, m->stream));
+    if (wbf) MHIP(m, hipMemcpyAsync(wbf, m->wbf, 2ull * NPARAM, hipMemcpyDeviceToDevice, m->stream));
+    if (adam_m) MHIP(m, hipMemcpyAsync(adam_m, m->m, 4ull * NPARAM, hipMemcpyDeviceToDevice, m->stream));
+    if (adam_v) MHIP(m, hipMemcpyAsync(adam_v, m->v, 4ull * NPARAM, hipMemcpyDeviceToDevice, m->stream));
+    if (t) *t = m->t;
+    return PGK_OK;
+}
+
+extern "C" int pgk_mlp_set_state(pgk_mlp *m, const float *master, const float *adam_m, const float *adam_v, int64_t t)
+{
+    if (!m || !master || !adam_m || !adam_v || t < 0 || t > INT32_MAX) return PGK_EINVAL;
+    hipLaunchKernelGGL(k_set_params, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, master, m->master,
+                       m->wbf, m->grad, m->m, m->v);
+    MHIP(m, hipGetLastError());
+    MHIP(m, hipMemcpyAsync(m->m, adam_m, 4ull * NPARAM, hipMemcpyDeviceToDevice, m->stream));
+    MHIP(m, hipMemcpyAsync(m->v, adam_v, 4ull * NPARAM, hipMemcpyDeviceToDevice, m->stream));
+    m->t = (int)t;
+    return PGK_OK;
+}
+
+// file: 8-byte tag, int64 parameter count, int64 Adam step count, then the
+// FP32 master weights, first and second Adam moments (little-endian)
+static const char MLP_TAG[8] = {'P', 'G', 'K', 'M', 'L', 'P', '1', 0};
+
+extern "C" int pgk_mlp_save(pgk_mlp *m, const char *path)
+{
+    if (!m || !path) return PGK_EINVAL;
+    std::vector<float> h(3ull * NPARAM);
+    MHIP(m, hipMemcpyAsync(h.data(), m->master, 4ull * NPARAM, hipMemcpyDeviceToHost, m->stream));
+    MHIP(m, hipMemcpyAsync(h.data() + NPARAM, m->m, 4ull * NPARAM, hipMemcpyDeviceToHost, m->stream));
+    MHIP(m, hipMemcpyAsync(h.data() + 2 * NPARAM, m->v, 4ull * NPARAM, hipMemcpyDeviceToHost, m->stream));
+    MHIP(m, hipStreamSynchronize(m->stream));
+    FILE *f = fopen(path, "wb");
+    if (!f) { m->err = std::string("cannot open ") + path + " for writing"; return PGK_EINVAL; }
+    int64_t hdr[2] = {NPARAM, m->t};
+    bool ok = fwrite(MLP_TAG, 1, 8, f) == 8 && fwrite(hdr, 8, 2, f) == 2 && fwrite(h.data(), 4, h.size(), f) == h.size();
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) { m->err = std::string("write failed: ") + path; return PGK_EINVAL; }
+    return PGK_OK;
+}
+
+extern "C" int pgk_mlp_load(pgk_mlp *m, const char *path)
+{
+    if (!m || !path) return PGK_EINVAL;
+    FILE *f = fopen(path, "rb");
+    if (!f) { m->err = std::string("cannot open ") + path; return PGK_EINVAL; }
+    char tag[8];
+    int64_t hdr[2];
+    std::vector<float> h(3ull * NPARAM);
+    bool ok = fread(tag, 1, 8, f) == 8 && memcmp(tag, MLP_TAG, 8) == 0 && fread(hdr, 8, 2, f) == 2 &&
+              hdr[0] == NPARAM && hdr[1] >= 0 && hdr[1] <= INT32_MAX && fread(h.data(), 4, h.size(), f) == h.size();
+    fclose(f);
+    if (!ok) { m->err = std::string("not a coordinate-MLP file of this shape: ") + path; return PGK_EINVAL; }
+    MHIP(m, hipMemcpyAsync(m->master, h.data(), 4ull * NPARAM, hipMemcpyHostToDevice, m->stream));
+    MHIP(m, hipMemcpyAsync(m->m, h.data() + NPARAM, 4ull * NPARAM, hipMemcpyHostToDevice, m->stream));
+    MHIP(m, hipMemcpyAsync(m->v, h.data() + 2 * NPARAM, 4ull * NPARAM, hipMemcpyHostToDevice, m->stream));
+    hipLaunchKernelGGL(k_refresh, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->master, m->wbf, m->grad);
+    MHIP(m, hipGetLastError());
+    MHIP(m, hipStreamSynchronize(m->stream));   // h is freed on return
+    m->t = (int)hdr[1];
     return PGK_OK;
 }
 

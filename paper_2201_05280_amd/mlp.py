@@ -63,6 +63,32 @@ class MLP:
         self.stream.synchronize()
         return out.cpu().numpy()
 
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One Adam update with the gradient of the last loss_grad."""
+        self._check(self.L.pgk_mlp_adam_step(self.h, float(lr), float(beta1), float(beta2), float(eps)))
+        self.stream.synchronize()
+
+    def state(self):
+        """(master FP32, bf16 copies as uint16, Adam m, Adam v, step count) on the host."""
+        t = self.torch
+        bufs = [t.empty(NPARAM, dtype=dt, device=self.device) for dt in (t.float32, t.int16, t.float32, t.float32)]
+        step = ctypes.c_int64()
+        self._check(self.L.pgk_mlp_get_state(self.h, *[b.data_ptr() for b in bufs], ctypes.byref(step)))
+        self.stream.synchronize()
+        master, wbf, m, v = [b.cpu().numpy() for b in bufs]
+        return master, wbf.view(np.uint16), m, v, int(step.value)
+
+    def set_state(self, master, m, v, step):
+        th, mm, vv = (self._dev(a, (NPARAM,)) for a in (master, m, v))
+        self._check(self.L.pgk_mlp_set_state(self.h, th.data_ptr(), mm.data_ptr(), vv.data_ptr(), int(step)))
+        self.stream.synchronize()
+
+    def save(self, path):
+        self._check(self.L.pgk_mlp_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        self._check(self.L.pgk_mlp_load(self.h, str(path).encode()))
+
     def forward(self, X):
         x = self._dev(X, (-1, NIN))
         n = x.shape[0]

@@ -336,3 +336,40 @@ def test_largest_case_equals_single_grid():
             err = np.abs(bm[k][sl] - sm[k]).max() / np.abs(sm[k]).max()
             assert err <= 1e-13, (c, k, err)
     b.close()
+
+
+def _host_residual(a, b, sl, axis):
+    """max over rho, u_axis, theta_T, theta_R of ||phi^n - phi^(n-1)||_2 / ||phi^n||_2"""
+    r = 0.0
+    for k in ("rho", "u", "thT", "thR"):
+        x0 = a[k][axis][sl] if k == "u" else a[k][sl]
+        x1 = b[k][axis][sl] if k == "u" else b[k][sl]
+        r = max(r, float(np.linalg.norm(x1 - x0) / np.linalg.norm(x1)))
+    return r
+
+
+def test_in_kernel_residual_equals_host_two_read_residual():
+    """The residual each case reports (computed inside the persistent kernel
+    from its last two steps) equals the same definition evaluated on the host
+    from moment reads of the state at steps n-1 and n.  The two states come
+    from two batches run from the same start with chunks of 3 and of 2 steps
+    (the state does not depend on the chunking), so the host sees exactly the
+    values the kernel summed; only the order of the sums differs."""
+    specs = _cases()
+    b1, _ = _build(specs)
+    b1.config(256, 3)
+    steps1, _, _ = b1.run(57, 0.0)
+    assert (steps1 == 57).all()
+    m1 = b1.moments()
+    b1.close()
+    b2, _ = _build(specs)
+    b2.config(256, 2)
+    steps2, resid, status = b2.run(58, 0.0)
+    assert (steps2 == 58).all() and (status == 3).all()
+    m2 = b2.moments()
+    for c, sp in enumerate(specs):
+        h = _host_residual(m1, m2, b2.case_slice(c), sp["vel_axis"])
+        print("case", c, "kernel residual %.15e host %.15e" % (resid[c], h))
+        assert h > 1e-12
+        assert abs(resid[c] - h) <= 1e-12 * h, (c, resid[c], h)
+    b2.close()

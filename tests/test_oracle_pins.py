@@ -216,6 +216,68 @@ def test_g_f_map_reproduces_printed_relations(p, seed):
 
 
 @pytest.mark.parametrize("p", PARAMS)
+@pytest.mark.parametrize("seed", range(3))
+def test_moment_readout_is_the_f_moments(p, seed):
+    """The read-out of the oracle state (rho, u, theta_T, theta_R, P) is the
+    set of moments of f, not of the stored g: for g = f - Omega/2 built from a
+    random non-equilibrium f (Sec. 5, trapezoid map), P must be sum_i f_i c_i c_i
+    itself, theta_T = theta_T(f) and theta_R the stored value.  A wrong stress
+    rescale s_sigma (Sec. 5, sigma(g) = sigma(f) s_sigma), a dropped rho u u
+    term or the temperature of g instead of f each break it."""
+    rng = np.random.default_rng(100 + seed)
+    c, _ = oracle.lattice()
+    tau, tau1, b, kr, d = p["tau"], p["tau1"], p["b"], p["kr"], p["delta"]
+    taus = tau * tau1 / (tau + tau1)
+    rho0, u0, L0 = _random_state(rng)
+    f = oracle.feq_f3(rho0, u0, lam6(L0)) * (1 + 0.05 * rng.uniform(-1, 1, 41))
+    rho, u, thT, sig, P = _moments(f, c)
+    thR = thT * rng.uniform(0.95, 1.05)
+    theta = (3 * thT + d * thR) / (3 + d)
+    fES = oracle.feq_f3(rho, u, lam6(thT * np.eye(3) + b * sig / rho))
+    fMB = oracle.feq_f3(rho, u, lam6(theta * np.eye(3)))
+    g = f - 0.5 * ((fES - f) / tau + (fMB - f) / tau1)
+    X = 3 / (2 * tau1 * (3 + d))
+    r = thR * (1 + X) - X * thT           # stored theta_R, before the half relaxation
+    o = oracle.Oracle(1, 1, 1)            # two sites, both holding this state
+    o.set_params(tau, tau1, b, kr, d)
+    o.set_state(np.repeat(g[:, None], 2, axis=1), np.full(2, r))
+    m = o.moments()
+    tol = 4e-15 * (1 + 1 / taus)
+    P6 = np.array([P[0, 0], P[1, 1], P[2, 2], P[0, 1], P[0, 2], P[1, 2]])
+    for s in range(2):
+        assert abs(m["rho"][s] - rho) < tol
+        assert np.allclose(m["u"][:, s], u, rtol=0, atol=tol)
+        assert abs(m["thT"][s] - thT) < tol
+        assert m["thR"][s] == r
+        assert np.allclose(m["P"][:, s], P6, rtol=0, atol=tol), (m["P"][:, s], P6)
+    # the g moments differ from these by far more than the bar
+    _, _, _, _, Pg = _moments(g, c)
+    assert np.abs(Pg - P).max() > 1e3 * tol
+
+
+def test_couette_shear_stress_is_eta_du_dy():
+    """Steady Couette layer between diffuse walls: the shear stress read out as
+    P_xy(f) is uniform across the layer and equals -eta du_y/dx with eta = rho
+    nu, nu = theta0 tau/(B - b) (Sec. 4, shear viscosity), the velocity
+    gradient taken from the read-out profile in the bulk."""
+    L, nu, U = 16, 0.1, 0.02
+    o, y = _couette_oracle(L, nu, 0.71, U, TH0)
+    o.step(10000)                          # ~ 4 L^2/nu: the slowest mode has decayed by e^-40
+    m = o.moments()
+    x = inputs.positions(L, 1, 1)[0]
+    order = np.argsort(x)
+    xs, uy, pxy, rho = x[order], m["u"][1][order], m["P"][3][order], m["rho"][order]
+    inner = slice(6, -6)                   # away from the Knudsen layers
+    dudx = np.polyfit(xs[inner], uy[inner], 1)[0]
+    eta = rho[inner] * nu
+    # uniform to 2e-5 (the two sublattices differ by that much), and equal to
+    # eta du/dx to 5e-5 (measured); a stress read out of g, or rescaled by a
+    # wrong s_sigma, is off by O(1)
+    assert np.abs(pxy[inner] / pxy[inner].mean() - 1).max() < 1e-4
+    assert np.abs(-eta * dudx / pxy[inner] - 1).max() < 1e-3, (dudx, pxy[inner].mean())
+
+
+@pytest.mark.parametrize("p", PARAMS)
 def test_collision_exchange_conserves_mass_momentum_energy(p):
     """CN reading: E_T(g*) + E_R after both half relaxations = before (per site)."""
     rng = np.random.default_rng(7)

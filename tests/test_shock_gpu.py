@@ -80,14 +80,20 @@ def test_full_line_matches_oracle(Ma, precision, bar):
         assert v <= bar, (k, v, e)
 
 
-@pytest.mark.parametrize("precision,bar", [(0, 1e-12), (1, 3e-5)])
-def test_long_run_matches_oracle(precision, bar):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_long_run_matches_oracle(precision):
     # 2000 steps of a 512-cell line: the shock forms from the tanh blend and the
-    # start-up waves cross the line and leave through the faces.  Between two
-    # Dirichlet faces a shock can sit anywhere (its translation is a neutral
-    # mode), so the FP32 storage rounding of the mass that crosses the faces
-    # shifts it a little every step: the FP32 bar is 3e-5 here, and the shock
-    # positions must agree to 2e-3 cells
+    # start-up waves cross the line and leave through the faces.  FP64: the
+    # whole line element by element at 1e-12.  FP32 storage: between two
+    # Dirichlet faces the shock's position is a neutral mode fixed only by the
+    # mass held between the faces, and the FP32 run ends the start-up
+    # transient with 2.4e-6 less mass than the FP64 one (the deficit grows
+    # while the waves leave and stops at steady state), which places its shock
+    # 7e-4 cells downstream.  The profiles are therefore compared with the two
+    # positions aligned, at the 1e-5 bar on every moment; the unaligned error
+    # (1.0e-5 measured) is held at 3e-5, the mass deficit at 5e-6 and the
+    # shift at 2e-3 cells.
+    import paper_2201_05280_amd as pgk
     from paper_2201_05280_amd import inputs
     from paper_2201_05280_amd.shock import profile_metrics
     L, steps = 512, 2000
@@ -96,19 +102,43 @@ def test_long_run_matches_oracle(precision, bar):
     if key not in _ORACLE:
         o = _oracle(L, up, down, p, f)
         o.step(steps)
-        _ORACLE[key] = o.moments()
+        _ORACLE[key] = (o.moments(), o.conserved())
+    ref, ref_c = _ORACLE[key]
     s = _solver(L, precision, up, down, p, f)
     s.step(steps)
     m = s.moments()
-    e = _rel(m, _ORACLE[key])
+    c = s.conserved()
     s.close()
+    e = _rel(m, ref)
     x = inputs.positions(L, 1, 1)[0]
     pg, tg = profile_metrics(x, m["rho"], up, down)
-    po, to = profile_metrics(x, _ORACLE[key]["rho"], up, down)
-    print("long shock parity", precision, e, "position", pg, po, "thickness", tg, to)
+    po, to = profile_metrics(x, ref["rho"], up, down)
+    dm = (c[0] - ref_c[0]) / ref_c[0]
+    print("long shock parity", precision, e, "position", pg, po, "thickness", tg, to, "mass", dm)
+    if precision == pgk.FP64:
+        for k, v in e.items():
+            assert v <= 1e-12, (k, v, e)
+        assert abs(pg - po) < 1e-9 and abs(dm) < 1e-14
+        return
+    # aligned: the FP32 fields sampled at x + (pg - po) against the oracle at x
+    order = np.argsort(x)
+    xs = x[order]
+    inside = (xs + (pg - po) >= xs[0]) & (xs + (pg - po) <= xs[-1])
+    al = {}
+    for k in ("rho", "u", "thT", "thR", "P"):
+        g, o = m[k], ref[k]
+        rows = [(g[i], o[i]) for i in range(g.shape[0])] if g.ndim == 2 else [(g, o)]
+        err = 0.0
+        for gi, oi in rows:
+            gs = np.interp(xs[inside] + (pg - po), xs, gi[order])
+            err = max(err, float(np.abs(gs - oi[order][inside]).max()))
+        al[k] = err / max(np.abs(o).max(), FLOOR[k])
+    print("aligned FP32 parity", al)
+    for k, v in al.items():
+        assert v <= 1e-5, (k, v, al)
     for k, v in e.items():
-        assert v <= bar, (k, v, e)
-    assert abs(pg - po) < 2e-3 and abs(tg / to - 1) < 1e-4
+        assert v <= 3e-5, (k, v, e)
+    assert abs(dm) < 5e-6 and abs(pg - po) < 2e-3 and abs(tg / to - 1) < 1e-4
 
 
 def test_full_size_shock_reaches_its_steady_state():
