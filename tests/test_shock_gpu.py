@@ -118,7 +118,7 @@ def test_long_run_matches_oracle(precision):
     if precision == pgk.FP64:
         for k, v in e.items():
             assert v <= 1e-12, (k, v, e)
-        assert abs(pg - po) < 1e-9 and abs(dm) < 1e-14
+        assert abs(pg - po) < 1e-9 and abs(dm) < 1e-13
         return
     # aligned: the FP32 fields sampled at x + (pg - po) against the oracle at x
     order = np.argsort(x)
