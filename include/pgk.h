@@ -49,6 +49,7 @@ extern "C" {
 #define PGK_EDEVICE     -3   /* a HIP call failed */
 #define PGK_EINFEASIBLE -4   /* requested transport coefficients cannot be reached */
 #define PGK_ENOTBOUND   -6   /* buffers not bound yet */
+#define PGK_ETOOBIG     -7   /* the request exceeds a fixed capacity of the library */
 
 /* population storage (Sec. 5 populations; the FP32 form stores deviations) */
 #define PGK_FP64     0       /* g_i in double precision */
@@ -387,6 +388,24 @@ int pgk_mlp_save(pgk_mlp *m, const char *path);
 int pgk_mlp_load(pgk_mlp *m, const char *path);
 const char *pgk_mlp_last_error(const pgk_mlp *m);
 
+/* Inference for callers that cannot allocate device memory at all (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the forward pass of pgk_mlp_forward, the same kernels and the same bits,
+ * from the FP32 parameters theta (device, PGK_MLP_NPARAM values, layout of
+ * pgk_mlp_set_params) without a pgk_mlp object.  X [n][6] and Y [n][4] are
+ * device arrays the caller owns.  The bf16 weights and activations live in a
+ * fixed device array inside the library, one per GPU (4.3 MB, kept until
+ * the process ends); its address is looked up once per GPU at the first call
+ * with that GPU current.  The call allocates nothing and never calls hipMalloc.
+ * Limits: n <= PGK_MLP_STATIC_NMAX points per call (PGK_ETOOBIG above it,
+ * before any GPU work); `stream` must belong to the current device.  Every
+ * call on a GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (different streams or host threads) race and must be serialised by the
+ * caller; calls in one stream are ordered.  PGK_EINVAL for a null pointer or
+ * n < 0, PGK_EDEVICE if the array's address cannot be obtained or a launch
+ * fails.  Asynchronous on `stream`. */
+#define PGK_MLP_STATIC_NMAX 4096
+int pgk_mlp_forward_static(const float *theta, const float *X, float *Y, int n, void *stream);
 void pgk_mlp_destroy(pgk_mlp *m);
 
 /* Steps taken since the last pgk_init_fields. */

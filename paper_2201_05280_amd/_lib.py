@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpgk.so")
 
 PGK_OK = 0
-ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EINFEASIBLE", -6: "ENOTBOUND"}
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EINFEASIBLE", -6: "ENOTBOUND", -7: "ETOOBIG"}
+MLP_STATIC_NMAX = 4096
 FP64, FP32DEV = 0, 1
 CN, LIT = 0, 1
 F3 = 0
@@ -29,7 +30,8 @@ EXPORTS = ["pgk_resolve", "pgk_lattice", "pgk_equilibrium", "pgk_buffer_sizes", 
            "pgk_batch_run", "pgk_batch_stall", "pgk_batch_tuned", "pgk_batch_read_moments", "pgk_batch_last_error",
            "pgk_batch_destroy", "pgk_mlp_bytes", "pgk_mlp_create", "pgk_mlp_set_params", "pgk_mlp_get_params",
            "pgk_mlp_forward", "pgk_mlp_loss_grad", "pgk_mlp_adam_step", "pgk_mlp_train", "pgk_mlp_get_state",
-           "pgk_mlp_set_state", "pgk_mlp_save", "pgk_mlp_load", "pgk_mlp_last_error", "pgk_mlp_destroy"]
+           "pgk_mlp_set_state", "pgk_mlp_save", "pgk_mlp_load", "pgk_mlp_last_error", "pgk_mlp_destroy",
+           "pgk_mlp_forward_static"]
 MLP_NPARAM = 50948
 CASE_RUNNING, CASE_CONVERGED, CASE_DIVERGED, CASE_MAXSTEPS, CASE_STALLED = 0, 1, 2, 3, 4
 NKERNEL = 4
@@ -137,6 +139,7 @@ def load():
     L.pgk_mlp_set_state.argtypes = [vp, vp, vp, vp, i64]
     L.pgk_mlp_save.argtypes = [vp, ctypes.c_char_p]
     L.pgk_mlp_load.argtypes = [vp, ctypes.c_char_p]
+    L.pgk_mlp_forward_static.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     L.pgk_mlp_last_error.argtypes = [vp]
     L.pgk_mlp_last_error.restype = ctypes.c_char_p
     L.pgk_mlp_destroy.argtypes = [vp]

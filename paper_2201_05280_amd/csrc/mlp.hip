@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -281,6 +282,13 @@ __global__ void k_set_params(const float *__restrict__ theta, float *__restrict_
     grad[i] = 0.f;
     m[i] = 0.f;
     v[i] = 0.f;
+}
+
+// bf16 copies of parameters, for the allocation-free inference entry point
+__global__ void k_to_bf16(const float *__restrict__ theta, uint16_t *__restrict__ wbf)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < NPARAM) wbf[i] = f2bf(theta[i]);
 }
 
 // bf16 copies of the master weights and a cleared gradient after a load
@@ -584,6 +592,68 @@ extern "C" int pgk_mlp_load(pgk_mlp *m, const char *path)
     MHIP(m, hipStreamSynchronize(m->stream));   // h is freed on return
     m->t = (int)hdr[1];
     return PGK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Inference without any allocation: the bf16 weights and the activations live
+// in a file-scope device array (one per GPU, held until the process ends)
+// instead of a pgk_mlp buffer.  In host code `scratch` only names the symbol;
+// its device address on each GPU comes from hipGetSymbolAddress, taken once per
+// device with that device current and kept in scratch_dev[].
+// ---------------------------------------------------------------------------
+constexpr int ST_NMAX = PGK_MLP_STATIC_NMAX;
+constexpr size_t ST_WBF = 0;                                     // bf16 weights
+constexpr size_t ST_Z = ST_WBF + ((2ull * NPARAM + 255) & ~(size_t)255);   // z of the current layer, fp32
+constexpr size_t ST_A0 = ST_Z + 4ull * ST_NMAX * H;              // activations, bf16 ping
+constexpr size_t ST_A1 = ST_A0 + 2ull * ST_NMAX * H;             // and pong
+constexpr size_t ST_BYTES = ST_A1 + 2ull * ST_NMAX * H;
+static_assert(ST_NMAX % 64 == 0, "padded point count must fit");
+
+static __device__ __align__(256) unsigned char scratch[ST_BYTES];
+
+constexpr int ST_MAXDEV = 64;
+static std::mutex scratch_mu;
+static void *scratch_dev[ST_MAXDEV];
+
+// device address of this GPU's scratch array (the current device)
+static int scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= ST_MAXDEV) return PGK_EDEVICE;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PGK_EDEVICE;
+        scratch_dev[dev] = p;
+    }
+    *out = scratch_dev[dev];
+    return PGK_OK;
+}
+
+extern "C" int pgk_mlp_forward_static(const float *theta, const float *X, float *Y, int n, void *stream)
+{
+    if (!theta || n < 0 || (n > 0 && (!X || !Y))) return PGK_EINVAL;
+    if (n > ST_NMAX) return PGK_ETOOBIG;
+    if (n == 0) return PGK_OK;
+    void *base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned char *b = (unsigned char *)base;
+    uint16_t *wbf = (uint16_t *)(b + ST_WBF), *a[2] = {(uint16_t *)(b + ST_A0), (uint16_t *)(b + ST_A1)};
+    float *z = (float *)(b + ST_Z);
+    const int np = (n + 63) / 64 * 64;
+    // every value a kernel reads below is written earlier in this call (rows
+    // n..np-1 included), so nothing needs clearing between calls
+    hipLaunchKernelGGL(k_to_bf16, dim3((NPARAM + 255) / 256), dim3(256), 0, st, theta, wbf);
+    hipLaunchKernelGGL(k_layer1, dim3((np * H + 255) / 256), dim3(256), 0, st, X, n, np, wbf, theta, z, a[0]);
+    const int offW[3] = {OFF_W2, OFF_W3, OFF_W4}, offB[3] = {OFF_B2, OFF_B3, OFF_B4};
+    for (int l = 0; l < 3; l++)
+        hipLaunchKernelGGL((k_gemm<uint16_t, EPI_FWD, true>), dim3(np / 64, H / 64, 1), dim3(256), 0, st,
+                           a[l & 1], H, 1, wbf + offW[l], 1, H, H, H, theta + offB[l], (const float *)nullptr, z,
+                           a[(l + 1) & 1], H, np);
+    hipLaunchKernelGGL(k_layer5, dim3((n * NOUT + 255) / 256), dim3(256), 0, st, a[1], n, wbf, theta, Y);
+    return hipGetLastError() == hipSuccess ? PGK_OK : PGK_EDEVICE;
 }
 
 extern "C" const char *pgk_mlp_last_error(const pgk_mlp *m) { return m ? m->err.c_str() : "null mlp"; }
