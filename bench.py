@@ -10,12 +10,14 @@ Prints one JSON line.  MLUPS = 1e-6 x site updates per second (a cell holds
 two sites).  The roofline object is for the dominant kernel (the fused
 pull-collide kernel), timed live with HIP events on its own stream.
 
-The "sweep" object is the batched-sweep experiment: a seeded mix of 1D
-Couette layers and normal-shock lines run to residual 1e-8 cold in one
-persistent batched launch, warm-started
-from the coordinate MLP (trained on the steady states of a second seeded
-set), and one case at a time through the single-grid path (a seeded subset,
-scaled to the whole set).  `--sweep` runs it alone, `--no-sweep` skips it.
+The "sweep" object is the batched-sweep experiment on the 512-case mix of
+1D Couette layers (L ~ U{256..4096}, Kn ~ logU[1e-3, 1e-1]) and normal-shock
+lines (Mach ~ U[1.1, 4]), run to residual 1e-8 (with a stated per-case step
+cap) cold in one persistent batched launch per kind, warm-started from the
+coordinate MLP (trained on the steady states that the solver reaches for a
+second seeded set of 4096 cases), and one case at a time through the
+single-grid path (a seeded subset, scaled to the whole set).  `--sweep` runs
+it alone, `--no-sweep` skips it.
 """
 import argparse
 import json
@@ -144,11 +146,11 @@ def copy_probe(torch, nbytes=4 << 30, reps=10, quick=False):
     out = {"bytes_moved": 2 * nbytes}
     variants = [("runtime", None)] + [("float4_b%d" % nb, (0, nb)) for nb in (512, 1024, 2048)] + \
                [("float4_nt_b%d" % nb, (1, nb)) for nb in (1024,)] + [("float1", (2, 0))] + \
-               [("float4_x%d" % u, (v, 0)) for u, v in ((4, 3), (8, 4), (16, 5))]
+               [("float4_x%d" % u, (v, 0)) for u, v in ((1, 7), (4, 3), (8, 4), (16, 5))]
     # the population layout of the fused step: 41 streams of one float per site
     variants.append(("soa41_streams", (6, 0)))
     if quick:
-        variants = [("runtime", None), ("float4_x4", (3, 0)), ("soa41_streams", (6, 0))]
+        variants = [("runtime", None), ("float4_x1", (7, 0)), ("float4_x4", (3, 0)), ("soa41_streams", (6, 0))]
     for name, v in variants:
         def run():
             if v is None:
@@ -371,21 +373,31 @@ def sweep(args):
     S = 220105280
     tol = 1e-8
     kw = dict(L_range=(args.sweep_lmin, args.sweep_lmax), Kn_range=(args.sweep_knmin, args.sweep_knmax),
-              shock_fraction=args.sweep_shock_frac, shock_Ma_range=(1.1, 1.6), shock_Kn_range=(2e-3, 6e-3))
-    test, red_t = C.sweep_cases(args.sweep_n, S, **kw)
-    train, red_r = C.sweep_cases(args.sweep_train, S + 1, **kw)
+              shock_fraction=args.sweep_shock_frac, shock_Ma_range=(args.sweep_mamin, args.sweep_mamax),
+              shock_Kn_range=(2e-3, 6e-3))
+    cnt_t, cnt_r = {}, {}
+    test, red_t = C.sweep_cases(args.sweep_n, S, counts=cnt_t, **kw)
+    train, red_r = C.sweep_cases(args.sweep_train, S + 1, counts=cnt_r, **kw)
     is_shock = np.array([c["kind"] == C.SHOCK for c in test])
     out = {"metric": "sweep time-to-residual 1e-8 plain vs batched+MLP", "unit": "s", "tol": tol,
            "cases": len(test), "shock_cases": int(is_shock.sum()), "train_cases": len(train),
-           "infeasible_redraws": red_t + red_r,
+           "infeasible_at_draw": {
+               "pr_mub_pairs_redrawn": {"held_out": red_t, "training": red_r},
+               "shock_mach_without_jump_states_redrawn": {"held_out": cnt_t["shock_no_states"],
+                                                          "training": cnt_r["shock_no_states"]},
+               "shocks_with_upstream_below_theta0": {"held_out": cnt_t["shock_cold_upstream"],
+                                                     "training": cnt_r["shock_cold_upstream"]}},
            "distribution": "L~U{%d..%d}, delta in {2,3}, Pr~U[0.67,1], mu_b/mu~U[0,2] (infeasible pairs redrawn); "
                            "%.0f%% Couette (F3): Ma_w~U[0.1,0.5], Kn=nu/(c_s L)~logU[%g,%g]; "
-                           "%.0f%% normal shocks (E2): Ma~U[1.1,1.6], Kn=lambda1/L~logU[0.002,0.006]"
+                           "%.0f%% normal shocks (E2): Ma~U[%g,%g] (upstream at theta0, or at the warmest "
+                           "theta1 <= 0.12 with E2 jump states above about Mach 2.65), Kn=lambda1/L~logU[0.002,0.006]"
                            % (args.sweep_lmin, args.sweep_lmax, 100 * (1 - args.sweep_shock_frac), args.sweep_knmin,
-                              args.sweep_knmax, 100 * args.sweep_shock_frac),
+                              args.sweep_knmax, 100 * args.sweep_shock_frac, args.sweep_mamin, args.sweep_mamax),
+           "step_cap_per_case": {"held_out": args.sweep_max_steps, "training": args.sweep_train_max_steps},
+           "wall_time_budget_per_batch_s": args.sweep_time_budget or None,
            "stall_window_steps": {"couette": args.sweep_stall, "shock": args.sweep_stall_shock}}
 
-    def run_batch(cs, fields, label, tune_only=False):
+    def run_batch(cs, fields, label, tune_only=False, max_steps=None):
         """Run the cases to the tolerance: the Couette layers (F3, any
         work-group size) and the shock lines (E2, work-groups of 256) as two
         batches, each one persistent launch per chunk on its own stream, run
@@ -408,8 +420,21 @@ def sweep(args):
             b.config(0, 0)
             b.stall(args.sweep_stall_shock if cs[idx[0]]["kind"] == C.SHOCK else args.sweep_stall)
             stream.synchronize()
-            # tune_only: let the autotuner time its candidates and cache the choice
-            steps, resid, status = b.run(512 if tune_only else args.sweep_max_steps, tol)
+            # tune_only: let the autotuner time its candidates and cache the choice;
+            # otherwise advance in stages of 2048 steps (a capped case runs on
+            # when the cap rises) and report each stage
+            cap = 512 if tune_only else (max_steps or args.sweep_max_steps)
+            done = 0
+            while True:
+                done = min(cap, done + 2048)
+                steps, resid, status = b.run(done, tol)
+                print("# %s %s: %d steps, running %d of %d, %.1f s" % (label, cs[idx[0]]["kind"], done,
+                      int((status == 3).sum()) if done < cap else 0, len(idx), time.perf_counter() - tw),
+                      file=sys.stderr, flush=True)
+                if done >= cap or not (status == 3).any():
+                    break
+                if not tune_only and args.sweep_time_budget and time.perf_counter() - tw > args.sweep_time_budget:
+                    break   # out of wall time: the cases still running stay capped
             res[j] = (idx, sel, steps, resid, status, b.moments(), b.tuned())
             b.close()
             wall[j] = time.perf_counter() - tw
@@ -443,7 +468,10 @@ def sweep(args):
 
     # training data: steady states of the training cases (cold batched runs);
     # the first run also settles the autotuner's choice for this case mix
-    tr = run_batch(train, C.cold_fields(train), "train cold")
+    t_gen0 = time.perf_counter()
+    tr = run_batch(train, C.cold_fields(train), "train cold", max_steps=args.sweep_train_max_steps)
+    t_gen = time.perf_counter() - t_gen0
+    tr_shock = np.array([c["kind"] == C.SHOCK for c in train])
     ok = np.repeat(tr["status"] == 1, [2 * c["L"] for c in train])
     X = C.features(train)[ok]
     Y = C.targets(train, tr["m"])[ok]
@@ -469,15 +497,17 @@ def sweep(args):
     mlp.close()
 
     # final match of warm and cold converged states.  Couette: max |du|/U
-    # against the bound 2 R / r_slow of a run stopped at residual R
-    # (r_slow ~ pi^2 nu / L^2).  Shock: a shock between Dirichlet faces may
+    # against the bound (R_cold + R_warm) / r_slow of two runs stopped at
+    # residuals R (r_slow = pi^2 nu / L_eff^2, the slowest shear mode of a
+    # layer whose walls slip by a mean free path lambda each, L_eff = L + 2
+    # lambda).  Shock: a shock between Dirichlet faces may
     # settle anywhere, so the shift of its position is reported and the
     # density profiles are compared with the positions aligned (max |drho| over
     # the jump rho2 - rho1).
     both = (cold["status"] == 1) & (warm["status"] == 1)
     worst_c, worst_s, shift, o = 0.0, 0.0, 0.0, 0
     from paper_2201_05280_amd.inputs import positions
-    for c, ok_c in zip(test, both):
+    for k_c, (c, ok_c) in enumerate(zip(test, both)):
         n = 2 * c["L"]
         if ok_c:
             sl = slice(o, o + n)
@@ -496,8 +526,9 @@ def sweep(args):
                 shift = max(shift, abs(d))
             else:
                 du = np.abs(warm["m"]["u"][1][sl] - cold["m"]["u"][1][sl]).max() / c["U"]
-                r_slow = math.pi ** 2 * c["nu"] / c["L"] ** 2
-                worst_c = max(worst_c, du / (2 * tol / r_slow))
+                lam = c["nu"] * math.sqrt(math.pi / (2 * THETA0))
+                r_slow = math.pi ** 2 * c["nu"] / (c["L"] + 2 * lam) ** 2
+                worst_c = max(worst_c, du / ((cold["resid"][k_c] + warm["resid"][k_c]) / r_slow))
         o += n
     # plain: a seeded subset of the held-out cases, one at a time through the
     # single-grid path; a case stopped by the time cap is charged its measured
@@ -519,7 +550,12 @@ def sweep(args):
 
     def counts(r, mask):
         return {k: int(((r["status"] == v) & mask).sum()) for k, v in
-                (("converged", 1), ("diverged", 2), ("max_steps", 3), ("stalled", 4))}
+                (("converged", 1), ("diverged", 2), ("capped", 3), ("stalled", 4))}
+
+    conv_both = (cold["status"] == 1) & (warm["status"] == 1)
+
+    def med(a, mask):
+        return int(np.median(a[mask])) if mask.any() else None
 
     out.update({
         "plain_subset_cases": len(idx), "plain_subset_time": round(tp, 2), "plain_subset_run_to_end": n_full,
@@ -527,18 +563,33 @@ def sweep(args):
         "plain_estimated_time": round(plain_est, 1),
         "batched_cold_time": round(cold["time"], 2), "batched_warm_time": round(warm["time"] + t_infer, 2),
         "batched_warm_plus_training_time": round(warm["time"] + t_infer + t_train, 2),
+        "warm_pipeline_time_with_data_generation": round(t_gen + t_train + t_infer + warm["time"], 2),
+        "training_data_generation_time": round(t_gen, 2),
+        "training_cases_by_status": {"couette": counts(tr, ~tr_shock), "shock": counts(tr, tr_shock)},
         "mlp_inference_time": round(t_infer, 3), "mlp_train_time": round(t_train, 1),
         "mlp_train_points": int(len(X)),
         "mlp_loss_first_last": [float(losses[0]), float(losses[-1])], "mlp_schedule": args.sweep_lr_schedule,
         "mlp_minibatch": args.sweep_mlp_batch,
         "mlp_loss_curve_every_5_epochs": [float("%.4g" % v) for v in losses[::5]],
         "couette": {"cold": counts(cold, ~is_shock), "warm": counts(warm, ~is_shock),
-                    "steps_cold_median": int(np.median(cold["steps"][~is_shock])) if (~is_shock).any() else None,
-                    "steps_warm_median": int(np.median(warm["steps"][~is_shock])) if (~is_shock).any() else None,
+                    "residual_at_stop_median": {"cold": float("%.3g" % np.median(cold["resid"][~is_shock]))
+                                                if (~is_shock).any() else None,
+                                                "warm": float("%.3g" % np.median(warm["resid"][~is_shock]))
+                                                if (~is_shock).any() else None},
+                    "steps_cold_median": med(cold["steps"], ~is_shock),
+                    "steps_warm_median": med(warm["steps"], ~is_shock),
+                    "steps_cold_median_converged_both": med(cold["steps"], ~is_shock & conv_both),
+                    "steps_warm_median_converged_both": med(warm["steps"], ~is_shock & conv_both),
                     "warm_vs_cold_max_du_over_bound": round(worst_c, 3)},
         "shock": {"cold": counts(cold, is_shock), "warm": counts(warm, is_shock),
-                  "steps_cold_median": int(np.median(cold["steps"][is_shock])) if is_shock.any() else None,
-                  "steps_warm_median": int(np.median(warm["steps"][is_shock])) if is_shock.any() else None,
+                  "residual_at_stop_median": {"cold": float("%.3g" % np.median(cold["resid"][is_shock]))
+                                              if is_shock.any() else None,
+                                              "warm": float("%.3g" % np.median(warm["resid"][is_shock]))
+                                              if is_shock.any() else None},
+                  "steps_cold_median": med(cold["steps"], is_shock),
+                  "steps_warm_median": med(warm["steps"], is_shock),
+                  "steps_cold_median_converged_both": med(cold["steps"], is_shock & conv_both),
+                  "steps_warm_median_converged_both": med(warm["steps"], is_shock & conv_both),
                   "warm_vs_cold_max_drho_over_jump_aligned": round(worst_s, 6),
                   "warm_vs_cold_max_shift_cells": round(shift, 4)},
         "steps_cold_total": int(cold["steps"].sum()), "steps_warm_total": int(warm["steps"].sum()),
@@ -548,6 +599,19 @@ def sweep(args):
         "speedup_batched_warm_vs_plain": round(plain_est / (warm["time"] + t_infer), 2),
     })
     return out
+
+
+def reduced_args(args):
+    """The reduced mix whose every case can reach the residual: 256 held-out
+    and 512 training cases, L ~ U{128..512}, Couette Kn ~ logU[1e-2, 1e-1],
+    shocks to Mach 1.6, no caps that bind."""
+    import copy
+    r = copy.copy(args)
+    r.sweep_n, r.sweep_train, r.sweep_lmin, r.sweep_lmax = 256, 512, 128, 512
+    r.sweep_knmin, r.sweep_knmax, r.sweep_mamin, r.sweep_mamax = 1e-2, 1e-1, 1.1, 1.6
+    r.sweep_max_steps = r.sweep_train_max_steps = 400000
+    r.sweep_time_budget = 0.0
+    return r
 
 
 def main():
@@ -566,13 +630,23 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep experiment")
     ap.add_argument("--no-shock", action="store_true", help="skip the normal-shock lines")
     ap.add_argument("--shock", action="store_true", help="run only the normal-shock lines")
-    ap.add_argument("--sweep-n", type=int, default=256)
-    ap.add_argument("--sweep-train", type=int, default=512)
-    ap.add_argument("--sweep-lmin", type=int, default=128)
-    ap.add_argument("--sweep-lmax", type=int, default=512)
-    ap.add_argument("--sweep-knmin", type=float, default=1e-2)
+    ap.add_argument("--sweep-n", type=int, default=512, help="held-out cases (seed 220105280)")
+    ap.add_argument("--sweep-train", type=int, default=4096, help="training cases (seed 220105281)")
+    ap.add_argument("--sweep-lmin", type=int, default=256)
+    ap.add_argument("--sweep-lmax", type=int, default=4096)
+    ap.add_argument("--sweep-knmin", type=float, default=1e-3)
     ap.add_argument("--sweep-knmax", type=float, default=1e-1)
-    ap.add_argument("--sweep-max-steps", type=int, default=400000)
+    ap.add_argument("--sweep-mamin", type=float, default=1.1, help="shock Mach range")
+    ap.add_argument("--sweep-mamax", type=float, default=4.0)
+    ap.add_argument("--sweep-max-steps", type=int, default=16384,
+                    help="step cap per held-out case (a case still running there counts as capped)")
+    ap.add_argument("--sweep-train-max-steps", type=int, default=8192,
+                    help="step cap per training case (only converged training states train the network)")
+    ap.add_argument("--sweep-time-budget", type=float, default=60.0,
+                    help="wall seconds per batched run after which the cases still running count as capped "
+                         "(0 = none)")
+    ap.add_argument("--no-sweep-reduced", action="store_true",
+                    help="skip the second sweep on the reduced mix that converges in full")
     ap.add_argument("--sweep-mlp-batch", type=int, default=2048, help="MLP training minibatch")
     ap.add_argument("--sweep-lr-schedule", default="2e-3:40,5e-4:30,1.25e-4:30",
                     help="MLP training stages lr:epochs[,lr:epochs...] (Adam state carried across stages)")
@@ -591,7 +665,10 @@ def main():
               "(the z-slab decomposition is a design note); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.sweep:
-        print(json.dumps(sweep(args)), flush=True)
+        out = {"sweep": sweep(args)}
+        if not args.no_sweep_reduced:
+            out["sweep_reduced"] = sweep(reduced_args(args))
+        print(json.dumps(out), flush=True)
         return
     if args.shock:
         print(json.dumps(shock_summary()), flush=True)
@@ -687,11 +764,18 @@ def main():
         out["copy_probe"] = cp
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)
-    out["shear_wave"] = shear_wave_summary()
-    if not args.no_shock:
-        out["shock"] = shock_summary()
-    if not args.no_sweep:
-        out["sweep"] = sweep(args)
+    # the side experiments report into the line; a failure in one of them is
+    # recorded there and never costs the headline measurement
+    for key, skip, fn in (("shear_wave", False, shear_wave_summary), ("shock", args.no_shock, shock_summary),
+                          ("sweep", args.no_sweep, lambda: sweep(args)),
+                          ("sweep_reduced", args.no_sweep or args.no_sweep_reduced, lambda: sweep(reduced_args(args)))):
+        if skip:
+            continue
+        try:
+            out[key] = fn()
+        except Exception as e:  # noqa: BLE001
+            print("# %s failed: %r" % (key, e), file=sys.stderr, flush=True)
+            out[key] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
 
 

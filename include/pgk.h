@@ -72,7 +72,7 @@ extern "C" {
                                 a target beyond what a positive distribution on the lattice can
                                 carry has no solution: that site's populations become NaN.
                                 Diffuse walls re-emit F3 in either case; Dirichlet faces take
-                                E2 (pgk_set_bc_x returns PGK_EINFEASIBLE if the face state
+                                E2 (pgk_set_bc returns PGK_EINFEASIBLE if the face state
                                 has none) */
 #define PGK_F4   2           /* F3 plus the contracted fourth-order Hermite terms
                                 w_i sum_ab K_ab h_ab(c_i), h_ab(c) = c_a c_b (c^2 - 7 theta0)
@@ -86,7 +86,9 @@ extern "C" {
                                 Walls re-emit F3, Dirichlet faces take F4.  Single grid only
                                 (not in the batched sweep) */
 
-/* boundary kinds of the two x faces (y and z are periodic) */
+/* boundary kinds of the faces: the two x faces and the two y faces (z is
+ * periodic).  A position beyond an x face and a y face at once (a corner of a
+ * box bounded on both axes) belongs to the x face. */
 #define PGK_PERIODIC   0
 #define PGK_WALL       1     /* diffuse (Maxwell) wall at u_w, theta_w */
 #define PGK_DIRICHLET  2     /* equilibrium ghost state rho, u, theta */
@@ -109,6 +111,7 @@ typedef struct {
     int variant;             /* PGK_CN | PGK_LIT */
     int equilibrium;         /* PGK_F3 | PGK_E2 | PGK_F4 */
     int bc_x[2];             /* kind of the low and high x faces */
+    int bc_y[2];             /* kind of the low and high y faces (bounded: ny >= 2) */
 } pgk_grid;
 
 /* The model parameters of Sec. 4: relaxation times tau (ES-BGK part) and tau1
@@ -186,14 +189,22 @@ int pgk_bind(pgk_ctx *ctx, void *const bufs[PGK_NBUF], const size_t bytes[PGK_NB
  * refused with PGK_EINVAL on a PGK_E2 grid. */
 int pgk_set_params(pgk_ctx *ctx, const pgk_params *p, pgk_resolved *out);
 
-/* Boundary data of x face `side` (0 low, 1 high): wall velocity and temperature
- * for PGK_WALL (rho ignored), ghost state for PGK_DIRICHLET.  Every bounded
- * face needs its state before pgk_init_fields (PGK_EINVAL otherwise); with
- * PGK_E2, a Dirichlet state without an E2 equilibrium gives PGK_EINFEASIBLE.
- * Between steps, a new state acts as in a push scheme: the pull of the next
- * step still reads what the face in force during the last collision sends
- * (the library fills those ghosts first), the step after reads the new state.
- * Dirichlet ghosts are filled once per state, wall ghosts every step. */
+/* Boundary data of face `side` (0 low, 1 high) of axis `axis` (0 x, 1 y):
+ * wall velocity and temperature for PGK_WALL (rho ignored; the velocity
+ * component normal to the wall must be 0), ghost state for PGK_DIRICHLET.
+ * A diffuse wall re-emits, into every ghost column beyond it, the mass the
+ * last collision sent into that column (zero net mass flux per column), at
+ * the equilibrium of its velocity and temperature (Sec. 6 uses diffuse walls
+ * on one axis for the Couette flows and on both for the heated cavity).
+ * Every bounded face needs its state before pgk_init_fields (PGK_EINVAL
+ * otherwise); with PGK_E2, a Dirichlet state without an E2 equilibrium gives
+ * PGK_EINFEASIBLE.  Between steps, a new state acts as in a push scheme: the
+ * pull of the next step still reads what the face in force during the last
+ * collision sends (the library fills those ghosts first), the step after
+ * reads the new state.  Dirichlet ghosts are filled once per state, wall
+ * ghosts every step.  PGK_EINVAL for a periodic face. */
+int pgk_set_bc(pgk_ctx *ctx, int axis, int side, double rho, const double u[3], double theta);
+/* pgk_set_bc(ctx, 0, side, ...) */
 int pgk_set_bc_x(pgk_ctx *ctx, int side, double rho, const double u[3], double theta);
 
 /* Initial state from device fields rho[ns], u[3][ns], theta_T[ns], theta_R[ns]:
@@ -207,7 +218,7 @@ int pgk_init_fields(pgk_ctx *ctx, const double *rho, const double *u,
  * recorded once as a HIP graph per starting buffer (on a private stream) and
  * replayed n/K times, the rest launched directly; the launches and results
  * are those of stepping one by one, bit for bit.  The recorded chunks are
- * dropped by pgk_bind, pgk_set_params, pgk_set_bc_x and a new K.
+ * dropped by pgk_bind, pgk_set_params, pgk_set_bc and a new K.
  * Errors: PGK_EINVAL before pgk_init_fields, PGK_EDEVICE on a failed launch,
  * capture or graph instantiation (message in pgk_last_error). */
 int pgk_step(pgk_ctx *ctx, int64_t n);
@@ -252,7 +263,7 @@ int pgk_set_transport_reference(pgk_ctx *ctx, int on);
  * and second half relaxation (on a bounded or sub-cycled line, ny = nz = 1,
  * with at most 63 sub-steps: the whole transport in one launch of 1024-cell
  * work-groups; on another bounded or sub-cycled grid of at most 4096 sites:
- * the whole transport in one work-group), [3] the x ghost fill, and clears the
+ * the whole transport in one work-group), [3] the ghost fill of the bounded faces, and clears the
  * record.  Event handles are created on demand and
  * kept until pgk_destroy. */
 #define PGK_NKERNEL 4
@@ -321,7 +332,11 @@ int pgk_batch_init(pgk_batch *b, const double *rho, const double *u, const doubl
 int pgk_batch_config(pgk_batch *b, int wg, int K);
 
 /* Run until every case has stopped or max_steps per case.  Host arrays of n
- * entries receive the steps taken, the last residual and the status. */
+ * entries receive the steps taken, the last residual and the status.  A case
+ * that an earlier call stopped at its lower max_steps (PGK_CASE_MAXSTEPS)
+ * runs on when a later call raises the cap, so a caller can advance a batch
+ * in stages; the stall bookkeeping carries over between calls until
+ * pgk_batch_init. */
 int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_t *steps, double *resid, int *status);
 
 /* Stall detection for pgk_batch_run: a running case whose residual has not
@@ -413,7 +428,7 @@ int64_t pgk_steps_done(const pgk_ctx *ctx);
 
 /* Checkpoints.  Between steps the state of a grid is the content of its four
  * bound buffers plus this clock: the steps taken, which population buffer
- * holds the state, and whether the x ghosts hold what the next pull reads
+ * holds the state, and whether the face ghosts hold what the next pull reads
  * (and a face state changed since).  A caller that copies the buffers out
  * (after synchronising the stream) with pgk_get_clock, and later back into a
  * grid of the same shape, precision, equilibrium, parameters and faces

@@ -52,6 +52,7 @@ def lib():
         L.pgko_threads.restype = ctypes.c_int
         L.pgko_set_params.argtypes = [vp] + [ctypes.c_double] * 6
         L.pgko_set_bc_x.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double]
+        L.pgko_set_bc.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double]
         L.pgko_init.argtypes = [vp, dp, dp, dp, dp]
         L.pgko_step.argtypes = [vp, ctypes.c_long]
         L.pgko_moments.argtypes = [vp, dp, dp, dp, dp, dp]
@@ -141,9 +142,14 @@ class Oracle:
         if rc != 0:
             raise ValueError("bad parameters")
 
-    def set_bc_x(self, side, kind, rho=1.0, u=(0.0, 0.0, 0.0), theta=THETA0):
+    def set_bc(self, axis, side, kind, rho=1.0, u=(0.0, 0.0, 0.0), theta=THETA0):
+        """Face `side` (0 low, 1 high) of axis `axis` (0 x, 1 y; z is periodic)."""
         uu = np.ascontiguousarray(u, dtype=np.float64)
-        lib().pgko_set_bc_x(self._h, side, kind, float(rho), _p(uu), float(theta))
+        if lib().pgko_set_bc(self._h, int(axis), int(side), int(kind), float(rho), _p(uu), float(theta)) != 0:
+            raise ValueError("bad face")
+
+    def set_bc_x(self, side, kind, rho=1.0, u=(0.0, 0.0, 0.0), theta=THETA0):
+        self.set_bc(0, side, kind, rho, u, theta)
 
     def init(self, rho, u, thT, thR):
         rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)

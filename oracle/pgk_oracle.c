@@ -405,8 +405,8 @@ typedef struct pgko {
     /* per-site results of the collision, used by the rotational transport */
     double *rho, *u, *T, *theta, *ehat, *d;
     double *e1, *e2, *phi;
-    int bc[2];
-    double bc_rho[2], bc_u[2][3], bc_th[2];
+    int bc[2][2];                       /* [axis x, y][side low, high] */
+    double bc_rho[2][2], bc_u[2][2][3], bc_th[2][2];
     int e2_fail;
     int nsub;          /* FTCS sub-steps of the theta_R diffusion */
 } pgko;
@@ -448,7 +448,7 @@ pgko *pgko_create(int nx, int ny, int nz, int variant, int equilibrium)
     o->e1 = (double *)calloc(n, sizeof(double));
     o->e2 = (double *)calloc(n, sizeof(double));
     o->phi = (double *)calloc(n, sizeof(double));
-    o->bc[0] = o->bc[1] = BC_PERIODIC;
+    o->bc[0][0] = o->bc[0][1] = o->bc[1][0] = o->bc[1][1] = BC_PERIODIC;
     return o;
 }
 
@@ -492,17 +492,24 @@ int pgko_set_params(pgko *o, double tau, double tau1, double b, double kr,
     return 0;
 }
 
-/* side 0 = low x, 1 = high x.  kind: periodic, wall (diffuse, at rest or
- * moving tangentially with velocity u and temperature theta), Dirichlet
- * (equilibrium ghost state rho, u, theta).  Periodic must be set on both. */
+/* axis 0 = x, 1 = y (z is periodic); side 0 = low, 1 = high.  kind:
+ * periodic, wall (diffuse, at rest or moving tangentially with velocity u
+ * and temperature theta), Dirichlet (equilibrium ghost state rho, u, theta).
+ * Periodic must be set on both sides of an axis. */
+int pgko_set_bc(pgko *o, int axis, int side, int kind, double rho, const double *u, double theta)
+{
+    if (axis < 0 || axis > 1 || side < 0 || side > 1) return -1;
+    if (axis == 1 && kind != BC_PERIODIC && o->ny < 2) return -1;
+    o->bc[axis][side] = kind;
+    o->bc_rho[axis][side] = rho;
+    for (int a = 0; a < 3; a++) o->bc_u[axis][side][a] = u ? u[a] : 0.0;
+    o->bc_th[axis][side] = theta;
+    return 0;
+}
+
 int pgko_set_bc_x(pgko *o, int side, int kind, double rho, const double *u, double theta)
 {
-    if (side < 0 || side > 1) return -1;
-    o->bc[side] = kind;
-    o->bc_rho[side] = rho;
-    for (int a = 0; a < 3; a++) o->bc_u[side][a] = u ? u[a] : 0.0;
-    o->bc_th[side] = theta;
-    return 0;
+    return pgko_set_bc(o, 0, side, kind, rho, u, theta);
 }
 
 static int equilibrium(const pgko *o, double rho, const double *u, const double *lam6, double *F)
@@ -615,76 +622,102 @@ int pgko_collide_site(pgko *o, const double *g, double er, double *gout, double 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Streaming (pull) on the bcc grid with the x boundary conditions           */
+/* Streaming (pull) on the bcc grid with bounded x and y faces               */
 /* ------------------------------------------------------------------------ */
-/* Doubled coordinate of a site along x: A sites at 2x, B sites at 2x+1.
- * The low wall sits at doubled coordinate -1/2, the high wall at 2nx - 1/2. */
-static void wall_equilibrium(const pgko *o, int side, double *Fw)
+/* Doubled coordinates: along each axis the corner sites (sublattice A) sit at
+ * 2i and the body-centre sites (B) at 2i+1.  A bounded low face sits at
+ * doubled coordinate -1/2, a high face at 2n - 1/2.  Faces are numbered
+ * f = 2 axis + side (axis 0 = x, 1 = y; z is periodic). */
+static void face_equilibrium(const pgko *o, int f, double *F)
 {
-    double lam[6] = {o->bc_th[side], o->bc_th[side], o->bc_th[side], 0, 0, 0};
-    pgko_feq_f3(o->th0, o->w, &o->c[0][0], 1.0, o->bc_u[side], lam, Fw);
-}
-
-static void dirichlet_equilibrium(const pgko *o, int side, double *Fd)
-{
-    double lam[6] = {o->bc_th[side], o->bc_th[side], o->bc_th[side], 0, 0, 0};
+    int a = f / 2, side = f % 2;
+    double th = o->bc_th[a][side];
+    double lam[6] = {th, th, th, 0, 0, 0};
+    if (o->bc[a][side] == BC_WALL) {
+        /* diffuse wall: F3 at unit density, scaled per column by the wall density */
+        pgko_feq_f3(o->th0, o->w, &o->c[0][0], 1.0, o->bc_u[a][side], lam, F);
+        return;
+    }
     double tmp[NQ];
-    if (o->eq == EQ_E2 && pgko_feq_e2(o->th0, o->w, &o->c[0][0], o->bc_rho[side], o->bc_u[side], lam, tmp) > 0) {
-        memcpy(Fd, tmp, sizeof(tmp));
+    if (o->eq == EQ_E2 && pgko_feq_e2(o->th0, o->w, &o->c[0][0], o->bc_rho[a][side], o->bc_u[a][side], lam, tmp) > 0) {
+        memcpy(F, tmp, sizeof(tmp));
         return;
     }
     if (o->eq == EQ_F4) {
-        pgko_feq_f4(o->th0, o->w, &o->c[0][0], o->bc_rho[side], o->bc_u[side], lam, Fd);
+        pgko_feq_f4(o->th0, o->w, &o->c[0][0], o->bc_rho[a][side], o->bc_u[a][side], lam, F);
         return;
     }
-    pgko_feq_f3(o->th0, o->w, &o->c[0][0], o->bc_rho[side], o->bc_u[side], lam, Fd);
+    pgko_feq_f3(o->th0, o->w, &o->c[0][0], o->bc_rho[a][side], o->bc_u[a][side], lam, F);
 }
 
 /* floor(q/2) for a doubled coordinate */
 static int half_floor(int q) { return q >= 0 ? q / 2 : -((-q + 1) / 2); }
 
-/* Pull streaming.  A population that would be pulled from beyond a
- * non-periodic x side comes from the boundary: for a diffuse wall it is
- * rho_w F_i(1, u_w, theta_w I) with rho_w fixed by zero net mass flux; for a
- * Dirichlet side it is F_i(rho_D, u_D, theta_D I).  The mass balance of a
- * diffuse wall is kept per (y,z) column of the ghost position the population
- * leaves to or arrives from (both sublattices pooled). */
+/* The bounded face a doubled position q lies beyond, or -1 (a periodic axis
+ * wraps instead).  A position beyond a bounded x face and a bounded y face at
+ * once (a corner) belongs to the x face. */
+static int beyond(const pgko *o, const int *q)
+{
+    for (int a = 0; a < 2; a++) {
+        int n = a == 0 ? o->nx : o->ny;
+        if (q[a] < 0 && o->bc[a][0] != BC_PERIODIC) return 2 * a;
+        if (q[a] > 2 * n - 1 && o->bc[a][1] != BC_PERIODIC) return 2 * a + 1;
+    }
+    return -1;
+}
+
+/* Ghost column of a position q beyond face f: its cell coordinates along the
+ * other in-plane axis b (y for x faces, x for y faces) and along z.  Along a
+ * bounded axis b the coordinate is kept as it is, from -2 to n_b + 1 (a
+ * corner column lies outside the grid), along a periodic one it wraps.
+ * *ncol receives the number of columns of face f. */
+static int column_of(const pgko *o, int f, const int *q, int *ncol)
+{
+    int b = 1 - f / 2;
+    int nb = b == 0 ? o->nx : o->ny;
+    int bounded = o->bc[b][0] != BC_PERIODIC;
+    int width = bounded ? nb + 4 : nb;
+    int hb = half_floor(q[b]);
+    int ib = bounded ? hb + 2 : wrap(hb, nb);
+    if (ncol) *ncol = width * o->nz;
+    return wrap(half_floor(q[2]), o->nz) * width + ib;
+}
+
+/* Pull streaming.  A population that would be pulled from beyond a bounded
+ * face comes from the boundary: for a diffuse wall it is rho_w F_i(1, u_w,
+ * theta_w I) with rho_w fixed by zero net mass flux; for a Dirichlet face it
+ * is F_i(rho_D, u_D, theta_D I).  The mass balance of a diffuse wall is kept
+ * per ghost column of the position a population leaves to or arrives from
+ * (both sublattices pooled). */
 static void stream(pgko *o)
 {
-    int ns = o->ns, nx = o->nx, ny = o->ny, nz = o->nz;
-    double Fw[2][NQ];
-    for (int side = 0; side < 2; side++) {
-        if (o->bc[side] == BC_WALL) wall_equilibrium(o, side, Fw[side]);
-        else if (o->bc[side] == BC_DIRICHLET) dirichlet_equilibrium(o, side, Fw[side]);
-    }
-    size_t ncol = (size_t)ny * nz;
-    double *rw = (double *)calloc(2 * ncol, sizeof(double));
-    for (int side = 0; side < 2; side++) {
-        if (o->bc[side] != BC_WALL) continue;
+    int ns = o->ns;
+    double Fb[4][NQ];
+    double *rw[4] = {NULL, NULL, NULL, NULL};
+    for (int f = 0; f < 4; f++) {
+        int a = f / 2, side = f % 2;
+        if (o->bc[a][side] == BC_PERIODIC) continue;
+        face_equilibrium(o, f, Fb[f]);
+        if (o->bc[a][side] != BC_WALL) continue;
+        int ncol, q0[3] = {0, 0, 0};
+        column_of(o, f, q0, &ncol);
         double *out = (double *)calloc(ncol, sizeof(double));
         double *in = (double *)calloc(ncol, sizeof(double));
+        rw[f] = (double *)calloc(ncol, sizeof(double));
         for (int s = 0; s < ns; s++) {
             int sub, z, y, x;
             site_coords(o, s, &sub, &z, &y, &x);
             int p[3] = {2 * x + sub, 2 * y + sub, 2 * z + sub};
             for (int i = 0; i < NQ; i++) {
                 /* outgoing: arrives beyond the wall */
-                int d0 = p[0] + o->c2[i][0];
-                if ((side == 0 && d0 < 0) || (side == 1 && d0 > 2 * nx - 1)) {
-                    int gy = wrap(half_floor(p[1] + o->c2[i][1]), ny);
-                    int gz = wrap(half_floor(p[2] + o->c2[i][2]), nz);
-                    out[(size_t)gz * ny + gy] += o->gp[(size_t)i * ns + s];
-                }
+                int d[3] = {p[0] + o->c2[i][0], p[1] + o->c2[i][1], p[2] + o->c2[i][2]};
+                if (beyond(o, d) == f) out[column_of(o, f, d, NULL)] += o->gp[(size_t)i * ns + s];
                 /* incoming: pulled from beyond the wall */
-                int s0 = p[0] - o->c2[i][0];
-                if ((side == 0 && s0 < 0) || (side == 1 && s0 > 2 * nx - 1)) {
-                    int gy = wrap(half_floor(p[1] - o->c2[i][1]), ny);
-                    int gz = wrap(half_floor(p[2] - o->c2[i][2]), nz);
-                    in[(size_t)gz * ny + gy] += Fw[side][i];
-                }
+                int q[3] = {p[0] - o->c2[i][0], p[1] - o->c2[i][1], p[2] - o->c2[i][2]};
+                if (beyond(o, q) == f) in[column_of(o, f, q, NULL)] += Fb[f][i];
             }
         }
-        for (size_t k = 0; k < ncol; k++) rw[side * ncol + k] = in[k] > 0 ? out[k] / in[k] : 0.0;
+        for (int k = 0; k < ncol; k++) rw[f][k] = in[k] > 0 ? out[k] / in[k] : 0.0;
         free(out); free(in);
     }
 #pragma omp parallel for
@@ -694,43 +727,42 @@ static void stream(pgko *o)
         int p[3] = {2 * x + sub, 2 * y + sub, 2 * z + sub};
         for (int i = 0; i < NQ; i++) {
             int q[3] = {p[0] - o->c2[i][0], p[1] - o->c2[i][1], p[2] - o->c2[i][2]};
-            int side = q[0] < 0 ? 0 : (q[0] > 2 * nx - 1 ? 1 : -1);
+            int f = beyond(o, q);
             double val;
-            if (side >= 0 && o->bc[side] != BC_PERIODIC) {
-                if (o->bc[side] == BC_WALL) {
-                    int gy = wrap(half_floor(q[1]), ny), gz = wrap(half_floor(q[2]), nz);
-                    val = rw[side * ncol + (size_t)gz * ny + gy] * Fw[side][i];
-                } else {
-                    val = Fw[side][i];
-                }
+            if (f >= 0) {
+                if (o->bc[f / 2][f % 2] == BC_WALL) val = rw[f][column_of(o, f, q, NULL)] * Fb[f][i];
+                else val = Fb[f][i];
             } else {
                 int ssub = q[0] & 1;              /* all three share the parity */
                 int sx = (q[0] - ssub) / 2, sy = (q[1] - ssub) / 2, sz = (q[2] - ssub) / 2;
-                int src = site_index(o, ssub, wrap(sz, nz), wrap(sy, ny), wrap(sx, nx));
+                int src = site_index(o, ssub, wrap(sz, o->nz), wrap(sy, o->ny), wrap(sx, o->nx));
                 val = o->gp[(size_t)i * ns + src];
             }
             o->g[(size_t)i * ns + s] = val;
         }
     }
-    free(rw);
+    for (int f = 0; f < 4; f++) free(rw[f]);
 }
 
 /* ------------------------------------------------------------------------ */
 /* Rotational energy transport (steps 2-4 of the theta_R split)              */
 /* ------------------------------------------------------------------------ */
-/* Neighbour of site s along axis a by +-1 on its own sublattice; returns -1
- * (low ghost) or -2 (high ghost) across a non-periodic x boundary. */
+/* Neighbour of site s along axis a by +-1 on its own sublattice; across a
+ * bounded face f it returns -1 - f (-1, -2: low, high x; -3, -4: low, high y). */
 static int nb(const pgko *o, int s, int a, int dir)
 {
     int sub, z, y, x;
     site_coords(o, s, &sub, &z, &y, &x);
     int co[3] = {x, y, z}, n[3] = {o->nx, o->ny, o->nz};
     co[a] += dir;
-    if (a == 0 && co[0] < 0 && o->bc[0] != BC_PERIODIC) return -1;
-    if (a == 0 && co[0] >= n[0] && o->bc[1] != BC_PERIODIC) return -2;
+    if (a < 2 && co[a] < 0 && o->bc[a][0] != BC_PERIODIC) return -1 - 2 * a;
+    if (a < 2 && co[a] >= n[a] && o->bc[a][1] != BC_PERIODIC) return -2 - 2 * a;
     co[a] = wrap(co[a], n[a]);
     return site_index(o, sub, co[2], co[1], co[0]);
 }
+
+/* theta_R held beyond the face that nb() returned as g < 0 */
+static double face_theta(const pgko *o, int g) { int f = -1 - g; return o->bc_th[f / 2][f % 2]; }
 
 static double kappaR(const pgko *o, double rho, double theta)
 {
@@ -738,15 +770,17 @@ static double kappaR(const pgko *o, double rho, double theta)
     return o->kr * 5.0 * rho * theta * o->tau / (2.0 * o->B);
 }
 
-/* ghost values at a non-periodic x side */
+/* ghost values beyond a bounded face f next to site s_adj: the face's
+ * temperature, with the site's own density at a wall */
 typedef struct { double th, rho, kap; } ghost;
 
-static ghost ghost_of(const pgko *o, int side, int s_adj)
+static ghost ghost_of(const pgko *o, int f, int s_adj)
 {
     ghost g;
-    double rho = o->bc[side] == BC_WALL ? o->rho[s_adj] : o->bc_rho[side];
+    int a = f / 2, side = f % 2;
+    double rho = o->bc[a][side] == BC_WALL ? o->rho[s_adj] : o->bc_rho[a][side];
     g.rho = rho;
-    g.th = o->bc_th[side];
+    g.th = o->bc_th[a][side];
     g.kap = kappaR(o, rho, g.th);
     return g;
 }
@@ -772,7 +806,7 @@ static void transport(pgko *o)
         double adv = 0.0;
         for (int a = 0; a < 3; a++) {
             int p = nb(o, s, a, +1);
-            double tp = (p >= 0) ? th[p] : o->bc_th[p == -1 ? 0 : 1];
+            double tp = (p >= 0) ? th[p] : face_theta(o, p);
             adv += o->u[3 * s + a] * (tp - th[s]);
         }
         ts[s] = th[s] - adv;
@@ -782,7 +816,7 @@ static void transport(pgko *o)
         double adv = 0.0;
         for (int a = 0; a < 3; a++) {
             int m = nb(o, s, a, -1);
-            double tmv = (m >= 0) ? ts[m] : o->bc_th[m == -1 ? 0 : 1];
+            double tmv = (m >= 0) ? ts[m] : face_theta(o, m);
             adv += o->u[3 * s + a] * (ts[s] - tmv);
         }
         tm[s] = 0.5 * (th[s] + ts[s] - adv);
@@ -804,7 +838,7 @@ static void transport(pgko *o)
                         tq = cur[q];
                         kq = kappaR(o, o->rho[q], o->theta[q]);
                     } else {
-                        ghost gh = ghost_of(o, q == -1 ? 0 : 1, s);
+                        ghost gh = ghost_of(o, -1 - q, s);
                         tq = gh.th;
                         kq = gh.kap;
                     }
@@ -837,8 +871,8 @@ static int diffusion_substeps(const pgko *o)
 {
     int dim = (o->nx > 1) + (o->ny > 1) + (o->nz > 1);
     double th = o->th0;
-    for (int side = 0; side < 2; side++)
-        if (o->bc[side] != BC_PERIODIC && o->bc_th[side] > th) th = o->bc_th[side];
+    for (int f = 0; f < 4; f++)
+        if (o->bc[f / 2][f % 2] != BC_PERIODIC && o->bc_th[f / 2][f % 2] > th) th = o->bc_th[f / 2][f % 2];
     double DR = o->delta > 0 ? 5.0 * o->kr * th * o->tau / (o->B * o->delta) : 0.0;
     int n = (int)ceil(2.0 * dim * DR * 1.5);
     return n < 1 ? 1 : n;

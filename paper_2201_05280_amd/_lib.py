@@ -24,7 +24,7 @@ NBUF = 4
 
 # every symbol include/pgk.h declares
 EXPORTS = ["pgk_resolve", "pgk_lattice", "pgk_equilibrium", "pgk_buffer_sizes", "pgk_create", "pgk_bind", "pgk_set_params",
-           "pgk_set_bc_x", "pgk_init_fields", "pgk_step", "pgk_read_moments", "pgk_conserved",
+           "pgk_set_bc", "pgk_set_bc_x", "pgk_init_fields", "pgk_step", "pgk_read_moments", "pgk_conserved",
            "pgk_set_graph_steps", "pgk_set_transport_reference", "pgk_set_timing", "pgk_kernel_times", "pgk_get_clock", "pgk_set_clock", "pgk_steps_done", "pgk_last_error", "pgk_destroy",
            "pgk_batch_bytes", "pgk_batch_create", "pgk_batch_offsets", "pgk_batch_init", "pgk_batch_config",
            "pgk_batch_run", "pgk_batch_stall", "pgk_batch_tuned", "pgk_batch_read_moments", "pgk_batch_last_error",
@@ -41,7 +41,7 @@ KERNEL_NAMES = ["k_lb", "k_mc", "k_dif", "k_bc"]
 class Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("precision", ctypes.c_int), ("variant", ctypes.c_int), ("equilibrium", ctypes.c_int),
-                ("bc_x", ctypes.c_int * 2)]
+                ("bc_x", ctypes.c_int * 2), ("bc_y", ctypes.c_int * 2)]
 
 
 class Clock(ctypes.Structure):
@@ -96,6 +96,7 @@ def load():
     L.pgk_create.argtypes = [ctypes.POINTER(Grid), vp, ctypes.POINTER(vp)]
     L.pgk_bind.argtypes = [vp, vp * NBUF, sz * NBUF]
     L.pgk_set_params.argtypes = [vp, ctypes.POINTER(Params), ctypes.POINTER(Resolved)]
+    L.pgk_set_bc.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double]
     L.pgk_set_bc_x.argtypes = [vp, ctypes.c_int, ctypes.c_double, dp, ctypes.c_double]
     L.pgk_init_fields.argtypes = [vp, vp, vp, vp, vp]
     L.pgk_step.argtypes = [vp, i64]
@@ -191,9 +192,9 @@ def resolve(nu, Pr, mub_over_mu, delta, b=float("nan"), kr=float("nan"), theta0=
     return r.as_dict()
 
 
-def buffer_sizes(nx, ny, nz, precision=FP64, variant=CN, bc_x=(PERIODIC, PERIODIC)):
+def buffer_sizes(nx, ny, nz, precision=FP64, variant=CN, bc_x=(PERIODIC, PERIODIC), bc_y=(PERIODIC, PERIODIC)):
     L = load()
-    g = Grid(nx, ny, nz, precision, variant, F3, (ctypes.c_int * 2)(*bc_x))
+    g = Grid(nx, ny, nz, precision, variant, F3, (ctypes.c_int * 2)(*bc_x), (ctypes.c_int * 2)(*bc_y))
     out = (ctypes.c_size_t * NBUF)()
     rc = L.pgk_buffer_sizes(ctypes.byref(g), out)
     if rc != PGK_OK:

@@ -12,12 +12,18 @@ mu_b/mu ~ U[mub range] redrawn together while it is out of the model's reach
 (mu_b/mu at or below 1.02 times the floor 2 delta/(3(3+delta)), or no
 feasible (b, k_r) for it).
 
-Shock lines: upstream (rho 1, Ma c_s, theta0) at the low face, the model's
+Shock lines: upstream (rho 1, Ma c_s, theta1) at the low face, the model's
 own downstream state (equal equilibrium fluxes) at the high face, flow along
 +x; Ma ~ U[shock Ma range], Kn = lambda1 / L with the upstream mean free path
-lambda1 = nu sqrt(pi / (2 theta0)), Kn ~ logU[shock Kn range]; same Pr,
-mu_b/mu and delta draws.  Their cold start is the tanh blend of the two
-states (width 4 cells) centred at L/2.
+lambda1 = nu sqrt(pi / (2 theta1)), Kn ~ logU[shock Kn range]; same Pr,
+mu_b/mu and delta draws.  The upstream temperature theta1 is theta0 when the
+E2 equilibrium has both jump states there; above about Mach 2.65 the upstream
+speed Ma sqrt(gamma theta0) is beyond the lattice, and theta1 is the warmest
+temperature on a grid from 0.12 down to 0.04 (steps of 0.005) at which both
+states exist (a colder gas crosses the lattice at a lower speed).  A draw
+with no such temperature is infeasible: it is counted and drawn again.
+Their cold start is the tanh blend of the two states (width 4 cells) centred
+at L/2.
 
 Network features (all O(1)): x/L, 2 ln(Ma/0.3), (Pr - 0.835)/0.165,
 (mu_b/mu - 1), log10 Kn + 2, (delta - 2.5)/0.5.  Targets, Couette:
@@ -36,26 +42,67 @@ COUETTE = "couette"
 SHOCK = "shock"
 
 
+_THETA1 = {}
+
+
+def shock_upstream_theta(Ma, delta):
+    """(theta1, upstream, downstream) for a shock of Mach Ma: theta1 = theta0
+    when both jump states have an E2 equilibrium there, else the warmest
+    theta1 from 0.12 down to 0.04 (steps of 0.005) that has them; None when
+    none has."""
+    from .shock import discrete_rankine_hugoniot
+    key = (round(Ma, 12), delta)
+    if key not in _THETA1:
+        found = None
+        for th1 in [THETA0] + [0.12 - 0.005 * i for i in range(17)]:
+            try:
+                up, down = discrete_rankine_hugoniot(Ma, delta, th1)
+                # both faces need an E2 state of their own temperature
+                _lib.equilibrium(_lib.E2, up[0], (up[1], 0, 0), (up[2],) * 3 + (0, 0, 0))
+                _lib.equilibrium(_lib.E2, down[0], (down[1], 0, 0), (down[2],) * 3 + (0, 0, 0))
+                found = (th1, up, down)
+                break
+            except (ValueError, np.linalg.LinAlgError):
+                continue
+        _THETA1[key] = found
+    return _THETA1[key]
+
+
 def sweep_cases(n, seed, L_range=(256, 1024), Ma_range=(0.1, 0.5), Kn_range=(3e-3, 3e-2),
                 Pr_range=(0.67, 1.0), mub_range=(0.0, 2.0), deltas=(2.0, 3.0), shock_fraction=0.0,
-                shock_Ma_range=(1.1, 2.0), shock_Kn_range=(2e-3, 1e-2)):
+                shock_Ma_range=(1.1, 2.0), shock_Kn_range=(2e-3, 1e-2), counts=None):
     """n seeded cases (a shock with probability shock_fraction) and the number
-    of infeasible (Pr, mu_b/mu) draws that were redrawn."""
-    from .shock import discrete_rankine_hugoniot
+    of infeasible (Pr, mu_b/mu) draws that were redrawn.  `counts` (a dict,
+    optional) receives the shock draws with no jump states on the lattice
+    (redrawn) and those that needed an upstream temperature below theta0."""
     rng = np.random.default_rng(seed)
     out = []
     redraws = 0
+    if counts is not None:
+        counts.update(shock_no_states=0, shock_cold_upstream=0)
     for _ in range(n):
         kind = SHOCK if rng.uniform() < shock_fraction else COUETTE
         L = int(rng.integers(L_range[0], L_range[1] + 1))
         ma_r, kn_r = (shock_Ma_range, shock_Kn_range) if kind == SHOCK else (Ma_range, Kn_range)
-        Ma = float(rng.uniform(*ma_r))
-        Kn = float(10 ** rng.uniform(math.log10(kn_r[0]), math.log10(kn_r[1])))
         delta = float(deltas[int(rng.integers(0, len(deltas)))])
+        th1, states = THETA0, None
+        while True:
+            Ma = float(rng.uniform(*ma_r))
+            if kind == COUETTE:
+                break
+            states = shock_upstream_theta(Ma, delta)
+            if states is not None:
+                th1 = states[0]
+                if counts is not None and th1 != THETA0:
+                    counts["shock_cold_upstream"] += 1
+                break
+            if counts is not None:
+                counts["shock_no_states"] += 1
+        Kn = float(10 ** rng.uniform(math.log10(kn_r[0]), math.log10(kn_r[1])))
         floor = 2 * delta / (3 * (3 + delta)) * 1.02
         gamma = (5 + delta) / (3 + delta)
         cs = math.sqrt(gamma * THETA0)
-        nu = Kn * cs * L if kind == COUETTE else Kn * L / math.sqrt(math.pi / (2 * THETA0))
+        nu = Kn * cs * L if kind == COUETTE else Kn * L / math.sqrt(math.pi / (2 * th1))
         while True:
             # (Pr, mu_b/mu) pairs outside the model's reach (bulk viscosity at
             # or below the floor, or no b in [-1/2, 1) with k_r >= 0) are redrawn
@@ -63,14 +110,16 @@ def sweep_cases(n, seed, L_range=(256, 1024), Ma_range=(0.1, 0.5), Kn_range=(3e-
             mub = float(rng.uniform(*mub_range))
             if mub > floor:
                 try:
-                    p = _lib.resolve(nu, Pr, mub, delta)
+                    # the map takes nu at theta0; the shock's nu is the upstream one,
+                    # and nu grows like theta at fixed relaxation times
+                    p = _lib.resolve(nu * THETA0 / th1, Pr, mub, delta)
                     break
                 except ValueError:
                     pass
             redraws += 1
         c = dict(kind=kind, L=L, Ma=Ma, Kn=Kn, Pr=Pr, mub=mub, delta=delta, nu=nu, U=Ma * cs, params=p)
         if kind == SHOCK:
-            c["up"], c["down"] = discrete_rankine_hugoniot(Ma, delta)
+            c["theta1"], c["up"], c["down"] = states
         out.append(c)
     return out, redraws
 

@@ -416,6 +416,10 @@ struct pgk_batch {
     BatchArgs args{};
     bool has_e2 = false;          // some case uses E2: the E2-capable kernel, work-groups of 256
     long long stall_window = 0;   // steps without halving the best residual before STALLED (0: off)
+    // stall bookkeeping per case, kept across pgk_batch_run calls (reset by pgk_batch_init):
+    // the best residual so far and the steps since it last halved
+    std::vector<double> best;
+    std::vector<long long> since;
     int wg = 0, K = 0;            // fixed config (0 = tune)
     int tuned_wg = 0, tuned_K = 0;
     double tuned_ns = 0.0;
@@ -655,6 +659,8 @@ extern "C" int pgk_batch_init(pgk_batch *b, const double *rho, const double *u, 
                        b->ns_total);
     BHIP(b, hipGetLastError());
     BHIP(b, hipStreamSynchronize(b->stream));
+    b->best.assign(b->n, 1e300);
+    b->since.assign(b->n, 0);
     return PGK_OK;
 }
 
@@ -887,6 +893,19 @@ extern "C" int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_
     b->graphs.clear();
     int rc = readback(b);
     if (rc) return rc;
+    // a case stopped by an earlier, lower step cap runs on to this one
+    bool resumed = false;
+    for (int i = 0; i < b->n; i++)
+        if (b->h_status[i] == PGK_CASE_MAXSTEPS && b->h_steps[i] < max_steps) {
+            b->h_status[i] = PGK_CASE_RUNNING;
+            resumed = true;
+        }
+    if (resumed)
+        BHIP(b, hipMemcpyAsync(b->args.status, b->h_status, sizeof(int) * b->n, hipMemcpyHostToDevice, b->stream));
+    if ((int)b->best.size() != b->n) {
+        b->best.assign(b->n, 1e300);
+        b->since.assign(b->n, 0);
+    }
     auto running = [&]() { return running_sites(b); };
     // automatic choice: tuned at the start and again whenever the number of
     // running cases has halved (the last, longest cases decide the wall time,
@@ -906,8 +925,8 @@ extern "C" int pgk_batch_run(pgk_batch *b, int64_t max_steps, double tol, int64_
     BHIP(b, hipEventCreate(&t0));
     BHIP(b, hipEventCreate(&t1));
     double site_updates = 0.0, ms_total = 0.0;
-    std::vector<double> best(b->n, 1e300);
-    std::vector<long long> since(b->n, 0);
+    std::vector<double> &best = b->best;
+    std::vector<long long> &since = b->since;
     while (true) {
         long long act = running();
         if (act == 0) break;

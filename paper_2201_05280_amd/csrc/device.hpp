@@ -20,15 +20,15 @@ constexpr int NSLOT = 4;  // ghost slots per x face: doubled x offsets 1..4 beyo
 
 struct Consts {
     int nx, ny, nz, ns;
-    int bc[2];
+    int bc[4];              // kinds of the faces f = 2 axis + side: low x, high x, low y, high y
     double th0;
     double w[6];            // shell weights
     float whi[6], wlo[6];   // the same as float hi + lo parts (w = whi + wlo to ~1e-15)
     double tau, tau1, b, delta;
     double X, Y, ssig, beta, kfac;
-    double thbc[2], rhobc[2];
-    double Fbc[2][NQ];      // wall equilibrium at unit density / Dirichlet equilibrium
-    double in_col[2];       // re-emitted mass per ghost column at unit wall density
+    double thbc[4], rhobc[4];
+    double Fbc[4][NQ];      // wall equilibrium at unit density / Dirichlet equilibrium
+    double in_col[4];       // re-emitted mass per ghost column at unit wall density (uniform columns)
     // division by nx, ny, nz: q = (umulhi(n, m) + n) >> sh for n < 2^31
     unsigned mx, my, mz;
     int shx, shy, shz;
@@ -73,8 +73,8 @@ __host__ inline int diffusion_substeps(const Consts &k, double kr)
 {
     int dim = (k.nx > 1) + (k.ny > 1) + (k.nz > 1);
     double th = k.th0;
-    for (int side = 0; side < 2; side++)
-        if (k.bc[side] != PGK_PERIODIC && k.thbc[side] > th) th = k.thbc[side];
+    for (int f = 0; f < 4; f++)
+        if (k.bc[f] != PGK_PERIODIC && k.thbc[f] > th) th = k.thbc[f];
     double B = 1.0 + k.tau / k.tau1;
     double DR = k.delta > 0 ? 5.0 * kr * th * k.tau / (B * k.delta) : 0.0;
     int n = (int)std::ceil(2.0 * dim * DR * 1.5);
@@ -183,30 +183,64 @@ __device__ __forceinline__ int wrapc(int i, int n)
 }
 
 
-// Index of the population q pulled by site (x,y,z,sub): returns the array
-// index and sets `ghost` (0 = interior, 1 = low-x ghost, 2 = high-x ghost).
+// Ghosts: the values a pull reads from beyond a bounded face.  Face f of
+// axis a = f/2 (x or y; z is periodic) keeps, for every population and each of
+// NSLOT doubled distances beyond the face, one value per ghost column: the
+// column is the cell coordinate along the other in-plane axis b and along z.
+// Along a bounded axis b a column may lie outside the grid by up to two cells
+// (the corners: a position beyond an x face and a y face at once belongs to
+// the x face), so x faces have ny + 4 columns per z when y is bounded.
+// Layout: x faces [2][NQ][NSLOT][nz][ghost_wy], then y faces [2][NQ][NSLOT][nz][nx].
+__host__ __device__ __forceinline__ int ghost_wy(const Consts &k) { return k.bc[2] != PGK_PERIODIC ? k.ny + 4 : k.ny; }
+
+__host__ __device__ __forceinline__ long long ghost_count(const Consts &k)
+{
+    long long n = 2LL * NQ * NSLOT * k.nz * ghost_wy(k);
+    if (k.bc[2] != PGK_PERIODIC) n += 2LL * NQ * NSLOT * k.nz * k.nx;
+    return n;
+}
+
+// index of ghost (face f, population q, slot, column col) in the ghost array
+__host__ __device__ __forceinline__ int ghost_index(int f, int q, int slot, int col, const Consts &k)
+{
+    if (f < 2) return ((f * NQ + q) * NSLOT + slot) * k.nz * ghost_wy(k) + col;
+    return 2 * NQ * NSLOT * k.nz * ghost_wy(k) + (((f - 2) * NQ + q) * NSLOT + slot) * k.nz * k.nx + col;
+}
+
+// Array index of the value of population q at doubled position (qx, qy, qz):
+// a site of the population arrays (periodic axes wrap; `ghost` = 0), or on a
+// bounded grid a ghost slot beyond face f (`ghost` = 1 + f).
+template <bool BOUNDED>
+__device__ __forceinline__ int position_index(int qx, int qy, int qz, int q, const Consts &k, int &ghost)
+{
+    const int ssub = qx & 1;
+    const int hx = (qx - ssub) >> 1, hy = (qy - ssub) >> 1, sz = wrapc((qz - ssub) >> 1, k.nz);
+    ghost = 0;
+    if (BOUNDED) {
+        int f = -1, slot = 0;
+        if (qx < 0 && k.bc[0] != PGK_PERIODIC) { f = 0; slot = -qx - 1; }
+        else if (qx > 2 * k.nx - 1 && k.bc[1] != PGK_PERIODIC) { f = 1; slot = qx - 2 * k.nx; }
+        else if (qy < 0 && k.bc[2] != PGK_PERIODIC) { f = 2; slot = -qy - 1; }
+        else if (qy > 2 * k.ny - 1 && k.bc[3] != PGK_PERIODIC) { f = 3; slot = qy - 2 * k.ny; }
+        if (f >= 0) {
+            ghost = 1 + f;
+            if (f < 2) {
+                const int w = ghost_wy(k);
+                const int iy = k.bc[2] != PGK_PERIODIC ? hy + 2 : wrapc(hy, k.ny);
+                return ghost_index(f, q, slot, sz * w + iy, k);
+            }
+            return ghost_index(f, q, slot, sz * k.nx + wrapc(hx, k.nx), k);
+        }
+    }
+    return ((ssub * k.nz + sz) * k.ny + wrapc(hy, k.ny)) * k.nx + wrapc(hx, k.nx);
+}
+
+// Index of the population Q pulled by site (x,y,z,sub), see position_index.
 template <int Q, bool BOUNDED>
 __device__ __forceinline__ int pull_index(int x, int y, int z, int sub, const Consts &k, int &ghost)
 {
     constexpr int cx = c2(Q, 0), cy = c2(Q, 1), cz = c2(Q, 2);
-    int qx = 2 * x + sub - cx, qy = 2 * y + sub - cy, qz = 2 * z + sub - cz;
-    int ssub = qx & 1;
-    int sx = (qx - ssub) >> 1, sy = wrapc((qy - ssub) >> 1, k.ny), sz = wrapc((qz - ssub) >> 1, k.nz);
-    ghost = 0;
-    if (BOUNDED) {
-        if (qx < 0 && k.bc[0] != PGK_PERIODIC) {
-            ghost = 1;
-            int slot = -qx - 1;
-            return ((0 * NQ + Q) * NSLOT + slot) * k.nz * k.ny + sz * k.ny + sy;
-        }
-        if (qx > 2 * k.nx - 1 && k.bc[1] != PGK_PERIODIC) {
-            ghost = 2;
-            int slot = qx - 2 * k.nx;
-            return ((1 * NQ + Q) * NSLOT + slot) * k.nz * k.ny + sz * k.ny + sy;
-        }
-    }
-    sx = wrapc(sx, k.nx);
-    return ((ssub * k.nz + sz) * k.ny + sy) * k.nx + sx;
+    return position_index<BOUNDED>(2 * x + sub - cx, 2 * y + sub - cy, 2 * z + sub - cz, Q, k, ghost);
 }
 
 template <typename S, bool BOUNDED, int Q>
@@ -674,8 +708,8 @@ __device__ __forceinline__ void lb_site_e2pair(int s, int r, const S *__restrict
 // ---------------------------------------------------------------------------
 // theta_R transport
 // ---------------------------------------------------------------------------
-// same-sublattice neighbour along axis a (0,1,2) by dir (+-1); returns -1 / -2
-// for the low / high x ghost of a bounded face
+// same-sublattice neighbour along axis a (0,1,2) by dir (+-1); across a bounded
+// face f it returns -1 - f (-1 / -2: low / high x, -3 / -4: low / high y)
 template <bool BOUNDED>
 __device__ __forceinline__ int nbr(int x, int y, int z, int sub, int a, int dir, const Consts &k)
 {
@@ -687,7 +721,12 @@ __device__ __forceinline__ int nbr(int x, int y, int z, int sub, int a, int dir,
         }
         x = wrapc(x, k.nx);
     } else if (a == 1) {
-        y = wrapc(y + dir, k.ny);
+        y += dir;
+        if (BOUNDED) {
+            if (y < 0 && k.bc[2] != PGK_PERIODIC) return -3;
+            if (y >= k.ny && k.bc[3] != PGK_PERIODIC) return -4;
+        }
+        y = wrapc(y, k.ny);
     } else {
         z = wrapc(z + dir, k.nz);
     }
@@ -699,14 +738,14 @@ __device__ __forceinline__ double theta_star(const double *__restrict__ th, cons
                                              int idx, const Consts &k)
 {
     // predictor at site idx (forward differences); ghosts keep their value
-    if (BOUNDED && idx < 0) return idx == -1 ? k.thbc[0] : k.thbc[1];
+    if (BOUNDED && idx < 0) return k.thbc[-1 - idx];
     int x, y, z, sub;
     decode(idx, k, x, y, z, sub);
     double t = th[idx], adv = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         int p = nbr<BOUNDED>(x, y, z, sub, a, +1, k);
-        double tp = (BOUNDED && p < 0) ? (p == -1 ? k.thbc[0] : k.thbc[1]) : th[p];
+        double tp = (BOUNDED && p < 0) ? k.thbc[-1 - p] : th[p];
         adv += (double)aux[(size_t)a * k.ns + idx] * (tp - t);
     }
     return t - adv;
@@ -749,10 +788,9 @@ __device__ __forceinline__ void dif_site(int s, const double *__restrict__ tin, 
             int q = nbr<BOUNDED>(x, y, z, sub, a, dir, k);
             double tq, kq;
             if (BOUNDED && q < 0) {
-                bool hi = q == -2;
-                tq = hi ? k.thbc[1] : k.thbc[0];
-                bool wall = (hi ? k.bc[1] : k.bc[0]) == PGK_WALL;
-                double rg = wall ? rho : (hi ? k.rhobc[1] : k.rhobc[0]);
+                const int f = -1 - q;
+                tq = k.thbc[f];
+                double rg = k.bc[f] == PGK_WALL ? rho : k.rhobc[f];
                 kq = k.kfac * rg * tq;
             } else {
                 tq = tin[q];
@@ -772,49 +810,88 @@ __device__ __forceinline__ void dif_site(int s, const double *__restrict__ tin, 
     }
 }
 
-// Ghost populations of x face `side`, column col, by one wavefront (lane
-// 0..63).  Diffuse wall: the density of the re-emitted populations comes from
-// zero net mass flux through the face in the last collision, the outgoing sum
-// spread over the lanes (lane l takes the candidates (q, sub, xi) numbered
-// l, l + 64, l + 128) and reduced by a butterfly; Dirichlet: the equilibrium
-// of the ghost state.  Lanes 0..40 write population q = lane.
+__host__ __device__ __forceinline__ int floor2(int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
+
+// Number of ghost columns of face f (see ghost_wy).
+__host__ __device__ __forceinline__ int face_columns(int f, const Consts &k)
+{
+    return f < 2 ? k.nz * ghost_wy(k) : k.nz * k.nx;
+}
+
+// Ghost populations of face f, column col, by one wavefront (lane 0..63).
+// Diffuse wall: the density of the re-emitted populations comes from zero net
+// mass flux through the column in the last collision: the mass sent into the
+// column (the outgoing sum, spread over the lanes: lane l takes the
+// candidates (q, sub, distance) numbered l, l + 64, l + 128) over the mass the
+// wall re-emits into it at unit density (the same candidates pulling from it;
+// uniform on a face whose other in-plane axis is periodic, k.in_col[f]),
+// reduced by a butterfly.  Dirichlet: the equilibrium of the ghost state.
+// Lanes 0..40 write population q = lane into every slot.
 template <typename S>
-__device__ __forceinline__ void bc_column(int side, int col, int lane, const S *__restrict__ src,
+__device__ __forceinline__ void bc_column(int f, int col, int lane, const S *__restrict__ src,
                                           S *__restrict__ gh, const Consts &k)
 {
-    int ncol = k.ny * k.nz;
-    if (k.bc[side] == PGK_PERIODIC) return;
-    int gy = col % k.ny, gz = col / k.ny;
+    if (k.bc[f] == PGK_PERIODIC) return;
+    const int a = f >> 1, side = f & 1, b = 1 - a;           // face axis, the other in-plane axis
+    const int na = a == 0 ? k.nx : k.ny, nb = b == 0 ? k.nx : k.ny;
+    const bool bb = k.bc[2 * b] != PGK_PERIODIC;              // axis b bounded
+    const bool xb = k.bc[0] != PGK_PERIODIC;
+    const int width = f < 2 ? ghost_wy(k) : k.nx;
+    const int gz = col / width, ib = col - gz * width;
+    const int gb = (f < 2 && bb) ? ib - 2 : ib;               // cell coordinate of the column along b
     double scale = 1.0;
-    if (k.bc[side] == PGK_WALL) {
-        double out = 0.0;
+    if (k.bc[f] == PGK_WALL) {
+        double out = 0.0, in = 0.0;
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            int idx = lane + 64 * j;                 // 160 candidates: q = 1..40, sub, xi
+            int idx = lane + 64 * j;                 // 160 candidates: q = 1..40, sub, distance di
             if (idx >= 4 * (NQ - 1)) break;
-            int q = 1 + (idx >> 2), sub = (idx >> 1) & 1, xi = idx & 1;
-            int cx = c2(q, 0), cy = c2(q, 1), cz = c2(q, 2);
-            if ((side == 0 && cx >= 0) || (side == 1 && cx <= 0)) continue;
-            if (xi == 1 && k.nx == 1) continue;
-            int x = side == 0 ? xi : k.nx - 1 - xi;
-            int dx = 2 * x + sub + cx;
-            bool crosses = side == 0 ? dx < 0 : dx > 2 * k.nx - 1;
-            if (!crosses) continue;
-            // ghost column of the destination: floor((2y + sub + cy)/2) = y + floor((sub + cy)/2)
-            int ky = (sub + cy) >= 0 ? (sub + cy) / 2 : -((-(sub + cy) + 1) / 2);
-            int kz = (sub + cz) >= 0 ? (sub + cz) / 2 : -((-(sub + cz) + 1) / 2);
-            int y = k.ny == 1 ? 0 : wrapc(gy - ky, k.ny), z = k.nz == 1 ? 0 : wrapc(gz - kz, k.nz);
-            int s = ((sub * k.nz + z) * k.ny + y) * k.nx + x;
-            out += (double)src[(size_t)q * k.ns + s] + (sizeof(S) == 4 ? k.w[shell_of(q)] : 0.0);
+            int q = 1 + (idx >> 2), sub = (idx >> 1) & 1, di = idx & 1;
+            if (di == 1 && na == 1) continue;
+            const int ca = c2(q, a), cb = c2(q, b), cz = c2(q, 2);
+            const int sa = side == 0 ? di : na - 1 - di;      // site coordinate along a
+            // outgoing: population q of a site near the face lands beyond it, in column gb
+            if ((side == 0 && ca < 0) || (side == 1 && ca > 0)) {
+                int da = 2 * sa + sub + ca;
+                bool crosses = side == 0 ? da < 0 : da > 2 * na - 1;
+                int sb = gb - floor2(sub + cb);
+                int db = 2 * sb + sub + cb;
+                bool ok = crosses && (bb ? (sb >= 0 && sb < nb) : true);
+                // a y face never takes what lands beyond a bounded x face
+                if (ok && f >= 2 && xb && (db < 0 || db > 2 * k.nx - 1)) ok = false;
+                if (ok) {
+                    int z = k.nz == 1 ? 0 : wrapc(gz - floor2(sub + cz), k.nz);
+                    int sbw = bb ? sb : wrapc(sb, nb);
+                    int x = a == 0 ? sa : sbw, y = a == 0 ? sbw : sa;
+                    int s = ((sub * k.nz + z) * k.ny + y) * k.nx + x;
+                    out += (double)src[(size_t)q * k.ns + s] + (sizeof(S) == 4 ? k.w[shell_of(q)] : 0.0);
+                }
+            }
+            // incoming: a site near the face pulls population q from column gb
+            // (along a periodic b every column takes the same: k.in_col[f])
+            if (bb && ((side == 0 && ca > 0) || (side == 1 && ca < 0))) {
+                int pa = 2 * sa + sub - ca;
+                bool crosses = side == 0 ? pa < 0 : pa > 2 * na - 1;
+                int sb = gb - floor2(sub - cb);
+                int pb = 2 * sb + sub - cb;
+                bool ok = crosses && (bb ? (sb >= 0 && sb < nb) : true);
+                if (ok && f >= 2 && xb && (pb < 0 || pb > 2 * k.nx - 1)) ok = false;
+                if (ok) in += k.Fbc[f][q];
+            }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) out += __shfl_xor(out, o, 64);
-        scale = out / k.in_col[side];
+        if (bb) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) in += __shfl_xor(in, o, 64);
+        }
+        double inc = bb ? in : k.in_col[f];
+        scale = inc > 0.0 ? out / inc : 0.0;
     }
     if (lane < NQ) {
-        double val = scale * k.Fbc[side][lane] - (sizeof(S) == 4 ? k.w[shell_of(lane)] : 0.0);
+        double val = scale * k.Fbc[f][lane] - (sizeof(S) == 4 ? k.w[shell_of(lane)] : 0.0);
 #pragma unroll
-        for (int slot = 0; slot < NSLOT; slot++) gh[((side * NQ + lane) * NSLOT + slot) * ncol + col] = (S)val;
+        for (int slot = 0; slot < NSLOT; slot++) gh[ghost_index(f, lane, slot, col, k)] = (S)val;
     }
 }
 
@@ -873,18 +950,11 @@ __device__ __forceinline__ void init_site(int s, S *__restrict__ dst, S *__restr
             }
             val = (S)(sizeof(S) == 4 ? X : F);
         }
-        // destination: position x - c_q
-        int qx = 2 * x + sub - cx, qy = 2 * y + sub - cy, qz = 2 * z + sub - cz;
-        int ssub = qx & 1;
-        int sy = wrapc((qy - ssub) >> 1, k.ny), sz = wrapc((qz - ssub) >> 1, k.nz);
-        if (BOUNDED && qx < 0 && k.bc[0] != PGK_PERIODIC) {
-            gh[((0 * NQ + q) * NSLOT + (-qx - 1)) * k.nz * k.ny + sz * k.ny + sy] = val;
-        } else if (BOUNDED && qx > 2 * k.nx - 1 && k.bc[1] != PGK_PERIODIC) {
-            gh[((1 * NQ + q) * NSLOT + (qx - 2 * k.nx)) * k.nz * k.ny + sz * k.ny + sy] = val;
-        } else {
-            int sx = wrapc((qx - ssub) >> 1, k.nx);
-            dst[(size_t)q * k.ns + ((ssub * k.nz + sz) * k.ny + sy) * k.nx + sx] = val;
-        }
+        // destination: position x - c_q (a ghost slot beyond a bounded face)
+        int ghost;
+        int idx = position_index<BOUNDED>(2 * x + sub - cx, 2 * y + sub - cy, 2 * z + sub - cz, q, k, ghost);
+        if (BOUNDED && ghost) gh[idx] = val;
+        else dst[(size_t)q * k.ns + idx] = val;
     }
 }
 

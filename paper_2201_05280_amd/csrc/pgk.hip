@@ -451,10 +451,20 @@ __global__ __launch_bounds__(TWG) void k_tr(const double *__restrict__ that_, co
 template <typename S>
 __global__ __launch_bounds__(64) void k_bc(const S *__restrict__ src, S *__restrict__ gh, Consts k)
 {
-    // one wavefront per (face, ghost column): 2 ny nz work-groups of 64
-    int ncol = k.ny * k.nz;
-    int side = blockIdx.x / ncol;
-    bc_column<S>(side, blockIdx.x - side * ncol, threadIdx.x, src, gh, k);
+    // one wavefront per (face, ghost column): the columns of the two x faces,
+    // then (y bounded) those of the two y faces
+    int col = blockIdx.x, f = 0;
+    while (f < 3 && col >= face_columns(f, k)) col -= face_columns(f++, k);
+    bc_column<S>(f, col, threadIdx.x, src, gh, k);
+}
+
+// work-groups of k_bc: one per ghost column of every face the grid bounds
+// (an x face is listed even when periodic; its work-groups return at once)
+static int bc_launches(const Consts &k)
+{
+    int n = 2 * face_columns(0, k);
+    if (k.bc[2] != PGK_PERIODIC) n += 2 * face_columns(2, k);
+    return n;
 }
 
 template <typename S, bool BOUNDED, int EQ>
@@ -537,8 +547,8 @@ struct pgk_ctx {
     int64_t steps = 0;
     Consts k{};
     pgk_resolved res{};
-    double bc_u[2][3]{};
-    bool bc_set[2] = {false, false};   // face state given by pgk_set_bc_x
+    double bc_u[4][3]{};
+    bool bc_set[4] = {false, false, false, false};   // face state given by pgk_set_bc
     // x ghosts: ghosts_ok = they hold what the next pull needs (filled from the
     // face states in force when the stored populations were collided, as the
     // streaming of that step would); face_changed = a face state changed since
@@ -616,9 +626,13 @@ static bool grid_ok(const pgk_grid *g)
     if (g->variant != PGK_CN && g->variant != PGK_LIT) return false;
     if (g->equilibrium != PGK_F3 && g->equilibrium != PGK_E2 && g->equilibrium != PGK_F4) return false;
     for (int s = 0; s < 2; s++)
-        if (g->bc_x[s] < PGK_PERIODIC || g->bc_x[s] > PGK_DIRICHLET) return false;
+        if (g->bc_x[s] < PGK_PERIODIC || g->bc_x[s] > PGK_DIRICHLET || g->bc_y[s] < PGK_PERIODIC ||
+            g->bc_y[s] > PGK_DIRICHLET)
+            return false;
     if ((g->bc_x[0] == PGK_PERIODIC) != (g->bc_x[1] == PGK_PERIODIC)) return false;
+    if ((g->bc_y[0] == PGK_PERIODIC) != (g->bc_y[1] == PGK_PERIODIC)) return false;
     if (g->bc_x[0] != PGK_PERIODIC && g->nx < 2) return false;
+    if (g->bc_y[0] != PGK_PERIODIC && g->ny < 2) return false;
     return true;
 }
 
@@ -638,7 +652,10 @@ static void aux_layout(const pgk_grid *g, size_t off[9])
     off[3] = off[2] + align256(5 * ns * elt);
     off[4] = off[3] + align256(nblk * 5 * 8);
     off[5] = off[4] + align256(8 * 8);
-    off[6] = off[5] + align256(2ull * NQ * NSLOT * g->ny * g->nz * elt);
+    Consts k{};
+    k.nx = g->nx; k.ny = g->ny; k.nz = g->nz;
+    k.bc[0] = g->bc_x[0]; k.bc[1] = g->bc_x[1]; k.bc[2] = g->bc_y[0]; k.bc[3] = g->bc_y[1];
+    off[6] = off[5] + align256((size_t)ghost_count(k) * elt);
     off[7] = off[6] + align256(ns * 8);
     // E2: the two multiplier sets of each site's last equilibria, [2 * E2_NL][ns]
     off[8] = off[7] + (g->equilibrium == PGK_E2 ? align256(2ull * E2_NL * ns * 8) : 0);
@@ -835,6 +852,7 @@ extern "C" int pgk_create(const pgk_grid *g, void *stream, pgk_ctx **out)
     c->k.nx = g->nx; c->k.ny = g->ny; c->k.nz = g->nz;
     c->k.ns = 2 * g->nx * g->ny * g->nz;
     c->k.bc[0] = g->bc_x[0]; c->k.bc[1] = g->bc_x[1];
+    c->k.bc[2] = g->bc_y[0]; c->k.bc[3] = g->bc_y[1];
     magic_div((unsigned)g->nx, c->k.mx, c->k.shx);
     magic_div((unsigned)g->ny, c->k.my, c->k.shy);
     magic_div((unsigned)g->nz, c->k.mz, c->k.shz);
@@ -883,31 +901,33 @@ static int fill_bc(pgk_ctx *c)
     Consts &k = c->k;
     k.nsub = diffusion_substeps(k, c->res.kr);
     k.isub = 1.0 / k.nsub;
-    for (int side = 0; side < 2; side++) {
-        if (k.bc[side] == PGK_PERIODIC || !c->bc_set[side]) continue;
-        double rho = k.bc[side] == PGK_WALL ? 1.0 : k.rhobc[side];
-        if (k.bc[side] == PGK_DIRICHLET && c->g.equilibrium == PGK_E2) {
-            double th = k.thbc[side], lam[6] = {th, th, th, 0.0, 0.0, 0.0}, l[E2_NL];
-            if (e2_solve(k.th0, k.w, rho, c->bc_u[side], lam, l) < 0)
+    for (int f = 0; f < 4; f++) {
+        if (k.bc[f] == PGK_PERIODIC || !c->bc_set[f]) continue;
+        double rho = k.bc[f] == PGK_WALL ? 1.0 : k.rhobc[f];
+        if (k.bc[f] == PGK_DIRICHLET && c->g.equilibrium == PGK_E2) {
+            double th = k.thbc[f], lam[6] = {th, th, th, 0.0, 0.0, 0.0}, l[E2_NL];
+            if (e2_solve(k.th0, k.w, rho, c->bc_u[f], lam, l) < 0)
                 return fail(c, PGK_EINFEASIBLE, "the Dirichlet face state has no E2 equilibrium on the lattice");
-            for (int q = 0; q < NQ; q++) k.Fbc[side][q] = e2_population(l, k.w, q);
-        } else if (k.bc[side] == PGK_DIRICHLET && c->g.equilibrium == PGK_F4) {
-            double th = k.thbc[side], lam[6] = {th, th, th, 0.0, 0.0, 0.0};
-            f4_host_lam(k.th0, k.w, k.f4inv, rho, c->bc_u[side], lam, k.Fbc[side]);
+            for (int q = 0; q < NQ; q++) k.Fbc[f][q] = e2_population(l, k.w, q);
+        } else if (k.bc[f] == PGK_DIRICHLET && c->g.equilibrium == PGK_F4) {
+            double th = k.thbc[f], lam[6] = {th, th, th, 0.0, 0.0, 0.0};
+            f4_host_lam(k.th0, k.w, k.f4inv, rho, c->bc_u[f], lam, k.Fbc[f]);
         } else {
-            f3_host(k.th0, k.w, rho, c->bc_u[side], k.thbc[side], k.Fbc[side]);
+            f3_host(k.th0, k.w, rho, c->bc_u[f], k.thbc[f], k.Fbc[f]);
         }
-        // mass re-emitted into one ghost column at unit density: every
+        // mass re-emitted into one ghost column at unit density when the
+        // face's other in-plane axis is periodic (every column alike): every
         // population pulled from beyond the face, over both sublattices
+        const int a = f / 2, side = f % 2, na = a == 0 ? k.nx : k.ny;
         double in = 0.0;
         for (int q = 0; q < NQ; q++)
             for (int sub = 0; sub < 2; sub++)
-                for (int x = 0; x < k.nx; x++) {
-                    int qx = 2 * x + sub - c2(q, 0);
-                    bool outside = side == 0 ? qx < 0 : qx > 2 * k.nx - 1;
-                    if (outside) in += k.Fbc[side][q];
+                for (int i = 0; i < na; i++) {
+                    int qa = 2 * i + sub - c2(q, a);
+                    bool outside = side == 0 ? qa < 0 : qa > 2 * na - 1;
+                    if (outside) in += k.Fbc[f][q];
                 }
-        k.in_col[side] = in;
+        k.in_col[f] = in;
     }
     return PGK_OK;
 }
@@ -971,31 +991,53 @@ extern "C" int pgk_set_params(pgk_ctx *c, const pgk_params *p, pgk_resolved *out
     return fill_bc(c);
 }
 
-extern "C" int pgk_set_bc_x(pgk_ctx *c, int side, double rho, const double u[3], double theta)
+extern "C" int pgk_set_bc(pgk_ctx *c, int axis, int side, double rho, const double u[3], double theta)
 {
-    if (!c || side < 0 || side > 1 || !(theta > 0)) return PGK_EINVAL;
-    if (c->k.bc[side] == PGK_PERIODIC) return fail(c, PGK_EINVAL, "face is periodic");
-    if (c->k.bc[side] == PGK_DIRICHLET && !(rho > 0)) return fail(c, PGK_EINVAL, "Dirichlet density must be positive");
-    if (u && u[0] != 0.0 && c->k.bc[side] == PGK_WALL) return fail(c, PGK_EINVAL, "a wall cannot move normal to itself");
+    if (!c || axis < 0 || axis > 1 || side < 0 || side > 1 || !(theta > 0)) return PGK_EINVAL;
+    const int f = 2 * axis + side;
+    if (c->k.bc[f] == PGK_PERIODIC) return fail(c, PGK_EINVAL, "face is periodic");
+    if (c->k.bc[f] == PGK_DIRICHLET && !(rho > 0)) return fail(c, PGK_EINVAL, "Dirichlet density must be positive");
+    if (u && u[axis] != 0.0 && c->k.bc[f] == PGK_WALL) return fail(c, PGK_EINVAL, "a wall cannot move normal to itself");
     int rc0 = settle_ghosts(c);   // the pending pull keeps the old face state
     if (rc0) return rc0;
     c->face_changed = true;
-    c->k.rhobc[side] = rho;
-    c->k.thbc[side] = theta;
-    c->bc_set[side] = true;
+    c->k.rhobc[f] = rho;
+    c->k.thbc[f] = theta;
+    c->bc_set[f] = true;
     c->drop_graphs();
-    for (int a = 0; a < 3; a++) c->bc_u[side][a] = u ? u[a] : 0.0;
+    for (int a = 0; a < 3; a++) c->bc_u[f][a] = u ? u[a] : 0.0;
     return c->params_set ? fill_bc(c) : PGK_OK;
 }
 
-static bool bounded(const pgk_ctx *c) { return c->k.bc[0] != PGK_PERIODIC; }
+extern "C" int pgk_set_bc_x(pgk_ctx *c, int side, double rho, const double u[3], double theta)
+{
+    return pgk_set_bc(c, 0, side, rho, u, theta);
+}
+
+static bool any_wall(const pgk_ctx *c)
+{
+    for (int f = 0; f < 4; f++)
+        if (c->k.bc[f] == PGK_WALL) return true;
+    return false;
+}
+
+// every bounded face has its state
+static int faces_set(pgk_ctx *c)
+{
+    for (int f = 0; f < 4; f++)
+        if (c->k.bc[f] != PGK_PERIODIC && !c->bc_set[f])
+            return fail(c, PGK_EINVAL, "a bounded face has no state (pgk_set_bc)");
+    return PGK_OK;
+}
+
+static bool bounded(const pgk_ctx *c) { return c->k.bc[0] != PGK_PERIODIC || c->k.bc[2] != PGK_PERIODIC; }
 
 // Fill the x ghosts the next pull reads, if they are not filled yet, from the
 // face states in force now (before a change of those states takes effect).
 static int settle_ghosts(pgk_ctx *c)
 {
     if (!c->initialised || c->steps == 0 || !bounded(c) || c->ghosts_ok) return PGK_OK;
-    int nbc = 2 * c->k.ny * c->k.nz;   // one wavefront per face column
+    int nbc = bc_launches(c->k);   // one wavefront per face column
     if (c->g.precision == PGK_FP64)
         hipLaunchKernelGGL((k_bc<double>), dim3(nbc), dim3(64), 0, c->stream, (const double *)c->buf[c->cur],
                            (double *)c->gh, c->k);
@@ -1028,9 +1070,7 @@ extern "C" int pgk_init_fields(pgk_ctx *c, const double *rho, const double *u, c
     if (!c->bound) return fail(c, PGK_ENOTBOUND, "buffers not bound");
     if (!c->params_set) return fail(c, PGK_EINVAL, "parameters not set");
     if (!rho || !u || !thT || !thR) return fail(c, PGK_EINVAL, "null field");
-    for (int side = 0; side < 2; side++)
-        if (c->k.bc[side] != PGK_PERIODIC && !c->bc_set[side])
-            return fail(c, PGK_EINVAL, "x face state not set (pgk_set_bc_x)");
+    if (int rcf = faces_set(c)) return rcf;
     c->cur = 0;
     c->steps = 0;
     // the initialisation pushes what the first pull reads; from the second
@@ -1054,7 +1094,7 @@ template <typename S, typename A, int VAR, bool BND, int EQ>
 static int step_t(pgk_ctx *c, int64_t n)
 {
     dim3 grid(c->nblk), block(WG);
-    int nbc = 2 * c->k.ny * c->k.nz;   // one wavefront per face column
+    int nbc = bc_launches(c->k);   // one wavefront per face column
     for (int64_t it = 0; it < n; it++) {
         S *src = (S *)c->buf[c->cur], *dst = (S *)c->buf[1 - c->cur];
         mark(c, -1);
@@ -1110,7 +1150,7 @@ static int step_t(pgk_ctx *c, int64_t n)
         c->steps++;
         // a wall re-emits what the last collision sent into it: new ghosts
         // every step; Dirichlet ghosts stay until a face state changes
-        if (BND && (c->k.bc[0] == PGK_WALL || c->k.bc[1] == PGK_WALL || c->face_changed)) c->ghosts_ok = false;
+        if (BND && (any_wall(c) || c->face_changed)) c->ghosts_ok = false;
         c->face_changed = false;
     }
     HIPCHECK(c, hipGetLastError());
@@ -1156,7 +1196,7 @@ extern "C" int pgk_step(pgk_ctx *c, int64_t n)
     // walls it refreshes them before every step, its first included)
     rc = settle_ghosts(c);
     if (rc) return rc;
-    const bool walls = c->k.bc[0] == PGK_WALL || c->k.bc[1] == PGK_WALL;
+    const bool walls = any_wall(c);
     // a chunk of an even number of steps returns the state to the buffer it started from
     const int p = c->cur;
     if (!c->graph[p]) {
@@ -1301,9 +1341,7 @@ extern "C" int pgk_set_clock(pgk_ctx *c, const pgk_clock *in)
     if (!c || !in) return PGK_EINVAL;
     if (!c->bound) return fail(c, PGK_ENOTBOUND, "buffers not bound");
     if (!c->params_set) return fail(c, PGK_EINVAL, "parameters not set");
-    for (int side = 0; side < 2; side++)
-        if (c->k.bc[side] != PGK_PERIODIC && !c->bc_set[side])
-            return fail(c, PGK_EINVAL, "x face state not set (pgk_set_bc_x)");
+    if (int rcf = faces_set(c)) return rcf;
     if (in->steps < 0 || (in->cur != 0 && in->cur != 1)) return fail(c, PGK_EINVAL, "bad clock");
     c->steps = in->steps;
     c->cur = in->cur;

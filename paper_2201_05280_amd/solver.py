@@ -23,12 +23,12 @@ class Solver:
     """One grid of nx*ny*nz bcc cells (2 sites per cell) on one GPU.
 
     precision: _lib.FP64 or _lib.FP32DEV; variant: _lib.CN or _lib.LIT;
-    equilibrium: _lib.F3 or _lib.E2; bc_x: kinds of the low and high x faces
-    (y and z are periodic).
+    equilibrium: _lib.F3, _lib.E2 or _lib.F4; bc_x, bc_y: kinds of the low and
+    high x and y faces (z is periodic).
     """
 
     def __init__(self, nx, ny, nz, precision=FP64, variant=CN, bc_x=(PERIODIC, PERIODIC),
-                 device=0, stream=None, equilibrium=F3):
+                 device=0, stream=None, equilibrium=F3, bc_y=(PERIODIC, PERIODIC)):
         torch = _torch()
         self.torch = torch
         self.L = _lib.load()
@@ -36,7 +36,8 @@ class Solver:
         self.ns = 2 * nx * ny * nz
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        g = _lib.Grid(nx, ny, nz, precision, variant, equilibrium, (ctypes.c_int * 2)(*bc_x))
+        g = _lib.Grid(nx, ny, nz, precision, variant, equilibrium, (ctypes.c_int * 2)(*bc_x),
+                      (ctypes.c_int * 2)(*bc_y))
         sizes = (ctypes.c_size_t * _lib.NBUF)()
         self._check(self.L.pgk_buffer_sizes(ctypes.byref(g), sizes), None)
         h = ctypes.c_void_p()
@@ -76,9 +77,13 @@ class Solver:
         self.resolved = r.as_dict()
         return self.resolved
 
-    def set_bc_x(self, side, rho=1.0, u=(0.0, 0.0, 0.0), theta=0.2948964908710633):
+    def set_bc(self, axis, side, rho=1.0, u=(0.0, 0.0, 0.0), theta=0.2948964908710633):
+        """State of face `side` (0 low, 1 high) of axis `axis` (0 x, 1 y)."""
         uu = (ctypes.c_double * 3)(*u)
-        self._check(self.L.pgk_set_bc_x(self.h, side, float(rho), uu, float(theta)))
+        self._check(self.L.pgk_set_bc(self.h, int(axis), int(side), float(rho), uu, float(theta)))
+
+    def set_bc_x(self, side, rho=1.0, u=(0.0, 0.0, 0.0), theta=0.2948964908710633):
+        self.set_bc(0, side, rho, u, theta)
 
     def _dev(self, a, shape):
         t = self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64).reshape(shape),

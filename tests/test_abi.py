@@ -69,11 +69,19 @@ def test_buffer_sizes_and_bad_grids():
     assert s[0] == s[1] == 41 * ns * 4
     assert s[2] == ns * 8
     s64 = _lib.buffer_sizes(64, 64, 1, precision=_lib.FP64)
-    assert s64[0] == 41 * ns * 8
+    assert s64[0] == 41 * ns * 8 and s64[2] == ns * 8
     with pytest.raises(ValueError):
         _lib.buffer_sizes(0, 4, 4)
     with pytest.raises(ValueError):
         _lib.buffer_sizes(8, 1, 1, bc_x=(_lib.WALL, _lib.PERIODIC))   # faces must pair
+    with pytest.raises(ValueError):
+        _lib.buffer_sizes(8, 4, 1, bc_y=(_lib.WALL, _lib.PERIODIC))
+    with pytest.raises(ValueError):
+        _lib.buffer_sizes(8, 1, 1, bc_y=(_lib.WALL, _lib.WALL))        # a bounded axis needs two cells
+    # walls on y: ghost columns of the x faces extend two cells beyond each y face
+    a = _lib.buffer_sizes(8, 6, 2, bc_x=(_lib.WALL, _lib.WALL))[3]
+    b = _lib.buffer_sizes(8, 6, 2, bc_x=(_lib.WALL, _lib.WALL), bc_y=(_lib.WALL, _lib.WALL))[3]
+    assert b > a
     with pytest.raises(ValueError):
         _lib.buffer_sizes(8, 1, 1, precision=7)
 

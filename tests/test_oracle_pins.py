@@ -870,3 +870,133 @@ def test_small_shear_wave_decays_at_the_linear_eigenvalue():
     t = np.arange(len(amp))
     rate = -np.polyfit(t[200:], np.log(amp[200:]), 1)[0]
     assert abs(rate / r_lin - 1) < 2e-5, (rate, r_lin)
+
+
+# ----------------------------------------------------------------------------
+# Walls on two axes (Sec. 6, heated cavity)
+# ----------------------------------------------------------------------------
+def _swap_xy(a, nx, ny):
+    """site field [..., sub, z=1, y, x] of an nx x ny x 1 grid -> the ny x nx grid with x and y exchanged"""
+    lead = a.shape[:-1]
+    return np.ascontiguousarray(a.reshape(lead + (2, 1, ny, nx)).swapaxes(-1, -2)).reshape(lead + (-1,))
+
+
+def test_walls_on_y_are_walls_on_x_turned_by_a_right_angle():
+    """The bcc lattice and RD3Q41 are symmetric under exchanging x and y, so a
+    Couette layer between two y walls (x periodic) must equal, site for site
+    and to round-off, the same layer between two x walls (y periodic) with
+    every field's x and y exchanged: a pin of the y-face ghosts (pull, wall
+    density per column) and of the y ghosts of the theta_R transport."""
+    nx, ny = 20, 3
+    p = resolve(0.15, 0.8, 1.1, 2.0)
+    f = inputs.random_smooth(nx, ny, 1, seed=4, amp_rho=0.01, amp_u=0.01, amp_th=0.01)
+    a = oracle.Oracle(nx, ny, 1)
+    a.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    a.set_bc(0, 0, oracle.WALL, 1.0, (0, 0, 0), TH0)
+    a.set_bc(0, 1, oracle.WALL, 1.0, (0, 0.03, 0.01), TH0 * 1.05)
+    a.init(f["rho"], f["u"], f["thT"], f["thR"])
+    b = oracle.Oracle(ny, nx, 1)
+    b.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    b.set_bc(1, 0, oracle.WALL, 1.0, (0, 0, 0), TH0)
+    b.set_bc(1, 1, oracle.WALL, 1.0, (0.03, 0, 0.01), TH0 * 1.05)
+    ub = _swap_xy(f["u"], nx, ny)[[1, 0, 2]]
+    b.init(_swap_xy(f["rho"], nx, ny), ub, _swap_xy(f["thT"], nx, ny), _swap_xy(f["thR"], nx, ny))
+    assert b.substeps() == a.substeps()
+    a.step(300)
+    b.step(300)
+    ma, mb = a.moments(), b.moments()
+    for k in ("rho", "thT", "thR"):
+        assert np.abs(_swap_xy(ma[k], nx, ny) - mb[k]).max() < 1e-12 * np.abs(ma[k]).max(), k
+    ua = _swap_xy(ma["u"], nx, ny)[[1, 0, 2]]
+    assert np.abs(ua - mb["u"]).max() < 1e-12, np.abs(ua - mb["u"]).max()
+    assert np.abs(ma["u"][1]).max() > 1e-3          # the layer is sheared
+
+
+def test_closed_box_keeps_its_mass_and_a_gas_at_rest_stays_at_rest():
+    """Diffuse walls on both axes (z periodic), the corners included: zero net
+    mass flux through every ghost column keeps the mass to round-off, and a gas
+    at rest at the temperature of all four walls is the steady state itself."""
+    p = resolve(0.1, 0.71, 0.8, 2.0)
+    o = oracle.Oracle(9, 7, 2)
+    o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    for axis in (0, 1):
+        for side in (0, 1):
+            o.set_bc(axis, side, oracle.WALL, 1.0, (0, 0, 0), TH0)
+    f = inputs.uniform(9, 7, 2)
+    o.init(f["rho"], f["u"], f["thT"], f["thR"])
+    o.step(50)
+    m = o.moments()
+    assert np.abs(m["rho"] - 1).max() < 1e-14 and np.abs(m["u"]).max() < 1e-15
+    assert np.abs(m["thT"] - TH0).max() < 1e-14 and np.abs(m["thR"] - TH0).max() < 1e-14
+    # walls at four temperatures, the top one moving (a lid-driven, heated box)
+    f = inputs.random_smooth(9, 7, 2, seed=3, amp_rho=0.02, amp_u=0.02, amp_th=0.02)
+    o.init(f["rho"], f["u"], f["thT"], f["thR"])
+    o.set_bc(0, 0, oracle.WALL, 1.0, (0, 0.01, 0), TH0 * 0.97)
+    o.set_bc(1, 1, oracle.WALL, 1.0, (0.04, 0, 0), TH0 * 1.04)
+    M0 = o.conserved()[0]
+    o.step(300)
+    assert abs(o.conserved()[0] / M0 - 1) < 1e-13
+
+
+def heated_cavity_series(x, y, nterm=400):
+    """Sec. 6: steady conduction in the unit square, the top wall at T1 and the
+    other three at T0: (T - T0)/(T1 - T0) = (2/pi) sum_n ((-1)^(n+1) + 1)/n
+    sin(n pi x) sinh(n pi y)/sinh(n pi)."""
+    n = np.arange(1, nterm + 1)[:, None]
+    c = ((-1.0) ** (n + 1) + 1) / n
+    # sinh(n pi y)/sinh(n pi), written without overflow
+    r = np.exp(n * np.pi * (y - 1)) * (1 - np.exp(-2 * n * np.pi * y)) / (1 - np.exp(-2 * n * np.pi))
+    return 2 / np.pi * (c * np.sin(n * np.pi * x) * r).sum(0)
+
+
+def test_heated_cavity_series_is_laplace_solution():
+    # the series itself: the boundary values and a harmonic interior (5-point Laplacian)
+    x = np.linspace(0.05, 0.95, 19)
+    assert np.abs(heated_cavity_series(x, np.full_like(x, 1.0)) - 1).max() < 2e-3 * 1 + 0.01 * (x.min() < 0.1)
+    assert np.abs(heated_cavity_series(x, np.zeros_like(x))).max() < 1e-12
+    h = 1e-3
+    X, Y = np.meshgrid(np.linspace(0.2, 0.8, 7), np.linspace(0.2, 0.8, 7))
+    X, Y = X.ravel(), Y.ravel()
+    lap = (heated_cavity_series(X + h, Y) + heated_cavity_series(X - h, Y) + heated_cavity_series(X, Y + h)
+           + heated_cavity_series(X, Y - h) - 4 * heated_cavity_series(X, Y)) / h ** 2
+    assert np.abs(lap).max() < 1e-3
+
+
+def _cavity(n, nu, steps, equilibrium=oracle.F3, dT=0.1 * TH0):
+    p = resolve(nu, 0.71, 0.8, 2.0)
+    o = oracle.Oracle(n, n, 1, equilibrium=equilibrium)
+    o.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+    for side in (0, 1):
+        o.set_bc(0, side, oracle.WALL, 1.0, (0, 0, 0), TH0)
+    o.set_bc(1, 0, oracle.WALL, 1.0, (0, 0, 0), TH0)
+    o.set_bc(1, 1, oracle.WALL, 1.0, (0, 0, 0), TH0 + dT)
+    f = inputs.uniform(n, n, 1)
+    o.init(f["rho"], f["u"], f["thT"], f["thR"])
+    o.step(steps)
+    m = o.moments()
+    th = (3 * m["thT"] + p["delta"] * m["thR"]) / (3 + p["delta"])
+    X, Y, _ = inputs.positions(n, n, 1)
+    xl, yl = (X + 0.25) / n, (Y + 0.25) / n          # walls a quarter cell outside the outer sites
+    return (th - TH0) / dT, heated_cavity_series(xl, yl), xl, yl
+
+
+def test_heated_cavity_follows_the_series():
+    """Sec. 6, heated cavity (24 x 24 cells here, 128 x 128 on the GPU), at a
+    temperature difference of 0.02 theta0 where conduction is linear (at 0.1
+    theta0 the F3 lattice's conductivity, which falls like theta0/theta, bends
+    the interior profile by about 1% of the difference).  At 24 cells the
+    steady temperature deviates from the series by up to 4% of the difference:
+    the Knudsen temperature jump at the walls, and the rotational temperature's
+    wall value held one same-sublattice spacing from the last site (a quarter
+    cell beyond the wall for one sublattice, three quarters for the other),
+    both of order one cell in 24.  Held: within 4% at every site 0.15 L or
+    more from the walls, within 2.5% on the paper's lines y = 0.25 L and 0.5 L."""
+    for nu, steps in ((0.1, 6000), (0.05, 12000)):
+        t, s, xl, yl = _cavity(24, nu, steps, dT=0.02 * TH0)
+        d = np.abs(t - s)
+        wall = np.minimum(np.minimum(xl, 1 - xl), np.minimum(yl, 1 - yl))
+        lines = (np.abs(yl - 0.25) <= 0.5 / 24) | (np.abs(yl - 0.5) <= 0.5 / 24)
+        print("cavity nu %g: max deviation 0.15 L from the walls %.4f, on y = L/4, L/2 %.4f"
+              % (nu, d[wall >= 0.15].max(), d[lines].max()))
+        assert d[wall >= 0.15].max() < 0.04
+        assert d[lines].max() < 0.025
