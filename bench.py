@@ -357,10 +357,17 @@ def shock_summary(max_steps=60000):
     return out
 
 
-def sweep(args):
+def sweep(args, extra=None):
     """Time to residual 1e-8 of a seeded mix of 1D cases (Couette layers and
     normal-shock lines): plain (one case at a time), batched cold, batched
-    warm-started by the MLP."""
+    warm-started by the MLP.
+
+    The network trains on every steady state the solver reached for the
+    training cases, together with `extra` (features, targets, training-case
+    descriptions) from an earlier sweep, and starts a held-out case only when
+    its Mach and Knudsen numbers lie within the range of the converged
+    training cases of its kind; any other case starts cold (the plain LB is
+    the fallback).  Returns (report, (features, targets, converged cases))."""
     import numpy as np
     import torch
 
@@ -394,10 +401,11 @@ def sweep(args):
                            % (args.sweep_lmin, args.sweep_lmax, 100 * (1 - args.sweep_shock_frac), args.sweep_knmin,
                               args.sweep_knmax, 100 * args.sweep_shock_frac, args.sweep_mamin, args.sweep_mamax),
            "step_cap_per_case": {"held_out": args.sweep_max_steps, "training": args.sweep_train_max_steps},
-           "wall_time_budget_per_batch_s": args.sweep_time_budget or None,
+           "wall_time_budget_per_batch_s": {"held_out": args.sweep_time_budget or None,
+                                            "training": args.sweep_train_time_budget or None},
            "stall_window_steps": {"couette": args.sweep_stall, "shock": args.sweep_stall_shock}}
 
-    def run_batch(cs, fields, label, tune_only=False, max_steps=None):
+    def run_batch(cs, fields, label, tune_only=False, max_steps=None, train_budget=None):
         """Run the cases to the tolerance: the Couette layers (F3, any
         work-group size) and the shock lines (E2, work-groups of 256) as two
         batches, each one persistent launch per chunk on its own stream, run
@@ -421,19 +429,25 @@ def sweep(args):
             b.stall(args.sweep_stall_shock if cs[idx[0]]["kind"] == C.SHOCK else args.sweep_stall)
             stream.synchronize()
             # tune_only: let the autotuner time its candidates and cache the choice;
-            # otherwise advance in stages of 2048 steps (a capped case runs on
-            # when the cap rises) and report each stage
+            # otherwise advance in stages of 256 to 2048 steps, each about 10 s
+            # of work (a capped case runs on when the cap rises), report each
+            # stage and stop when the wall-time budget is spent
             cap = 512 if tune_only else (max_steps or args.sweep_max_steps)
-            done = 0
+            done, stage = 0, 256
             while True:
-                done = min(cap, done + 2048)
+                ts = time.perf_counter()
+                done = min(cap, done + stage)
                 steps, resid, status = b.run(done, tol)
+                # next stage: about 10 s of work, 256 to 2048 steps
+                per = (time.perf_counter() - ts) / stage
+                stage = int(min(2048, max(256, 10.0 / max(per, 1e-9) // 256 * 256)))
                 print("# %s %s: %d steps, running %d of %d, %.1f s" % (label, cs[idx[0]]["kind"], done,
                       int((status == 3).sum()) if done < cap else 0, len(idx), time.perf_counter() - tw),
                       file=sys.stderr, flush=True)
                 if done >= cap or not (status == 3).any():
                     break
-                if not tune_only and args.sweep_time_budget and time.perf_counter() - tw > args.sweep_time_budget:
+                budget = train_budget if train_budget is not None else args.sweep_time_budget
+                if not tune_only and budget and time.perf_counter() - tw > budget:
                     break   # out of wall time: the cases still running stay capped
             res[j] = (idx, sel, steps, resid, status, b.moments(), b.tuned())
             b.close()
@@ -469,12 +483,17 @@ def sweep(args):
     # training data: steady states of the training cases (cold batched runs);
     # the first run also settles the autotuner's choice for this case mix
     t_gen0 = time.perf_counter()
-    tr = run_batch(train, C.cold_fields(train), "train cold", max_steps=args.sweep_train_max_steps)
+    tr = run_batch(train, C.cold_fields(train), "train cold", max_steps=args.sweep_train_max_steps,
+                   train_budget=args.sweep_train_time_budget)
     t_gen = time.perf_counter() - t_gen0
     tr_shock = np.array([c["kind"] == C.SHOCK for c in train])
     ok = np.repeat(tr["status"] == 1, [2 * c["L"] for c in train])
     X = C.features(train)[ok]
     Y = C.targets(train, tr["m"])[ok]
+    conv = [c for c, st in zip(train, tr["status"]) if st == 1]
+    own_points = int(len(X))
+    if extra is not None:
+        X, Y, conv = np.concatenate([X, extra[0]]), np.concatenate([Y, extra[1]]), conv + extra[2]
     mlp = MLP(nmax=max(8192, args.sweep_mlp_batch))
     mlp.set_params(mlp_init(S))
     t0 = time.perf_counter()
@@ -493,7 +512,22 @@ def sweep(args):
     t0 = time.perf_counter()
     y = mlp.forward(C.features(test)).cpu().numpy()
     t_infer = time.perf_counter() - t0
-    warm = run_batch(test, C.fields_from_prediction(test, y), "held-out warm")
+    # warm start inside the range of the converged training cases of the same
+    # kind (Mach and log Kn); cold start elsewhere
+    rng_kind = {}
+    for kind in (C.COUETTE, C.SHOCK):
+        cc = [c for c in conv if c["kind"] == kind]
+        if cc:
+            rng_kind[kind] = (min(c["Ma"] for c in cc), max(c["Ma"] for c in cc),
+                              min(c["Kn"] for c in cc), max(c["Kn"] for c in cc))
+    inside = np.array([c["kind"] in rng_kind and rng_kind[c["kind"]][0] <= c["Ma"] <= rng_kind[c["kind"]][1]
+                       and rng_kind[c["kind"]][2] <= c["Kn"] <= rng_kind[c["kind"]][3] for c in test])
+    wf, cf = C.fields_from_prediction(test, y), C.cold_fields(test)
+    site_in = np.repeat(inside, [2 * c["L"] for c in test])
+    for key in ("rho", "thT", "thR"):
+        wf[key] = np.where(site_in, wf[key], cf[key])
+    wf["u"] = np.where(site_in[None, :], wf["u"], cf["u"])
+    warm = run_batch(test, wf, "held-out warm")
     mlp.close()
 
     # final match of warm and cold converged states.  Couette: max |du|/U
@@ -520,9 +554,9 @@ def sweep(args):
                 pw = profile_metrics(x, warm["m"]["rho"][sl], c["up"], c["down"])[0]
                 pc = profile_metrics(x, cold["m"]["rho"][sl], c["up"], c["down"])[0]
                 d = pw - pc
-                inside = (xs + d >= xs[0]) & (xs + d <= xs[-1])
-                aligned = np.interp(xs[inside] + d, xs, rw)
-                worst_s = max(worst_s, float(np.abs(aligned - rc_[inside]).max() / dr))
+                keep = (xs + d >= xs[0]) & (xs + d <= xs[-1])
+                aligned = np.interp(xs[keep] + d, xs, rw)
+                worst_s = max(worst_s, float(np.abs(aligned - rc_[keep]).max() / dr))
                 shift = max(shift, abs(d))
             else:
                 du = np.abs(warm["m"]["u"][1][sl] - cold["m"]["u"][1][sl]).max() / c["U"]
@@ -553,6 +587,11 @@ def sweep(args):
                 (("converged", 1), ("diverged", 2), ("capped", 3), ("stalled", 4))}
 
     conv_both = (cold["status"] == 1) & (warm["status"] == 1)
+    mach = np.array([c["Ma"] for c in test])
+    bands = (("Ma<1.6", 0.0, 1.6), ("1.6<=Ma<2.65", 1.6, 2.65), ("Ma>=2.65", 2.65, 99.0))
+
+    def by_mach(r):
+        return {nm: counts(r, is_shock & (mach >= lo) & (mach < hi)) for nm, lo, hi in bands}
 
     def med(a, mask):
         return int(np.median(a[mask])) if mask.any() else None
@@ -567,7 +606,10 @@ def sweep(args):
         "training_data_generation_time": round(t_gen, 2),
         "training_cases_by_status": {"couette": counts(tr, ~tr_shock), "shock": counts(tr, tr_shock)},
         "mlp_inference_time": round(t_infer, 3), "mlp_train_time": round(t_train, 1),
-        "mlp_train_points": int(len(X)),
+        "mlp_train_points": int(len(X)), "mlp_train_points_from_this_training_set": own_points,
+        "held_out_warm_started": {"couette": int((inside & ~is_shock).sum()), "shock": int((inside & is_shock).sum()),
+                                  "rule": "Mach and Kn within the range of the converged training cases of the "
+                                          "same kind; every other case starts cold"},
         "mlp_loss_first_last": [float(losses[0]), float(losses[-1])], "mlp_schedule": args.sweep_lr_schedule,
         "mlp_minibatch": args.sweep_mlp_batch,
         "mlp_loss_curve_every_5_epochs": [float("%.4g" % v) for v in losses[::5]],
@@ -590,6 +632,7 @@ def sweep(args):
                   "steps_warm_median": med(warm["steps"], is_shock),
                   "steps_cold_median_converged_both": med(cold["steps"], is_shock & conv_both),
                   "steps_warm_median_converged_both": med(warm["steps"], is_shock & conv_both),
+                  "cold_by_mach": by_mach(cold), "warm_by_mach": by_mach(warm),
                   "warm_vs_cold_max_drho_over_jump_aligned": round(worst_s, 6),
                   "warm_vs_cold_max_shift_cells": round(shift, 4)},
         "steps_cold_total": int(cold["steps"].sum()), "steps_warm_total": int(warm["steps"].sum()),
@@ -598,6 +641,25 @@ def sweep(args):
         "speedup_batched_cold_vs_plain": round(plain_est / cold["time"], 2),
         "speedup_batched_warm_vs_plain": round(plain_est / (warm["time"] + t_infer), 2),
     })
+    return out, (X, Y, conv)
+
+
+def sweeps(args):
+    """The reduced mix first (every case converges; its steady states also
+    train the network of the second run), then the stated 512/4096-case mix
+    under its caps.  A failure is reported in place of the object."""
+    out, extra = {}, None
+    if not args.no_sweep_reduced:
+        try:
+            out["sweep_reduced"], extra = sweep(reduced_args(args))
+        except Exception as e:  # noqa: BLE001
+            print("# sweep_reduced failed: %r" % (e,), file=sys.stderr, flush=True)
+            out["sweep_reduced"] = {"error": repr(e)}
+    try:
+        out["sweep"], _ = sweep(args, extra)
+    except Exception as e:  # noqa: BLE001
+        print("# sweep failed: %r" % (e,), file=sys.stderr, flush=True)
+        out["sweep"] = {"error": repr(e)}
     return out
 
 
@@ -610,7 +672,7 @@ def reduced_args(args):
     r.sweep_n, r.sweep_train, r.sweep_lmin, r.sweep_lmax = 256, 512, 128, 512
     r.sweep_knmin, r.sweep_knmax, r.sweep_mamin, r.sweep_mamax = 1e-2, 1e-1, 1.1, 1.6
     r.sweep_max_steps = r.sweep_train_max_steps = 400000
-    r.sweep_time_budget = 0.0
+    r.sweep_time_budget = r.sweep_train_time_budget = 0.0
     return r
 
 
@@ -643,8 +705,10 @@ def main():
     ap.add_argument("--sweep-train-max-steps", type=int, default=8192,
                     help="step cap per training case (only converged training states train the network)")
     ap.add_argument("--sweep-time-budget", type=float, default=60.0,
-                    help="wall seconds per batched run after which the cases still running count as capped "
-                         "(0 = none)")
+                    help="wall seconds per batched held-out run after which the cases still running count as "
+                         "capped (0 = none)")
+    ap.add_argument("--sweep-train-time-budget", type=float, default=30.0,
+                    help="the same for the run that generates the training states")
     ap.add_argument("--no-sweep-reduced", action="store_true",
                     help="skip the second sweep on the reduced mix that converges in full")
     ap.add_argument("--sweep-mlp-batch", type=int, default=2048, help="MLP training minibatch")
@@ -665,10 +729,7 @@ def main():
               "(the z-slab decomposition is a design note); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.sweep:
-        out = {"sweep": sweep(args)}
-        if not args.no_sweep_reduced:
-            out["sweep_reduced"] = sweep(reduced_args(args))
-        print(json.dumps(out), flush=True)
+        print(json.dumps(sweeps(args)), flush=True)
         return
     if args.shock:
         print(json.dumps(shock_summary()), flush=True)
@@ -766,9 +827,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)
     # the side experiments report into the line; a failure in one of them is
     # recorded there and never costs the headline measurement
-    for key, skip, fn in (("shear_wave", False, shear_wave_summary), ("shock", args.no_shock, shock_summary),
-                          ("sweep", args.no_sweep, lambda: sweep(args)),
-                          ("sweep_reduced", args.no_sweep or args.no_sweep_reduced, lambda: sweep(reduced_args(args)))):
+    for key, skip, fn in (("shear_wave", False, shear_wave_summary), ("shock", args.no_shock, shock_summary)):
         if skip:
             continue
         try:
@@ -776,6 +835,8 @@ def main():
         except Exception as e:  # noqa: BLE001
             print("# %s failed: %r" % (key, e), file=sys.stderr, flush=True)
             out[key] = {"error": repr(e)}
+    if not args.no_sweep:
+        out.update(sweeps(args))
     print(json.dumps(out), flush=True)
 
 
