@@ -254,16 +254,16 @@ __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
             double *lm = a.lmul + (size_t)2 * E2_NL * off;
             for (int s = tid; s < ns; s += NTH) {
                 double r;
-                lb_site<double, double, VAR, true, PGK_E2>(s, src, dst, gh, thR, that_, aux, k, r, lm);
+                lb_site<double, double, VAR, BND_X, PGK_E2>(s, src, dst, gh, thR, that_, aux, k, r, lm);
             }
         } else {
             for (int s = tid; s < ns; s += NTH) {
                 double r;
-                lb_site<double, double, VAR, true, PGK_F3>(s, src, dst, gh, thR, that_, aux, k, r);
+                lb_site<double, double, VAR, BND_X, PGK_F3>(s, src, dst, gh, thR, that_, aux, k, r);
             }
         }
         __syncthreads();
-        for (int s = tid; s < ns; s += NTH) mc_site<double, true>(s, that_, aux, tmc, k);
+        for (int s = tid; s < ns; s += NTH) mc_site<double, BND_X>(s, that_, aux, tmc, k);
         __syncthreads();
         if (k.nx <= 64 * DW_P) {
             if (tid < 128) dif_chain<VAR>(tid >> 6, tmc, aux, that_, thR, k);
@@ -290,13 +290,13 @@ __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
         } else {
             double *tin = tmc, *tout = tmc2;
             for (int it = 0; it + 1 < k.nsub; it++) {
-                for (int s = tid; s < ns; s += NTH) dif_site<double, VAR, true, false>(s, tin, tout, that_, aux, thR, k);
+                for (int s = tid; s < ns; s += NTH) dif_site<double, VAR, BND_X, false>(s, tin, tout, that_, aux, thR, k);
                 __syncthreads();
                 double *t = tin;
                 tin = tout;
                 tout = t;
             }
-            for (int s = tid; s < ns; s += NTH) dif_site<double, VAR, true, true>(s, tin, tout, that_, aux, thR, k);
+            for (int s = tid; s < ns; s += NTH) dif_site<double, VAR, BND_X, true>(s, tin, tout, that_, aux, thR, k);
         }
         __syncthreads();
         cur ^= 1;
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
             double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
             for (int s = tid; s < ns; s += NTH) {
                 Mom m;
-                Solve so = moments_site<double, true>(s, nsrc, gh, thR, k, m);
+                Solve so = moments_site<double, BND_X>(s, nsrc, gh, thR, k, m);
                 double ua = bc.vel_axis == 0 ? so.u[0] : (bc.vel_axis == 1 ? so.u[1] : so.u[2]);
                 double phi[4] = {so.rho, ua, so.T, so.r};
                 if (!(so.rho > 0.0) || !(so.T > 0.0) || !(so.r > 0.0) || !isfinite(so.u[0]) ||
@@ -364,10 +364,10 @@ __global__ __launch_bounds__(NTH) void k_batch_init(BatchArgs a, const double *_
     }
     for (int s = threadIdx.x; s < k.ns; s += NTH) {
         if (bc.eq == PGK_E2)
-            init_site<double, true, PGK_E2>(s, dst, gh, a.thR + off, rho + off, u + off, thT + off, thRin + off, k,
+            init_site<double, BND_X, PGK_E2>(s, dst, gh, a.thR + off, rho + off, u + off, thT + off, thRin + off, k,
                                             (size_t)ns_total);
         else
-            init_site<double, true, PGK_F3>(s, dst, gh, a.thR + off, rho + off, u + off, thT + off, thRin + off, k,
+            init_site<double, BND_X, PGK_F3>(s, dst, gh, a.thR + off, rho + off, u + off, thT + off, thRin + off, k,
                                             (size_t)ns_total);
     }
     if (threadIdx.x == 0) {
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(NTH) void k_batch_moments(BatchArgs a, double *__re
     __syncthreads();
     for (int s = threadIdx.x; s < k.ns; s += NTH) {
         Mom m;
-        Solve so = moments_site<double, true>(s, src, gh, a.thR + off, k, m);
+        Solve so = moments_site<double, BND_X>(s, src, gh, a.thR + off, k, m);
         if (orho) orho[off + s] = so.rho;
         if (ou)
             for (int i = 0; i < 3; i++) ou[i * ns_total + off + s] = so.u[i];

@@ -17,6 +17,9 @@ namespace pgk {
 
 constexpr int WG = 256;
 constexpr int NSLOT = 4;  // ghost slots per x face: doubled x offsets 1..4 beyond the face
+// which faces a grid has, a template level of the step kernels: none (every
+// axis periodic), faces on x only, faces on x and y
+constexpr int BND_NONE = 0, BND_X = 1, BND_XY = 2;
 
 struct Consts {
     int nx, ny, nz, ns;
@@ -209,8 +212,11 @@ __host__ __device__ __forceinline__ int ghost_index(int f, int q, int slot, int 
 
 // Array index of the value of population q at doubled position (qx, qy, qz):
 // a site of the population arrays (periodic axes wrap; `ghost` = 0), or on a
-// bounded grid a ghost slot beyond face f (`ghost` = 1 + f).
-template <bool BOUNDED>
+// bounded grid a ghost slot beyond face f (`ghost` = 1 + f).  BOUNDED is the
+// grid's level: BND_NONE (every axis periodic), BND_X (faces on x only, y
+// periodic) or BND_XY (faces on x and on y); the lower levels leave out the
+// tests and index arithmetic of the faces they do not have.
+template <int BOUNDED>
 __device__ __forceinline__ int position_index(int qx, int qy, int qz, int q, const Consts &k, int &ghost)
 {
     const int ssub = qx & 1;
@@ -220,10 +226,14 @@ __device__ __forceinline__ int position_index(int qx, int qy, int qz, int q, con
         int f = -1, slot = 0;
         if (qx < 0 && k.bc[0] != PGK_PERIODIC) { f = 0; slot = -qx - 1; }
         else if (qx > 2 * k.nx - 1 && k.bc[1] != PGK_PERIODIC) { f = 1; slot = qx - 2 * k.nx; }
-        else if (qy < 0 && k.bc[2] != PGK_PERIODIC) { f = 2; slot = -qy - 1; }
-        else if (qy > 2 * k.ny - 1 && k.bc[3] != PGK_PERIODIC) { f = 3; slot = qy - 2 * k.ny; }
+        else if (BOUNDED >= BND_XY && qy < 0 && k.bc[2] != PGK_PERIODIC) { f = 2; slot = -qy - 1; }
+        else if (BOUNDED >= BND_XY && qy > 2 * k.ny - 1 && k.bc[3] != PGK_PERIODIC) { f = 3; slot = qy - 2 * k.ny; }
         if (f >= 0) {
             ghost = 1 + f;
+            if (BOUNDED < BND_XY) {
+                // x faces of a grid periodic in y: ny columns per z
+                return ((f * NQ + q) * NSLOT + slot) * k.nz * k.ny + sz * k.ny + wrapc(hy, k.ny);
+            }
             if (f < 2) {
                 const int w = ghost_wy(k);
                 const int iy = k.bc[2] != PGK_PERIODIC ? hy + 2 : wrapc(hy, k.ny);
@@ -236,14 +246,14 @@ __device__ __forceinline__ int position_index(int qx, int qy, int qz, int q, con
 }
 
 // Index of the population Q pulled by site (x,y,z,sub), see position_index.
-template <int Q, bool BOUNDED>
+template <int Q, int BOUNDED>
 __device__ __forceinline__ int pull_index(int x, int y, int z, int sub, const Consts &k, int &ghost)
 {
     constexpr int cx = c2(Q, 0), cy = c2(Q, 1), cz = c2(Q, 2);
     return position_index<BOUNDED>(2 * x + sub - cx, 2 * y + sub - cy, 2 * z + sub - cz, Q, k, ghost);
 }
 
-template <typename S, bool BOUNDED, int Q>
+template <typename S, int BOUNDED, int Q>
 __device__ __forceinline__ void load_one(const S *__restrict__ src, const S *__restrict__ gh,
                                          int x, int y, int z, int sub, const Consts &k, S *v)
 {
@@ -253,7 +263,7 @@ __device__ __forceinline__ void load_one(const S *__restrict__ src, const S *__r
     else v[Q] = src[(size_t)Q * k.ns + idx];
 }
 
-template <typename S, bool BOUNDED, int Q = 0>
+template <typename S, int BOUNDED, int Q = 0>
 __device__ __forceinline__ void load_all(const S *__restrict__ src, const S *__restrict__ gh,
                                          int x, int y, int z, int sub, const Consts &k, S *v)
 {
@@ -592,7 +602,7 @@ __device__ __forceinline__ void block_sum(double *val, double *out)
 // moments of g (time level n) and the stored theta_R in r_out
 // lmul (E2 only, may be null): per-site store [2 E2_NL][ns] of the two
 // multiplier sets of the last step; each Newton run starts from them
-template <typename S, typename A, int VAR, bool BOUNDED, int EQ = PGK_F3>
+template <typename S, typename A, int VAR, int BOUNDED, int EQ = PGK_F3>
 __device__ __forceinline__ Mom lb_site(int s, const S *__restrict__ src, S *__restrict__ dst,
                                        const S *__restrict__ gh, double *__restrict__ thR,
                                        double *__restrict__ that_, A *__restrict__ aux, const Consts &k,
@@ -601,7 +611,7 @@ __device__ __forceinline__ Mom lb_site(int s, const S *__restrict__ src, S *__re
     int x, y, z, sub;
     decode(s, k, x, y, z, sub);
     S v[NQ];
-    if constexpr (BOUNDED) load_all<S, true>(src, gh, x, y, z, sub, k, v);
+    if constexpr (BOUNDED) load_all<S, BOUNDED>(src, gh, x, y, z, sub, k, v);
     else load_periodic<S>(src, pull_map(x, y, z, sub, k), k.ns, v);
     double r = thR[s];
     Mom m = moments<S>(v, k);
@@ -667,7 +677,7 @@ __device__ __forceinline__ Mom lb_site(int s, const S *__restrict__ src, S *__re
 // collides with each lane storing one member of every opposite pair, and lane
 // 0 hands the fields to the transport.
 // The arithmetic per site is that of lb_site<..., PGK_E2>.
-template <typename S, typename A, int VAR, bool BOUNDED>
+template <typename S, typename A, int VAR, int BOUNDED>
 __device__ __forceinline__ void lb_site_e2pair(int s, int r, const S *__restrict__ src, S *__restrict__ dst,
                                                const S *__restrict__ gh, double *__restrict__ thR,
                                                double *__restrict__ that_, A *__restrict__ aux, const Consts &k,
@@ -676,7 +686,7 @@ __device__ __forceinline__ void lb_site_e2pair(int s, int r, const S *__restrict
     int x, y, z, sub;
     decode(s, k, x, y, z, sub);
     S v[NQ];
-    if constexpr (BOUNDED) load_all<S, true>(src, gh, x, y, z, sub, k, v);
+    if constexpr (BOUNDED) load_all<S, BOUNDED>(src, gh, x, y, z, sub, k, v);
     else load_periodic<S>(src, pull_map(x, y, z, sub, k), k.ns, v);
     Mom m = moments<S>(v, k);
     Solve so = site_solve(m, thR[s], k);
@@ -710,7 +720,7 @@ __device__ __forceinline__ void lb_site_e2pair(int s, int r, const S *__restrict
 // ---------------------------------------------------------------------------
 // same-sublattice neighbour along axis a (0,1,2) by dir (+-1); across a bounded
 // face f it returns -1 - f (-1 / -2: low / high x, -3 / -4: low / high y)
-template <bool BOUNDED>
+template <int BOUNDED>
 __device__ __forceinline__ int nbr(int x, int y, int z, int sub, int a, int dir, const Consts &k)
 {
     if (a == 0) {
@@ -722,7 +732,7 @@ __device__ __forceinline__ int nbr(int x, int y, int z, int sub, int a, int dir,
         x = wrapc(x, k.nx);
     } else if (a == 1) {
         y += dir;
-        if (BOUNDED) {
+        if (BOUNDED >= BND_XY) {
             if (y < 0 && k.bc[2] != PGK_PERIODIC) return -3;
             if (y >= k.ny && k.bc[3] != PGK_PERIODIC) return -4;
         }
@@ -733,7 +743,7 @@ __device__ __forceinline__ int nbr(int x, int y, int z, int sub, int a, int dir,
     return ((sub * k.nz + z) * k.ny + y) * k.nx + x;
 }
 
-template <typename A, bool BOUNDED>
+template <typename A, int BOUNDED>
 __device__ __forceinline__ double theta_star(const double *__restrict__ th, const A *__restrict__ aux,
                                              int idx, const Consts &k)
 {
@@ -751,7 +761,7 @@ __device__ __forceinline__ double theta_star(const double *__restrict__ th, cons
     return t - adv;
 }
 
-template <typename A, bool BOUNDED>
+template <typename A, int BOUNDED>
 __device__ __forceinline__ void mc_site(int s, const double *__restrict__ that_, const A *__restrict__ aux,
                                         double *__restrict__ tmc, const Consts &k)
 {
@@ -770,7 +780,7 @@ __device__ __forceinline__ void mc_site(int s, const double *__restrict__ that_,
 
 // one FTCS sub-step of the theta_R diffusion from tin; the last sub-step
 // (FINAL) also applies the second half of the relaxation and writes theta_R
-template <typename A, int VAR, bool BOUNDED, bool FINAL>
+template <typename A, int VAR, int BOUNDED, bool FINAL>
 __device__ __forceinline__ void dif_site(int s, const double *__restrict__ tin, double *__restrict__ tout,
                                          const double *__restrict__ that_, const A *__restrict__ aux,
                                          double *__restrict__ thR, const Consts &k)
@@ -898,7 +908,7 @@ __device__ __forceinline__ void bc_column(int f, int col, int lane, const S *__r
 // push F_i(rho, u, theta_T I) of site s to where the next pull reads it:
 // population i of site x is read from position x - c_i (a ghost slot when that
 // lies beyond a bounded face)
-template <typename S, bool BOUNDED, int EQ = PGK_F3>
+template <typename S, int BOUNDED, int EQ = PGK_F3>
 __device__ __forceinline__ void init_site(int s, S *__restrict__ dst, S *__restrict__ gh, double *__restrict__ thR,
                                           const double *__restrict__ rho, const double *__restrict__ u,
                                           const double *__restrict__ thT, const double *__restrict__ thRin,
@@ -959,14 +969,14 @@ __device__ __forceinline__ void init_site(int s, S *__restrict__ dst, S *__restr
 }
 
 // f-moments of site s at the current time level (after the g -> f map)
-template <typename S, bool BOUNDED>
+template <typename S, int BOUNDED>
 __device__ __forceinline__ Solve moments_site(int s, const S *__restrict__ src, const S *__restrict__ gh,
                                               const double *__restrict__ thR, const Consts &k, Mom &m)
 {
     int x, y, z, sub;
     decode(s, k, x, y, z, sub);
     S v[NQ];
-    if constexpr (BOUNDED) load_all<S, true>(src, gh, x, y, z, sub, k, v);
+    if constexpr (BOUNDED) load_all<S, BOUNDED>(src, gh, x, y, z, sub, k, v);
     else load_periodic<S>(src, pull_map(x, y, z, sub, k), k.ns, v);
     m = moments<S>(v, k);
     return site_solve(m, thR[s], k);

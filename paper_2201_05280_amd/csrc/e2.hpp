@@ -106,7 +106,8 @@ __host__ __device__ __forceinline__ double e2_maxchange(const double *dl, double
 }
 
 // In-place Cholesky solve of the packed SPD system J x = b; false if J is not
-// positive definite.
+// positive definite.  The diagonal of the factor is kept as its reciprocal,
+// so the two triangular solves multiply instead of divide.
 __host__ __device__ __forceinline__ bool e2_cholesky_solve(double *J, double *b)
 {
 #pragma unroll
@@ -115,9 +116,8 @@ __host__ __device__ __forceinline__ bool e2_cholesky_solve(double *J, double *b)
 #pragma unroll
         for (int k = 0; k < j; k++) d -= J[e2_ij(k, j)] * J[e2_ij(k, j)];
         if (!(d > 0.0)) return false;
-        double r = sqrt(d);
-        J[e2_ij(j, j)] = r;
-        double ir = 1.0 / r;
+        double ir = 1.0 / sqrt(d);
+        J[e2_ij(j, j)] = ir;       // 1 / U[j][j]
 #pragma unroll
         for (int i = j + 1; i < E2_NL; i++) {
             double t = J[e2_ij(j, i)];
@@ -132,7 +132,7 @@ __host__ __device__ __forceinline__ bool e2_cholesky_solve(double *J, double *b)
         double t = b[i];
 #pragma unroll
         for (int k = 0; k < i; k++) t -= J[e2_ij(k, i)] * b[k];
-        b[i] = t / J[e2_ij(i, i)];
+        b[i] = t * J[e2_ij(i, i)];
     }
     // U x = y
 #pragma unroll
@@ -140,7 +140,7 @@ __host__ __device__ __forceinline__ bool e2_cholesky_solve(double *J, double *b)
         double t = b[i];
 #pragma unroll
         for (int k = i + 1; k < E2_NL; k++) t -= J[e2_ij(i, k)] * b[k];
-        b[i] = t / J[e2_ij(i, i)];
+        b[i] = t * J[e2_ij(i, i)];
     }
     return true;
 }

@@ -37,10 +37,10 @@ namespace pgk {
 // 256 a step of the 256^3 benchmark grid takes 1.5% less (fewer, longer-lived
 // groups) and the kernel fits the 128 registers this allows without spilling;
 // 256 for FP64 storage and for F4 with faces, which would spill at 128.
-template <typename S, bool BOUNDED, int EQ>
+template <typename S, int BOUNDED, int EQ>
 constexpr int lb_wg() { return sizeof(S) == 4 && (EQ == PGK_F3 || !BOUNDED) ? 1024 : WG; }
 
-template <typename S, typename A, int VAR, bool BOUNDED, int EQ, int NT>
+template <typename S, typename A, int VAR, int BOUNDED, int EQ, int NT>
 __global__ __launch_bounds__(NT) void k_lb(const S *__restrict__ src, S *__restrict__ dst, const S *__restrict__ gh,
                                            double *__restrict__ thR, double *__restrict__ that_, A *__restrict__ aux,
                                            double *__restrict__ lmul, Consts k)
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(NT) void k_lb(const S *__restrict__ src, S *__restr
 }
 
 // E2 grids: two lanes per site, one Newton solve each (lb_site_e2pair)
-template <typename S, typename A, int VAR, bool BOUNDED>
+template <typename S, typename A, int VAR, int BOUNDED>
 __global__ __launch_bounds__(WG) void k_lb_e2(const S *__restrict__ src, S *__restrict__ dst,
                                               const S *__restrict__ gh, double *__restrict__ thR,
                                               double *__restrict__ that_, A *__restrict__ aux,
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(WG) void k_lb_e2(const S *__restrict__ src, S *__re
     if (s < k.ns) lb_site_e2pair<S, A, VAR, BOUNDED>(s, t & 1, src, dst, gh, thR, that_, aux, k, lmul);
 }
 
-template <typename A, bool BOUNDED>
+template <typename A, int BOUNDED>
 __global__ __launch_bounds__(WG) void k_mc(const double *__restrict__ that_, const A *__restrict__ aux,
                                            double *__restrict__ tmc, Consts k)
 {
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(WG) void k_mc(const double *__restrict__ that_, con
     if (s < k.ns) mc_site<A, BOUNDED>(s, that_, aux, tmc, k);
 }
 
-template <typename A, int VAR, bool BOUNDED, bool FINAL>
+template <typename A, int VAR, int BOUNDED, bool FINAL>
 __global__ __launch_bounds__(WG) void k_dif(const double *__restrict__ tin, double *__restrict__ tout,
                                             const double *__restrict__ that_, const A *__restrict__ aux,
                                             double *__restrict__ thR, Consts k)
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(WG) void k_dif(const double *__restrict__ tin, doub
 // arithmetic is that of k_mc and k_dif, so the results are the same bits.
 constexpr int TR_SMALL = 4096, TR_SMALL_WG = 1024;
 
-template <typename A, int VAR, bool BOUNDED>
+template <typename A, int VAR, int BOUNDED>
 __global__ __launch_bounds__(TR_SMALL_WG) void k_tr_small(const double *__restrict__ that_,
                                                           const A *__restrict__ aux, double *__restrict__ thR,
                                                           Consts k)
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(TR_SMALL_WG) void k_tr_small(const double *__restri
 // k_mc + k_dif to round-off (a last bit here and there), not bit for bit.
 constexpr int TL_C = 1024, TL_WG = 1024, TL_HMAX = 64, TL_L = TL_C + 2 * TL_HMAX;
 
-template <typename A, int VAR, bool BOUNDED>
+template <typename A, int VAR, int BOUNDED>
 __global__ __launch_bounds__(TL_WG) void k_tr_line(const double *__restrict__ that_, const A *__restrict__ aux,
                                                    double *__restrict__ thR, Consts k)
 {
@@ -467,7 +467,7 @@ static int bc_launches(const Consts &k)
     return n;
 }
 
-template <typename S, bool BOUNDED, int EQ>
+template <typename S, int BOUNDED, int EQ>
 __global__ __launch_bounds__(WG) void k_init(S *__restrict__ dst, S *__restrict__ gh, double *__restrict__ thR,
                                              const double *__restrict__ rho, const double *__restrict__ u,
                                              const double *__restrict__ thT, const double *__restrict__ thRin,
@@ -482,7 +482,7 @@ __global__ __launch_bounds__(WG) void k_init(S *__restrict__ dst, S *__restrict_
     }
 }
 
-template <typename S, bool BOUNDED, bool REDUCE>
+template <typename S, int BOUNDED, bool REDUCE>
 __global__ __launch_bounds__(WG) void k_moments(const S *__restrict__ src, const S *__restrict__ gh,
                                                 const double *__restrict__ thR, double *__restrict__ orho,
                                                 double *__restrict__ ou, double *__restrict__ othT,
@@ -1032,6 +1032,12 @@ static int faces_set(pgk_ctx *c)
 
 static bool bounded(const pgk_ctx *c) { return c->k.bc[0] != PGK_PERIODIC || c->k.bc[2] != PGK_PERIODIC; }
 
+// the kernels' face level: BND_NONE, BND_X (faces on x only) or BND_XY
+static int face_level(const pgk_ctx *c)
+{
+    return c->k.bc[2] != PGK_PERIODIC ? BND_XY : c->k.bc[0] != PGK_PERIODIC ? BND_X : BND_NONE;
+}
+
 // Fill the x ghosts the next pull reads, if they are not filled yet, from the
 // face states in force now (before a change of those states takes effect).
 static int settle_ghosts(pgk_ctx *c)
@@ -1055,10 +1061,10 @@ static int init_t(pgk_ctx *c, const double *rho, const double *u, const double *
     dim3 grid(c->nblk), block(WG);
     S *dst = (S *)c->buf[c->cur];
     if (bounded(c))
-        hipLaunchKernelGGL((k_init<S, true, EQ>), grid, block, 0, c->stream, dst, (S *)c->gh,
+        hipLaunchKernelGGL((k_init<S, BND_XY, EQ>), grid, block, 0, c->stream, dst, (S *)c->gh,
                            (double *)c->buf[PGK_BUF_THETAR], rho, u, thT, thR, c->lmul, c->k);
     else
-        hipLaunchKernelGGL((k_init<S, false, EQ>), grid, block, 0, c->stream, dst, (S *)c->gh,
+        hipLaunchKernelGGL((k_init<S, BND_NONE, EQ>), grid, block, 0, c->stream, dst, (S *)c->gh,
                            (double *)c->buf[PGK_BUF_THETAR], rho, u, thT, thR, c->lmul, c->k);
     HIPCHECK(c, hipGetLastError());
     return PGK_OK;
@@ -1090,7 +1096,7 @@ extern "C" int pgk_init_fields(pgk_ctx *c, const double *rho, const double *u, c
     return rc;
 }
 
-template <typename S, typename A, int VAR, bool BND, int EQ>
+template <typename S, typename A, int VAR, int BND, int EQ>
 static int step_t(pgk_ctx *c, int64_t n)
 {
     dim3 grid(c->nblk), block(WG);
@@ -1162,9 +1168,14 @@ using StepFn = int (*)(pgk_ctx *, int64_t);
 template <typename S, typename A, int EQ>
 static StepFn step_fn_v(const pgk_ctx *c)
 {
-    bool b = bounded(c);
-    if (c->g.variant == PGK_CN) return b ? &step_t<S, A, PGK_CN, true, EQ> : &step_t<S, A, PGK_CN, false, EQ>;
-    return b ? &step_t<S, A, PGK_LIT, true, EQ> : &step_t<S, A, PGK_LIT, false, EQ>;
+    const int b = face_level(c);
+    if (c->g.variant == PGK_CN)
+        return b == BND_XY ? &step_t<S, A, PGK_CN, BND_XY, EQ>
+             : b == BND_X  ? &step_t<S, A, PGK_CN, BND_X, EQ>
+                           : &step_t<S, A, PGK_CN, BND_NONE, EQ>;
+    return b == BND_XY ? &step_t<S, A, PGK_LIT, BND_XY, EQ>
+         : b == BND_X  ? &step_t<S, A, PGK_LIT, BND_X, EQ>
+                       : &step_t<S, A, PGK_LIT, BND_NONE, EQ>;
 }
 
 static StepFn step_fn(const pgk_ctx *c)
@@ -1250,10 +1261,10 @@ static int moments_t(pgk_ctx *c, double *rho, double *u, double *thT, double *th
     int rc0 = settle_ghosts(c);
     if (rc0) return rc0;
     if (bounded(c))
-        hipLaunchKernelGGL((k_moments<S, true, REDUCE>), grid, block, 0, c->stream, src, (const S *)c->gh,
+        hipLaunchKernelGGL((k_moments<S, BND_XY, REDUCE>), grid, block, 0, c->stream, src, (const S *)c->gh,
                            (const double *)c->buf[PGK_BUF_THETAR], rho, u, thT, thR, P, c->partial, c->k);
     else
-        hipLaunchKernelGGL((k_moments<S, false, REDUCE>), grid, block, 0, c->stream, src, (const S *)c->gh,
+        hipLaunchKernelGGL((k_moments<S, BND_NONE, REDUCE>), grid, block, 0, c->stream, src, (const S *)c->gh,
                            (const double *)c->buf[PGK_BUF_THETAR], rho, u, thT, thR, P, c->partial, c->k);
     HIPCHECK(c, hipGetLastError());
     return PGK_OK;
