@@ -2,12 +2,13 @@
 // layers of 128 (SiLU) -> 4 outputs, BF16 weights and activations with FP32
 // accumulation, FP32 master weights and Adam.
 //
-// The three 128x128 layers run on the matrix cores: a 64x64 work-group tile
-// of C = A B is built from 16x16x16 bf16 MFMA blocks (four waves, each a 16x64
-// slab).  The same tile routine gives the forward products, the data
-// gradients dA = dZ W and the split-K weight gradients dW = dZ^T A.  The
-// 6-wide first layer and the 4-wide last layer are small and run on the
-// vector ALUs.  Parameter order: W1[128][6], b1, W2[128][128], b2, W3, b3,
+// Inference: the three 128x128 layers run on the matrix cores as 64x64
+// work-group tiles of 16x16x16 bf16 MFMA blocks (four waves, each a 16x64
+// slab), the 6-wide first layer and the 4-wide last layer on the vector ALUs.
+// Training: one fused kernel per minibatch runs the forward and backward
+// passes of 32 points per work-group with the activations in LDS and the
+// 128x128 products on 16x16x32 bf16 MFMA blocks; a second kernel sums the
+// work-groups' gradient slots and applies Adam.  Parameter order: W1[128][6], b1, W2[128][128], b2, W3, b3,
 // W4, b4, W5[4][128], b5.
 #include <hip/hip_runtime.h>
 
@@ -54,18 +55,12 @@ __device__ inline float dsilu(float z)
     return s * (1.0f + z * (1.0f - s));
 }
 
-template <typename T> __device__ inline short as_bf(T v);
-template <> __device__ inline short as_bf<uint16_t>(uint16_t v) { return (short)v; }
-template <> __device__ inline short as_bf<float>(float v) { return (short)f2bf(v); }
-
-enum { EPI_FWD = 0, EPI_BWD = 1, EPI_WGRAD = 2 };
-
-// C[m][n] = sum_k A(m,k) B(k,n), A(m,k) = A[m*am + k*ak], B(k,n) = B[k*bk + n*bn].
-// Work-group tile 64x64 (M0 = 64*blockIdx.x, N0 = 64*blockIdx.y), K range
-// [kb, ke) (split K over blockIdx.z for the weight gradient).  Epilogues:
-//   EPI_FWD   z = C + bias[n] -> zout[m][n] (fp32), silu(z) -> aout[m][n] (bf16)
-//   EPI_BWD   dz = C * dsilu(zin[m][n]) -> zout[m][n] (fp32)
-//   EPI_WGRAD atomicAdd(C) into zout[m][n] (fp32)
+// One 128x128 layer of the forward pass as a product on the matrix cores:
+// C[m][n] = sum_k A[m][k] B[n][k] with A (activations, bf16 [m][lda]) and B
+// (weights W[n][k], bf16) contiguous along k; work-group tile 64x64 (M0 =
+// 64 blockIdx.x, N0 = 64 blockIdx.y), four waves each a 16x64 slab of
+// 16x16x16 bf16 blocks.  Epilogue: z = C + bias[n] -> zout[m][n] (fp32),
+// silu(z) -> aout[m][n] (bf16), rows m < mvalid.
 // four consecutive bf16 values (8-byte aligned) as one MFMA operand
 __device__ inline v4i16 load4_bf(const uint16_t *p)
 {
@@ -78,46 +73,29 @@ __device__ inline v4i16 load4_bf(const uint16_t *p)
     return r;
 }
 
-// CONTIG: A and B are contiguous along k (ak = bk = 1, A in bf16): operands
-// come in 8-byte loads
-template <typename TA, int EPI, bool CONTIG = false>
-__global__ __launch_bounds__(256) void k_gemm(const TA *__restrict__ A, int am, int ak,
-                                              const uint16_t *__restrict__ B, int bk, int bn, int K, int kchunk,
-                                              const float *__restrict__ bias, const float *__restrict__ zin,
-                                              float *__restrict__ zout, uint16_t *__restrict__ aout, int ldc,
-                                              int mvalid)
+__global__ __launch_bounds__(256) void k_gemm(const uint16_t *__restrict__ A, int lda,
+                                              const uint16_t *__restrict__ B, int ldb, int K,
+                                              const float *__restrict__ bias, float *__restrict__ zout,
+                                              uint16_t *__restrict__ aout, int ldc, int mvalid)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m0 = blockIdx.x * 64 + wave * 16, n0 = blockIdx.y * 64;
-    const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
     const int r = lane & 15, kq = (lane >> 4) * 4;
     v4f32 acc[4];
     for (int b = 0; b < 4; b++) acc[b] = v4f32{0.f, 0.f, 0.f, 0.f};
     // K in blocks of four 16-deep MFMA steps: all loads of a block are issued
     // before its products, so their latencies overlap
     constexpr int KB = 4;
-    for (int k1 = kb; k1 < ke; k1 += 16 * KB) {
+    for (int k1 = 0; k1 < K; k1 += 16 * KB) {
         v4i16 a[KB], bb[KB][4];
 #pragma unroll
         for (int s = 0; s < KB; s++) {
             const int k0 = k1 + 16 * s;
-            const bool in = k0 < ke;
-            if constexpr (CONTIG) {
-                const uint16_t *Ab = reinterpret_cast<const uint16_t *>(A);
-                a[s] = in ? load4_bf(Ab + (size_t)(m0 + r) * am + k0 + kq) : v4i16{0, 0, 0, 0};
+            const bool in = k0 < K;
+            a[s] = in ? load4_bf(A + (size_t)(m0 + r) * lda + k0 + kq) : v4i16{0, 0, 0, 0};
 #pragma unroll
-                for (int b = 0; b < 4; b++)
-                    bb[s][b] = in ? load4_bf(B + (size_t)(n0 + 16 * b + r) * bn + k0 + kq) : v4i16{0, 0, 0, 0};
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; j++)
-                    a[s][j] = in ? as_bf<TA>(A[(size_t)(m0 + r) * am + (size_t)(k0 + kq + j) * ak]) : 0;
-#pragma unroll
-                for (int b = 0; b < 4; b++)
-#pragma unroll
-                    for (int j = 0; j < 4; j++)
-                        bb[s][b][j] = in ? (short)B[(size_t)(k0 + kq + j) * bk + (size_t)(n0 + 16 * b + r) * bn] : 0;
-            }
+            for (int b = 0; b < 4; b++)
+                bb[s][b] = in ? load4_bf(B + (size_t)(n0 + 16 * b + r) * ldb + k0 + kq) : v4i16{0, 0, 0, 0};
         }
 #pragma unroll
         for (int s = 0; s < KB; s++)
@@ -128,17 +106,10 @@ __global__ __launch_bounds__(256) void k_gemm(const TA *__restrict__ A, int am, 
     for (int b = 0; b < 4; b++)
         for (int j = 0; j < 4; j++) {
             int m = m0 + kq + j, n = n0 + 16 * b + r;
-            float c = acc[b][j];
-            if (EPI == EPI_WGRAD) {
-                atomicAdd(&zout[(size_t)m * ldc + n], c);
-            } else if (m < mvalid) {
-                if (EPI == EPI_FWD) {
-                    float z = c + bias[n];
-                    zout[(size_t)m * ldc + n] = z;
-                    aout[(size_t)m * ldc + n] = f2bf(silu(z));
-                } else {
-                    zout[(size_t)m * ldc + n] = c * dsilu(zin[(size_t)m * ldc + n]);
-                }
+            if (m < mvalid) {
+                float z = acc[b][j] + bias[n];
+                zout[(size_t)m * ldc + n] = z;
+                aout[(size_t)m * ldc + n] = f2bf(silu(z));
             }
         }
 }
@@ -166,87 +137,6 @@ __global__ void k_layer5(const uint16_t *__restrict__ a4, int n, const uint16_t 
     float y = master[OFF_B5 + o];
     for (int k = 0; k < H; k++) y += bf2f(wbf[OFF_W5 + o * H + k]) * bf2f(a4[p * H + k]);
     Y[i] = y;
-}
-
-// dy = 2 (yhat - y)/(4 N) (zero on padding rows) and the loss sum
-// dy = 2 (yhat - Y) scale (gradient of the minibatch's mean loss); the
-// squared errors are summed into *loss with weight lscale
-__global__ void k_loss(const float *__restrict__ yhat, const float *__restrict__ Y, int n, int npad, float scale,
-                       float lscale, float *__restrict__ dy, float *__restrict__ loss)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    float l = 0.f;
-    if (i < npad * NOUT) {
-        int p = i / NOUT;
-        float d = p < n ? yhat[i] - Y[i] : 0.f;
-        dy[i] = 2.f * d * scale;
-        l = d * d * lscale;
-    }
-    for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
-    if ((threadIdx.x & 63) == 0) atomicAdd(loss, l);
-}
-
-// dz4 = (dy W5) * dsilu(z4)
-__global__ void k_layer5_bwd(const float *__restrict__ dy, const float *__restrict__ z4,
-                             const uint16_t *__restrict__ wbf, int npad, float *__restrict__ dz4)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < npad * H) {
-        int p = i / H, k = i - p * H;
-        float da = 0.f;
-        for (int o = 0; o < NOUT; o++) da += dy[p * NOUT + o] * bf2f(wbf[OFF_W5 + o * H + k]);
-        dz4[i] = da * dsilu(z4[i]);
-    }
-}
-
-// Reductions over the points of a minibatch: work-group b takes points
-// [b GP, (b + 1) GP), thread k one hidden unit, and adds its partial sums to
-// the gradient (one atomic per value and work-group).
-constexpr int GP = 32;
-
-// last layer: dW5[o][k] = sum_p dy[p][o] a4[p][k], db5[o] = sum_p dy[p][o]
-__global__ __launch_bounds__(H) void k_layer5_wgrad(const float *__restrict__ dy, const uint16_t *__restrict__ a4,
-                                                    int n, float *__restrict__ grad)
-{
-    const int k = threadIdx.x, p0 = blockIdx.x * GP, p1 = min(n, p0 + GP);
-    float g[NOUT] = {0.f, 0.f, 0.f, 0.f}, gb = 0.f;
-    for (int p = p0; p < p1; p++) {
-        float a = bf2f(a4[(size_t)p * H + k]);
-#pragma unroll
-        for (int o = 0; o < NOUT; o++) g[o] += dy[p * NOUT + o] * a;
-        if (k < NOUT) gb += dy[p * NOUT + k];
-    }
-#pragma unroll
-    for (int o = 0; o < NOUT; o++) atomicAdd(&grad[OFF_W5 + o * H + k], g[o]);
-    if (k < NOUT) atomicAdd(&grad[OFF_B5 + k], gb);
-}
-
-// bias gradient: column sums of dz[npad][H] (padding rows are zero)
-__global__ void k_bias_grad(const float *__restrict__ dz, int npad, float *__restrict__ gb)
-{
-    int o = blockIdx.x, t = threadIdx.x;
-    float s = 0.f;
-    for (int p = t; p < npad; p += blockDim.x) s += dz[p * H + o];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    __shared__ float red[4];
-    if ((t & 63) == 0) red[t >> 6] = s;
-    __syncthreads();
-    if (t == 0) atomicAdd(&gb[o], red[0] + red[1] + red[2] + red[3]);
-}
-
-// first layer: dW1[o][j] = sum_p dz1[p][o] X[p][j]
-__global__ __launch_bounds__(H) void k_layer1_wgrad(const float *__restrict__ dz1, const float *__restrict__ X,
-                                                    int n, float *__restrict__ grad)
-{
-    const int o = threadIdx.x, p0 = blockIdx.x * GP, p1 = min(n, p0 + GP);
-    float g[NIN] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int p = p0; p < p1; p++) {
-        float d = dz1[(size_t)p * H + o];
-#pragma unroll
-        for (int j = 0; j < NIN; j++) g[j] += d * X[p * NIN + j];
-    }
-#pragma unroll
-    for (int j = 0; j < NIN; j++) atomicAdd(&grad[OFF_W1 + o * NIN + j], g[j]);
 }
 
 __global__ void k_zero(float *__restrict__ a, int n)
@@ -300,6 +190,296 @@ __global__ void k_refresh(const float *__restrict__ master, uint16_t *__restrict
     grad[i] = 0.f;
 }
 
+
+// ---------------------------------------------------------------------------
+// Fused training pass of one minibatch: forward, loss and backward of FB_P
+// points per work-group of four waves, all five layers, the 128x128 products
+// on gfx950's 16x16x32 bf16 matrix instructions.  Activations and dL/dz stay
+// in LDS, row-major ([point][unit], A operands of the products over units) and
+// transposed ([unit][point], operands of the weight gradients, a product over
+// points); z goes to global memory and is read back by the lane that wrote it.
+// Each work-group writes its share of every gradient and of the loss to its
+// own slot of a partial buffer; k_sum_adam adds the slots in a fixed order (so
+// the gradient is the same bits on every run) and applies Adam.  The bf16
+// roundings are those of the tiled path and the reference: weights,
+// activations entering layers 2-5, and dL/dz of layers 2-4 where it meets a
+// weight or an activation; x, dL/dy and dL/dz1 stay in fp32.
+//
+// Fragment layout of the 16x16x32 product D = A B (lane l, r = l % 16,
+// g = l / 16): A holds A[r][8g .. 8g+7], B holds B[8g .. 8g+7][r], D holds
+// D[4g + j][r], j = 0..3.
+constexpr int FB_P = 32;          // points per work-group
+constexpr int FB_WG = 256;
+constexpr int RS = H + 8;         // row stride (bf16) of [point][unit] arrays: rows 16 bytes apart mod 256
+constexpr int TS = FB_P + 8;      // row stride of [unit][point] arrays
+constexpr int WS = H + 8;         // row stride of the staged 128x128 weight
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+
+// eight bf16 at a 16-byte aligned address as one matrix operand
+__device__ inline v8bf ld8(const uint16_t *p) { return __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u *>(p)); }
+
+__device__ inline v4f32 mma(v8bf a, v8bf b, v4f32 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+
+// W[o][i] (bf16, 128x128 at wbf + off) into sW, row-major or transposed
+template <bool TRANSPOSE>
+__device__ inline void stage_w(const uint16_t *__restrict__ wbf, int off, uint16_t *sW)
+{
+    for (int c = threadIdx.x; c < H * H / 8; c += FB_WG) {
+        const int o = c >> 4, i0 = (c & 15) * 8;
+        const v4u v = *reinterpret_cast<const v4u *>(wbf + off + o * H + i0);
+        if (!TRANSPOSE) {
+            *reinterpret_cast<v4u *>(sW + o * WS + i0) = v;
+        } else {
+            const uint16_t *e = reinterpret_cast<const uint16_t *>(&v);
+#pragma unroll
+            for (int k = 0; k < 8; k++) sW[(i0 + k) * WS + o] = e[k];
+        }
+    }
+}
+
+// column sums over the work-group's points of a [point][unit] tile held in the
+// product layout (wave w: rows 16 (w % 2) + 4g + j, columns 64 (w / 2) + 16 t
+// + r) into red[2][H] (one row per half of the points)
+__device__ inline void col_sums(const v4f32 *d, float *red)
+{
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        float s = (d[t][0] + d[t][1]) + (d[t][2] + d[t][3]);
+        s += __shfl_xor(s, 16, 64);
+        s += __shfl_xor(s, 32, 64);
+        if (g == 0) red[(w & 1) * H + 64 * (w >> 1) + 16 * t + r] = s;
+    }
+}
+
+__global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const float *__restrict__ Y, int n,
+                                              float scale, float lscale, const uint16_t *__restrict__ wbf,
+                                              const float *__restrict__ master, float *__restrict__ z1,
+                                              float *__restrict__ z2, float *__restrict__ z3, float *__restrict__ z4,
+                                              float *__restrict__ gpart, float *__restrict__ lpart)
+{
+    __shared__ __align__(16) uint16_t sW[H * WS];
+    __shared__ __align__(16) uint16_t sRow[2][FB_P * RS];
+    __shared__ __align__(16) uint16_t sT[4][H * TS];
+    __shared__ __align__(16) uint16_t sDzT[H * TS];
+    __shared__ float sX[FB_P * NIN], sDy[FB_P * NOUT], sRed[2 * H], sLoss[FB_WG / 64];
+
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, r = l & 15, g = l >> 4;
+    const int rb = w & 1, ch = w >> 1;                 // rows 16 rb .., columns 64 ch ..
+    const int p0 = blockIdx.x * FB_P;
+    float *gp = gpart + (size_t)blockIdx.x * NPARAM;
+    // the 128x128 layers li = 0, 1, 2 (W2, W3, W4) and their biases; z of layer li + 1
+    auto offW = [](int li) { return OFF_W2 + li * (H * H + H); };
+    auto offB = [](int li) { return OFF_W2 + li * (H * H + H) + H * H; };
+    auto zb = [&](int i) { return i == 0 ? z1 : i == 1 ? z2 : i == 2 ? z3 : z4; };
+    static_assert(OFF_W3 == OFF_W2 + H * H + H && OFF_W4 == OFF_W3 + H * H + H && OFF_B4 == OFF_W4 + H * H,
+                  "layer offsets");
+
+    for (int i = tid; i < FB_P * NIN; i += FB_WG) sX[i] = p0 + i / NIN < n ? X[(size_t)p0 * NIN + i] : 0.f;
+    stage_w<false>(wbf, OFF_W2, sW);
+    __syncthreads();
+
+    // layer 1 (vector ALUs): z1 = W1 x + b1
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        const int o = 64 * ch + 16 * t + r;
+        uint16_t a4[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int p = 16 * rb + 4 * g + j;
+            float z = master[OFF_B1 + o];
+            for (int k = 0; k < NIN; k++) z += bf2f(wbf[OFF_W1 + o * NIN + k]) * sX[p * NIN + k];
+            z1[(size_t)(p0 + p) * H + o] = z;
+            a4[j] = f2bf(silu(z));
+            sRow[0][p * RS + o] = a4[j];
+        }
+        *reinterpret_cast<uint2 *>(&sT[0][o * TS + 16 * rb + 4 * g]) =
+            make_uint2(a4[0] | ((uint32_t)a4[1] << 16), a4[2] | ((uint32_t)a4[3] << 16));
+    }
+    __syncthreads();
+
+    // layers 2-4 on the matrix cores
+    for (int li = 0; li < 3; li++) {
+        const uint16_t *in = sRow[li & 1];
+        uint16_t *out = sRow[(li + 1) & 1];
+        v4f32 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) acc[t] = v4f32{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < H / 32; ks++) {
+            const v8bf a = ld8(in + (16 * rb + r) * RS + 32 * ks + 8 * g);
+#pragma unroll
+            for (int t = 0; t < 4; t++) acc[t] = mma(a, ld8(sW + (64 * ch + 16 * t + r) * WS + 32 * ks + 8 * g), acc[t]);
+        }
+        __syncthreads();
+        if (li < 2) stage_w<false>(wbf, offW(li + 1), sW);
+        float *zo = zb(li + 1);
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int o = 64 * ch + 16 * t + r;
+            const float bias = master[offB(li) + o];
+            uint16_t a4[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int p = 16 * rb + 4 * g + j;
+                const float z = acc[t][j] + bias;
+                zo[(size_t)(p0 + p) * H + o] = z;
+                a4[j] = f2bf(silu(z));
+                out[p * RS + o] = a4[j];
+            }
+            *reinterpret_cast<uint2 *>(&sT[li + 1][o * TS + 16 * rb + 4 * g]) =
+                make_uint2(a4[0] | ((uint32_t)a4[1] << 16), a4[2] | ((uint32_t)a4[3] << 16));
+        }
+        __syncthreads();
+    }
+    const uint16_t *a4s = sRow[1];                    // a4, row-major
+
+    // layer 5, the loss and dL/dy = 2 (y - Y) scale (zero on padding rows)
+    float lt = 0.f;
+    if (tid < FB_P * NOUT) {
+        const int p = tid >> 2, o5 = tid & 3;
+        float y = master[OFF_B5 + o5];
+        for (int k = 0; k < H; k++) y += bf2f(wbf[OFF_W5 + o5 * H + k]) * bf2f(a4s[p * RS + k]);
+        const float d = p0 + p < n ? y - Y[(size_t)(p0 + p) * NOUT + o5] : 0.f;
+        sDy[tid] = 2.f * d * scale;
+        lt = d * d * lscale;
+    }
+    for (int off = 32; off > 0; off >>= 1) lt += __shfl_xor(lt, off, 64);
+    if (l == 0) sLoss[w] = lt;
+    __syncthreads();
+    if (tid == 0) lpart[blockIdx.x] = (sLoss[0] + sLoss[1]) + (sLoss[2] + sLoss[3]);
+    // dW5 = dy^T a4, db5 = sum dy
+    for (int idx = tid; idx < NOUT * H; idx += FB_WG) {
+        const int o5 = idx >> 7, k = idx & (H - 1);
+        float s = 0.f;
+        for (int p = 0; p < FB_P; p++) s += sDy[p * NOUT + o5] * bf2f(a4s[p * RS + k]);
+        gp[OFF_W5 + idx] = s;
+    }
+    if (tid < NOUT) {
+        float s = 0.f;
+        for (int p = 0; p < FB_P; p++) s += sDy[p * NOUT + tid];
+        gp[OFF_B5 + tid] = s;
+    }
+    // dz4 = (dy W5) * dsilu(z4), in the product layout
+    v4f32 dz[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        const int o = 64 * ch + 16 * t + r;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int p = 16 * rb + 4 * g + j;
+            float da = 0.f;
+            for (int o5 = 0; o5 < NOUT; o5++) da += sDy[p * NOUT + o5] * bf2f(wbf[OFF_W5 + o5 * H + o]);
+            dz[t][j] = da * dsilu(z4[(size_t)(p0 + p) * H + o]);
+        }
+    }
+    __syncthreads();
+
+    // layers 4, 3, 2: weight and bias gradients, then dL/dz of the layer below
+    uint16_t *dzRow = sRow[0];
+    for (int li = 2; li >= 0; li--) {
+        col_sums(dz, sRed);
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int o = 64 * ch + 16 * t + r;
+            uint16_t b4[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                b4[j] = f2bf(dz[t][j]);
+                dzRow[(16 * rb + 4 * g + j) * RS + o] = b4[j];
+            }
+            *reinterpret_cast<uint2 *>(&sDzT[o * TS + 16 * rb + 4 * g]) =
+                make_uint2(b4[0] | ((uint32_t)b4[1] << 16), b4[2] | ((uint32_t)b4[3] << 16));
+        }
+        stage_w<true>(wbf, offW(li), sW);
+        __syncthreads();
+        if (tid < H) gp[offB(li) + tid] = sRed[tid] + sRed[H + tid];
+        // dW[o][i] = sum_p r(dz)[p][o] a[p][i]: wave w takes o in [32 w, 32 w + 32)
+        {
+            const uint16_t *aT = sT[li];
+            v4f32 acc[2][8];
+#pragma unroll
+            for (int mi = 0; mi < 2; mi++) {
+                const v8bf a = ld8(sDzT + (32 * w + 16 * mi + r) * TS + 8 * g);
+#pragma unroll
+                for (int nt = 0; nt < 8; nt++)
+                    acc[mi][nt] = mma(a, ld8(aT + (16 * nt + r) * TS + 8 * g), v4f32{0.f, 0.f, 0.f, 0.f});
+            }
+#pragma unroll
+            for (int mi = 0; mi < 2; mi++)
+#pragma unroll
+                for (int nt = 0; nt < 8; nt++)
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        gp[offW(li) + (32 * w + 16 * mi + 4 * g + j) * H + 16 * nt + r] = acc[mi][nt][j];
+        }
+        // da[p][i] = sum_o r(dz)[p][o] W[o][i]; dz of the layer below = da dsilu(z)
+        v4f32 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) acc[t] = v4f32{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < H / 32; ks++) {
+            const v8bf a = ld8(dzRow + (16 * rb + r) * RS + 32 * ks + 8 * g);
+#pragma unroll
+            for (int t = 0; t < 4; t++) acc[t] = mma(a, ld8(sW + (64 * ch + 16 * t + r) * WS + 32 * ks + 8 * g), acc[t]);
+        }
+        const float *zi = zb(li);
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const int o = 64 * ch + 16 * t + r;
+#pragma unroll
+            for (int j = 0; j < 4; j++) dz[t][j] = acc[t][j] * dsilu(zi[(size_t)(p0 + 16 * rb + 4 * g + j) * H + o]);
+        }
+        __syncthreads();
+    }
+
+    // layer 1: db1 = sum dz1, dW1 = dz1^T x (both in fp32)
+    float *sDz1 = reinterpret_cast<float *>(sT[1]);   // [FB_P][H] fp32 over the free a2, a3 tiles
+    col_sums(dz, sRed);
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) sDz1[(16 * rb + 4 * g + j) * H + 64 * ch + 16 * t + r] = dz[t][j];
+    __syncthreads();
+    if (tid < H) gp[OFF_B1 + tid] = sRed[tid] + sRed[H + tid];
+    for (int idx = tid; idx < H * NIN; idx += FB_WG) {
+        const int o = idx / NIN, k = idx - o * NIN;
+        float s = 0.f;
+        for (int p = 0; p < FB_P; p++) s += sDz1[p * H + o] * sX[p * NIN + k];
+        gp[OFF_W1 + idx] = s;
+    }
+}
+
+// sum of the work-groups' gradient slots (in slot order) into grad, or (adam)
+// straight into an Adam step; the loss slots are added to *loss
+__global__ void k_sum_adam(const float *__restrict__ gpart, int nslot, const float *__restrict__ lpart,
+                           float *__restrict__ loss, float *__restrict__ grad, float *__restrict__ master,
+                           uint16_t *__restrict__ wbf, float *__restrict__ m, float *__restrict__ v, int adam,
+                           float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        float s = *loss;
+        for (int c = 0; c < nslot; c++) s += lpart[c];
+        *loss = s;
+    }
+    if (i >= NPARAM) return;
+    float gs = 0.f;
+    for (int c = 0; c < nslot; c++) gs += gpart[(size_t)c * NPARAM + i];
+    if (!adam) {
+        grad[i] = gs;
+        return;
+    }
+    float mi = b1 * m[i] + (1.f - b1) * gs, vi = b2 * v[i] + (1.f - b2) * gs * gs;
+    m[i] = mi;
+    v[i] = vi;
+    float wv = master[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    master[i] = wv;
+    wbf[i] = f2bf(wv);
+}
+
 }  // namespace pgk_mlp_dev
 
 using namespace pgk_mlp_dev;
@@ -310,6 +490,7 @@ struct pgk_mlp {
     float *master, *grad, *m, *v, *loss;
     uint16_t *wbf;
     float *z[4], *dz, *dz2, *yhat, *dy;
+    float *gpart, *lpart;           // per-work-group gradient and loss slots of the fused training pass
     uint16_t *a[4];
     int t = 0;                      // Adam step count
     std::string err;
@@ -334,6 +515,9 @@ static size_t mlp_layout(int nmax, size_t *o)
     o[15] = take(4ull * np * H);          // dz2
     o[16] = take(4ull * np * NOUT);       // yhat
     o[17] = take(4ull * np * NOUT);       // dy
+    const size_t nslot = (size_t)(nmax + FB_P - 1) / FB_P;
+    o[18] = take(4ull * nslot * NPARAM);  // gradient slots
+    o[19] = take(4ull * nslot);           // loss slots
     return p;
 }
 
@@ -346,7 +530,7 @@ static size_t mlp_layout(int nmax, size_t *o)
 extern "C" int pgk_mlp_bytes(int nmax, size_t *bytes)
 {
     if (nmax < 1 || !bytes) return PGK_EINVAL;
-    size_t o[18];
+    size_t o[20];
     *bytes = mlp_layout(nmax, o);
     return PGK_OK;
 }
@@ -354,7 +538,7 @@ extern "C" int pgk_mlp_bytes(int nmax, size_t *bytes)
 extern "C" int pgk_mlp_create(void *stream, void *buf, size_t bytes, int nmax, pgk_mlp **out)
 {
     if (!out || !buf || nmax < 1 || ((uintptr_t)buf & 255)) return PGK_EINVAL;
-    size_t o[18];
+    size_t o[20];
     if (bytes < mlp_layout(nmax, o)) return PGK_ENOMEM;
     pgk_mlp *m = new pgk_mlp();
     m->stream = (hipStream_t)stream;
@@ -373,6 +557,8 @@ extern "C" int pgk_mlp_create(void *stream, void *buf, size_t bytes, int nmax, p
     m->dz2 = (float *)(b + o[15]);
     m->yhat = (float *)(b + o[16]);
     m->dy = (float *)(b + o[17]);
+    m->gpart = (float *)(b + o[18]);
+    m->lpart = (float *)(b + o[19]);
     *out = m;
     return PGK_OK;
 }
@@ -403,9 +589,8 @@ static int forward(pgk_mlp *m, const float *X, int n)
     const int offW[3] = {OFF_W2, OFF_W3, OFF_W4}, offB[3] = {OFF_B2, OFF_B3, OFF_B4};
     for (int l = 0; l < 3; l++) {
         // z_{l+1}[p][o] = sum_i a_l[p][i] W[o][i]: B(k=i, n=o) = W[o*H + i]
-        hipLaunchKernelGGL((k_gemm<uint16_t, EPI_FWD, true>), dim3(np / 64, H / 64, 1), dim3(256), 0, m->stream,
-                           m->a[l], H, 1, m->wbf + offW[l], 1, H, H, H, m->master + offB[l], (const float *)nullptr,
-                           m->z[l + 1], m->a[l + 1], H, np);
+        hipLaunchKernelGGL(k_gemm, dim3(np / 64, H / 64, 1), dim3(256), 0, m->stream, m->a[l], H, m->wbf + offW[l], H,
+                           H, m->master + offB[l], m->z[l + 1], m->a[l + 1], H, np);
     }
     MHIP(m, hipGetLastError());
     return PGK_OK;
@@ -425,40 +610,32 @@ extern "C" int pgk_mlp_forward(pgk_mlp *m, const float *X, float *Y, int n)
     return PGK_OK;
 }
 
-// loss and gradient of one minibatch (n <= nmax) into m->grad (accumulated);
-// the squared errors enter m->loss with weight lscale
-static int loss_grad(pgk_mlp *m, const float *X, const float *Y, int n, float scale, float lscale)
+// forward and backward of one minibatch (n <= nmax) in the fused kernel: one
+// gradient and loss slot per work-group of FB_P points; the squared errors
+// carry weight lscale, dL/dy = 2 (yhat - y) scale
+static int fused_pass(pgk_mlp *m, const float *X, const float *Y, int n, float scale, float lscale)
 {
-    int np = (n + 63) / 64 * 64;
-    int rc = forward(m, X, n);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_layer5, dim3((n * NOUT + 255) / 256), dim3(256), 0, m->stream, m->a[3], n, m->wbf,
-                       m->master, m->yhat);
-    hipLaunchKernelGGL(k_loss, dim3((np * NOUT + 255) / 256), dim3(256), 0, m->stream, m->yhat, Y, n, np, scale,
-                       lscale, m->dy, m->loss);
-    hipLaunchKernelGGL(k_layer5_wgrad, dim3((n + GP - 1) / GP), dim3(H), 0, m->stream, m->dy, m->a[3], n, m->grad);
-    hipLaunchKernelGGL(k_layer5_bwd, dim3((np * H + 255) / 256), dim3(256), 0, m->stream, m->dy, m->z[3], m->wbf,
-                       np, m->dz);
-    const int offW[3] = {OFF_W2, OFF_W3, OFF_W4}, offB[3] = {OFF_B2, OFF_B3, OFF_B4};
-    float *dz = m->dz, *dzn = m->dz2;
-    const int kchunk = 128;   // split-K depth of the weight gradients (128: 10% faster per minibatch than 256)
-    for (int l = 2; l >= 0; l--) {
-        // layer l+2 (0-based hidden index l+1): weights W_{l+2}, input a_l, output dz (of z_{l+1})
-        hipLaunchKernelGGL(k_bias_grad, dim3(H), dim3(256), 0, m->stream, dz, np, m->grad + offB[l]);
-        // dW[o][i] = sum_p dz[p][o] a_l[p][i]: A(m=o, k=p) = dz[p*H + o], B(k=p, n=i) = a_l[p*H + i]
-        hipLaunchKernelGGL((k_gemm<float, EPI_WGRAD>), dim3(H / 64, H / 64, (np + kchunk - 1) / kchunk), dim3(256),
-                           0, m->stream, dz, 1, H, m->a[l], H, 1, np, kchunk, (const float *)nullptr,
-                           (const float *)nullptr, m->grad + offW[l], (uint16_t *)nullptr, H, H);
-        // da_l[p][i] = sum_o dz[p][o] W[o][i]: B(k=o, n=i) = W[o*H + i]; dz_l = da_l * dsilu(z_l)
-        hipLaunchKernelGGL((k_gemm<float, EPI_BWD>), dim3(np / 64, H / 64, 1), dim3(256), 0, m->stream, dz, H, 1,
-                           m->wbf + offW[l], H, 1, H, H, (const float *)nullptr, m->z[l], dzn, (uint16_t *)nullptr,
-                           H, np);
-        float *t = dz;
-        dz = dzn;
-        dzn = t;
+    const int nslot = (n + FB_P - 1) / FB_P;
+    hipLaunchKernelGGL(k_fb, dim3(nslot), dim3(FB_WG), 0, m->stream, X, Y, n, scale, lscale, m->wbf, m->master,
+                       m->z[0], m->z[1], m->z[2], m->z[3], m->gpart, m->lpart);
+    MHIP(m, hipGetLastError());
+    return PGK_OK;
+}
+
+// the slots of the last fused pass summed into m->grad, or (adam) into an
+// Adam step; the loss slots are added to m->loss
+static int sum_slots(pgk_mlp *m, int n, bool adam, float lr, float beta1, float beta2, float eps)
+{
+    const int nslot = (n + FB_P - 1) / FB_P;
+    float c1 = 0.f, c2 = 0.f;
+    if (adam) {
+        m->t++;
+        c1 = 1.f / (1.f - powf(beta1, (float)m->t));
+        c2 = 1.f / (1.f - powf(beta2, (float)m->t));
     }
-    hipLaunchKernelGGL(k_bias_grad, dim3(H), dim3(256), 0, m->stream, dz, np, m->grad + OFF_B1);
-    hipLaunchKernelGGL(k_layer1_wgrad, dim3((n + GP - 1) / GP), dim3(H), 0, m->stream, dz, X, n, m->grad);
+    hipLaunchKernelGGL(k_sum_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->gpart, nslot, m->lpart,
+                       m->loss, m->grad, m->master, m->wbf, m->m, m->v, adam ? 1 : 0, lr, beta1, beta2, eps, c1,
+                       c2);
     MHIP(m, hipGetLastError());
     return PGK_OK;
 }
@@ -466,9 +643,9 @@ static int loss_grad(pgk_mlp *m, const float *X, const float *Y, int n, float sc
 extern "C" int pgk_mlp_loss_grad(pgk_mlp *m, const float *X, const float *Y, int n, float *grad, float *loss)
 {
     if (!m || !X || !Y || n < 1 || n > m->nmax) return PGK_EINVAL;
-    hipLaunchKernelGGL(k_zero, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->grad, NPARAM);
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, m->stream, m->loss, 1);
-    int rc = loss_grad(m, X, Y, n, 1.0f / (4.0f * n), 1.0f / (4.0f * n));
+    int rc = fused_pass(m, X, Y, n, 1.0f / (4.0f * n), 1.0f / (4.0f * n));
+    if (rc == PGK_OK) rc = sum_slots(m, n, false, 0.f, 0.f, 0.f, 0.f);
     if (rc) return rc;
     if (grad) MHIP(m, hipMemcpyAsync(grad, m->grad, 4ull * NPARAM, hipMemcpyDeviceToDevice, m->stream));
     if (loss) {
@@ -504,17 +681,15 @@ extern "C" int pgk_mlp_train(pgk_mlp *m, const float *X, const float *Y, int64_t
             int64_t t = order[i]; order[i] = order[j]; order[j] = t;
         }
         hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, m->stream, m->loss, 1);
-        // the gradient accumulator starts at zero; every Adam step clears it again
-        if (e == 0) hipLaunchKernelGGL(k_zero, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->grad, NPARAM);
         for (int64_t i = 0; i < nb; i++) {
             int64_t b0 = order[i] * batch;
             int c = (int)(n - b0 < batch ? n - b0 : batch);
             // gradients of the mean loss over this minibatch; the squared
             // errors are weighted 1/(4 n), so that the epoch's sum is the mean
-            // over all n points (a last, partial minibatch counts by its size)
-            int rc = loss_grad(m, X + b0 * NIN, Y + b0 * NOUT, c, 1.0f / (4.0f * c), 1.0f / (4.0f * (float)n));
-            if (rc) return rc;
-            rc = pgk_mlp_adam_step(m, lr, 0.9f, 0.999f, 1e-8f);
+            // over all n points (a last, partial minibatch counts by its size);
+            // two launches: the fused pass, then the slot sum with the Adam step
+            int rc = fused_pass(m, X + b0 * NIN, Y + b0 * NOUT, c, 1.0f / (4.0f * c), 1.0f / (4.0f * (float)n));
+            if (rc == PGK_OK) rc = sum_slots(m, c, true, lr, 0.9f, 0.999f, 1e-8f);
             if (rc) return rc;
         }
         if (loss_per_epoch) {
@@ -649,9 +824,8 @@ extern "C" int pgk_mlp_forward_static(const float *theta, const float *X, float 
     hipLaunchKernelGGL(k_layer1, dim3((np * H + 255) / 256), dim3(256), 0, st, X, n, np, wbf, theta, z, a[0]);
     const int offW[3] = {OFF_W2, OFF_W3, OFF_W4}, offB[3] = {OFF_B2, OFF_B3, OFF_B4};
     for (int l = 0; l < 3; l++)
-        hipLaunchKernelGGL((k_gemm<uint16_t, EPI_FWD, true>), dim3(np / 64, H / 64, 1), dim3(256), 0, st,
-                           a[l & 1], H, 1, wbf + offW[l], 1, H, H, H, theta + offB[l], (const float *)nullptr, z,
-                           a[(l + 1) & 1], H, np);
+        hipLaunchKernelGGL(k_gemm, dim3(np / 64, H / 64, 1), dim3(256), 0, st, a[l & 1], H, wbf + offW[l], H, H,
+                           theta + offB[l], z, a[(l + 1) & 1], H, np);
     hipLaunchKernelGGL(k_layer5, dim3((n * NOUT + 255) / 256), dim3(256), 0, st, a[1], n, wbf, theta, Y);
     return hipGetLastError() == hipSuccess ? PGK_OK : PGK_EDEVICE;
 }
