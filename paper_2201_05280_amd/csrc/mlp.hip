@@ -145,7 +145,18 @@ __global__ void k_zero(float *__restrict__ a, int n)
     if (i < n) a[i] = 0.f;
 }
 
-__global__ void k_adam(float *__restrict__ master, uint16_t *__restrict__ wbf, float *__restrict__ grad,
+// bf16 copy of parameter i; the three 128x128 weights also go transposed into
+// wbfT ([layer][in][out], the operand layout of the backward products)
+__device__ inline void put_bf(uint16_t *__restrict__ wbf, uint16_t *__restrict__ wbfT, int i, float w)
+{
+    const uint16_t b = f2bf(w);
+    wbf[i] = b;
+    const int rel = i - OFF_W2, li = rel / (H * H + H), rem = rel - li * (H * H + H);
+    if (rel >= 0 && li < 3 && rem < H * H) wbfT[li * H * H + (rem % H) * H + rem / H] = b;
+}
+
+__global__ void k_adam(float *__restrict__ master, uint16_t *__restrict__ wbf, uint16_t *__restrict__ wbfT,
+                       float *__restrict__ grad,
                        float *__restrict__ m, float *__restrict__ v, float lr, float b1, float b2, float eps,
                        float c1, float c2)
 {
@@ -157,18 +168,18 @@ __global__ void k_adam(float *__restrict__ master, uint16_t *__restrict__ wbf, f
     v[i] = vi;
     float w = master[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
     master[i] = w;
-    wbf[i] = f2bf(w);
+    put_bf(wbf, wbfT, i, w);
     grad[i] = 0.f;
 }
 
 __global__ void k_set_params(const float *__restrict__ theta, float *__restrict__ master,
-                             uint16_t *__restrict__ wbf, float *__restrict__ grad, float *__restrict__ m,
-                             float *__restrict__ v)
+                             uint16_t *__restrict__ wbf, uint16_t *__restrict__ wbfT, float *__restrict__ grad,
+                             float *__restrict__ m, float *__restrict__ v)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NPARAM) return;
     master[i] = theta[i];
-    wbf[i] = f2bf(theta[i]);
+    put_bf(wbf, wbfT, i, theta[i]);
     grad[i] = 0.f;
     m[i] = 0.f;
     v[i] = 0.f;
@@ -182,18 +193,19 @@ __global__ void k_to_bf16(const float *__restrict__ theta, uint16_t *__restrict_
 }
 
 // bf16 copies of the master weights and a cleared gradient after a load
-__global__ void k_refresh(const float *__restrict__ master, uint16_t *__restrict__ wbf, float *__restrict__ grad)
+__global__ void k_refresh(const float *__restrict__ master, uint16_t *__restrict__ wbf, uint16_t *__restrict__ wbfT,
+                          float *__restrict__ grad)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NPARAM) return;
-    wbf[i] = f2bf(master[i]);
+    put_bf(wbf, wbfT, i, master[i]);
     grad[i] = 0.f;
 }
 
 
 // ---------------------------------------------------------------------------
 // Fused training pass of one minibatch: forward, loss and backward of FB_P
-// points per work-group of four waves, all five layers, the 128x128 products
+// points per work-group of eight waves, all five layers, the 128x128 products
 // on gfx950's 16x16x32 bf16 matrix instructions.  Activations and dL/dz stay
 // in LDS, row-major ([point][unit], A operands of the products over units) and
 // transposed ([unit][point], operands of the weight gradients, a product over
@@ -207,9 +219,10 @@ __global__ void k_refresh(const float *__restrict__ master, uint16_t *__restrict
 //
 // Fragment layout of the 16x16x32 product D = A B (lane l, r = l % 16,
 // g = l / 16): A holds A[r][8g .. 8g+7], B holds B[8g .. 8g+7][r], D holds
-// D[4g + j][r], j = 0..3.
+// D[4g + j][r], j = 0..3.  A [point][unit] tile is split over the waves as
+// rows 16 (w % 2) .. + 16 and columns 32 (w / 2) .. + 32 (two 16-wide tiles).
 constexpr int FB_P = 32;          // points per work-group
-constexpr int FB_WG = 256;
+constexpr int FB_WG = 512;        // eight waves
 constexpr int RS = H + 8;         // row stride (bf16) of [point][unit] arrays: rows 16 bytes apart mod 256
 constexpr int TS = FB_P + 8;      // row stride of [unit][point] arrays
 constexpr int WS = H + 8;         // row stride of the staged 128x128 weight
@@ -222,52 +235,51 @@ __device__ inline v8bf ld8(const uint16_t *p) { return __builtin_bit_cast(v8bf, 
 
 __device__ inline v4f32 mma(v8bf a, v8bf b, v4f32 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 
-// W[o][i] (bf16, 128x128 at wbf + off) into sW, row-major or transposed
-template <bool TRANSPOSE>
-__device__ inline void stage_w(const uint16_t *__restrict__ wbf, int off, uint16_t *sW)
+// a 128x128 bf16 matrix (row-major, 128 per row) into sW with row stride WS
+__device__ inline void stage_w(const uint16_t *__restrict__ src, uint16_t *sW)
 {
     for (int c = threadIdx.x; c < H * H / 8; c += FB_WG) {
         const int o = c >> 4, i0 = (c & 15) * 8;
-        const v4u v = *reinterpret_cast<const v4u *>(wbf + off + o * H + i0);
-        if (!TRANSPOSE) {
-            *reinterpret_cast<v4u *>(sW + o * WS + i0) = v;
-        } else {
-            const uint16_t *e = reinterpret_cast<const uint16_t *>(&v);
-#pragma unroll
-            for (int k = 0; k < 8; k++) sW[(i0 + k) * WS + o] = e[k];
-        }
+        *reinterpret_cast<v4u *>(sW + o * WS + i0) = *reinterpret_cast<const v4u *>(src + o * H + i0);
     }
 }
 
 // column sums over the work-group's points of a [point][unit] tile held in the
-// product layout (wave w: rows 16 (w % 2) + 4g + j, columns 64 (w / 2) + 16 t
-// + r) into red[2][H] (one row per half of the points)
+// product layout into red[2][H] (one row per half of the points)
 __device__ inline void col_sums(const v4f32 *d, float *red)
 {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, g = l >> 4;
 #pragma unroll
-    for (int t = 0; t < 4; t++) {
+    for (int t = 0; t < 2; t++) {
         float s = (d[t][0] + d[t][1]) + (d[t][2] + d[t][3]);
         s += __shfl_xor(s, 16, 64);
         s += __shfl_xor(s, 32, 64);
-        if (g == 0) red[(w & 1) * H + 64 * (w >> 1) + 16 * t + r] = s;
+        if (g == 0) red[(w & 1) * H + 32 * (w >> 1) + 16 * t + r] = s;
     }
+}
+
+// four bf16 of consecutive points as one 8-byte store into a [unit][point] array
+__device__ inline void put4(uint16_t *dst, const uint16_t *b4)
+{
+    *reinterpret_cast<uint2 *>(dst) = make_uint2(b4[0] | ((uint32_t)b4[1] << 16), b4[2] | ((uint32_t)b4[3] << 16));
 }
 
 __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const float *__restrict__ Y, int n,
                                               float scale, float lscale, const uint16_t *__restrict__ wbf,
-                                              const float *__restrict__ master, float *__restrict__ z1,
-                                              float *__restrict__ z2, float *__restrict__ z3, float *__restrict__ z4,
-                                              float *__restrict__ gpart, float *__restrict__ lpart)
+                                              const uint16_t *__restrict__ wbfT, const float *__restrict__ master,
+                                              float *__restrict__ z1, float *__restrict__ z2, float *__restrict__ z3,
+                                              float *__restrict__ z4, float *__restrict__ gpart,
+                                              float *__restrict__ lpart)
 {
     __shared__ __align__(16) uint16_t sW[H * WS];
     __shared__ __align__(16) uint16_t sRow[2][FB_P * RS];
     __shared__ __align__(16) uint16_t sT[4][H * TS];
     __shared__ __align__(16) uint16_t sDzT[H * TS];
     __shared__ float sX[FB_P * NIN], sDy[FB_P * NOUT], sRed[2 * H], sLoss[FB_WG / 64];
+    __shared__ float sW1[H * NIN], sW5[NOUT * H], sB[4 * H + NOUT];   // bf16 weights as float; biases
 
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, r = l & 15, g = l >> 4;
-    const int rb = w & 1, ch = w >> 1;                 // rows 16 rb .., columns 64 ch ..
+    const int rb = w & 1, cq = w >> 1;                 // rows 16 rb .., columns 32 cq ..
     const int p0 = blockIdx.x * FB_P;
     float *gp = gpart + (size_t)blockIdx.x * NPARAM;
     // the 128x128 layers li = 0, 1, 2 (W2, W3, W4) and their biases; z of layer li + 1
@@ -278,25 +290,28 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
                   "layer offsets");
 
     for (int i = tid; i < FB_P * NIN; i += FB_WG) sX[i] = p0 + i / NIN < n ? X[(size_t)p0 * NIN + i] : 0.f;
-    stage_w<false>(wbf, OFF_W2, sW);
+    for (int i = tid; i < H * NIN; i += FB_WG) sW1[i] = bf2f(wbf[OFF_W1 + i]);
+    for (int i = tid; i < NOUT * H; i += FB_WG) sW5[i] = bf2f(wbf[OFF_W5 + i]);
+    for (int i = tid; i < 4 * H + NOUT; i += FB_WG)
+        sB[i] = master[i < H ? OFF_B1 + i : i < 4 * H ? offB(i / H - 1) + i % H : OFF_B5 + i - 4 * H];
+    stage_w(wbf + OFF_W2, sW);
     __syncthreads();
 
     // layer 1 (vector ALUs): z1 = W1 x + b1
 #pragma unroll
-    for (int t = 0; t < 4; t++) {
-        const int o = 64 * ch + 16 * t + r;
+    for (int t = 0; t < 2; t++) {
+        const int o = 32 * cq + 16 * t + r;
         uint16_t a4[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             const int p = 16 * rb + 4 * g + j;
-            float z = master[OFF_B1 + o];
-            for (int k = 0; k < NIN; k++) z += bf2f(wbf[OFF_W1 + o * NIN + k]) * sX[p * NIN + k];
+            float z = sB[o];
+            for (int k = 0; k < NIN; k++) z += sW1[o * NIN + k] * sX[p * NIN + k];
             z1[(size_t)(p0 + p) * H + o] = z;
             a4[j] = f2bf(silu(z));
             sRow[0][p * RS + o] = a4[j];
         }
-        *reinterpret_cast<uint2 *>(&sT[0][o * TS + 16 * rb + 4 * g]) =
-            make_uint2(a4[0] | ((uint32_t)a4[1] << 16), a4[2] | ((uint32_t)a4[3] << 16));
+        put4(&sT[0][o * TS + 16 * rb + 4 * g], a4);
     }
     __syncthreads();
 
@@ -304,22 +319,20 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
     for (int li = 0; li < 3; li++) {
         const uint16_t *in = sRow[li & 1];
         uint16_t *out = sRow[(li + 1) & 1];
-        v4f32 acc[4];
-#pragma unroll
-        for (int t = 0; t < 4; t++) acc[t] = v4f32{0.f, 0.f, 0.f, 0.f};
+        v4f32 acc[2] = {v4f32{0.f, 0.f, 0.f, 0.f}, v4f32{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
         for (int ks = 0; ks < H / 32; ks++) {
             const v8bf a = ld8(in + (16 * rb + r) * RS + 32 * ks + 8 * g);
 #pragma unroll
-            for (int t = 0; t < 4; t++) acc[t] = mma(a, ld8(sW + (64 * ch + 16 * t + r) * WS + 32 * ks + 8 * g), acc[t]);
+            for (int t = 0; t < 2; t++) acc[t] = mma(a, ld8(sW + (32 * cq + 16 * t + r) * WS + 32 * ks + 8 * g), acc[t]);
         }
         __syncthreads();
-        if (li < 2) stage_w<false>(wbf, offW(li + 1), sW);
+        if (li < 2) stage_w(wbf + offW(li + 1), sW);
         float *zo = zb(li + 1);
 #pragma unroll
-        for (int t = 0; t < 4; t++) {
-            const int o = 64 * ch + 16 * t + r;
-            const float bias = master[offB(li) + o];
+        for (int t = 0; t < 2; t++) {
+            const int o = 32 * cq + 16 * t + r;
+            const float bias = sB[(li + 1) * H + o];
             uint16_t a4[4];
 #pragma unroll
             for (int j = 0; j < 4; j++) {
@@ -329,27 +342,38 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
                 a4[j] = f2bf(silu(z));
                 out[p * RS + o] = a4[j];
             }
-            *reinterpret_cast<uint2 *>(&sT[li + 1][o * TS + 16 * rb + 4 * g]) =
-                make_uint2(a4[0] | ((uint32_t)a4[1] << 16), a4[2] | ((uint32_t)a4[3] << 16));
+            put4(&sT[li + 1][o * TS + 16 * rb + 4 * g], a4);
         }
         __syncthreads();
     }
     const uint16_t *a4s = sRow[1];                    // a4, row-major
 
-    // layer 5, the loss and dL/dy = 2 (y - Y) scale (zero on padding rows)
-    float lt = 0.f;
-    if (tid < FB_P * NOUT) {
-        const int p = tid >> 2, o5 = tid & 3;
-        float y = master[OFF_B5 + o5];
-        for (int k = 0; k < H; k++) y += bf2f(wbf[OFF_W5 + o5 * H + k]) * bf2f(a4s[p * RS + k]);
-        const float d = p0 + p < n ? y - Y[(size_t)(p0 + p) * NOUT + o5] : 0.f;
-        sDy[tid] = 2.f * d * scale;
-        lt = d * d * lscale;
+    // layer 5, the loss and dL/dy = 2 (y - Y) scale (zero on padding rows):
+    // thread pairs split the 128-term sums
+    {
+        const int q = tid >> 1, p = q >> 2, o5 = q & 3, h = tid & 1;
+        float y = 0.f;
+        if (q < FB_P * NOUT)
+            for (int k = 64 * h; k < 64 * h + 64; k++) y += sW5[o5 * H + k] * bf2f(a4s[p * RS + k]);
+        y += __shfl_xor(y, 1, 64);
+        float lt = 0.f;
+        if (q < FB_P * NOUT) {
+            y += sB[4 * H + o5];
+            const float d = p0 + p < n ? y - Y[(size_t)(p0 + p) * NOUT + o5] : 0.f;
+            if (h == 0) {
+                sDy[q] = 2.f * d * scale;
+                lt = d * d * lscale;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) lt += __shfl_xor(lt, off, 64);
+        if (l == 0) sLoss[w] = lt;
     }
-    for (int off = 32; off > 0; off >>= 1) lt += __shfl_xor(lt, off, 64);
-    if (l == 0) sLoss[w] = lt;
     __syncthreads();
-    if (tid == 0) lpart[blockIdx.x] = (sLoss[0] + sLoss[1]) + (sLoss[2] + sLoss[3]);
+    if (tid == 0) {
+        float s = 0.f;
+        for (int i = 0; i < FB_WG / 64; i++) s += sLoss[i];
+        lpart[blockIdx.x] = s;
+    }
     // dW5 = dy^T a4, db5 = sum dy
     for (int idx = tid; idx < NOUT * H; idx += FB_WG) {
         const int o5 = idx >> 7, k = idx & (H - 1);
@@ -363,15 +387,15 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
         gp[OFF_B5 + tid] = s;
     }
     // dz4 = (dy W5) * dsilu(z4), in the product layout
-    v4f32 dz[4];
+    v4f32 dz[2];
 #pragma unroll
-    for (int t = 0; t < 4; t++) {
-        const int o = 64 * ch + 16 * t + r;
+    for (int t = 0; t < 2; t++) {
+        const int o = 32 * cq + 16 * t + r;
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             const int p = 16 * rb + 4 * g + j;
             float da = 0.f;
-            for (int o5 = 0; o5 < NOUT; o5++) da += sDy[p * NOUT + o5] * bf2f(wbf[OFF_W5 + o5 * H + o]);
+            for (int o5 = 0; o5 < NOUT; o5++) da += sDy[p * NOUT + o5] * sW5[o5 * H + o];
             dz[t][j] = da * dsilu(z4[(size_t)(p0 + p) * H + o]);
         }
     }
@@ -382,53 +406,42 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
     for (int li = 2; li >= 0; li--) {
         col_sums(dz, sRed);
 #pragma unroll
-        for (int t = 0; t < 4; t++) {
-            const int o = 64 * ch + 16 * t + r;
+        for (int t = 0; t < 2; t++) {
+            const int o = 32 * cq + 16 * t + r;
             uint16_t b4[4];
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 b4[j] = f2bf(dz[t][j]);
                 dzRow[(16 * rb + 4 * g + j) * RS + o] = b4[j];
             }
-            *reinterpret_cast<uint2 *>(&sDzT[o * TS + 16 * rb + 4 * g]) =
-                make_uint2(b4[0] | ((uint32_t)b4[1] << 16), b4[2] | ((uint32_t)b4[3] << 16));
+            put4(&sDzT[o * TS + 16 * rb + 4 * g], b4);
         }
-        stage_w<true>(wbf, offW(li), sW);
+        stage_w(wbfT + li * H * H, sW);               // W transposed: sW[i][o] = W[o][i]
         __syncthreads();
         if (tid < H) gp[offB(li) + tid] = sRed[tid] + sRed[H + tid];
-        // dW[o][i] = sum_p r(dz)[p][o] a[p][i]: wave w takes o in [32 w, 32 w + 32)
+        // dW[o][i] = sum_p r(dz)[p][o] a[p][i]: wave w takes o in [16 w, 16 w + 16)
         {
             const uint16_t *aT = sT[li];
-            v4f32 acc[2][8];
+            const v8bf a = ld8(sDzT + (16 * w + r) * TS + 8 * g);
 #pragma unroll
-            for (int mi = 0; mi < 2; mi++) {
-                const v8bf a = ld8(sDzT + (32 * w + 16 * mi + r) * TS + 8 * g);
+            for (int nt = 0; nt < 8; nt++) {
+                const v4f32 c = mma(a, ld8(aT + (16 * nt + r) * TS + 8 * g), v4f32{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
-                for (int nt = 0; nt < 8; nt++)
-                    acc[mi][nt] = mma(a, ld8(aT + (16 * nt + r) * TS + 8 * g), v4f32{0.f, 0.f, 0.f, 0.f});
+                for (int j = 0; j < 4; j++) gp[offW(li) + (16 * w + 4 * g + j) * H + 16 * nt + r] = c[j];
             }
-#pragma unroll
-            for (int mi = 0; mi < 2; mi++)
-#pragma unroll
-                for (int nt = 0; nt < 8; nt++)
-#pragma unroll
-                    for (int j = 0; j < 4; j++)
-                        gp[offW(li) + (32 * w + 16 * mi + 4 * g + j) * H + 16 * nt + r] = acc[mi][nt][j];
         }
         // da[p][i] = sum_o r(dz)[p][o] W[o][i]; dz of the layer below = da dsilu(z)
-        v4f32 acc[4];
-#pragma unroll
-        for (int t = 0; t < 4; t++) acc[t] = v4f32{0.f, 0.f, 0.f, 0.f};
+        v4f32 acc[2] = {v4f32{0.f, 0.f, 0.f, 0.f}, v4f32{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
         for (int ks = 0; ks < H / 32; ks++) {
             const v8bf a = ld8(dzRow + (16 * rb + r) * RS + 32 * ks + 8 * g);
 #pragma unroll
-            for (int t = 0; t < 4; t++) acc[t] = mma(a, ld8(sW + (64 * ch + 16 * t + r) * WS + 32 * ks + 8 * g), acc[t]);
+            for (int t = 0; t < 2; t++) acc[t] = mma(a, ld8(sW + (32 * cq + 16 * t + r) * WS + 32 * ks + 8 * g), acc[t]);
         }
         const float *zi = zb(li);
 #pragma unroll
-        for (int t = 0; t < 4; t++) {
-            const int o = 64 * ch + 16 * t + r;
+        for (int t = 0; t < 2; t++) {
+            const int o = 32 * cq + 16 * t + r;
 #pragma unroll
             for (int j = 0; j < 4; j++) dz[t][j] = acc[t][j] * dsilu(zi[(size_t)(p0 + 16 * rb + 4 * g + j) * H + o]);
         }
@@ -439,9 +452,9 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
     float *sDz1 = reinterpret_cast<float *>(sT[1]);   // [FB_P][H] fp32 over the free a2, a3 tiles
     col_sums(dz, sRed);
 #pragma unroll
-    for (int t = 0; t < 4; t++)
+    for (int t = 0; t < 2; t++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) sDz1[(16 * rb + 4 * g + j) * H + 64 * ch + 16 * t + r] = dz[t][j];
+        for (int j = 0; j < 4; j++) sDz1[(16 * rb + 4 * g + j) * H + 32 * cq + 16 * t + r] = dz[t][j];
     __syncthreads();
     if (tid < H) gp[OFF_B1 + tid] = sRed[tid] + sRed[H + tid];
     for (int idx = tid; idx < H * NIN; idx += FB_WG) {
@@ -456,8 +469,9 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
 // straight into an Adam step; the loss slots are added to *loss
 __global__ void k_sum_adam(const float *__restrict__ gpart, int nslot, const float *__restrict__ lpart,
                            float *__restrict__ loss, float *__restrict__ grad, float *__restrict__ master,
-                           uint16_t *__restrict__ wbf, float *__restrict__ m, float *__restrict__ v, int adam,
-                           float lr, float b1, float b2, float eps, float c1, float c2)
+                           uint16_t *__restrict__ wbf, uint16_t *__restrict__ wbfT, float *__restrict__ m,
+                           float *__restrict__ v, int adam, float lr, float b1, float b2, float eps, float c1,
+                           float c2)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
@@ -466,8 +480,17 @@ __global__ void k_sum_adam(const float *__restrict__ gpart, int nslot, const flo
         *loss = s;
     }
     if (i >= NPARAM) return;
-    float gs = 0.f;
-    for (int c = 0; c < nslot; c++) gs += gpart[(size_t)c * NPARAM + i];
+    // eight running sums (slot c into sum c % 8), so that eight loads are in
+    // flight, combined in a fixed tree: the same bits on every run
+    float s8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int c = 0;
+    for (; c + 8 <= nslot; c += 8)
+#pragma unroll
+        for (int u = 0; u < 8; u++) s8[u] += gpart[(size_t)(c + u) * NPARAM + i];
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+        if (c + u < nslot) s8[u] += gpart[(size_t)(c + u) * NPARAM + i];
+    const float gs = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
     if (!adam) {
         grad[i] = gs;
         return;
@@ -477,7 +500,7 @@ __global__ void k_sum_adam(const float *__restrict__ gpart, int nslot, const flo
     v[i] = vi;
     float wv = master[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
     master[i] = wv;
-    wbf[i] = f2bf(wv);
+    put_bf(wbf, wbfT, i, wv);
 }
 
 }  // namespace pgk_mlp_dev
@@ -491,6 +514,7 @@ struct pgk_mlp {
     uint16_t *wbf;
     float *z[4], *dz, *dz2, *yhat, *dy;
     float *gpart, *lpart;           // per-work-group gradient and loss slots of the fused training pass
+    uint16_t *wbfT;                 // transposed bf16 copies of W2, W3, W4
     uint16_t *a[4];
     int t = 0;                      // Adam step count
     std::string err;
@@ -518,6 +542,7 @@ static size_t mlp_layout(int nmax, size_t *o)
     const size_t nslot = (size_t)(nmax + FB_P - 1) / FB_P;
     o[18] = take(4ull * nslot * NPARAM);  // gradient slots
     o[19] = take(4ull * nslot);           // loss slots
+    o[20] = take(2ull * 3 * H * H);       // transposed bf16 W2, W3, W4
     return p;
 }
 
@@ -530,7 +555,7 @@ static size_t mlp_layout(int nmax, size_t *o)
 extern "C" int pgk_mlp_bytes(int nmax, size_t *bytes)
 {
     if (nmax < 1 || !bytes) return PGK_EINVAL;
-    size_t o[20];
+    size_t o[21];
     *bytes = mlp_layout(nmax, o);
     return PGK_OK;
 }
@@ -538,7 +563,7 @@ extern "C" int pgk_mlp_bytes(int nmax, size_t *bytes)
 extern "C" int pgk_mlp_create(void *stream, void *buf, size_t bytes, int nmax, pgk_mlp **out)
 {
     if (!out || !buf || nmax < 1 || ((uintptr_t)buf & 255)) return PGK_EINVAL;
-    size_t o[20];
+    size_t o[21];
     if (bytes < mlp_layout(nmax, o)) return PGK_ENOMEM;
     pgk_mlp *m = new pgk_mlp();
     m->stream = (hipStream_t)stream;
@@ -559,6 +584,7 @@ extern "C" int pgk_mlp_create(void *stream, void *buf, size_t bytes, int nmax, p
     m->dy = (float *)(b + o[17]);
     m->gpart = (float *)(b + o[18]);
     m->lpart = (float *)(b + o[19]);
+    m->wbfT = (uint16_t *)(b + o[20]);
     *out = m;
     return PGK_OK;
 }
@@ -567,7 +593,7 @@ extern "C" int pgk_mlp_set_params(pgk_mlp *m, const float *theta)
 {
     if (!m || !theta) return PGK_EINVAL;
     hipLaunchKernelGGL(k_set_params, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, theta, m->master,
-                       m->wbf, m->grad, m->m, m->v);
+                       m->wbf, m->wbfT, m->grad, m->m, m->v);
     MHIP(m, hipGetLastError());
     m->t = 0;
     return PGK_OK;
@@ -616,8 +642,8 @@ extern "C" int pgk_mlp_forward(pgk_mlp *m, const float *X, float *Y, int n)
 static int fused_pass(pgk_mlp *m, const float *X, const float *Y, int n, float scale, float lscale)
 {
     const int nslot = (n + FB_P - 1) / FB_P;
-    hipLaunchKernelGGL(k_fb, dim3(nslot), dim3(FB_WG), 0, m->stream, X, Y, n, scale, lscale, m->wbf, m->master,
-                       m->z[0], m->z[1], m->z[2], m->z[3], m->gpart, m->lpart);
+    hipLaunchKernelGGL(k_fb, dim3(nslot), dim3(FB_WG), 0, m->stream, X, Y, n, scale, lscale, m->wbf, m->wbfT,
+                       m->master, m->z[0], m->z[1], m->z[2], m->z[3], m->gpart, m->lpart);
     MHIP(m, hipGetLastError());
     return PGK_OK;
 }
@@ -634,8 +660,8 @@ static int sum_slots(pgk_mlp *m, int n, bool adam, float lr, float beta1, float 
         c2 = 1.f / (1.f - powf(beta2, (float)m->t));
     }
     hipLaunchKernelGGL(k_sum_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->gpart, nslot, m->lpart,
-                       m->loss, m->grad, m->master, m->wbf, m->m, m->v, adam ? 1 : 0, lr, beta1, beta2, eps, c1,
-                       c2);
+                       m->loss, m->grad, m->master, m->wbf, m->wbfT, m->m, m->v, adam ? 1 : 0, lr, beta1, beta2,
+                       eps, c1, c2);
     MHIP(m, hipGetLastError());
     return PGK_OK;
 }
@@ -660,8 +686,8 @@ extern "C" int pgk_mlp_adam_step(pgk_mlp *m, float lr, float beta1, float beta2,
     if (!m) return PGK_EINVAL;
     m->t++;
     float c1 = 1.f / (1.f - powf(beta1, (float)m->t)), c2 = 1.f / (1.f - powf(beta2, (float)m->t));
-    hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->master, m->wbf, m->grad, m->m,
-                       m->v, lr, beta1, beta2, eps, c1, c2);
+    hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->master, m->wbf, m->wbfT,
+                       m->grad, m->m, m->v, lr, beta1, beta2, eps, c1, c2);
     MHIP(m, hipGetLastError());
     return PGK_OK;
 }
@@ -718,7 +744,7 @@ extern "C" int pgk_mlp_set_state(pgk_mlp *m, const float *master, const float *a
 {
     if (!m || !master || !adam_m || !adam_v || t < 0 || t > INT32_MAX) return PGK_EINVAL;
     hipLaunchKernelGGL(k_set_params, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, master, m->master,
-                       m->wbf, m->grad, m->m, m->v);
+                       m->wbf, m->wbfT, m->grad, m->m, m->v);
     MHIP(m, hipGetLastError());
     MHIP(m, hipMemcpyAsync(m->m, adam_m, 4ull * NPARAM, hipMemcpyDeviceToDevice, m->stream));
     MHIP(m, hipMemcpyAsync(m->v, adam_v, 4ull * NPARAM, hipMemcpyDeviceToDevice, m->stream));
@@ -762,7 +788,8 @@ extern "C" int pgk_mlp_load(pgk_mlp *m, const char *path)
     MHIP(m, hipMemcpyAsync(m->master, h.data(), 4ull * NPARAM, hipMemcpyHostToDevice, m->stream));
     MHIP(m, hipMemcpyAsync(m->m, h.data() + NPARAM, 4ull * NPARAM, hipMemcpyHostToDevice, m->stream));
     MHIP(m, hipMemcpyAsync(m->v, h.data() + 2 * NPARAM, 4ull * NPARAM, hipMemcpyHostToDevice, m->stream));
-    hipLaunchKernelGGL(k_refresh, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->master, m->wbf, m->grad);
+    hipLaunchKernelGGL(k_refresh, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->master, m->wbf, m->wbfT,
+                       m->grad);
     MHIP(m, hipGetLastError());
     MHIP(m, hipStreamSynchronize(m->stream));   // h is freed on return
     m->t = (int)hdr[1];
