@@ -284,7 +284,8 @@ int pgk_kernel_times(pgk_ctx *ctx, double ms[PGK_NKERNEL], int64_t launches[PGK_
  * temperature turns non-positive or non-finite (DIVERGED), or at max_steps.
  * Work-group size and K come from a built-in autotuner unless set: at the
  * start of a run and again whenever the number of running cases has halved,
- * one chunk of each candidate is timed on the live state (or the choice for
+ * one chunk of each candidate (work-groups of 256 or 512 threads, E2 batches
+ * 256 only; K = 32, 64, 128 or 256 steps) is timed on the live state (or the choice for
  * that mix is read from the JSON cache, $PGK_TUNE_CACHE or
  * ~/.cache/pgk_tune.json, keyed by the running case count and the longest
  * running case).

@@ -837,7 +837,7 @@ static int tune(pgk_batch *b, int variant, int &wg, int &K)
         K = hit->second.second;
         return PGK_OK;
     }
-    const int cand[][2] = {{256, 32}, {512, 32}, {256, 128}, {512, 128}};
+    const int cand[][2] = {{256, 32}, {512, 32}, {256, 64}, {512, 64}, {256, 128}, {512, 128}, {256, 256}, {512, 256}};
     double best = 1e300;
     int bw = 0, bk = 0, rc;
     hipEvent_t e0, e1;

@@ -205,23 +205,27 @@ __global__ void k_refresh(const float *__restrict__ master, uint16_t *__restrict
 
 // ---------------------------------------------------------------------------
 // Fused training pass of one minibatch: forward, loss and backward of FB_P
-// points per work-group of eight waves, all five layers, the 128x128 products
-// on gfx950's 16x16x32 bf16 matrix instructions.  Activations and dL/dz stay
-// in LDS, row-major ([point][unit], A operands of the products over units) and
-// transposed ([unit][point], operands of the weight gradients, a product over
-// points); z goes to global memory and is read back by the lane that wrote it.
-// Each work-group writes its share of every gradient and of the loss to its
-// own slot of a partial buffer; k_sum_adam adds the slots in a fixed order (so
-// the gradient is the same bits on every run) and applies Adam.  The bf16
-// roundings are those of the tiled path and the reference: weights,
-// activations entering layers 2-5, and dL/dz of layers 2-4 where it meets a
-// weight or an activation; x, dL/dy and dL/dz1 stay in fp32.
+// points per work-group of eight waves, all five layers, the products over
+// units on gfx950's 16x16x32 bf16 matrix instructions and the weight
+// gradients (a product over the work-group's 16 points) on 16x16x16 ones.
+// Activations and dL/dz stay in LDS, row-major ([point][unit], A operands of
+// the products over units) and transposed ([unit][point], operands of the
+// weight gradients); z goes to global memory and is read back by the lane
+// that wrote it.  Each work-group writes its share of every gradient and of
+// the loss to its own slot of a partial buffer; k_sum_adam adds the slots in a
+// fixed order (the gradient is the same bits on every run) and applies Adam.
+// The bf16 roundings are those of the reference: weights, activations
+// entering layers 2-5, and dL/dz of layers 2-4 where it meets a weight or an
+// activation; x, dL/dy and dL/dz1 stay in fp32.  SiLU and its derivative take
+// the hardware exponential and reciprocal here (a few fp32 ulps; the
+// activations they feed are rounded to bf16).
 //
-// Fragment layout of the 16x16x32 product D = A B (lane l, r = l % 16,
-// g = l / 16): A holds A[r][8g .. 8g+7], B holds B[8g .. 8g+7][r], D holds
-// D[4g + j][r], j = 0..3.  A [point][unit] tile is split over the waves as
-// rows 16 (w % 2) .. + 16 and columns 32 (w / 2) .. + 32 (two 16-wide tiles).
-constexpr int FB_P = 32;          // points per work-group
+// Fragment layouts (lane l, r = l % 16, g = l / 16): 16x16x32, A holds
+// A[r][8g .. 8g+7], B holds B[8g .. 8g+7][r]; 16x16x16, A[r][4g .. 4g+3],
+// B[4g .. 4g+3][r]; both give D[4g + j][r], j = 0..3.  A [point][unit] tile
+// (16 x 128) is split over the waves by columns: wave w holds units 16 w ..
+// 16 w + 15.
+constexpr int FB_P = 16;          // points per work-group
 constexpr int FB_WG = 512;        // eight waves
 constexpr int RS = H + 8;         // row stride (bf16) of [point][unit] arrays: rows 16 bytes apart mod 256
 constexpr int TS = FB_P + 8;      // row stride of [unit][point] arrays
@@ -233,7 +237,15 @@ typedef unsigned v4u __attribute__((ext_vector_type(4)));
 // eight bf16 at a 16-byte aligned address as one matrix operand
 __device__ inline v8bf ld8(const uint16_t *p) { return __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u *>(p)); }
 
-__device__ inline v4f32 mma(v8bf a, v8bf b, v4f32 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+__device__ inline v4f32 mma32(v8bf a, v8bf b, v4f32 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+
+__device__ inline float silu_fast(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+
+__device__ inline float dsilu_fast(float z)
+{
+    float s = __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
 
 // a 128x128 bf16 matrix (row-major, 128 per row) into sW with row stride WS
 __device__ inline void stage_w(const uint16_t *__restrict__ src, uint16_t *sW)
@@ -245,17 +257,24 @@ __device__ inline void stage_w(const uint16_t *__restrict__ src, uint16_t *sW)
 }
 
 // column sums over the work-group's points of a [point][unit] tile held in the
-// product layout into red[2][H] (one row per half of the points)
-__device__ inline void col_sums(const v4f32 *d, float *red)
+// product layout into red[H]
+__device__ inline void col_sums(v4f32 d, float *red)
 {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, g = l >> 4;
-#pragma unroll
-    for (int t = 0; t < 2; t++) {
-        float s = (d[t][0] + d[t][1]) + (d[t][2] + d[t][3]);
-        s += __shfl_xor(s, 16, 64);
-        s += __shfl_xor(s, 32, 64);
-        if (g == 0) red[(w & 1) * H + 32 * (w >> 1) + 16 * t + r] = s;
-    }
+    float s = (d[0] + d[1]) + (d[2] + d[3]);
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+    if (g == 0) red[16 * w + r] = s;
+}
+
+// work-group barrier that orders LDS only: the global stores of the fused pass
+// (z, read back later by the lane that wrote it, and the gradient slots, read by
+// the next kernel) stay in flight across it
+__device__ inline void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // four bf16 of consecutive points as one 8-byte store into a [unit][point] array
@@ -275,11 +294,11 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
     __shared__ __align__(16) uint16_t sRow[2][FB_P * RS];
     __shared__ __align__(16) uint16_t sT[4][H * TS];
     __shared__ __align__(16) uint16_t sDzT[H * TS];
-    __shared__ float sX[FB_P * NIN], sDy[FB_P * NOUT], sRed[2 * H], sLoss[FB_WG / 64];
+    __shared__ float sX[FB_P * NIN], sDy[FB_P * NOUT], sRed[H], sLoss[FB_WG / 64];
     __shared__ float sW1[H * NIN], sW5[NOUT * H], sB[4 * H + NOUT];   // bf16 weights as float; biases
 
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, r = l & 15, g = l >> 4;
-    const int rb = w & 1, cq = w >> 1;                 // rows 16 rb .., columns 32 cq ..
+    const int o = 16 * w + r;                          // this lane's unit in the product layout
     const int p0 = blockIdx.x * FB_P;
     float *gp = gpart + (size_t)blockIdx.x * NPARAM;
     // the 128x128 layers li = 0, 1, 2 (W2, W3, W4) and their biases; z of layer li + 1
@@ -295,91 +314,81 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
     for (int i = tid; i < 4 * H + NOUT; i += FB_WG)
         sB[i] = master[i < H ? OFF_B1 + i : i < 4 * H ? offB(i / H - 1) + i % H : OFF_B5 + i - 4 * H];
     stage_w(wbf + OFF_W2, sW);
-    __syncthreads();
+    lds_barrier();
 
     // layer 1 (vector ALUs): z1 = W1 x + b1
-#pragma unroll
-    for (int t = 0; t < 2; t++) {
-        const int o = 32 * cq + 16 * t + r;
+    {
         uint16_t a4[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
-            const int p = 16 * rb + 4 * g + j;
+            const int p = 4 * g + j;
             float z = sB[o];
             for (int k = 0; k < NIN; k++) z += sW1[o * NIN + k] * sX[p * NIN + k];
             z1[(size_t)(p0 + p) * H + o] = z;
-            a4[j] = f2bf(silu(z));
+            a4[j] = f2bf(silu_fast(z));
             sRow[0][p * RS + o] = a4[j];
         }
-        put4(&sT[0][o * TS + 16 * rb + 4 * g], a4);
+        put4(&sT[0][o * TS + 4 * g], a4);
     }
-    __syncthreads();
+    lds_barrier();
 
     // layers 2-4 on the matrix cores
     for (int li = 0; li < 3; li++) {
         const uint16_t *in = sRow[li & 1];
         uint16_t *out = sRow[(li + 1) & 1];
-        v4f32 acc[2] = {v4f32{0.f, 0.f, 0.f, 0.f}, v4f32{0.f, 0.f, 0.f, 0.f}};
+        v4f32 acc = v4f32{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ks = 0; ks < H / 32; ks++) {
-            const v8bf a = ld8(in + (16 * rb + r) * RS + 32 * ks + 8 * g);
-#pragma unroll
-            for (int t = 0; t < 2; t++) acc[t] = mma(a, ld8(sW + (32 * cq + 16 * t + r) * WS + 32 * ks + 8 * g), acc[t]);
-        }
-        __syncthreads();
+        for (int ks = 0; ks < H / 32; ks++)
+            acc = mma32(ld8(in + r * RS + 32 * ks + 8 * g), ld8(sW + o * WS + 32 * ks + 8 * g), acc);
+        lds_barrier();
         if (li < 2) stage_w(wbf + offW(li + 1), sW);
         float *zo = zb(li + 1);
+        const float bias = sB[(li + 1) * H + o];
+        uint16_t a4[4];
 #pragma unroll
-        for (int t = 0; t < 2; t++) {
-            const int o = 32 * cq + 16 * t + r;
-            const float bias = sB[(li + 1) * H + o];
-            uint16_t a4[4];
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int p = 16 * rb + 4 * g + j;
-                const float z = acc[t][j] + bias;
-                zo[(size_t)(p0 + p) * H + o] = z;
-                a4[j] = f2bf(silu(z));
-                out[p * RS + o] = a4[j];
-            }
-            put4(&sT[li + 1][o * TS + 16 * rb + 4 * g], a4);
+        for (int j = 0; j < 4; j++) {
+            const int p = 4 * g + j;
+            const float z = acc[j] + bias;
+            zo[(size_t)(p0 + p) * H + o] = z;
+            a4[j] = f2bf(silu_fast(z));
+            out[p * RS + o] = a4[j];
         }
-        __syncthreads();
+        put4(&sT[li + 1][o * TS + 4 * g], a4);
+        lds_barrier();
     }
     const uint16_t *a4s = sRow[1];                    // a4, row-major
 
     // layer 5, the loss and dL/dy = 2 (y - Y) scale (zero on padding rows):
-    // thread pairs split the 128-term sums
+    // eight threads per output split the 128-term sums
     {
-        const int q = tid >> 1, p = q >> 2, o5 = q & 3, h = tid & 1;
+        const int q = tid >> 3, p = q >> 2, o5 = q & 3, h = tid & 7;
         float y = 0.f;
-        if (q < FB_P * NOUT)
-            for (int k = 64 * h; k < 64 * h + 64; k++) y += sW5[o5 * H + k] * bf2f(a4s[p * RS + k]);
+        for (int k = 16 * h; k < 16 * h + 16; k++) y += sW5[o5 * H + k] * bf2f(a4s[p * RS + k]);
         y += __shfl_xor(y, 1, 64);
+        y += __shfl_xor(y, 2, 64);
+        y += __shfl_xor(y, 4, 64);
+        y += sB[4 * H + o5];
+        const float d = p0 + p < n ? y - Y[(size_t)(p0 + p) * NOUT + o5] : 0.f;
         float lt = 0.f;
-        if (q < FB_P * NOUT) {
-            y += sB[4 * H + o5];
-            const float d = p0 + p < n ? y - Y[(size_t)(p0 + p) * NOUT + o5] : 0.f;
-            if (h == 0) {
-                sDy[q] = 2.f * d * scale;
-                lt = d * d * lscale;
-            }
+        if (h == 0) {
+            sDy[q] = 2.f * d * scale;
+            lt = d * d * lscale;
         }
         for (int off = 32; off > 0; off >>= 1) lt += __shfl_xor(lt, off, 64);
         if (l == 0) sLoss[w] = lt;
     }
-    __syncthreads();
+    lds_barrier();
     if (tid == 0) {
         float s = 0.f;
         for (int i = 0; i < FB_WG / 64; i++) s += sLoss[i];
         lpart[blockIdx.x] = s;
     }
     // dW5 = dy^T a4, db5 = sum dy
-    for (int idx = tid; idx < NOUT * H; idx += FB_WG) {
-        const int o5 = idx >> 7, k = idx & (H - 1);
+    {
+        const int o5 = tid >> 7, k = tid & (H - 1);
         float s = 0.f;
         for (int p = 0; p < FB_P; p++) s += sDy[p * NOUT + o5] * bf2f(a4s[p * RS + k]);
-        gp[OFF_W5 + idx] = s;
+        gp[OFF_W5 + tid] = s;
     }
     if (tid < NOUT) {
         float s = 0.f;
@@ -387,110 +396,111 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
         gp[OFF_B5 + tid] = s;
     }
     // dz4 = (dy W5) * dsilu(z4), in the product layout
-    v4f32 dz[2];
+    v4f32 dz;
 #pragma unroll
-    for (int t = 0; t < 2; t++) {
-        const int o = 32 * cq + 16 * t + r;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int p = 16 * rb + 4 * g + j;
-            float da = 0.f;
-            for (int o5 = 0; o5 < NOUT; o5++) da += sDy[p * NOUT + o5] * sW5[o5 * H + o];
-            dz[t][j] = da * dsilu(z4[(size_t)(p0 + p) * H + o]);
-        }
+    for (int j = 0; j < 4; j++) {
+        const int p = 4 * g + j;
+        float da = 0.f;
+        for (int o5 = 0; o5 < NOUT; o5++) da += sDy[p * NOUT + o5] * sW5[o5 * H + o];
+        dz[j] = da * dsilu_fast(z4[(size_t)(p0 + p) * H + o]);
     }
-    __syncthreads();
+    lds_barrier();
 
     // layers 4, 3, 2: weight and bias gradients, then dL/dz of the layer below
     uint16_t *dzRow = sRow[0];
     for (int li = 2; li >= 0; li--) {
         col_sums(dz, sRed);
-#pragma unroll
-        for (int t = 0; t < 2; t++) {
-            const int o = 32 * cq + 16 * t + r;
+        {
             uint16_t b4[4];
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                b4[j] = f2bf(dz[t][j]);
-                dzRow[(16 * rb + 4 * g + j) * RS + o] = b4[j];
+                b4[j] = f2bf(dz[j]);
+                dzRow[(4 * g + j) * RS + o] = b4[j];
             }
-            put4(&sDzT[o * TS + 16 * rb + 4 * g], b4);
+            put4(&sDzT[o * TS + 4 * g], b4);
         }
         stage_w(wbfT + li * H * H, sW);               // W transposed: sW[i][o] = W[o][i]
-        __syncthreads();
-        if (tid < H) gp[offB(li) + tid] = sRed[tid] + sRed[H + tid];
-        // dW[o][i] = sum_p r(dz)[p][o] a[p][i]: wave w takes o in [16 w, 16 w + 16)
+        lds_barrier();
+        if (tid < H) gp[offB(li) + tid] = sRed[tid];
+        // dW[o][i] = sum_p r(dz)[p][o] a[p][i] over the 16 points: wave w takes o in [16 w, 16 w + 16)
         {
             const uint16_t *aT = sT[li];
-            const v8bf a = ld8(sDzT + (16 * w + r) * TS + 8 * g);
+            const v4i16 a = load4_bf(sDzT + o * TS + 4 * g);
 #pragma unroll
             for (int nt = 0; nt < 8; nt++) {
-                const v4f32 c = mma(a, ld8(aT + (16 * nt + r) * TS + 8 * g), v4f32{0.f, 0.f, 0.f, 0.f});
+                const v4f32 c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, load4_bf(aT + (16 * nt + r) * TS + 4 * g),
+                                                                           v4f32{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
 #pragma unroll
                 for (int j = 0; j < 4; j++) gp[offW(li) + (16 * w + 4 * g + j) * H + 16 * nt + r] = c[j];
             }
         }
         // da[p][i] = sum_o r(dz)[p][o] W[o][i]; dz of the layer below = da dsilu(z)
-        v4f32 acc[2] = {v4f32{0.f, 0.f, 0.f, 0.f}, v4f32{0.f, 0.f, 0.f, 0.f}};
+        v4f32 acc = v4f32{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ks = 0; ks < H / 32; ks++) {
-            const v8bf a = ld8(dzRow + (16 * rb + r) * RS + 32 * ks + 8 * g);
-#pragma unroll
-            for (int t = 0; t < 2; t++) acc[t] = mma(a, ld8(sW + (32 * cq + 16 * t + r) * WS + 32 * ks + 8 * g), acc[t]);
-        }
+        for (int ks = 0; ks < H / 32; ks++)
+            acc = mma32(ld8(dzRow + r * RS + 32 * ks + 8 * g), ld8(sW + o * WS + 32 * ks + 8 * g), acc);
         const float *zi = zb(li);
 #pragma unroll
-        for (int t = 0; t < 2; t++) {
-            const int o = 32 * cq + 16 * t + r;
-#pragma unroll
-            for (int j = 0; j < 4; j++) dz[t][j] = acc[t][j] * dsilu(zi[(size_t)(p0 + 16 * rb + 4 * g + j) * H + o]);
-        }
-        __syncthreads();
+        for (int j = 0; j < 4; j++) dz[j] = acc[j] * dsilu_fast(zi[(size_t)(p0 + 4 * g + j) * H + o]);
+        lds_barrier();
     }
 
     // layer 1: db1 = sum dz1, dW1 = dz1^T x (both in fp32)
     float *sDz1 = reinterpret_cast<float *>(sT[1]);   // [FB_P][H] fp32 over the free a2, a3 tiles
     col_sums(dz, sRed);
 #pragma unroll
-    for (int t = 0; t < 2; t++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) sDz1[(16 * rb + 4 * g + j) * H + 32 * cq + 16 * t + r] = dz[t][j];
-    __syncthreads();
-    if (tid < H) gp[OFF_B1 + tid] = sRed[tid] + sRed[H + tid];
+    for (int j = 0; j < 4; j++) sDz1[(4 * g + j) * H + o] = dz[j];
+    lds_barrier();
+    if (tid < H) gp[OFF_B1 + tid] = sRed[tid];
     for (int idx = tid; idx < H * NIN; idx += FB_WG) {
-        const int o = idx / NIN, k = idx - o * NIN;
+        const int oo = idx / NIN, k = idx - oo * NIN;
         float s = 0.f;
-        for (int p = 0; p < FB_P; p++) s += sDz1[p * H + o] * sX[p * NIN + k];
+        for (int p = 0; p < FB_P; p++) s += sDz1[p * H + oo] * sX[p * NIN + k];
         gp[OFF_W1 + idx] = s;
     }
 }
 
-// sum of the work-groups' gradient slots (in slot order) into grad, or (adam)
-// straight into an Adam step; the loss slots are added to *loss
-__global__ void k_sum_adam(const float *__restrict__ gpart, int nslot, const float *__restrict__ lpart,
-                           float *__restrict__ loss, float *__restrict__ grad, float *__restrict__ master,
-                           uint16_t *__restrict__ wbf, uint16_t *__restrict__ wbfT, float *__restrict__ m,
-                           float *__restrict__ v, int adam, float lr, float b1, float b2, float eps, float c1,
-                           float c2)
+// Sum of the work-groups' gradient slots into grad, or (adam) straight into an
+// Adam step; the loss slots are added to *loss.  Eight threads per parameter
+// (slots c = part mod 8, sixteen loads in flight each), combined in a fixed
+// order: the same bits on every run.
+constexpr int SA_P = 32;          // parameters per work-group of 256
+__global__ __launch_bounds__(256) void k_sum_adam(const float *__restrict__ gpart, int nslot,
+                                                  const float *__restrict__ lpart, float *__restrict__ loss,
+                                                  float *__restrict__ grad, float *__restrict__ master,
+                                                  uint16_t *__restrict__ wbf, uint16_t *__restrict__ wbfT,
+                                                  float *__restrict__ m, float *__restrict__ v, int adam, float lr,
+                                                  float b1, float b2, float eps, float c1, float c2)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
+    __shared__ float red[8][SA_P];
+    const int q = threadIdx.x & (SA_P - 1), part = threadIdx.x >> 5;
+    const int i = blockIdx.x * SA_P + q;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         float s = *loss;
         for (int c = 0; c < nslot; c++) s += lpart[c];
         *loss = s;
     }
-    if (i >= NPARAM) return;
-    // eight running sums (slot c into sum c % 8), so that eight loads are in
-    // flight, combined in a fixed tree: the same bits on every run
-    float s8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    int c = 0;
-    for (; c + 8 <= nslot; c += 8)
+    float s16[16];
 #pragma unroll
-        for (int u = 0; u < 8; u++) s8[u] += gpart[(size_t)(c + u) * NPARAM + i];
+    for (int u = 0; u < 16; u++) s16[u] = 0.f;
+    if (i < NPARAM) {
+        int c = part;
+        for (; c + 8 * 15 < nslot; c += 128)
 #pragma unroll
-    for (int u = 0; u < 8; u++)
-        if (c + u < nslot) s8[u] += gpart[(size_t)(c + u) * NPARAM + i];
-    const float gs = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+            for (int u = 0; u < 16; u++) s16[u] += gpart[(size_t)(c + 8 * u) * NPARAM + i];
+#pragma unroll
+        for (int u = 0; u < 16; u++)
+            if (c + 8 * u < nslot) s16[u] += gpart[(size_t)(c + 8 * u) * NPARAM + i];
+    }
+#pragma unroll
+    for (int h = 8; h > 0; h >>= 1)
+#pragma unroll
+        for (int u = 0; u < h; u++) s16[u] += s16[u + h];
+    red[part][q] = s16[0];
+    __syncthreads();
+    if (part != 0 || i >= NPARAM) return;
+    const float gs = ((red[0][q] + red[1][q]) + (red[2][q] + red[3][q])) +
+                     ((red[4][q] + red[5][q]) + (red[6][q] + red[7][q]));
     if (!adam) {
         grad[i] = gs;
         return;
@@ -659,7 +669,7 @@ static int sum_slots(pgk_mlp *m, int n, bool adam, float lr, float beta1, float 
         c1 = 1.f / (1.f - powf(beta1, (float)m->t));
         c2 = 1.f / (1.f - powf(beta2, (float)m->t));
     }
-    hipLaunchKernelGGL(k_sum_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->gpart, nslot, m->lpart,
+    hipLaunchKernelGGL(k_sum_adam, dim3((NPARAM + SA_P - 1) / SA_P), dim3(256), 0, m->stream, m->gpart, nslot, m->lpart,
                        m->loss, m->grad, m->master, m->wbf, m->wbfT, m->m, m->v, adam ? 1 : 0, lr, beta1, beta2,
                        eps, c1, c2);
     MHIP(m, hipGetLastError());
