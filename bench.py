@@ -357,6 +357,48 @@ def shock_summary(max_steps=60000):
     return out
 
 
+def mlp_train_summary(n=291240, epochs=100, batch=2048):
+    """Training rate of the warm-start network: n seeded synthetic points with
+    the sweep's input shape (six features uniform in [-1, 1], four smooth
+    targets), He-uniform start, epochs of minibatch Adam at 2e-3 / 5e-4 /
+    1.25e-4 (40 / 30 / 30 epochs, the sweep's schedule).  The flop count per
+    point is the forward product's 100,864 plus twice that for the backward
+    pass (data and weight gradients)."""
+    import numpy as np
+    import torch
+
+    from paper_2201_05280_amd.inputs import mlp_init
+    from paper_2201_05280_amd.mlp import MLP
+
+    rng = np.random.default_rng(220105282)
+    X = rng.uniform(-1, 1, (n, 6)).astype(np.float32)
+    Y = np.stack([np.sin(2 * X[:, 0]) * X[:, 1], X[:, 2] ** 2 - 0.3, np.cos(X[:, 3] + X[:, 4]),
+                  0.5 * X[:, 5] * X[:, 0]], 1).astype(np.float32)
+    m = MLP(nmax=max(8192, batch))
+    m.set_params(mlp_init(220105280))
+    m.train(X[:8192], Y[:8192], epochs=1, batch=batch, lr=1e-3, seed=1)   # untimed warm-up
+    m.set_params(mlp_init(220105280))
+    stages = [(2e-3, 40), (5e-4, 30), (1.25e-4, 30)]
+    total = sum(e for _, e in stages)
+    stages = [(lr, e * epochs // total) for lr, e in stages]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    for k, (lr, ep) in enumerate(stages):
+        losses += list(m.train(X, Y, epochs=ep, batch=batch, lr=lr, seed=7 + k))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    m.close()
+    ep = sum(e for _, e in stages)
+    nmb = ep * ((n + batch - 1) // batch)
+    flop = 3 * 100864 * n * ep
+    return {"points": n, "epochs": ep, "minibatch": batch, "seconds": round(dt, 3),
+            "us_per_minibatch": round(dt / nmb * 1e6, 1), "points_per_s": round(n * ep / dt),
+            "TFLOPs": round(flop / dt / 1e12, 2), "bf16_peak_TFLOPs": 2500.0,
+            "loss_first_last": [float("%.4g" % losses[0]), float("%.4g" % losses[-1])],
+            "data": "synthetic, seeded"}
+
+
 def sweep(args, extra=None):
     """Time to residual 1e-8 of a seeded mix of 1D cases (Couette layers and
     normal-shock lines): plain (one case at a time), batched cold, batched
@@ -692,6 +734,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep experiment")
     ap.add_argument("--no-shock", action="store_true", help="skip the normal-shock lines")
     ap.add_argument("--shock", action="store_true", help="run only the normal-shock lines")
+    ap.add_argument("--mlp-train", action="store_true", help="run only the warm-start network's training rate")
     ap.add_argument("--sweep-n", type=int, default=512, help="held-out cases (seed 220105280)")
     ap.add_argument("--sweep-train", type=int, default=4096, help="training cases (seed 220105281)")
     ap.add_argument("--sweep-lmin", type=int, default=256)
@@ -733,6 +776,9 @@ def main():
         return
     if args.shock:
         print(json.dumps(shock_summary()), flush=True)
+        return
+    if args.mlp_train:
+        print(json.dumps({"mlp_train": mlp_train_summary()}), flush=True)
         return
 
     import torch
@@ -827,7 +873,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)
     # the side experiments report into the line; a failure in one of them is
     # recorded there and never costs the headline measurement
-    for key, skip, fn in (("shear_wave", False, shear_wave_summary), ("shock", args.no_shock, shock_summary)):
+    for key, skip, fn in (("shear_wave", False, shear_wave_summary), ("shock", args.no_shock, shock_summary),
+                          ("mlp_train", args.no_sweep, mlp_train_summary)):
         if skip:
             continue
         try:

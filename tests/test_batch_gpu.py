@@ -373,3 +373,47 @@ def test_in_kernel_residual_equals_host_two_read_residual():
         assert h > 1e-12
         assert abs(resid[c] - h) <= 1e-12 * h, (c, resid[c], h)
     b2.close()
+
+
+def test_single_grid_runs_stop_at_the_batched_step():
+    """The plain path (one case at a time through the single-grid solver, the
+    residual taken from two moment reads at the end of every chunk of K steps)
+    stops each case at the step where the batched kernel stopped it with the
+    same K: the two evaluate one residual definition on the same states."""
+    import paper_2201_05280_amd as pgk
+    from paper_2201_05280_amd import _lib
+    from paper_2201_05280_amd import cases as C
+    from paper_2201_05280_amd.batch import Batch
+    cs, _ = C.sweep_cases(4, 11, L_range=(24, 64), Kn_range=(0.05, 0.1), shock_fraction=0.0)
+    K, tol = 32, 1e-6
+    f = C.cold_fields(cs)
+    b = Batch(C.to_batch_cases(cs))
+    b.init(f["rho"], f["u"], f["thT"], f["thR"])
+    b.config(256, K)
+    steps, resid, status = b.run(200000, tol)
+    b.close()
+    assert (status == _lib.CASE_CONVERGED).all(), status
+    for c, case in enumerate(cs):
+        p = case["params"]
+        s = pgk.Solver(case["L"], 1, 1, precision=pgk.FP64, bc_x=(pgk.WALL, pgk.WALL))
+        s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+        s.set_bc_x(0, 1.0, (0, 0, 0), TH0)
+        s.set_bc_x(1, 1.0, (0, case["U"], 0), TH0)
+        g = C.cold_fields([case])
+        s.init(g["rho"], g["u"], g["thT"], g["thR"])
+        n, r = 0, 1.0
+        while r > tol and n < 200000:
+            s.step(K - 1)
+            a = s.moments()
+            s.step(1)
+            bm = s.moments()
+            n += K
+            r = 0.0
+            for k, v in (("rho", None), ("u", 1), ("thT", None), ("thR", None)):
+                x0 = a[k] if v is None else a[k][v]
+                x1 = bm[k] if v is None else bm[k][v]
+                r = max(r, float(np.linalg.norm(x1 - x0) / np.linalg.norm(x1)))
+        s.close()
+        print("case", c, "L", case["L"], "batched", int(steps[c]), resid[c], "single grid", n, r)
+        assert n == int(steps[c]), (c, n, steps[c])
+        assert abs(r - resid[c]) <= 1e-9 * resid[c]
