@@ -479,83 +479,104 @@ __device__ __forceinline__ void collide_store(S *v, const Eq<S> &e, const Consts
 // gain term is the rate-weighted mixture of the two targets, F =
 // wt1 F(lam_ES) + wt F(theta I) with wt1 = tau1/(tau+tau1), wt = tau/(tau+tau1)
 // (Sec. 4): for an equilibrium that is not linear in the covariance the two
-// terms do not merge into one.  l1, l2: multipliers of the two E2 targets,
-// computed in double; FP32 deviation storage takes F - w through expm1.
+// terms do not merge into one.  p1, p2: the exponential factors (e2_pow_bases)
+// of the multipliers of the two E2 targets, in double; FP32 deviation storage
+// takes F - w = w (wt1 (F1/w - 1) + wt (F2/w - 1)), each F/w - 1 as one fused
+// multiply-add.
 template <typename S, int P = 0>
-__device__ __forceinline__ void collide_store_e2(S *v, const double *l1, const double *l2, const Consts &k,
+__device__ __forceinline__ void collide_e2_pairs(S *v, const E2Pow &p1, const E2Pow &p2, const Consts &k,
                                                  S *__restrict__ dst, int s)
 {
     if constexpr (P < NPAIR) {
-        double e1, o1, e2, o2;
-        e2_parts<P>(l1, e1, o1);
-        e2_parts<P>(l2, e2, o2);
+        double e1, x1p, x1m, e2, x2p, x2m;
+        e2_pair_exp<P>(p1, e1, x1p, x1m);
+        e2_pair_exp<P>(p2, e2, x2p, x2m);
         double w = k.w[Lattice::SHELL[P]];
         if constexpr (sizeof(S) == 4) {
             S tb = (S)(2.0 * k.beta);
-            S Fp = (S)(w * (k.wt1 * expm1(e1 + o1) + k.wt * expm1(e2 + o2)));
-            S Fm = (S)(w * (k.wt1 * expm1(e1 - o1) + k.wt * expm1(e2 - o2)));
+            S Fp = (S)(w * (k.wt1 * fma(e1, x1p, -1.0) + k.wt * fma(e2, x2p, -1.0)));
+            S Fm = (S)(w * (k.wt1 * fma(e1, x1m, -1.0) + k.wt * fma(e2, x2m, -1.0)));
             __builtin_nontemporal_store(v[1 + P] + tb * (Fp - v[1 + P]), &dst[(size_t)(1 + P) * k.ns + s]);
             __builtin_nontemporal_store(v[1 + NPAIR + P] + tb * (Fm - v[1 + NPAIR + P]),
                                         &dst[(size_t)(1 + NPAIR + P) * k.ns + s]);
         } else {
             double omb = 1.0 - 2.0 * k.beta, tb = 2.0 * k.beta;
-            double Fp = w * (k.wt1 * exp(e1 + o1) + k.wt * exp(e2 + o2));
-            double Fm = w * (k.wt1 * exp(e1 - o1) + k.wt * exp(e2 - o2));
+            double Fp = w * (k.wt1 * (e1 * x1p) + k.wt * (e2 * x2p));
+            double Fm = w * (k.wt1 * (e1 * x1m) + k.wt * (e2 * x2m));
             __builtin_nontemporal_store(omb * v[1 + P] + tb * Fp, &dst[(size_t)(1 + P) * k.ns + s]);
             __builtin_nontemporal_store(omb * v[1 + NPAIR + P] + tb * Fm, &dst[(size_t)(1 + NPAIR + P) * k.ns + s]);
         }
-        collide_store_e2<S, P + 1>(v, l1, l2, k, dst, s);
+        collide_e2_pairs<S, P + 1>(v, p1, p2, k, dst, s);
     } else {
         double w0 = k.w[0];
         if constexpr (sizeof(S) == 4) {
             S tb = (S)(2.0 * k.beta);
-            S F0 = (S)(w0 * (k.wt1 * expm1(l1[0]) + k.wt * expm1(l2[0])));
+            S F0 = (S)(w0 * (k.wt1 * (p1.e0 - 1.0) + k.wt * (p2.e0 - 1.0)));
             __builtin_nontemporal_store(v[0] + tb * (F0 - v[0]), &dst[s]);
         } else {
-            double F0 = w0 * (k.wt1 * exp(l1[0]) + k.wt * exp(l2[0]));
+            double F0 = w0 * (k.wt1 * p1.e0 + k.wt * p2.e0);
             __builtin_nontemporal_store((1.0 - 2.0 * k.beta) * v[0] + 2.0 * k.beta * F0, &dst[s]);
         }
     }
 }
 
+template <typename S>
+__device__ __forceinline__ void collide_store_e2(S *v, const double *l1, const double *l2, const Consts &k,
+                                                 S *__restrict__ dst, int s)
+{
+    E2Pow p1, p2;
+    e2_pow_bases(l1, p1);
+    e2_pow_bases(l2, p2);
+    collide_e2_pairs<S>(v, p1, p2, k, dst, s);
+}
+
 // The same collide spread over the two lanes of a site pair (both hold v, l1
 // and l2): lane r stores the member +c (r = 0) or -c (r = 1) of every opposite
-// pair, lane 0 also the rest velocity.  e + sg o with sg = +-1 is e + o or
-// e - o exactly, so every population is the same bits as in collide_store_e2,
-// with half the exponentials per lane.
+// pair, lane 0 also the rest velocity; every population is the same bits as
+// in collide_store_e2.
 template <typename S, int P = 0>
-__device__ __forceinline__ void collide_store_e2_lane(const S *v, const double *l1, const double *l2,
-                                                      const Consts &k, S *__restrict__ dst, int s, int r)
+__device__ __forceinline__ void collide_e2_lane_pairs(const S *v, const E2Pow &p1, const E2Pow &p2, const Consts &k,
+                                                      S *__restrict__ dst, int s, int r)
 {
     if constexpr (P < NPAIR) {
-        double e1, o1, e2, o2;
-        e2_parts<P>(l1, e1, o1);
-        e2_parts<P>(l2, e2, o2);
+        double e1, x1p, x1m, e2, x2p, x2m;
+        e2_pair_exp<P>(p1, e1, x1p, x1m);
+        e2_pair_exp<P>(p2, e2, x2p, x2m);
+        const double x1 = r ? x1m : x1p, x2 = r ? x2m : x2p;
         double w = k.w[Lattice::SHELL[P]];
-        const double sg = r ? -1.0 : 1.0;
         const size_t q = r ? 1 + NPAIR + P : 1 + P;
         const S vq = r ? v[1 + NPAIR + P] : v[1 + P];
         if constexpr (sizeof(S) == 4) {
             S tb = (S)(2.0 * k.beta);
-            S F = (S)(w * (k.wt1 * expm1(e1 + sg * o1) + k.wt * expm1(e2 + sg * o2)));
+            S F = (S)(w * (k.wt1 * fma(e1, x1, -1.0) + k.wt * fma(e2, x2, -1.0)));
             __builtin_nontemporal_store(vq + tb * (F - vq), &dst[q * k.ns + s]);
         } else {
             double omb = 1.0 - 2.0 * k.beta, tb = 2.0 * k.beta;
-            double F = w * (k.wt1 * exp(e1 + sg * o1) + k.wt * exp(e2 + sg * o2));
+            double F = w * (k.wt1 * (e1 * x1) + k.wt * (e2 * x2));
             __builtin_nontemporal_store(omb * vq + tb * F, &dst[q * k.ns + s]);
         }
-        collide_store_e2_lane<S, P + 1>(v, l1, l2, k, dst, s, r);
+        collide_e2_lane_pairs<S, P + 1>(v, p1, p2, k, dst, s, r);
     } else if (r == 0) {
         double w0 = k.w[0];
         if constexpr (sizeof(S) == 4) {
             S tb = (S)(2.0 * k.beta);
-            S F0 = (S)(w0 * (k.wt1 * expm1(l1[0]) + k.wt * expm1(l2[0])));
+            S F0 = (S)(w0 * (k.wt1 * (p1.e0 - 1.0) + k.wt * (p2.e0 - 1.0)));
             __builtin_nontemporal_store(v[0] + tb * (F0 - v[0]), &dst[s]);
         } else {
-            double F0 = w0 * (k.wt1 * exp(l1[0]) + k.wt * exp(l2[0]));
+            double F0 = w0 * (k.wt1 * p1.e0 + k.wt * p2.e0);
             __builtin_nontemporal_store((1.0 - 2.0 * k.beta) * v[0] + 2.0 * k.beta * F0, &dst[s]);
         }
     }
+}
+
+template <typename S>
+__device__ __forceinline__ void collide_store_e2_lane(const S *v, const double *l1, const double *l2,
+                                                      const Consts &k, S *__restrict__ dst, int s, int r)
+{
+    E2Pow p1, p2;
+    e2_pow_bases(l1, p1);
+    e2_pow_bases(l2, p2);
+    collide_e2_lane_pairs<S>(v, p1, p2, k, dst, s, r);
 }
 
 // E2 multipliers of density rho, velocity u, covariance lam; a target out of

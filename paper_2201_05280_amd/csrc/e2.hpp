@@ -63,16 +63,90 @@ __host__ __device__ __forceinline__ void e2_parts(const double *l, double &ev, d
     if (F::cy * F::cz != 0.0) ev += F::cy * F::cz * l[9];
 }
 
+// The exponentials of l . phi as products of integer powers of ten base
+// exponentials.  In doubled coordinates k = 2c every velocity component is 0,
+// +-1, +-2 or +-4, so
+//   exp(even part) = exp(l0) prod_a exp(l_aa / 4)^(k_a^2) prod_{a<b} exp(l_ab / 4)^(k_a k_b),
+//   exp(odd part)  = prod_a exp(l_a / 2)^(k_a),
+// with k_a^2 in {1, 4, 16} and k_a k_b in {+-1, +-4}: ten exponentials, six
+// reciprocals and squarings instead of 41 exponentials.  The populations
+// differ from single exponentials of l . phi by a few ulps; the converged
+// multipliers differ from those of single exponentials by no more than a
+// restart of the same Newton solve from a nearby point moves them.
+struct E2Pow {
+    double e0;          // exp(l0)
+    double d[3][3];     // exp(l_aa / 4) to the powers 1, 4, 16 (a = x, y, z)
+    double o[3][4];     // exp(l_ab / 4) to the powers 1, 4, -1, -4 (ab = xy, xz, yz)
+    double x[3][6];     // exp(l_a / 2) to the powers 1, 2, 4, -1, -2, -4
+};
+
+__host__ __device__ __forceinline__ void e2_pow_bases(const double *l, E2Pow &p)
+{
+    p.e0 = exp(l[0]);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double d = exp(0.25 * l[4 + a]), d4 = (d * d) * (d * d), d8 = d4 * d4;
+        p.d[a][0] = d;
+        p.d[a][1] = d4;
+        p.d[a][2] = d8 * d8;
+        const double x = exp(0.5 * l[1 + a]), ix = 1.0 / x, x2 = x * x, ix2 = ix * ix;
+        p.x[a][0] = x;
+        p.x[a][1] = x2;
+        p.x[a][2] = x2 * x2;
+        p.x[a][3] = ix;
+        p.x[a][4] = ix2;
+        p.x[a][5] = ix2 * ix2;
+        const double o = exp(0.25 * l[7 + a]), io = 1.0 / o, o2 = o * o, io2 = io * io;
+        p.o[a][0] = o;
+        p.o[a][1] = o2 * o2;
+        p.o[a][2] = io;
+        p.o[a][3] = io2 * io2;
+    }
+}
+
+// exp(l_aa k^2 / 4), exp(l_ab kk / 4), exp(l_a k / 2) for compile-time k, kk
+template <int K>
+__host__ __device__ __forceinline__ double e2_dpow(const E2Pow &p, int a)
+{
+    constexpr int s = K * K;
+    static_assert(s == 0 || s == 1 || s == 4 || s == 16, "doubled component");
+    return s == 0 ? 1.0 : s == 1 ? p.d[a][0] : s == 4 ? p.d[a][1] : p.d[a][2];
+}
+template <int KK>
+__host__ __device__ __forceinline__ double e2_opow(const E2Pow &p, int b)
+{
+    static_assert(KK == 0 || KK == 1 || KK == 4 || KK == -1 || KK == -4, "doubled product");
+    return KK == 0 ? 1.0 : KK == 1 ? p.o[b][0] : KK == 4 ? p.o[b][1] : KK == -1 ? p.o[b][2] : p.o[b][3];
+}
+template <int K>
+__host__ __device__ __forceinline__ double e2_xpow(const E2Pow &p, int a)
+{
+    static_assert(K == 0 || K == 1 || K == 2 || K == 4 || K == -1 || K == -2 || K == -4, "doubled component");
+    return K == 0 ? 1.0 : K == 1 ? p.x[a][0] : K == 2 ? p.x[a][1] : K == 4 ? p.x[a][2]
+         : K == -1 ? p.x[a][3] : K == -2 ? p.x[a][4] : p.x[a][5];
+}
+
+// exp(even part) and exp(+-odd part) of l . phi for pair P
+template <int P>
+__host__ __device__ __forceinline__ void e2_pair_exp(const E2Pow &p, double &ev, double &xp, double &xm)
+{
+    constexpr int kx = Lattice::REP2[P][0], ky = Lattice::REP2[P][1], kz = Lattice::REP2[P][2];
+    ev = ((p.e0 * e2_dpow<kx>(p, 0)) * (e2_dpow<ky>(p, 1) * e2_dpow<kz>(p, 2))) *
+         ((e2_opow<kx * ky>(p, 0) * e2_opow<kx * kz>(p, 1)) * e2_opow<ky * kz>(p, 2));
+    xp = (e2_xpow<kx>(p, 0) * e2_xpow<ky>(p, 1)) * e2_xpow<kz>(p, 2);
+    xm = (e2_xpow<-kx>(p, 0) * e2_xpow<-ky>(p, 1)) * e2_xpow<-kz>(p, 2);
+}
+
 // moments and Jacobian contributions of pair P (F+ and F- of weight w)
 template <int P = 0>
-__host__ __device__ __forceinline__ void e2_accumulate(const double *l, const double *w6, double *mom, double *J)
+__host__ __device__ __forceinline__ void e2_accumulate(const E2Pow &pw, const double *w6, double *mom, double *J)
 {
     if constexpr (P < NPAIR) {
         using F = E2Phi<P>;
-        double ev, od;
-        e2_parts<P>(l, ev, od);
-        double w = w6[Lattice::SHELL[P]];
-        double fp = w * exp(ev + od), fm = w * exp(ev - od);
+        double ev, xp, xm;
+        e2_pair_exp<P>(pw, ev, xp, xm);
+        double w = w6[Lattice::SHELL[P]] * ev;
+        double fp = w * xp, fm = w * xm;
         double s = fp + fm, d = fp - fm;
 #pragma unroll
         for (int k = 0; k < E2_NL; k++) {
@@ -87,7 +161,7 @@ __host__ __device__ __forceinline__ void e2_accumulate(const double *l, const do
                 J[e2_ij(k, m)] += pk * pm * ((F::odd(k) != F::odd(m)) ? d : s);
             }
         }
-        e2_accumulate<P + 1>(l, w6, mom, J);
+        e2_accumulate<P + 1>(pw, w6, mom, J);
     }
 }
 
@@ -204,10 +278,12 @@ __host__ __device__ __forceinline__ int e2_newton(const double *w6, const double
         for (int k = 0; k < E2_NL; k++) mom[k] = 0.0;
 #pragma unroll
         for (int k = 0; k < E2_NL * (E2_NL + 1) / 2; k++) J[k] = 0.0;
-        double f0 = w6[0] * exp(l[0]);   // rest velocity: phi = (1, 0, ...)
+        E2Pow pw;
+        e2_pow_bases(l, pw);
+        double f0 = w6[0] * pw.e0;   // rest velocity: phi = (1, 0, ...)
         mom[0] = f0;
         J[0] = f0;
-        e2_accumulate(l, w6, mom, J);
+        e2_accumulate(pw, w6, mom, J);
         double rhs[E2_NL], res = 0.0;
 #pragma unroll
         for (int k = 0; k < E2_NL; k++) {
