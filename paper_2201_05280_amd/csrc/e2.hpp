@@ -7,7 +7,7 @@
 // The multipliers come from Newton's method on those ten equations, started
 // from the continuous Gaussian N(u, lam) / N(0, theta0 I) (or from a nearby
 // solution) and damped so that no exponent changes by more than 2 in one
-// iteration; a Cholesky solve of the (symmetric positive definite) Jacobian
+// iteration; a U^T D U factorization of the (symmetric positive definite) Jacobian
 // sum_i F_i phi_i phi_i^T gives the step.  It stops once the moments are met
 // to 1e-14 and the last step moved no exponent by more than 1e-8, so that the
 // result is the constrained minimiser to round-off, not a function of the
@@ -179,42 +179,49 @@ __host__ __device__ __forceinline__ double e2_maxchange(const double *dl, double
     }
 }
 
-// In-place Cholesky solve of the packed SPD system J x = b; false if J is not
-// positive definite.  The diagonal of the factor is kept as its reciprocal,
-// so the two triangular solves multiply instead of divide.
+// In-place solve of the packed SPD system J x = b by the factorization
+// J = U^T D U (U unit upper triangular, D diagonal; no square roots, one
+// reciprocal per column); false if J is not positive definite (a pivot
+// d_j <= 0).  U overwrites the upper triangle of J.
 __host__ __device__ __forceinline__ bool e2_cholesky_solve(double *J, double *b)
 {
+    double dinv[E2_NL], dd[E2_NL];
 #pragma unroll
     for (int j = 0; j < E2_NL; j++) {
+        double wk[E2_NL];   // U[k][j] d_k, k < j
         double d = J[e2_ij(j, j)];
 #pragma unroll
-        for (int k = 0; k < j; k++) d -= J[e2_ij(k, j)] * J[e2_ij(k, j)];
+        for (int k = 0; k < j; k++) {
+            wk[k] = J[e2_ij(k, j)] * dd[k];
+            d -= wk[k] * J[e2_ij(k, j)];
+        }
         if (!(d > 0.0)) return false;
-        double ir = 1.0 / sqrt(d);
-        J[e2_ij(j, j)] = ir;       // 1 / U[j][j]
+        dd[j] = d;
+        dinv[j] = 1.0 / d;
 #pragma unroll
         for (int i = j + 1; i < E2_NL; i++) {
             double t = J[e2_ij(j, i)];
 #pragma unroll
-            for (int k = 0; k < j; k++) t -= J[e2_ij(k, j)] * J[e2_ij(k, i)];
-            J[e2_ij(j, i)] = t * ir;   // U[j][i] of J = U^T U
+            for (int k = 0; k < j; k++) t -= wk[k] * J[e2_ij(k, i)];
+            J[e2_ij(j, i)] = t * dinv[j];   // U[j][i]
         }
     }
-    // U^T y = b
+    // U^T y = b, then z = y / d, then U x = z
 #pragma unroll
     for (int i = 0; i < E2_NL; i++) {
         double t = b[i];
 #pragma unroll
         for (int k = 0; k < i; k++) t -= J[e2_ij(k, i)] * b[k];
-        b[i] = t * J[e2_ij(i, i)];
+        b[i] = t;
     }
-    // U x = y
+#pragma unroll
+    for (int i = 0; i < E2_NL; i++) b[i] *= dinv[i];
 #pragma unroll
     for (int i = E2_NL - 1; i >= 0; i--) {
         double t = b[i];
 #pragma unroll
         for (int k = i + 1; k < E2_NL; k++) t -= J[e2_ij(i, k)] * b[k];
-        b[i] = t * J[e2_ij(i, i)];
+        b[i] = t;
     }
     return true;
 }
