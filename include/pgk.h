@@ -366,9 +366,9 @@ void pgk_batch_destroy(pgk_batch *b);
  * W1[128][6], b1[128], W2[128][128], b2, W3, b3, W4, b4, W5[4][128], b5[4].
  * Loss: mean squared error over points and outputs.  X is [n][6], Y [n][4],
  * row-major FP32 device arrays.  One device buffer (pgk_mlp_bytes) holds the
- * parameters, the Adam state, the activations of up to nmax points and one
- * gradient slot per 32 of them: a minibatch's gradient is the sum of its
- * slots in a fixed order, the same bits on every run.
+ * parameters, the Adam state and the working set of a minibatch of up to nmax
+ * points; a minibatch's gradient is summed in a fixed order (the same bits on
+ * every run).
  * ------------------------------------------------------------------------ */
 #define PGK_MLP_NPARAM 50948
 typedef struct pgk_mlp pgk_mlp;

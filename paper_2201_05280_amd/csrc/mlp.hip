@@ -6,9 +6,10 @@
 // work-group tiles of 16x16x16 bf16 MFMA blocks (four waves, each a 16x64
 // slab), the 6-wide first layer and the 4-wide last layer on the vector ALUs.
 // Training: one fused kernel per minibatch runs the forward and backward
-// passes of 32 points per work-group with the activations in LDS and the
-// 128x128 products on 16x16x32 bf16 MFMA blocks; a second kernel sums the
-// work-groups' gradient slots and applies Adam.  Parameter order: W1[128][6], b1, W2[128][128], b2, W3, b3,
+// passes of 16 points per work-group with the activations in LDS and the
+// 128x128 products on 16x16x32 bf16 MFMA blocks; a second kernel contracts the
+// bf16 factors of the weight gradients over the whole minibatch on MFMA, sums
+// the small-gradient slots and applies Adam.  Parameter order: W1[128][6], b1, W2[128][128], b2, W3, b3,
 // W4, b4, W5[4][128], b5.
 #include <hip/hip_runtime.h>
 
@@ -204,32 +205,40 @@ __global__ void k_refresh(const float *__restrict__ master, uint16_t *__restrict
 
 
 // ---------------------------------------------------------------------------
-// Fused training pass of one minibatch: forward, loss and backward of FB_P
-// points per work-group of eight waves, all five layers, the products over
-// units on gfx950's 16x16x32 bf16 matrix instructions and the weight
-// gradients (a product over the work-group's 16 points) on 16x16x16 ones.
-// Activations and dL/dz stay in LDS, row-major ([point][unit], A operands of
-// the products over units) and transposed ([unit][point], operands of the
-// weight gradients); z goes to global memory and is read back by the lane
-// that wrote it.  Each work-group writes its share of every gradient and of
-// the loss to its own slot of a partial buffer; k_sum_adam adds the slots in a
-// fixed order (the gradient is the same bits on every run) and applies Adam.
-// The bf16 roundings are those of the reference: weights, activations
-// entering layers 2-5, and dL/dz of layers 2-4 where it meets a weight or an
-// activation; x, dL/dy and dL/dz1 stay in fp32.  SiLU and its derivative take
-// the hardware exponential and reciprocal here (a few fp32 ulps; the
-// activations they feed are rounded to bf16).
+// Training pass of one minibatch in two kernels.
 //
-// Fragment layouts (lane l, r = l % 16, g = l / 16): 16x16x32, A holds
-// A[r][8g .. 8g+7], B holds B[8g .. 8g+7][r]; 16x16x16, A[r][4g .. 4g+3],
-// B[4g .. 4g+3][r]; both give D[4g + j][r], j = 0..3.  A [point][unit] tile
-// (16 x 128) is split over the waves by columns: wave w holds units 16 w ..
-// 16 w + 15.
+// k_fb: forward, loss and backward of FB_P points per work-group of eight
+// waves, all five layers, the products over units on gfx950's 16x16x32 bf16
+// matrix instructions.  Activations and dL/dz stay in LDS, z in registers.
+// The weight gradients of
+// the 128x128 layers, dW = sum_p r(dz)[p][o] a[p][i], are contractions over
+// all points of the minibatch: the work-group writes their bf16 factors
+// (r(dz) and a, transposed: [unit][point]) to global memory, and its share of
+// the small gradients (W1, W5, the biases) and of the loss to its own slot.
+//
+// k_grad_adam: one work-group per 16x16 tile of dW2, dW3, dW4 contracts the
+// factors over the whole minibatch (four waves, each every fourth 32-point
+// step, summed in a fixed order), a few more sum the small slots in slot
+// order; each then applies Adam to its parameters.  The gradient is the same
+// bits on every run.
+//
+// The bf16 roundings are those of the reference: weights, activations entering
+// layers 2-5, and dL/dz of layers 2-4 where it meets a weight or an activation;
+// x, dL/dy and dL/dz1 stay in fp32.  SiLU and its derivative take the hardware
+// exponential and reciprocal here (a few fp32 ulps; the activations they feed
+// are rounded to bf16).
+//
+// Fragment layout of the 16x16x32 product D = A B (lane l, r = l % 16,
+// g = l / 16): A holds A[r][8g .. 8g+7], B holds B[8g .. 8g+7][r], D holds
+// D[4g + j][r], j = 0..3.  A [point][unit] tile (16 x 128) is split over the
+// waves of k_fb by columns: wave w holds units 16 w .. 16 w + 15.
 constexpr int FB_P = 16;          // points per work-group
 constexpr int FB_WG = 512;        // eight waves
 constexpr int RS = H + 8;         // row stride (bf16) of [point][unit] arrays: rows 16 bytes apart mod 256
-constexpr int TS = FB_P + 8;      // row stride of [unit][point] arrays
 constexpr int WS = H + 8;         // row stride of the staged 128x128 weight
+// small-gradient slot: W1, b1, b2, b3, b4, W5, b5
+constexpr int SM_W1 = 0, SM_B1 = SM_W1 + H * NIN, SM_B2 = SM_B1 + H, SM_W5 = SM_B2 + 3 * H, SM_B5 = SM_W5 + NOUT * H;
+constexpr int NSMALL = SM_B5 + NOUT;
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
@@ -256,6 +265,28 @@ __device__ inline void stage_w(const uint16_t *__restrict__ src, uint16_t *sW)
     }
 }
 
+// the same staging split in two: the loads into registers (issued early, so
+// that their latency overlaps other work) and the stores into sW
+struct WPre {
+    v4u v[H * H / 8 / FB_WG];
+};
+__device__ inline void w_load(const uint16_t *__restrict__ src, WPre &pre)
+{
+#pragma unroll
+    for (int k = 0; k < H * H / 8 / FB_WG; k++) {
+        const int c = threadIdx.x + k * FB_WG, o = c >> 4, i0 = (c & 15) * 8;
+        pre.v[k] = *reinterpret_cast<const v4u *>(src + o * H + i0);
+    }
+}
+__device__ inline void w_store(const WPre &pre, uint16_t *sW)
+{
+#pragma unroll
+    for (int k = 0; k < H * H / 8 / FB_WG; k++) {
+        const int c = threadIdx.x + k * FB_WG, o = c >> 4, i0 = (c & 15) * 8;
+        *reinterpret_cast<v4u *>(sW + o * WS + i0) = pre.v[k];
+    }
+}
+
 // column sums over the work-group's points of a [point][unit] tile held in the
 // product layout into red[H]
 __device__ inline void col_sums(v4f32 d, float *red)
@@ -267,9 +298,8 @@ __device__ inline void col_sums(v4f32 d, float *red)
     if (g == 0) red[16 * w + r] = s;
 }
 
-// work-group barrier that orders LDS only: the global stores of the fused pass
-// (z, read back later by the lane that wrote it, and the gradient slots, read by
-// the next kernel) stay in flight across it
+// work-group barrier that orders LDS only: the global stores of the pass (the
+// factors and slots, read by the next kernel) stay in flight across it
 __device__ inline void lds_barrier()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -277,34 +307,38 @@ __device__ inline void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// four bf16 of consecutive points as one 8-byte store into a [unit][point] array
+// four bf16 of consecutive points as one 8-byte store
 __device__ inline void put4(uint16_t *dst, const uint16_t *b4)
 {
     *reinterpret_cast<uint2 *>(dst) = make_uint2(b4[0] | ((uint32_t)b4[1] << 16), b4[2] | ((uint32_t)b4[3] << 16));
 }
 
+// fT: bf16 factors [2][3][H][ldp]; fT[0][li] = r(dz) of layer li + 2, fT[1][li]
+// = a of layer li + 1 (the input of W_{li+2}), point p of the minibatch at
+// column p; small: [slot][NSMALL]; lpart: [slot]
 __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const float *__restrict__ Y, int n,
                                               float scale, float lscale, const uint16_t *__restrict__ wbf,
                                               const uint16_t *__restrict__ wbfT, const float *__restrict__ master,
-                                              float *__restrict__ z1, float *__restrict__ z2, float *__restrict__ z3,
-                                              float *__restrict__ z4, float *__restrict__ gpart,
+                                              uint16_t *__restrict__ fT, int ldp, float *__restrict__ small,
                                               float *__restrict__ lpart)
 {
     __shared__ __align__(16) uint16_t sW[H * WS];
     __shared__ __align__(16) uint16_t sRow[2][FB_P * RS];
-    __shared__ __align__(16) uint16_t sT[4][H * TS];
-    __shared__ __align__(16) uint16_t sDzT[H * TS];
-    __shared__ float sX[FB_P * NIN], sDy[FB_P * NOUT], sRed[H], sLoss[FB_WG / 64];
+    __shared__ float sX[FB_P * NIN], sDy[FB_P * NOUT], sRed[H], sLoss[FB_WG / 64], sDz1[FB_P * H];
     __shared__ float sW1[H * NIN], sW5[NOUT * H], sB[4 * H + NOUT];   // bf16 weights as float; biases
 
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, r = l & 15, g = l >> 4;
     const int o = 16 * w + r;                          // this lane's unit in the product layout
     const int p0 = blockIdx.x * FB_P;
-    float *gp = gpart + (size_t)blockIdx.x * NPARAM;
+    float *sm = small + (size_t)blockIdx.x * NSMALL;
     // the 128x128 layers li = 0, 1, 2 (W2, W3, W4) and their biases; z of layer li + 1
     auto offW = [](int li) { return OFF_W2 + li * (H * H + H); };
     auto offB = [](int li) { return OFF_W2 + li * (H * H + H) + H * H; };
-    auto zb = [&](int i) { return i == 0 ? z1 : i == 1 ? z2 : i == 2 ? z3 : z4; };
+    // a lane holds the same points and unit in every layer: it keeps its z of
+    // layers 1-4 in registers for the backward pass
+    float zk[4][4];
+    // this lane's four consecutive points of unit u in factor f of layer li
+    auto fcol = [&](int f, int li, int u) { return fT + ((size_t)(f * 3 + li) * H + u) * ldp + p0 + 4 * g; };
     static_assert(OFF_W3 == OFF_W2 + H * H + H && OFF_W4 == OFF_W3 + H * H + H && OFF_B4 == OFF_W4 + H * H,
                   "layer offsets");
 
@@ -324,36 +358,39 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
             const int p = 4 * g + j;
             float z = sB[o];
             for (int k = 0; k < NIN; k++) z += sW1[o * NIN + k] * sX[p * NIN + k];
-            z1[(size_t)(p0 + p) * H + o] = z;
+            zk[0][j] = z;
             a4[j] = f2bf(silu_fast(z));
             sRow[0][p * RS + o] = a4[j];
         }
-        put4(&sT[0][o * TS + 4 * g], a4);
+        put4(fcol(1, 0, o), a4);
     }
     lds_barrier();
 
     // layers 2-4 on the matrix cores
+    WPre pre;
+#pragma unroll
     for (int li = 0; li < 3; li++) {
         const uint16_t *in = sRow[li & 1];
         uint16_t *out = sRow[(li + 1) & 1];
+        // the next weights (W3, W4, then W4 transposed for the backward pass) load during this product
+        w_load(li < 2 ? wbf + offW(li + 1) : wbfT + 2 * H * H, pre);
         v4f32 acc = v4f32{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < H / 32; ks++)
             acc = mma32(ld8(in + r * RS + 32 * ks + 8 * g), ld8(sW + o * WS + 32 * ks + 8 * g), acc);
         lds_barrier();
-        if (li < 2) stage_w(wbf + offW(li + 1), sW);
-        float *zo = zb(li + 1);
+        if (li < 2) w_store(pre, sW);
         const float bias = sB[(li + 1) * H + o];
         uint16_t a4[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             const int p = 4 * g + j;
             const float z = acc[j] + bias;
-            zo[(size_t)(p0 + p) * H + o] = z;
+            zk[li + 1][j] = z;
             a4[j] = f2bf(silu_fast(z));
             out[p * RS + o] = a4[j];
         }
-        put4(&sT[li + 1][o * TS + 4 * g], a4);
+        if (li < 2) put4(fcol(1, li + 1, o), a4);
         lds_barrier();
     }
     const uint16_t *a4s = sRow[1];                    // a4, row-major
@@ -388,12 +425,12 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
         const int o5 = tid >> 7, k = tid & (H - 1);
         float s = 0.f;
         for (int p = 0; p < FB_P; p++) s += sDy[p * NOUT + o5] * bf2f(a4s[p * RS + k]);
-        gp[OFF_W5 + tid] = s;
+        sm[SM_W5 + tid] = s;
     }
     if (tid < NOUT) {
         float s = 0.f;
         for (int p = 0; p < FB_P; p++) s += sDy[p * NOUT + tid];
-        gp[OFF_B5 + tid] = s;
+        sm[SM_B5 + tid] = s;
     }
     // dz4 = (dy W5) * dsilu(z4), in the product layout
     v4f32 dz;
@@ -402,12 +439,14 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
         const int p = 4 * g + j;
         float da = 0.f;
         for (int o5 = 0; o5 < NOUT; o5++) da += sDy[p * NOUT + o5] * sW5[o5 * H + o];
-        dz[j] = da * dsilu_fast(z4[(size_t)(p0 + p) * H + o]);
+        dz[j] = da * dsilu_fast(zk[3][j]);
     }
     lds_barrier();
 
-    // layers 4, 3, 2: weight and bias gradients, then dL/dz of the layer below
+    // layers 4, 3, 2: bias gradients and the r(dz) factor of the weight
+    // gradients, then dL/dz of the layer below
     uint16_t *dzRow = sRow[0];
+#pragma unroll
     for (int li = 2; li >= 0; li--) {
         col_sums(dz, sRed);
         {
@@ -417,90 +456,42 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
                 b4[j] = f2bf(dz[j]);
                 dzRow[(4 * g + j) * RS + o] = b4[j];
             }
-            put4(&sDzT[o * TS + 4 * g], b4);
+            put4(fcol(0, li, o), b4);
         }
-        stage_w(wbfT + li * H * H, sW);               // W transposed: sW[i][o] = W[o][i]
+        w_store(pre, sW);                             // W transposed: sW[i][o] = W[o][i]
         lds_barrier();
-        if (tid < H) gp[offB(li) + tid] = sRed[tid];
-        // dW[o][i] = sum_p r(dz)[p][o] a[p][i] over the 16 points: wave w takes o in [16 w, 16 w + 16)
-        {
-            const uint16_t *aT = sT[li];
-            const v4i16 a = load4_bf(sDzT + o * TS + 4 * g);
-#pragma unroll
-            for (int nt = 0; nt < 8; nt++) {
-                const v4f32 c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, load4_bf(aT + (16 * nt + r) * TS + 4 * g),
-                                                                           v4f32{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-#pragma unroll
-                for (int j = 0; j < 4; j++) gp[offW(li) + (16 * w + 4 * g + j) * H + 16 * nt + r] = c[j];
-            }
-        }
+        if (li > 0) w_load(wbfT + (li - 1) * H * H, pre);
+        if (tid < H) sm[SM_B2 + li * H + tid] = sRed[tid];
         // da[p][i] = sum_o r(dz)[p][o] W[o][i]; dz of the layer below = da dsilu(z)
         v4f32 acc = v4f32{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ks = 0; ks < H / 32; ks++)
             acc = mma32(ld8(dzRow + r * RS + 32 * ks + 8 * g), ld8(sW + o * WS + 32 * ks + 8 * g), acc);
-        const float *zi = zb(li);
 #pragma unroll
-        for (int j = 0; j < 4; j++) dz[j] = acc[j] * dsilu_fast(zi[(size_t)(p0 + 4 * g + j) * H + o]);
+        for (int j = 0; j < 4; j++) dz[j] = acc[j] * dsilu_fast(zk[li][j]);
         lds_barrier();
     }
 
     // layer 1: db1 = sum dz1, dW1 = dz1^T x (both in fp32)
-    float *sDz1 = reinterpret_cast<float *>(sT[1]);   // [FB_P][H] fp32 over the free a2, a3 tiles
     col_sums(dz, sRed);
 #pragma unroll
     for (int j = 0; j < 4; j++) sDz1[(4 * g + j) * H + o] = dz[j];
     lds_barrier();
-    if (tid < H) gp[OFF_B1 + tid] = sRed[tid];
+    if (tid < H) sm[SM_B1 + tid] = sRed[tid];
     for (int idx = tid; idx < H * NIN; idx += FB_WG) {
         const int oo = idx / NIN, k = idx - oo * NIN;
         float s = 0.f;
         for (int p = 0; p < FB_P; p++) s += sDz1[p * H + oo] * sX[p * NIN + k];
-        gp[OFF_W1 + idx] = s;
+        sm[SM_W1 + idx] = s;
     }
 }
 
-// Sum of the work-groups' gradient slots into grad, or (adam) straight into an
-// Adam step; the loss slots are added to *loss.  Eight threads per parameter
-// (slots c = part mod 8, sixteen loads in flight each), combined in a fixed
-// order: the same bits on every run.
-constexpr int SA_P = 32;          // parameters per work-group of 256
-__global__ __launch_bounds__(256) void k_sum_adam(const float *__restrict__ gpart, int nslot,
-                                                  const float *__restrict__ lpart, float *__restrict__ loss,
-                                                  float *__restrict__ grad, float *__restrict__ master,
-                                                  uint16_t *__restrict__ wbf, uint16_t *__restrict__ wbfT,
-                                                  float *__restrict__ m, float *__restrict__ v, int adam, float lr,
-                                                  float b1, float b2, float eps, float c1, float c2)
+// gradient gs of parameter i into grad, or (adam) an Adam step
+__device__ inline void apply_grad(int i, float gs, float *__restrict__ grad, float *__restrict__ master,
+                                  uint16_t *__restrict__ wbf, uint16_t *__restrict__ wbfT, float *__restrict__ m,
+                                  float *__restrict__ v, int adam, float lr, float b1, float b2, float eps, float c1,
+                                  float c2)
 {
-    __shared__ float red[8][SA_P];
-    const int q = threadIdx.x & (SA_P - 1), part = threadIdx.x >> 5;
-    const int i = blockIdx.x * SA_P + q;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        float s = *loss;
-        for (int c = 0; c < nslot; c++) s += lpart[c];
-        *loss = s;
-    }
-    float s16[16];
-#pragma unroll
-    for (int u = 0; u < 16; u++) s16[u] = 0.f;
-    if (i < NPARAM) {
-        int c = part;
-        for (; c + 8 * 15 < nslot; c += 128)
-#pragma unroll
-            for (int u = 0; u < 16; u++) s16[u] += gpart[(size_t)(c + 8 * u) * NPARAM + i];
-#pragma unroll
-        for (int u = 0; u < 16; u++)
-            if (c + 8 * u < nslot) s16[u] += gpart[(size_t)(c + 8 * u) * NPARAM + i];
-    }
-#pragma unroll
-    for (int h = 8; h > 0; h >>= 1)
-#pragma unroll
-        for (int u = 0; u < h; u++) s16[u] += s16[u + h];
-    red[part][q] = s16[0];
-    __syncthreads();
-    if (part != 0 || i >= NPARAM) return;
-    const float gs = ((red[0][q] + red[1][q]) + (red[2][q] + red[3][q])) +
-                     ((red[4][q] + red[5][q]) + (red[6][q] + red[7][q]));
     if (!adam) {
         grad[i] = gs;
         return;
@@ -513,6 +504,94 @@ __global__ __launch_bounds__(256) void k_sum_adam(const float *__restrict__ gpar
     put_bf(wbf, wbfT, i, wv);
 }
 
+// parameter index of small-slot entry e
+__device__ inline int small_param(int e)
+{
+    return e < SM_B1 ? OFF_W1 + e : e < SM_B2 ? OFF_B1 + e - SM_B1
+         : e < SM_W5 ? OFF_W2 + ((e - SM_B2) / H) * (H * H + H) + H * H + (e - SM_B2) % H
+         : e < SM_B5 ? OFF_W5 + e - SM_W5 : OFF_B5 + e - SM_B5;
+}
+
+constexpr int GA_TILES = 3 * (H / 16) * (H / 16);               // 16x16 tiles of dW2, dW3, dW4
+constexpr int GA_WG = 512;
+constexpr int GA_SMALL = (NSMALL + 63) / 64;                    // 64 small-slot entries per work-group
+
+// Work-groups 0 .. GA_TILES-1: one 16x16 tile of dW2-dW4 over np points (np a
+// multiple of 16), eight waves each taking every eighth 32-point step, eight
+// steps' loads issued before their products; the waves' sums are added in a
+// fixed order.  The rest: 64 small-slot entries each, eight threads per entry
+// (slots c = part mod 8, sixteen loads in flight), added in a fixed order;
+// work-group GA_TILES also adds the loss slots to *loss.
+__global__ __launch_bounds__(GA_WG) void k_grad_adam(const uint16_t *__restrict__ fT, int ldp, int np,
+                                                     const float *__restrict__ small, int nslot,
+                                                     const float *__restrict__ lpart, float *__restrict__ loss,
+                                                     float *__restrict__ grad, float *__restrict__ master,
+                                                     uint16_t *__restrict__ wbf, uint16_t *__restrict__ wbfT,
+                                                     float *__restrict__ m, float *__restrict__ v, int adam, float lr,
+                                                     float b1, float b2, float eps, float c1, float c2)
+{
+    __shared__ float red[8][256];
+    const int tid = threadIdx.x;
+    if (blockIdx.x < GA_TILES) {
+        const int li = blockIdx.x / 64, t = blockIdx.x % 64, to = t >> 3, ti = t & 7;
+        const int w = tid >> 6, l = tid & 63, r = l & 15, g = l >> 4;
+        const uint16_t *dzT = fT + ((size_t)(0 * 3 + li) * H + 16 * to + r) * ldp;
+        const uint16_t *aT = fT + ((size_t)(1 * 3 + li) * H + 16 * ti + r) * ldp;
+        const v8bf zero = __builtin_bit_cast(v8bf, v4u{0u, 0u, 0u, 0u});
+        v4f32 acc = v4f32{0.f, 0.f, 0.f, 0.f};
+        const int nst = (np + 31) / 32;
+        for (int s0 = w; s0 < nst; s0 += 64) {
+            v8bf fa[8], fb[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int p = 32 * (s0 + 8 * u) + 8 * g;
+                const bool in = p < np;
+                fa[u] = in ? ld8(dzT + p) : zero;
+                fb[u] = in ? ld8(aT + p) : zero;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) acc = mma32(fa[u], fb[u], acc);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) red[w][(4 * g + j) * 16 + r] = acc[j];
+        __syncthreads();
+        if (tid >= 256) return;
+        const float gs = ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) +
+                         ((red[4][tid] + red[5][tid]) + (red[6][tid] + red[7][tid]));
+        const int i = OFF_W2 + li * (H * H + H) + (16 * to + (tid >> 4)) * H + 16 * ti + (tid & 15);
+        apply_grad(i, gs, grad, master, wbf, wbfT, m, v, adam, lr, b1, b2, eps, c1, c2);
+        return;
+    }
+    const int q = tid & 63, part = tid >> 6;
+    const int e = (blockIdx.x - GA_TILES) * 64 + q;
+    if (blockIdx.x == GA_TILES && tid == 0) {
+        float s = *loss;
+        for (int c = 0; c < nslot; c++) s += lpart[c];
+        *loss = s;
+    }
+    float s16[16];
+#pragma unroll
+    for (int u = 0; u < 16; u++) s16[u] = 0.f;
+    if (e < NSMALL) {
+        int c = part;
+        for (; c + 8 * 15 < nslot; c += 128)
+#pragma unroll
+            for (int u = 0; u < 16; u++) s16[u] += small[(size_t)(c + 8 * u) * NSMALL + e];
+#pragma unroll
+        for (int u = 0; u < 16; u++)
+            if (c + 8 * u < nslot) s16[u] += small[(size_t)(c + 8 * u) * NSMALL + e];
+    }
+#pragma unroll
+    for (int hh = 8; hh > 0; hh >>= 1)
+#pragma unroll
+        for (int u = 0; u < hh; u++) s16[u] += s16[u + hh];
+    red[part][q] = s16[0];
+    __syncthreads();
+    if (part != 0 || e >= NSMALL) return;
+    const float gs = ((red[0][q] + red[1][q]) + (red[2][q] + red[3][q])) + ((red[4][q] + red[5][q]) + (red[6][q] + red[7][q]));
+    apply_grad(small_param(e), gs, grad, master, wbf, wbfT, m, v, adam, lr, b1, b2, eps, c1, c2);
+}
+
 }  // namespace pgk_mlp_dev
 
 using namespace pgk_mlp_dev;
@@ -523,7 +602,9 @@ struct pgk_mlp {
     float *master, *grad, *m, *v, *loss;
     uint16_t *wbf;
     float *z[4], *dz, *dz2, *yhat, *dy;
-    float *gpart, *lpart;           // per-work-group gradient and loss slots of the fused training pass
+    float *small, *lpart;           // per-work-group slots of the small gradients and of the loss
+    uint16_t *fT;                   // bf16 factors of the 128x128 weight gradients, [2][3][H][ldp]
+    int ldp = 0;                    // points per factor row (nmax rounded up to 16)
     uint16_t *wbfT;                 // transposed bf16 copies of W2, W3, W4
     uint16_t *a[4];
     int t = 0;                      // Adam step count
@@ -550,9 +631,10 @@ static size_t mlp_layout(int nmax, size_t *o)
     o[16] = take(4ull * np * NOUT);       // yhat
     o[17] = take(4ull * np * NOUT);       // dy
     const size_t nslot = (size_t)(nmax + FB_P - 1) / FB_P;
-    o[18] = take(4ull * nslot * NPARAM);  // gradient slots
+    o[18] = take(4ull * nslot * NSMALL);  // small-gradient slots
     o[19] = take(4ull * nslot);           // loss slots
     o[20] = take(2ull * 3 * H * H);       // transposed bf16 W2, W3, W4
+    o[21] = take(2ull * 2 * 3 * H * (nslot * FB_P));   // weight-gradient factors
     return p;
 }
 
@@ -565,7 +647,7 @@ static size_t mlp_layout(int nmax, size_t *o)
 extern "C" int pgk_mlp_bytes(int nmax, size_t *bytes)
 {
     if (nmax < 1 || !bytes) return PGK_EINVAL;
-    size_t o[21];
+    size_t o[22];
     *bytes = mlp_layout(nmax, o);
     return PGK_OK;
 }
@@ -573,7 +655,7 @@ extern "C" int pgk_mlp_bytes(int nmax, size_t *bytes)
 extern "C" int pgk_mlp_create(void *stream, void *buf, size_t bytes, int nmax, pgk_mlp **out)
 {
     if (!out || !buf || nmax < 1 || ((uintptr_t)buf & 255)) return PGK_EINVAL;
-    size_t o[21];
+    size_t o[22];
     if (bytes < mlp_layout(nmax, o)) return PGK_ENOMEM;
     pgk_mlp *m = new pgk_mlp();
     m->stream = (hipStream_t)stream;
@@ -592,9 +674,11 @@ extern "C" int pgk_mlp_create(void *stream, void *buf, size_t bytes, int nmax, p
     m->dz2 = (float *)(b + o[15]);
     m->yhat = (float *)(b + o[16]);
     m->dy = (float *)(b + o[17]);
-    m->gpart = (float *)(b + o[18]);
+    m->small = (float *)(b + o[18]);
     m->lpart = (float *)(b + o[19]);
     m->wbfT = (uint16_t *)(b + o[20]);
+    m->fT = (uint16_t *)(b + o[21]);
+    m->ldp = (nmax + FB_P - 1) / FB_P * FB_P;
     *out = m;
     return PGK_OK;
 }
@@ -653,13 +737,14 @@ static int fused_pass(pgk_mlp *m, const float *X, const float *Y, int n, float s
 {
     const int nslot = (n + FB_P - 1) / FB_P;
     hipLaunchKernelGGL(k_fb, dim3(nslot), dim3(FB_WG), 0, m->stream, X, Y, n, scale, lscale, m->wbf, m->wbfT,
-                       m->master, m->z[0], m->z[1], m->z[2], m->z[3], m->gpart, m->lpart);
+                       m->master, m->fT, m->ldp, m->small, m->lpart);
     MHIP(m, hipGetLastError());
     return PGK_OK;
 }
 
-// the slots of the last fused pass summed into m->grad, or (adam) into an
-// Adam step; the loss slots are added to m->loss
+// the gradient of the last fused pass (the weight-gradient contractions and
+// the small slots) into m->grad, or (adam) into an Adam step; the loss slots
+// are added to m->loss
 static int sum_slots(pgk_mlp *m, int n, bool adam, float lr, float beta1, float beta2, float eps)
 {
     const int nslot = (n + FB_P - 1) / FB_P;
@@ -669,9 +754,9 @@ static int sum_slots(pgk_mlp *m, int n, bool adam, float lr, float beta1, float 
         c1 = 1.f / (1.f - powf(beta1, (float)m->t));
         c2 = 1.f / (1.f - powf(beta2, (float)m->t));
     }
-    hipLaunchKernelGGL(k_sum_adam, dim3((NPARAM + SA_P - 1) / SA_P), dim3(256), 0, m->stream, m->gpart, nslot, m->lpart,
-                       m->loss, m->grad, m->master, m->wbf, m->wbfT, m->m, m->v, adam ? 1 : 0, lr, beta1, beta2,
-                       eps, c1, c2);
+    hipLaunchKernelGGL(k_grad_adam, dim3(GA_TILES + GA_SMALL), dim3(GA_WG), 0, m->stream, m->fT, m->ldp, nslot * FB_P,
+                       m->small, nslot, m->lpart, m->loss, m->grad, m->master, m->wbf, m->wbfT, m->m, m->v,
+                       adam ? 1 : 0, lr, beta1, beta2, eps, c1, c2);
     MHIP(m, hipGetLastError());
     return PGK_OK;
 }
