@@ -387,7 +387,13 @@ int pgk_mlp_adam_step(pgk_mlp *m, float lr, float beta1, float beta2, float eps)
  * contiguous minibatches visited in a seeded random order; loss_per_epoch
  * (host, may be NULL) receives each epoch's loss, the squared errors met
  * during the epoch summed over all n points and divided by 4 n (every point
- * counts once, whatever the size of the last minibatch) */
+ * counts once, whatever the size of the last minibatch).  An epoch is one
+ * replayed HIP graph (recorded on a private stream, launched on the handle's
+ * stream); the host writes the epoch's minibatch records (24 bytes each) into
+ * the working set, so n / batch, rounded up, may be at most
+ * 4 * 128 * nmax / 24 (nmax rounded up to 64): PGK_EINVAL beyond it, as when
+ * the Adam step count would pass 2^31 - 1; PGK_EDEVICE if capture fails.
+ * Synchronises the handle's stream. */
 int pgk_mlp_train(pgk_mlp *m, const float *X, const float *Y, int64_t n, int batch, int epochs, float lr,
                   uint64_t seed, float *loss_per_epoch);
 /* The whole trainable state: FP32 master weights, their bfloat16 copies (the

@@ -313,6 +313,16 @@ __device__ inline void put4(uint16_t *dst, const uint16_t *b4)
     *reinterpret_cast<uint2 *>(dst) = make_uint2(b4[0] | ((uint32_t)b4[1] << 16), b4[2] | ((uint32_t)b4[3] << 16));
 }
 
+// One minibatch of a graph-replayed epoch, written by the host before each
+// replay: its first point and size, the weight of its dL/dy, and the Adam
+// bias corrections of its step.  Each graph node holds the address of its own
+// record, so a null record means the kernel arguments name the minibatch.
+struct MbRec {
+    int64_t b0;
+    int n;
+    float scale, c1, c2;
+};
+
 // fT: bf16 factors [2][3][H][ldp]; fT[0][li] = r(dz) of layer li + 2, fT[1][li]
 // = a of layer li + 1 (the input of W_{li+2}), point p of the minibatch at
 // column p; small: [slot][NSMALL]; lpart: [slot]
@@ -320,8 +330,16 @@ __global__ __launch_bounds__(FB_WG) void k_fb(const float *__restrict__ X, const
                                               float scale, float lscale, const uint16_t *__restrict__ wbf,
                                               const uint16_t *__restrict__ wbfT, const float *__restrict__ master,
                                               uint16_t *__restrict__ fT, int ldp, float *__restrict__ small,
-                                              float *__restrict__ lpart)
+                                              float *__restrict__ lpart, const MbRec *__restrict__ rec)
 {
+    if (rec) {
+        const MbRec mb = *rec;
+        n = mb.n;
+        X += mb.b0 * NIN;
+        Y += mb.b0 * NOUT;
+        scale = mb.scale;
+        if ((int)blockIdx.x * FB_P >= n) return;     // the grid covers a full minibatch
+    }
     __shared__ __align__(16) uint16_t sW[H * WS];
     __shared__ __align__(16) uint16_t sRow[2][FB_P * RS];
     __shared__ float sX[FB_P * NIN], sDy[FB_P * NOUT], sRed[H], sLoss[FB_WG / 64], sDz1[FB_P * H];
@@ -528,10 +546,18 @@ __global__ __launch_bounds__(GA_WG) void k_grad_adam(const uint16_t *__restrict_
                                                      float *__restrict__ grad, float *__restrict__ master,
                                                      uint16_t *__restrict__ wbf, uint16_t *__restrict__ wbfT,
                                                      float *__restrict__ m, float *__restrict__ v, int adam, float lr,
-                                                     float b1, float b2, float eps, float c1, float c2)
+                                                     float b1, float b2, float eps, float c1, float c2,
+                                                     const MbRec *__restrict__ rec)
 {
     __shared__ float red[8][256];
     const int tid = threadIdx.x;
+    if (rec) {
+        const MbRec mb = *rec;
+        nslot = (mb.n + FB_P - 1) / FB_P;
+        np = nslot * FB_P;
+        c1 = mb.c1;
+        c2 = mb.c2;
+    }
     if (blockIdx.x < GA_TILES) {
         const int li = blockIdx.x / 64, t = blockIdx.x % 64, to = t >> 3, ti = t & 7;
         const int w = tid >> 6, l = tid & 63, r = l & 15, g = l >> 4;
@@ -555,41 +581,44 @@ __global__ __launch_bounds__(GA_WG) void k_grad_adam(const uint16_t *__restrict_
 #pragma unroll
         for (int j = 0; j < 4; j++) red[w][(4 * g + j) * 16 + r] = acc[j];
         __syncthreads();
-        if (tid >= 256) return;
-        const float gs = ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) +
-                         ((red[4][tid] + red[5][tid]) + (red[6][tid] + red[7][tid]));
-        const int i = OFF_W2 + li * (H * H + H) + (16 * to + (tid >> 4)) * H + 16 * ti + (tid & 15);
-        apply_grad(i, gs, grad, master, wbf, wbfT, m, v, adam, lr, b1, b2, eps, c1, c2);
-        return;
+        if (tid < 256) {
+            const float gs = ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) +
+                             ((red[4][tid] + red[5][tid]) + (red[6][tid] + red[7][tid]));
+            const int i = OFF_W2 + li * (H * H + H) + (16 * to + (tid >> 4)) * H + 16 * ti + (tid & 15);
+            apply_grad(i, gs, grad, master, wbf, wbfT, m, v, adam, lr, b1, b2, eps, c1, c2);
+        }
+    } else {
+        const int q = tid & 63, part = tid >> 6;
+        const int e = (blockIdx.x - GA_TILES) * 64 + q;
+        if (blockIdx.x == GA_TILES && tid == 0) {
+            float s = *loss;
+            for (int c = 0; c < nslot; c++) s += lpart[c];
+            *loss = s;
+        }
+        float s16[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) s16[u] = 0.f;
+        if (e < NSMALL) {
+            int c = part;
+            for (; c + 8 * 15 < nslot; c += 128)
+#pragma unroll
+                for (int u = 0; u < 16; u++) s16[u] += small[(size_t)(c + 8 * u) * NSMALL + e];
+#pragma unroll
+            for (int u = 0; u < 16; u++)
+                if (c + 8 * u < nslot) s16[u] += small[(size_t)(c + 8 * u) * NSMALL + e];
+        }
+#pragma unroll
+        for (int hh = 8; hh > 0; hh >>= 1)
+#pragma unroll
+            for (int u = 0; u < hh; u++) s16[u] += s16[u + hh];
+        red[part][q] = s16[0];
+        __syncthreads();
+        if (part == 0 && e < NSMALL) {
+            const float gs = ((red[0][q] + red[1][q]) + (red[2][q] + red[3][q])) +
+                             ((red[4][q] + red[5][q]) + (red[6][q] + red[7][q]));
+            apply_grad(small_param(e), gs, grad, master, wbf, wbfT, m, v, adam, lr, b1, b2, eps, c1, c2);
+        }
     }
-    const int q = tid & 63, part = tid >> 6;
-    const int e = (blockIdx.x - GA_TILES) * 64 + q;
-    if (blockIdx.x == GA_TILES && tid == 0) {
-        float s = *loss;
-        for (int c = 0; c < nslot; c++) s += lpart[c];
-        *loss = s;
-    }
-    float s16[16];
-#pragma unroll
-    for (int u = 0; u < 16; u++) s16[u] = 0.f;
-    if (e < NSMALL) {
-        int c = part;
-        for (; c + 8 * 15 < nslot; c += 128)
-#pragma unroll
-            for (int u = 0; u < 16; u++) s16[u] += small[(size_t)(c + 8 * u) * NSMALL + e];
-#pragma unroll
-        for (int u = 0; u < 16; u++)
-            if (c + 8 * u < nslot) s16[u] += small[(size_t)(c + 8 * u) * NSMALL + e];
-    }
-#pragma unroll
-    for (int hh = 8; hh > 0; hh >>= 1)
-#pragma unroll
-        for (int u = 0; u < hh; u++) s16[u] += s16[u + hh];
-    red[part][q] = s16[0];
-    __syncthreads();
-    if (part != 0 || e >= NSMALL) return;
-    const float gs = ((red[0][q] + red[1][q]) + (red[2][q] + red[3][q])) + ((red[4][q] + red[5][q]) + (red[6][q] + red[7][q]));
-    apply_grad(small_param(e), gs, grad, master, wbf, wbfT, m, v, adam, lr, b1, b2, eps, c1, c2);
 }
 
 }  // namespace pgk_mlp_dev
@@ -737,7 +766,7 @@ static int fused_pass(pgk_mlp *m, const float *X, const float *Y, int n, float s
 {
     const int nslot = (n + FB_P - 1) / FB_P;
     hipLaunchKernelGGL(k_fb, dim3(nslot), dim3(FB_WG), 0, m->stream, X, Y, n, scale, lscale, m->wbf, m->wbfT,
-                       m->master, m->fT, m->ldp, m->small, m->lpart);
+                       m->master, m->fT, m->ldp, m->small, m->lpart, nullptr);
     MHIP(m, hipGetLastError());
     return PGK_OK;
 }
@@ -756,7 +785,7 @@ static int sum_slots(pgk_mlp *m, int n, bool adam, float lr, float beta1, float 
     }
     hipLaunchKernelGGL(k_grad_adam, dim3(GA_TILES + GA_SMALL), dim3(GA_WG), 0, m->stream, m->fT, m->ldp, nslot * FB_P,
                        m->small, nslot, m->lpart, m->loss, m->grad, m->master, m->wbf, m->wbfT, m->m, m->v,
-                       adam ? 1 : 0, lr, beta1, beta2, eps, c1, c2);
+                       adam ? 1 : 0, lr, beta1, beta2, eps, c1, c2, nullptr);
     MHIP(m, hipGetLastError());
     return PGK_OK;
 }
@@ -787,32 +816,87 @@ extern "C" int pgk_mlp_adam_step(pgk_mlp *m, float lr, float beta1, float beta2,
     return PGK_OK;
 }
 
+// Training epochs as one replayed HIP graph: the graph zeroes the loss and
+// holds, per minibatch, k_fb and k_grad_adam, each node with the address of
+// its minibatch's record (MbRec).  Before each replay the host shuffles the
+// minibatch order and writes the epoch's records (first point, size, Adam
+// bias corrections) into the first activation buffer, which the training pass
+// does not use.  The same minibatches, in the same order, with the same
+// arithmetic as direct launches.
+struct TrainRes {
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    MbRec *hrec = nullptr;
+    ~TrainRes()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cs) (void)hipStreamDestroy(cs);
+        if (hrec) (void)hipHostFree(hrec);
+    }
+};
+
 extern "C" int pgk_mlp_train(pgk_mlp *m, const float *X, const float *Y, int64_t n, int batch, int epochs, float lr,
                              uint64_t seed, float *loss_per_epoch)
 {
     if (!m || !X || !Y || n < 1 || batch < 1 || batch > m->nmax || epochs < 0) return PGK_EINVAL;
-    int64_t nb = (n + batch - 1) / batch;
+    const int64_t nb = (n + batch - 1) / batch;
+    if ((size_t)nb * sizeof(MbRec) > 4ull * m->npmax * H) {
+        m->err = "too many minibatches for the record buffer (raise nmax)";
+        return PGK_EINVAL;
+    }
+    if ((int64_t)m->t + nb * epochs > INT32_MAX) {
+        m->err = "Adam step count would overflow";
+        return PGK_EINVAL;
+    }
+    if (epochs == 0) return PGK_OK;
+    TrainRes res;
+    MHIP(m, hipHostMalloc((void **)&res.hrec, (size_t)nb * sizeof(MbRec), hipHostMallocDefault));
     std::vector<int64_t> order(nb);
+    MbRec *drec = reinterpret_cast<MbRec *>(m->z[0]);
+    const float lscale = 1.0f / (4.0f * (float)n), beta1 = 0.9f, beta2 = 0.999f;
+    // record the epoch
+    MHIP(m, hipStreamCreateWithFlags(&res.cs, hipStreamNonBlocking));
+    MHIP(m, hipStreamBeginCapture(res.cs, hipStreamCaptureModeThreadLocal));
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, res.cs, m->loss, 1);
+    const int nwg = (batch + FB_P - 1) / FB_P;
+    for (int64_t i = 0; i < nb; i++) {
+        hipLaunchKernelGGL(k_fb, dim3(nwg), dim3(FB_WG), 0, res.cs, X, Y, 0, 0.f, lscale, m->wbf, m->wbfT, m->master,
+                           m->fT, m->ldp, m->small, m->lpart, drec + i);
+        hipLaunchKernelGGL(k_grad_adam, dim3(GA_TILES + GA_SMALL), dim3(GA_WG), 0, res.cs, m->fT, m->ldp, 0, m->small,
+                           0, m->lpart, m->loss, m->grad, m->master, m->wbf, m->wbfT, m->m, m->v, 1, lr, beta1, beta2,
+                           1e-8f, 0.f, 0.f, drec + i);
+    }
+    hipError_t ce = hipStreamEndCapture(res.cs, &res.graph);
+    if (ce != hipSuccess) {
+        m->err = std::string("graph capture: ") + hipGetErrorString(ce);
+        return PGK_EDEVICE;
+    }
+    MHIP(m, hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
     uint64_t s = seed ? seed : 0x9E3779B97F4A7C15ull;
     for (int e = 0; e < epochs; e++) {
+        MHIP(m, hipStreamSynchronize(m->stream));   // the last epoch's records have been read
         for (int64_t i = 0; i < nb; i++) order[i] = i;
         for (int64_t i = nb - 1; i > 0; i--) {     // Fisher-Yates with xorshift64*
             s ^= s >> 12; s ^= s << 25; s ^= s >> 27;
             int64_t j = (int64_t)((s * 2685821657736338717ull) % (uint64_t)(i + 1));
             int64_t t = order[i]; order[i] = order[j]; order[j] = t;
         }
-        hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, m->stream, m->loss, 1);
         for (int64_t i = 0; i < nb; i++) {
-            int64_t b0 = order[i] * batch;
-            int c = (int)(n - b0 < batch ? n - b0 : batch);
-            // gradients of the mean loss over this minibatch; the squared
-            // errors are weighted 1/(4 n), so that the epoch's sum is the mean
-            // over all n points (a last, partial minibatch counts by its size);
-            // two launches: the fused pass, then the slot sum with the Adam step
-            int rc = fused_pass(m, X + b0 * NIN, Y + b0 * NOUT, c, 1.0f / (4.0f * c), 1.0f / (4.0f * (float)n));
-            if (rc == PGK_OK) rc = sum_slots(m, c, true, lr, 0.9f, 0.999f, 1e-8f);
-            if (rc) return rc;
+            MbRec &r = res.hrec[i];
+            r.b0 = order[i] * batch;
+            r.n = (int)(n - r.b0 < batch ? n - r.b0 : batch);
+            r.scale = 1.0f / (4.0f * r.n);
+            const float t = (float)(m->t + 1);   // the bias corrections of direct Adam steps
+            r.c1 = 1.f / (1.f - powf(beta1, t));
+            r.c2 = 1.f / (1.f - powf(beta2, t));
+            m->t++;
         }
+        MHIP(m, hipMemcpyAsync(drec, res.hrec, (size_t)nb * sizeof(MbRec), hipMemcpyHostToDevice, m->stream));
+        MHIP(m, hipGraphLaunch(res.exec, m->stream));
+        // the squared errors are weighted 1/(4 n): the epoch's sum is the
+        // mean over all n points, whatever the size of the last minibatch
         if (loss_per_epoch) {
             float l;
             MHIP(m, hipMemcpyAsync(&l, m->loss, 4, hipMemcpyDeviceToHost, m->stream));
@@ -820,6 +904,7 @@ extern "C" int pgk_mlp_train(pgk_mlp *m, const float *X, const float *Y, int64_t
             loss_per_epoch[e] = l;
         }
     }
+    MHIP(m, hipStreamSynchronize(m->stream));
     return PGK_OK;
 }
 

@@ -179,3 +179,59 @@ def test_state_save_load_resumes_training_bit_for_bit(tmp_path):
         b.load(bad)
     a.close()
     b.close()
+
+
+def _epoch_orders(nb, epochs, seed):
+    """The library's minibatch order: Fisher-Yates with xorshift64* per epoch."""
+    s = seed or 0x9E3779B97F4A7C15
+    mask = (1 << 64) - 1
+    out = []
+    for _ in range(epochs):
+        o = list(range(nb))
+        for i in range(nb - 1, 0, -1):
+            s ^= s >> 12
+            s ^= (s << 25) & mask
+            s ^= s >> 27
+            j = ((s * 2685821657736338717) & mask) % (i + 1)
+            o[i], o[j] = o[j], o[i]
+        out.append(o)
+    return out
+
+
+def test_graph_replayed_epochs_equal_direct_minibatch_steps():
+    """pgk_mlp_train replays one recorded epoch (each minibatch node reading the
+    record the host wrote for it) with the loss read back between replays; three
+    epochs of two minibatches (one partial) equal the same minibatches taken in
+    the same order by loss_grad + adam_step: weights, moments and step count,
+    and the epoch losses."""
+    from paper_2201_05280_amd.mlp import MLP
+    th = M.init(23)
+    n, batch, epochs, seed = 400, 256, 3, 9
+    X, Y = _data(n, 51)
+    a = MLP(nmax=512)
+    a.set_params(th)
+    losses = a.train(X, Y, epochs=epochs, batch=batch, lr=1e-3, seed=seed)
+    sa = a.state()
+    b = MLP(nmax=512)
+    b.set_params(th)
+    nb = (n + batch - 1) // batch
+    ref_losses = []
+    for order in _epoch_orders(nb, epochs, seed):
+        el = 0.0
+        for idx in order:
+            b0 = idx * batch
+            c = min(batch, n - b0)
+            lb, _ = b.loss_grad(X[b0:b0 + c], Y[b0:b0 + c])
+            b.adam_step(1e-3)
+            el += lb * c / n
+        ref_losses.append(el)
+    sb = b.state()
+    assert sa[4] == sb[4] == nb * epochs
+    for name, x, y in (("master", sa[0], sb[0]), ("m", sa[2], sb[2]), ("v", sa[3], sb[3])):
+        err = np.abs(x - y).max() / np.abs(y).max()
+        print(name, "max rel diff", err)
+        assert err < 1e-6, (name, err)
+    print("epoch losses", losses, ref_losses)
+    assert np.allclose(losses, ref_losses, rtol=1e-6, atol=0)
+    a.close()
+    b.close()
