@@ -245,12 +245,51 @@ __device__ __forceinline__ int position_index(int qx, int qy, int qz, int q, con
     return ((ssub * k.nz + sz) * k.ny + wrapc(hy, k.ny)) * k.nx + wrapc(hx, k.nx);
 }
 
-// Index of the population Q pulled by site (x,y,z,sub), see position_index.
+// Index of the population Q pulled by site (x,y,z,sub): position_index for a
+// position x - c_Q of a site inside the grid, where the sign of the
+// compile-time c_Q decides which face the pull can cross (c_a > 0 only the low
+// face of axis a, c_a < 0 only the high one, c_a = 0 none).  Every candidate
+// index is computed and one is selected, so the kernels that pull on bounded
+// grids run the same instructions on every lane, with no branch per
+// population.  The faces are tested in position_index's order (x before y: the
+// corners belong to the x faces).
 template <int Q, int BOUNDED>
 __device__ __forceinline__ int pull_index(int x, int y, int z, int sub, const Consts &k, int &ghost)
 {
     constexpr int cx = c2(Q, 0), cy = c2(Q, 1), cz = c2(Q, 2);
-    return position_index<BOUNDED>(2 * x + sub - cx, 2 * y + sub - cy, 2 * z + sub - cz, Q, k, ghost);
+    const int qx = 2 * x + sub - cx, qy = 2 * y + sub - cy, qz = 2 * z + sub - cz;
+    if constexpr (!BOUNDED) return position_index<BOUNDED>(qx, qy, qz, Q, k, ghost);
+    const int ssub = qx & 1;
+    const int hx = (qx - ssub) >> 1, hy = (qy - ssub) >> 1, sz = wrapc((qz - ssub) >> 1, k.nz);
+    const int wx = wrapc(hx, k.nx), wy = wrapc(hy, k.ny);
+    int idx = ((ssub * k.nz + sz) * k.ny + wy) * k.nx + wx;
+    ghost = 0;
+    // y faces (BND_XY), then x faces, so that an x-face ghost wins a corner
+    if constexpr (BOUNDED >= BND_XY && cy != 0) {
+        constexpr int f = cy > 0 ? 2 : 3;
+        const bool gy = cy > 0 ? (qy < 0 && k.bc[2] != PGK_PERIODIC)
+                               : (qy > 2 * k.ny - 1 && k.bc[3] != PGK_PERIODIC);
+        const int slot = cy > 0 ? -qy - 1 : qy - 2 * k.ny;
+        const int gi = ghost_index(f, Q, slot, sz * k.nx + wx, k);
+        idx = gy ? gi : idx;
+        ghost = gy ? 1 + f : ghost;
+    }
+    if constexpr (cx != 0) {
+        constexpr int f = cx > 0 ? 0 : 1;
+        const bool gx = cx > 0 ? (qx < 0 && k.bc[0] != PGK_PERIODIC)
+                               : (qx > 2 * k.nx - 1 && k.bc[1] != PGK_PERIODIC);
+        const int slot = cx > 0 ? -qx - 1 : qx - 2 * k.nx;
+        int gi;
+        if constexpr (BOUNDED < BND_XY) {
+            gi = ((f * NQ + Q) * NSLOT + slot) * k.nz * k.ny + sz * k.ny + wy;
+        } else {
+            const int iy = k.bc[2] != PGK_PERIODIC ? hy + 2 : wy;
+            gi = ghost_index(f, Q, slot, sz * ghost_wy(k) + iy, k);
+        }
+        idx = gx ? gi : idx;
+        ghost = gx ? 1 + f : ghost;
+    }
+    return idx;
 }
 
 template <typename S, int BOUNDED, int Q>
@@ -259,8 +298,12 @@ __device__ __forceinline__ void load_one(const S *__restrict__ src, const S *__r
 {
     int ghost;
     int idx = pull_index<Q, BOUNDED>(x, y, z, sub, k, ghost);
-    if (BOUNDED && ghost) v[Q] = gh[idx];
-    else v[Q] = src[(size_t)Q * k.ns + idx];
+    if constexpr (BOUNDED) {
+        const S *base = ghost ? gh : src + (size_t)Q * k.ns;
+        v[Q] = base[idx];
+    } else {
+        v[Q] = src[(size_t)Q * k.ns + idx];
+    }
 }
 
 template <typename S, int BOUNDED, int Q = 0>
