@@ -245,75 +245,113 @@ __device__ __forceinline__ int position_index(int qx, int qy, int qz, int q, con
     return ((ssub * k.nz + sz) * k.ny + wrapc(hy, k.ny)) * k.nx + wrapc(hx, k.nx);
 }
 
-// Index of the population Q pulled by site (x,y,z,sub): position_index for a
-// position x - c_Q of a site inside the grid, where the sign of the
-// compile-time c_Q decides which face the pull can cross (c_a > 0 only the low
-// face of axis a, c_a < 0 only the high one, c_a = 0 none).  Every candidate
-// index is computed and one is selected, so the kernels that pull on bounded
-// grids run the same instructions on every lane, with no branch per
-// population.  The faces are tested in position_index's order (x before y: the
-// corners belong to the x faces).
+// Ghost columns of the pull sources of one site on a grid with faces, the
+// companion of PullMap: the column (coordinates along the face) of every
+// source position for the x faces and (BND_XY) the y faces, for offsets -2..2
+// and for the half velocities, and the doubled site coordinates that decide
+// whether a source lies beyond a face.  The slot of a source beyond a face is
+// linear in the doubled coordinate, so slot * (slot stride) splits into a
+// per-site product (xsm, ysm) and a constant per population.
+template <int BOUNDED>
+struct GhostMap {
+    int xs, ys;             // 2x + sub, 2y + sub
+    int xsm, ysm;           // xs * nz * (x-face columns per z), ys * nz * nx
+    int xcz;                // x-face columns per z: ny, or ny + 4 with y bounded
+    Off5 XZ, XY;            // x-face column parts: wrapped z * xcz, y column
+    int hxz[2], hxy[2];     // the same for half velocities: [0] c > 0, [1] c < 0
+    Off5 YZ;                // y-face column part wrapped z * nx (the x part is PullMap.X)
+    int hyz[2];
+};
+
+template <int BOUNDED>
+__device__ __forceinline__ GhostMap<BOUNDED> ghost_map(int x, int y, int z, int sub, const Consts &k)
+{
+    GhostMap<BOUNDED> g;
+    g.xs = 2 * x + sub;
+    g.ys = 2 * y + sub;
+    const bool yb = BOUNDED >= BND_XY && k.bc[2] != PGK_PERIODIC;
+    g.xcz = yb ? k.ny + 4 : k.ny;
+    g.xsm = g.xs * (k.nz * g.xcz);
+    g.ysm = g.ys * (k.nz * k.nx);
+    const int zz[5] = {wrap2(z - 2, k.nz), wrap2(z - 1, k.nz), z, wrap2(z + 1, k.nz), wrap2(z + 2, k.nz)};
+    int yy[5];
+    for (int d = 0; d < 5; d++) yy[d] = yb ? y + d : wrap2(y + d - 2, k.ny);   // iy = hy + 2 with y bounded
+    g.XZ = {zz[0] * g.xcz, zz[1] * g.xcz, zz[2] * g.xcz, zz[3] * g.xcz, zz[4] * g.xcz};
+    g.XY = {yy[0], yy[1], yy[2], yy[3], yy[4]};
+    g.YZ = {zz[0] * k.nx, zz[1] * k.nx, zz[2] * k.nx, zz[3] * k.nx, zz[4] * k.nx};
+    const bool b = sub != 0;
+    g.hxz[0] = b ? g.XZ.z0 : g.XZ.m1; g.hxz[1] = b ? g.XZ.p1 : g.XZ.z0;
+    g.hxy[0] = b ? g.XY.z0 : g.XY.m1; g.hxy[1] = b ? g.XY.p1 : g.XY.z0;
+    g.hyz[0] = b ? g.YZ.z0 : g.YZ.m1; g.hyz[1] = b ? g.YZ.p1 : g.YZ.z0;
+    return g;
+}
+
+// Index of the population Q pulled by a site inside a grid with faces: the
+// index position_index gives for position x - c_Q, from the site's maps.  The
+// sign of the compile-time c_Q decides which face the pull can cross (c_a > 0
+// only the low face of axis a, c_a < 0 only the high one, c_a = 0 none);
+// every candidate index is computed and one selected, so the kernels that pull
+// on bounded grids run the same instructions on every lane, with no branch
+// per population.  An x face wins a corner, as in position_index.
 template <int Q, int BOUNDED>
-__device__ __forceinline__ int pull_index(int x, int y, int z, int sub, const Consts &k, int &ghost)
+__device__ __forceinline__ int pull_index_b(const PullMap &p, const GhostMap<BOUNDED> &g, const Consts &k,
+                                            int &ghost)
 {
     constexpr int cx = c2(Q, 0), cy = c2(Q, 1), cz = c2(Q, 2);
-    const int qx = 2 * x + sub - cx, qy = 2 * y + sub - cy, qz = 2 * z + sub - cz;
-    if constexpr (!BOUNDED) return position_index<BOUNDED>(qx, qy, qz, Q, k, ghost);
-    const int ssub = qx & 1;
-    const int hx = (qx - ssub) >> 1, hy = (qy - ssub) >> 1, sz = wrapc((qz - ssub) >> 1, k.nz);
-    const int wx = wrapc(hx, k.nx), wy = wrapc(hy, k.ny);
-    int idx = ((ssub * k.nz + sz) * k.ny + wy) * k.nx + wx;
+    constexpr bool half = (cx & 1) != 0;   // all three components odd
+    int idx = (int)pull_off<Q>(p);
     ghost = 0;
-    // y faces (BND_XY), then x faces, so that an x-face ghost wins a corner
     if constexpr (BOUNDED >= BND_XY && cy != 0) {
         constexpr int f = cy > 0 ? 2 : 3;
-        const bool gy = cy > 0 ? (qy < 0 && k.bc[2] != PGK_PERIODIC)
-                               : (qy > 2 * k.ny - 1 && k.bc[3] != PGK_PERIODIC);
-        const int slot = cy > 0 ? -qy - 1 : qy - 2 * k.ny;
-        const int gi = ghost_index(f, Q, slot, sz * k.nx + wx, k);
+        // beyond the face: qy = ys - cy < 0, or qy > 2 ny - 1
+        const bool gy = cy > 0 ? (g.ys < cy && k.bc[2] != PGK_PERIODIC)
+                               : (g.ys - cy > 2 * k.ny - 1 && k.bc[3] != PGK_PERIODIC);
+        int col;
+        if constexpr (half) col = g.hyz[cz > 0 ? 0 : 1] + p.hx[cx > 0 ? 0 : 1];
+        else col = g.YZ.template at<-cz / 2>() + p.X.template at<-cx / 2>();
+        // slot = cy - 1 - ys (low face) or ys - cy - 2 ny (high face)
+        const int base = 2 * NQ * NSLOT * k.nz * g.xcz + ((f - 2) * NQ + Q) * NSLOT * k.nz * k.nx;
+        const int gi = cy > 0 ? base + (cy - 1) * k.nz * k.nx - g.ysm + col
+                              : base - (cy + 2 * k.ny) * k.nz * k.nx + g.ysm + col;
         idx = gy ? gi : idx;
         ghost = gy ? 1 + f : ghost;
     }
     if constexpr (cx != 0) {
         constexpr int f = cx > 0 ? 0 : 1;
-        const bool gx = cx > 0 ? (qx < 0 && k.bc[0] != PGK_PERIODIC)
-                               : (qx > 2 * k.nx - 1 && k.bc[1] != PGK_PERIODIC);
-        const int slot = cx > 0 ? -qx - 1 : qx - 2 * k.nx;
-        int gi;
-        if constexpr (BOUNDED < BND_XY) {
-            gi = ((f * NQ + Q) * NSLOT + slot) * k.nz * k.ny + sz * k.ny + wy;
-        } else {
-            const int iy = k.bc[2] != PGK_PERIODIC ? hy + 2 : wy;
-            gi = ghost_index(f, Q, slot, sz * ghost_wy(k) + iy, k);
-        }
+        const bool gx = cx > 0 ? (g.xs < cx && k.bc[0] != PGK_PERIODIC)
+                               : (g.xs - cx > 2 * k.nx - 1 && k.bc[1] != PGK_PERIODIC);
+        int col;
+        if constexpr (half) col = g.hxz[cz > 0 ? 0 : 1] + g.hxy[cy > 0 ? 0 : 1];
+        else col = g.XZ.template at<-cz / 2>() + g.XY.template at<-cy / 2>();
+        const int base = (f * NQ + Q) * NSLOT * k.nz * g.xcz;
+        const int gi = cx > 0 ? base + (cx - 1) * k.nz * g.xcz - g.xsm + col
+                              : base - (cx + 2 * k.nx) * k.nz * g.xcz + g.xsm + col;
         idx = gx ? gi : idx;
         ghost = gx ? 1 + f : ghost;
     }
     return idx;
 }
 
-template <typename S, int BOUNDED, int Q>
-__device__ __forceinline__ void load_one(const S *__restrict__ src, const S *__restrict__ gh,
-                                         int x, int y, int z, int sub, const Consts &k, S *v)
+template <typename S, int BOUNDED, int Q = 0>
+__device__ __forceinline__ void load_bounded(const S *__restrict__ src, const S *__restrict__ gh, const PullMap &p,
+                                             const GhostMap<BOUNDED> &g, const Consts &k, S *v)
 {
-    int ghost;
-    int idx = pull_index<Q, BOUNDED>(x, y, z, sub, k, ghost);
-    if constexpr (BOUNDED) {
+    if constexpr (Q < NQ) {
+        int ghost;
+        const int idx = pull_index_b<Q, BOUNDED>(p, g, k, ghost);
         const S *base = ghost ? gh : src + (size_t)Q * k.ns;
         v[Q] = base[idx];
-    } else {
-        v[Q] = src[(size_t)Q * k.ns + idx];
+        load_bounded<S, BOUNDED, Q + 1>(src, gh, p, g, k, v);
     }
 }
 
-template <typename S, int BOUNDED, int Q = 0>
+// the 41 populations pulled by site (x, y, z, sub) of a grid with faces
+template <typename S, int BOUNDED>
 __device__ __forceinline__ void load_all(const S *__restrict__ src, const S *__restrict__ gh,
                                          int x, int y, int z, int sub, const Consts &k, S *v)
 {
-    if constexpr (Q < NQ) {
-        load_one<S, BOUNDED, Q>(src, gh, x, y, z, sub, k, v);
-        load_all<S, BOUNDED, Q + 1>(src, gh, x, y, z, sub, k, v);
-    }
+    static_assert(BOUNDED != BND_NONE, "periodic grids pull through load_periodic");
+    load_bounded<S, BOUNDED>(src, gh, pull_map(x, y, z, sub, k), ghost_map<BOUNDED>(x, y, z, sub, k), k, v);
 }
 
 // Sums over the stored values v (g, or h = g - w): rho, j, Pi.
