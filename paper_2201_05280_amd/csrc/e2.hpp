@@ -73,6 +73,26 @@ __host__ __device__ __forceinline__ void e2_parts(const double *l, double &ev, d
 // differ from single exponentials of l . phi by a few ulps; the converged
 // multipliers differ from those of single exponentials by no more than a
 // restart of the same Newton solve from a nearby point moves them.
+// 1 / d for a positive normal d (the base exponentials of the odd powers): on
+// the device the hardware reciprocal refined by two Newton-Raphson steps
+// r <- r + r (1 - d r), within an ulp of the rounded quotient at a third of
+// the instructions of the IEEE division; on the host the division itself.
+// The converged multipliers do not depend on it beyond round-off: the moments
+// decide when the solve stops.  (In the factorization the refinement's extra
+// live values cost the batched kernel more register spills than it saves.)
+__host__ __device__ __forceinline__ double e2_rcp(double d)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+#else
+    return 1.0 / d;
+#endif
+}
+
 struct E2Pow {
     double e0;          // exp(l0)
     double d[3][3];     // exp(l_aa / 4) to the powers 1, 4, 16 (a = x, y, z)
@@ -89,14 +109,14 @@ __host__ __device__ __forceinline__ void e2_pow_bases(const double *l, E2Pow &p)
         p.d[a][0] = d;
         p.d[a][1] = d4;
         p.d[a][2] = d8 * d8;
-        const double x = exp(0.5 * l[1 + a]), ix = 1.0 / x, x2 = x * x, ix2 = ix * ix;
+        const double x = exp(0.5 * l[1 + a]), ix = e2_rcp(x), x2 = x * x, ix2 = ix * ix;
         p.x[a][0] = x;
         p.x[a][1] = x2;
         p.x[a][2] = x2 * x2;
         p.x[a][3] = ix;
         p.x[a][4] = ix2;
         p.x[a][5] = ix2 * ix2;
-        const double o = exp(0.25 * l[7 + a]), io = 1.0 / o, o2 = o * o, io2 = io * io;
+        const double o = exp(0.25 * l[7 + a]), io = e2_rcp(o), o2 = o * o, io2 = io * io;
         p.o[a][0] = o;
         p.o[a][1] = o2 * o2;
         p.o[a][2] = io;
