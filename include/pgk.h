@@ -261,8 +261,9 @@ int pgk_set_transport_reference(pgk_ctx *ctx, int on);
  * advection (on a periodic grid with one diffusion sub-step: the single fused
  * transport kernel, advection + diffusion + second half), [2] the diffusion
  * and second half relaxation (on a bounded or sub-cycled line, ny = nz = 1,
- * with at most 63 sub-steps: the whole transport in one launch of 1024-cell
- * work-groups; on another bounded or sub-cycled grid of at most 4096 sites:
+ * with at most 63 sub-steps: the whole transport in one launch of work-groups
+ * of 256 threads, each producing 256 - 2 (n_sub + 1) cells; on another bounded
+ * or sub-cycled grid of at most 4096 sites:
  * the whole transport in one work-group), [3] the ghost fill of the bounded faces, and clears the
  * record.  Event handles are created on demand and
  * kept until pgk_destroy. */

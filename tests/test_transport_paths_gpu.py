@@ -71,3 +71,65 @@ def test_lds_transport_kernels_match_the_reference_kernels(precision):
             else:
                 err = diff / max(float(np.abs(b[k]).max()), FLOOR[k])
                 assert err <= bar, (label, precision, k, err)
+
+
+def _line_substeps(p, th_max):
+    """FTCS sub-steps per step of the theta_R diffusion on a line: the host
+    rule n = ceil(3 D_R), D_R = 5 k_r theta tau / (B delta), B = 1 + tau/tau1,
+    theta the largest of theta0 and the face temperatures."""
+    B = 1.0 + p["tau"] / p["tau1"]
+    return int(np.ceil(3.0 * 5.0 * p["kr"] * th_max * p["tau"] / (B * p["delta"])))
+
+
+def _nu_for_substeps(n, th_max):
+    """A viscosity in the middle of the range whose line diffusion takes
+    exactly n sub-steps (clear of the rounding at either end)."""
+    def first_nu_with(m):
+        lo, hi = 1e-3, 100.0
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if _line_substeps(resolve(mid, 0.71, 0.8, 2.0), th_max) < m:
+                lo = mid
+            else:
+                hi = mid
+        return hi
+    nu = 0.5 * (first_nu_with(n) + first_nu_with(n + 1))
+    assert _line_substeps(resolve(nu, 0.71, 0.8, 2.0), th_max) == n
+    return nu
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_line_kernel_at_its_sub_step_limit(precision):
+    """Lines between walls at 63 sub-steps (the line kernel's limit: each
+    work-group then produces 256 - 128 = 128 cells, so a 2100-cell line takes
+    17 work-groups per sublattice) and at 64 (beyond it; with 4200 sites, more
+    than the one-work-group kernel takes, the reference kernels run): the
+    timing records show which path ran, and the line kernel matches the
+    reference kernels to round-off."""
+    import paper_2201_05280_amd as pgk
+    th0 = oracle.THETA0
+    walls = [(pgk.WALL, 1.0, (0.0, 0.0, 0.0), 0.95 * th0), (pgk.WALL, 1.0, (0.0, 0.03, 0.0), 1.05 * th0)]
+    bar = 1e-13 if precision == 0 else 1e-6
+    dims, steps = (2100, 1, 1), 12
+    for n in (63, 64):
+        p = resolve(_nu_for_substeps(n, 1.05 * th0), 0.71, 0.8, 2.0)
+        f = inputs.random_smooth(*dims, seed=n, amp_u=0.03, amp_th=0.05)
+        s = pgk.Solver(*dims, precision=precision, bc_x=(pgk.WALL, pgk.WALL))
+        s.set_params(p["tau"], p["tau1"], p["b"], p["kr"], p["delta"])
+        for side in (0, 1):
+            _, rho, u, th = walls[side]
+            s.set_bc_x(side, rho, u, th)
+        s.init(f["rho"], f["u"], f["thT"], f["thR"])
+        s.set_timing(True)
+        s.step(steps)
+        kt = s.kernel_times()
+        a = s.moments()
+        s.close()
+        # the line kernel is one record per step under the diffusion entry; the
+        # reference path records its MacCormack launch and then its sub-steps
+        assert kt["k_dif"][1] == steps, kt
+        assert kt["k_mc"][1] == (0 if n <= 63 else steps), kt
+        b = _run(dims, p, f, precision, walls, True, steps)
+        for k in FLOOR:
+            err = float(np.abs(a[k] - b[k]).max()) / max(float(np.abs(b[k]).max()), FLOOR[k])
+            assert err <= bar, (n, precision, k, err)
