@@ -167,12 +167,19 @@ def test_state_save_load_resumes_training_bit_for_bit(tmp_path):
     for x0, x1 in zip(s0[:4], s1[:4]):
         assert np.array_equal(x0, x1)
     assert s0[4] == s1[4] == 8
-    # one more minibatch step from the same state on both gives the same weights
-    # up to the order of the float atomics of the gradient sums
+    # one more minibatch step, and one more trained epoch, from the same state
+    # on both give the same bits (the gradient sums run in a fixed order)
     for net in (a, b):
         net.loss_grad(X[:256], Y[:256])
         net.adam_step(1e-3)
-    assert np.abs(a.state()[0] - b.state()[0]).max() < 1e-6
+    assert np.array_equal(a.state()[0], b.state()[0])
+    la = a.train(X, Y, epochs=1, batch=256, lr=1e-3, seed=4)
+    lb = b.train(X, Y, epochs=1, batch=256, lr=1e-3, seed=4)
+    sa, sb = a.state(), b.state()
+    assert np.array_equal(la, lb)
+    for x0, x1 in zip(sa[:4], sb[:4]):
+        assert np.array_equal(x0, x1)
+    assert sa[4] == sb[4] == 13
     with pytest.raises(RuntimeError):
         bad = tmp_path / "bad.bin"
         bad.write_bytes(b"not a network")
