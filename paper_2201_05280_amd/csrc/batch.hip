@@ -103,6 +103,14 @@ __device__ __forceinline__ void dif_line_coef(int s, const double *__restrict__ 
     cp = c[1];
 }
 
+// one FTCS sub-step of a cell, with its fused multiply-adds written out so
+// that every diffusion path of the batched kernel (registers, LDS, global
+// memory) gives the same bits whatever the launch shape picks
+__device__ __forceinline__ double ftcs(double t, double tm, double tp, double cm, double cp)
+{
+    return fma(cp, tp - t, fma(cm, tm - t, t));
+}
+
 __device__ __forceinline__ double dif_line(int s, const double *tin, const double *cm, const double *cp,
                                            const Consts &k)
 {
@@ -113,7 +121,22 @@ __device__ __forceinline__ double dif_line(int s, const double *tin, const doubl
     else tm = k.bc[0] != PGK_PERIODIC ? k.thbc[0] : tin[s + k.nx - 1];
     if (x + 1 < k.nx) tp = tin[s + 1];
     else tp = k.bc[1] != PGK_PERIODIC ? k.thbc[1] : tin[s + 1 - k.nx];
-    return t + cm[s] * (tm - t) + cp[s] * (tp - t);
+    return ftcs(t, tm, tp, cm[s], cp[s]);
+}
+
+// The same sub-step with the line in global memory (lines too long for LDS):
+// the conductances of dif_line_coef recomputed from aux at every sub-step
+template <int VAR>
+__device__ __forceinline__ double dif_line_global(int s, const double *__restrict__ tin,
+                                                  const double *__restrict__ aux, const Consts &k)
+{
+    double cm, cp;
+    dif_line_coef<VAR>(s, aux, k, cm, cp);
+    const int sub = s >= k.nx, x = s - sub * k.nx;
+    const double t = tin[s];
+    const double tm = x > 0 ? tin[s - 1] : k.thbc[0];   // bounded faces (every batched case)
+    const double tp = x + 1 < k.nx ? tin[s + 1] : k.thbc[1];
+    return ftcs(t, tm, tp, cm, cp);
 }
 
 // The same sub-steps with the line in registers: wavefront `sub` holds the
@@ -174,7 +197,7 @@ __device__ __forceinline__ void dif_chain(int sub, const double *__restrict__ tm
             double d = j + 1 < DW_P ? lane_bcast(t[j + 1], 0) : 0.0;             // x + 1, lane 63
             double tm = lane == 0 ? b : a, tp = lane == 63 ? d : c;
             if (lane + 64 * j == L - 1) tp = k.thbc[1];
-            tn[j] = t[j] + cm[j] * (tm - t[j]) + cp[j] * (tp - t[j]);
+            tn[j] = ftcs(t[j], tm, tp, cm[j], cp[j]);
         }
 #pragma unroll
         for (int j = 0; j < DW_P; j++) t[j] = tn[j];
@@ -185,6 +208,74 @@ __device__ __forceinline__ void dif_chain(int sub, const double *__restrict__ tm
         if (x < L) {
             int s = sub * L + x;
             double v = thR[s];
+            if (VAR == PGK_CN) thR[s] = t[j] + (that_[s] - v);
+            else thR[s] = (t[j] + k.X * v) * k.inv1X;
+        }
+    }
+}
+
+// The same sub-steps for longer lines on every wavefront of the work-group:
+// W = NTH / 128 wavefronts per sublattice, wavefront w of a sublattice holding
+// the segment x in [w S, (w + 1) S), S = 64 DQ_P, lane l the cells
+// x = w S + l + 64 j (j < DQ_P).  Inside a segment the neighbours come by
+// cross-lane moves as in dif_chain; the cells on either side of a segment come
+// from the neighbouring wavefronts through LDS (each publishes its first and
+// last cell), with one barrier per sub-step (double-buffered slots: a
+// wavefront writes the other slot next sub-step, and cannot write this one
+// again before every wavefront has passed the next barrier).  Every thread of
+// the work-group must call it.  Bounded faces only; the arithmetic is that of
+// dif_line.
+constexpr int DQ_P = 8;    // cells per lane: lines of up to 512 W cells
+
+template <int VAR, int NTH>
+__device__ __forceinline__ void dif_wchain(const double *__restrict__ tmc, const double *__restrict__ aux,
+                                           const double *__restrict__ that_, double *__restrict__ thR,
+                                           const Consts &k, double *xch)
+{
+    constexpr int W = NTH / 128;
+    constexpr int S = 64 * DQ_P;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sub = wave / W, w = wave - sub * W, x0 = w * S, L = k.nx;
+    double t[DQ_P], cm[DQ_P], cp[DQ_P];
+#pragma unroll
+    for (int j = 0; j < DQ_P; j++) {
+        const int x = x0 + lane + 64 * j;
+        t[j] = cm[j] = cp[j] = 0.0;
+        if (x < L) {
+            const int s = sub * L + x;
+            t[j] = tmc[s];
+            dif_line_coef<VAR>(s, aux, k, cm[j], cp[j]);
+        }
+    }
+    // xch: [parity][sublattice][wavefront][first, last]
+    auto slot = [&](int par, int ww, int end) { return ((par * 2 + sub) * W + ww) * 2 + end; };
+    for (int it = 0; it < k.nsub; it++) {
+        const int par = it & 1;
+        if (lane == 0) xch[slot(par, w, 0)] = t[0];
+        if (lane == 63) xch[slot(par, w, 1)] = t[DQ_P - 1];
+        __syncthreads();
+        const double left = w > 0 ? xch[slot(par, w - 1, 1)] : k.thbc[0];    // cell x0 - 1
+        const double right = w + 1 < W ? xch[slot(par, w + 1, 0)] : 0.0;     // cell x0 + S
+        double tn[DQ_P];
+#pragma unroll
+        for (int j = 0; j < DQ_P; j++) {
+            double a = lane_prev(t[j]);                                       // x - 1, lanes 1..63
+            double b = j > 0 ? lane_bcast(t[j - 1], 63) : left;               // x - 1, lane 0
+            double c = lane_next(t[j]);                                       // x + 1, lanes 0..62
+            double d = j + 1 < DQ_P ? lane_bcast(t[j + 1], 0) : right;        // x + 1, lane 63
+            double tm = lane == 0 ? b : a, tp = lane == 63 ? d : c;
+            if (x0 + lane + 64 * j == L - 1) tp = k.thbc[1];
+            tn[j] = ftcs(t[j], tm, tp, cm[j], cp[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < DQ_P; j++) t[j] = tn[j];
+    }
+#pragma unroll
+    for (int j = 0; j < DQ_P; j++) {
+        const int x = x0 + lane + 64 * j;
+        if (x < L) {
+            const int s = sub * L + x;
+            const double v = thR[s];
             if (VAR == PGK_CN) thR[s] = t[j] + (that_[s] - v);
             else thR[s] = (t[j] + k.X * v) * k.inv1X;
         }
@@ -267,6 +358,10 @@ __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
         __syncthreads();
         if (k.nx <= 64 * DW_P) {
             if (tid < 128) dif_chain<VAR>(tid >> 6, tmc, aux, that_, thR, k);
+        } else if (k.nx <= (NTH / 128) * 64 * DQ_P && (NTH == 256 || ns > a.lds_sites)) {
+            // (with 512 threads the LDS path below is the faster one where it fits)
+            __shared__ double xch[2 * 2 * (NTH / 128) * 2];
+            dif_wchain<VAR, NTH>(tmc, aux, that_, thR, k, xch);
         } else if (ns <= a.lds_sites) {
             extern __shared__ double lds[];
             double *tin = lds, *tout = lds + a.lds_sites, *cm = lds + 2 * a.lds_sites, *cp = lds + 3 * a.lds_sites;
@@ -290,13 +385,17 @@ __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
         } else {
             double *tin = tmc, *tout = tmc2;
             for (int it = 0; it + 1 < k.nsub; it++) {
-                for (int s = tid; s < ns; s += NTH) dif_site<double, VAR, BND_X, false>(s, tin, tout, that_, aux, thR, k);
+                for (int s = tid; s < ns; s += NTH) tout[s] = dif_line_global<VAR>(s, tin, aux, k);
                 __syncthreads();
                 double *t = tin;
                 tin = tout;
                 tout = t;
             }
-            for (int s = tid; s < ns; s += NTH) dif_site<double, VAR, BND_X, true>(s, tin, tout, that_, aux, thR, k);
+            for (int s = tid; s < ns; s += NTH) {
+                double tdif = dif_line_global<VAR>(s, tin, aux, k), v = thR[s];
+                if (VAR == PGK_CN) thR[s] = tdif + (that_[s] - v);
+                else thR[s] = (tdif + k.X * v) * k.inv1X;
+            }
         }
         __syncthreads();
         cur ^= 1;
