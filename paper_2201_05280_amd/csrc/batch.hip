@@ -44,11 +44,13 @@ struct BatchArgs {
     long long max_steps;
     double tol;
     int lds_sites;      // cases with ns <= lds_sites diffuse theta_R in LDS
+    int chain_sites;    // cases with ns <= chain_sites may keep their conductances in the dynamic LDS
 };
 
 // dynamic LDS of k_batch: theta ping-pong and the two face coefficients
 constexpr int LDS_ARRAYS = 4;
 constexpr int LDS_SITES_MAX = 2048;   // 64 KiB
+constexpr int CHAIN_SITES_MAX = 8192; // 128 KiB of conductances (two per site)
 
 constexpr int GHOSTS_PER_CASE = 2 * NQ * NSLOT;   // ny = nz = 1
 
@@ -216,35 +218,49 @@ __device__ __forceinline__ void dif_chain(int sub, const double *__restrict__ tm
 
 // The same sub-steps for longer lines on every wavefront of the work-group:
 // W = NTH / 128 wavefronts per sublattice, wavefront w of a sublattice holding
-// the segment x in [w S, (w + 1) S), S = 64 DQ_P, lane l the cells
-// x = w S + l + 64 j (j < DQ_P).  Inside a segment the neighbours come by
+// the segment x in [w S, (w + 1) S), S = 64 P, lane l the cells
+// x = w S + l + 64 j (j < P).  Inside a segment the neighbours come by
 // cross-lane moves as in dif_chain; the cells on either side of a segment come
 // from the neighbouring wavefronts through LDS (each publishes its first and
 // last cell), with one barrier per sub-step (double-buffered slots: a
 // wavefront writes the other slot next sub-step, and cannot write this one
-// again before every wavefront has passed the next barrier).  Every thread of
-// the work-group must call it.  Bounded faces only; the arithmetic is that of
-// dif_line.
-constexpr int DQ_P = 8;    // cells per lane: lines of up to 512 W cells
+// again before every wavefront has passed the next barrier).  LDSC: the two
+// conductances of each cell live in cl ([2][ns], each read only by the thread
+// that wrote it) instead of registers, which leaves room for P = 16.  Every
+// thread of the work-group must call it.  Bounded faces only; the arithmetic
+// is that of dif_line.
+constexpr int DQ_P = 8;    // cells per lane with the conductances in registers: lines of up to 512 W cells
+// with the conductances in LDS, only with 256 threads (the 512-thread kernel
+// has no registers to spare): 32 cells per lane, lines of up to 4096 cells
+constexpr int DQL_P = 32;
 
-template <int VAR, int NTH>
+template <int VAR, int NTH, int P, bool LDSC>
 __device__ __forceinline__ void dif_wchain(const double *__restrict__ tmc, const double *__restrict__ aux,
                                            const double *__restrict__ that_, double *__restrict__ thR,
-                                           const Consts &k, double *xch)
+                                           const Consts &k, double *xch, double *cl)
 {
     constexpr int W = NTH / 128;
-    constexpr int S = 64 * DQ_P;
+    constexpr int S = 64 * P;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int sub = wave / W, w = wave - sub * W, x0 = w * S, L = k.nx;
-    double t[DQ_P], cm[DQ_P], cp[DQ_P];
+    double t[P], cmr[LDSC ? 1 : P], cpr[LDSC ? 1 : P];
 #pragma unroll
-    for (int j = 0; j < DQ_P; j++) {
+    for (int j = 0; j < P; j++) {
         const int x = x0 + lane + 64 * j;
-        t[j] = cm[j] = cp[j] = 0.0;
+        t[j] = 0.0;
+        if constexpr (!LDSC) cmr[j] = cpr[j] = 0.0;
         if (x < L) {
             const int s = sub * L + x;
+            double cm, cp;
             t[j] = tmc[s];
-            dif_line_coef<VAR>(s, aux, k, cm[j], cp[j]);
+            dif_line_coef<VAR>(s, aux, k, cm, cp);
+            if constexpr (LDSC) {
+                cl[s] = cm;
+                cl[k.ns + s] = cp;
+            } else {
+                cmr[j] = cm;
+                cpr[j] = cp;
+            }
         }
     }
     // xch: [parity][sublattice][wavefront][first, last]
@@ -252,26 +268,37 @@ __device__ __forceinline__ void dif_wchain(const double *__restrict__ tmc, const
     for (int it = 0; it < k.nsub; it++) {
         const int par = it & 1;
         if (lane == 0) xch[slot(par, w, 0)] = t[0];
-        if (lane == 63) xch[slot(par, w, 1)] = t[DQ_P - 1];
+        if (lane == 63) xch[slot(par, w, 1)] = t[P - 1];
         __syncthreads();
-        const double left = w > 0 ? xch[slot(par, w - 1, 1)] : k.thbc[0];    // cell x0 - 1
         const double right = w + 1 < W ? xch[slot(par, w + 1, 0)] : 0.0;     // cell x0 + S
-        double tn[DQ_P];
+        // in place, j ascending: slot j + 1 still holds the old values, and the
+        // old lane-63 value of slot j - 1 is carried (cell x0 - 1 for j = 0)
+        double carry = w > 0 ? xch[slot(par, w - 1, 1)] : k.thbc[0];
 #pragma unroll
-        for (int j = 0; j < DQ_P; j++) {
-            double a = lane_prev(t[j]);                                       // x - 1, lanes 1..63
-            double b = j > 0 ? lane_bcast(t[j - 1], 63) : left;               // x - 1, lane 0
-            double c = lane_next(t[j]);                                       // x + 1, lanes 0..62
-            double d = j + 1 < DQ_P ? lane_bcast(t[j + 1], 0) : right;        // x + 1, lane 63
-            double tm = lane == 0 ? b : a, tp = lane == 63 ? d : c;
-            if (x0 + lane + 64 * j == L - 1) tp = k.thbc[1];
-            tn[j] = ftcs(t[j], tm, tp, cm[j], cp[j]);
+        for (int j = 0; j < P; j++) {
+            const double old = t[j];
+            double a = lane_prev(old);                                        // x - 1, lanes 1..63
+            double c = lane_next(old);                                        // x + 1, lanes 0..62
+            double d = j + 1 < P ? lane_bcast(t[j + 1], 0) : right;           // x + 1, lane 63
+            double tm = lane == 0 ? carry : a, tp = lane == 63 ? d : c;
+            carry = lane_bcast(old, 63);
+            const int x = x0 + lane + 64 * j;
+            if (x == L - 1) tp = k.thbc[1];
+            double cm, cp;
+            if constexpr (LDSC) {
+                const bool in = x < L;
+                const int s = sub * L + (in ? x : 0);
+                cm = in ? cl[s] : 0.0;
+                cp = in ? cl[k.ns + s] : 0.0;
+            } else {
+                cm = cmr[j];
+                cp = cpr[j];
+            }
+            t[j] = ftcs(old, tm, tp, cm, cp);
         }
-#pragma unroll
-        for (int j = 0; j < DQ_P; j++) t[j] = tn[j];
     }
 #pragma unroll
-    for (int j = 0; j < DQ_P; j++) {
+    for (int j = 0; j < P; j++) {
         const int x = x0 + lane + 64 * j;
         if (x < L) {
             const int s = sub * L + x;
@@ -321,6 +348,7 @@ __device__ __forceinline__ void bc_line(const double *__restrict__ src, double *
 template <int VAR, int NTH, bool E2CAP>
 __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
 {
+    __shared__ double xch[2 * 2 * (NTH / 128) * 2];   // segment ends of the diffusion chains
     const int c = a.order[blockIdx.x];
     if (a.status[c] != PGK_CASE_RUNNING) return;
     const BatchCase &bc = a.cases[c];
@@ -360,8 +388,12 @@ __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
             if (tid < 128) dif_chain<VAR>(tid >> 6, tmc, aux, that_, thR, k);
         } else if (k.nx <= (NTH / 128) * 64 * DQ_P && (NTH == 256 || ns > a.lds_sites)) {
             // (with 512 threads the LDS path below is the faster one where it fits)
-            __shared__ double xch[2 * 2 * (NTH / 128) * 2];
-            dif_wchain<VAR, NTH>(tmc, aux, that_, thR, k, xch);
+            dif_wchain<VAR, NTH, DQ_P, false>(tmc, aux, that_, thR, k, xch, nullptr);
+        } else if (NTH == 256 && ns > a.lds_sites && k.nx <= (NTH / 128) * 64 * DQL_P && ns <= a.chain_sites) {
+            if constexpr (NTH == 256) {
+                extern __shared__ double lds[];
+                dif_wchain<VAR, NTH, DQL_P, true>(tmc, aux, that_, thR, k, xch, lds);
+            }
         } else if (ns <= a.lds_sites) {
             extern __shared__ double lds[];
             double *tin = lds, *tout = lds + a.lds_sites, *cm = lds + 2 * a.lds_sites, *cp = lds + 3 * a.lds_sites;
@@ -725,6 +757,7 @@ extern "C" int pgk_batch_create(const pgk_case *cases, int n, void *stream, void
     long long maxns = 0;
     for (auto &c : b->host_cases) maxns = std::max<long long>(maxns, c.k.ns);
     a.lds_sites = (int)std::min<long long>(maxns, LDS_SITES_MAX);
+    a.chain_sites = (int)std::min<long long>(maxns, CHAIN_SITES_MAX);
     // slots ordered by size, longest first (the cost model: work per step)
     std::vector<int> order(n);
     for (int i = 0; i < n; i++) order[i] = i;
@@ -773,6 +806,27 @@ extern "C" int pgk_batch_config(pgk_batch *b, int wg, int K)
     return PGK_OK;
 }
 
+// dynamic LDS of a launch: the arrays of the LDS diffusion path, or the
+// conductances of the longest chain, whichever is larger
+static size_t batch_lds_bytes(const BatchArgs &a)
+{
+    return std::max(sizeof(double) * LDS_ARRAYS * a.lds_sites, sizeof(double) * 2 * a.chain_sites);
+}
+
+// let every batched kernel take `bytes` of dynamic LDS (above the default 64 KiB)
+static hipError_t allow_batch_lds(size_t bytes)
+{
+    if (bytes <= 65536) return hipSuccess;
+    const void *fns[] = {(const void *)&k_batch<PGK_CN, 256, true>, (const void *)&k_batch<PGK_LIT, 256, true>,
+                         (const void *)&k_batch<PGK_CN, 256, false>, (const void *)&k_batch<PGK_CN, 512, false>,
+                         (const void *)&k_batch<PGK_LIT, 256, false>, (const void *)&k_batch<PGK_LIT, 512, false>};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // the instantiated graph of one chunk (wg, K, variant), captured on first use
 static int chunk_graph(pgk_batch *b, int wg, int K, int variant, hipGraphExec_t *out)
 {
@@ -780,8 +834,9 @@ static int chunk_graph(pgk_batch *b, int wg, int K, int variant, hipGraphExec_t 
     auto it = b->graphs.find(key);
     if (it == b->graphs.end()) {
         hipGraph_t g;
+        BHIP(b, allow_batch_lds(batch_lds_bytes(b->args)));
         BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        const size_t lds = sizeof(double) * LDS_ARRAYS * b->args.lds_sites;
+        const size_t lds = batch_lds_bytes(b->args);
         dim3 grid(b->n);
         if (b->has_e2) {
             // the E2 Newton needs more registers than two wavefronts per SIMD leave

@@ -38,10 +38,15 @@ def _cases():
          dict(rho=(1.0, 1.05), u=((0.02, 0, 0), (0.019, 0, 0)), theta=(TH0, TH0 * 1.03))),
         # several diffusion sub-steps per step, in LDS
         (40, pgk.WALL, (0.6, 0.71, 0.8, 2.0), dict(u=((0, 0, 0), (0, 0.04, 0)), theta=(TH0, TH0 * 1.05))),
-        # 700 cells: beyond the register-resident diffusion (512 cells), diffused in LDS
+        # 700 cells: beyond the two-wavefront chain (512 cells): the chain over
+        # every wavefront with 256 threads, the LDS path with 512
         (700, pgk.WALL, (0.4, 0.8, 1.0, 3.0), dict(u=((0, 0.0, 0), (0, 0.02, 0)), theta=(TH0, TH0 * 1.02))),
-        # 2060 sites: beyond the LDS diffusion path (2048 sites), diffused in global memory
+        # 2060 sites: beyond the LDS path (2048 sites): the chain with its
+        # conductances in LDS with 256 threads, the register chain with 512
         (1030, pgk.WALL, (0.3, 0.8, 1.0, 2.0), dict(u=((0, 0.01, 0), (0, 0.03, 0)), theta=(TH0 * 1.01, TH0))),
+        # 8400 sites: beyond every chain (8192 sites of conductances in LDS):
+        # diffused in global memory
+        (4200, pgk.WALL, (0.3, 0.8, 1.0, 2.0), dict(u=((0, 0.0, 0), (0, 0.02, 0)), theta=(TH0, TH0 * 1.01))),
     ]
     for L, bc, tg, faces in specs:
         p = resolve(*tg)
