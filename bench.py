@@ -564,7 +564,7 @@ def sweep(args, extra=None):
                               min(c["Kn"] for c in cc), max(c["Kn"] for c in cc))
     inside = np.array([c["kind"] in rng_kind and rng_kind[c["kind"]][0] <= c["Ma"] <= rng_kind[c["kind"]][1]
                        and rng_kind[c["kind"]][2] <= c["Kn"] <= rng_kind[c["kind"]][3] for c in test])
-    wf, cf = C.fields_from_prediction(test, y), C.cold_fields(test)
+    wf, cf = C.fields_from_prediction(test, y, recentre_shocks=args.sweep_recentre), C.cold_fields(test)
     site_in = np.repeat(inside, [2 * c["L"] for c in test])
     for key in ("rho", "thT", "thR"):
         wf[key] = np.where(site_in, wf[key], cf[key])
@@ -670,7 +670,8 @@ def sweep(args, extra=None):
         "mlp_train_points": int(len(X)), "mlp_train_points_from_this_training_set": own_points,
         "held_out_warm_started": {"couette": int((inside & ~is_shock).sum()), "shock": int((inside & is_shock).sum()),
                                   "rule": "Mach and Kn within the range of the converged training cases of the "
-                                          "same kind; every other case starts cold"},
+                                          "same kind; every other case starts cold",
+                                  "shock_profiles_recentred_at_L/2": bool(args.sweep_recentre)},
         "warm_fallback_to_cold_start": {
             "cases": len(redo), "rerun_time": round(t_redo, 2),
             "rule": "a warm-started case whose run diverged runs again from the cold start (included in the "
@@ -782,6 +783,8 @@ def main():
     ap.add_argument("--sweep-mlp-batch", type=int, default=2048, help="MLP training minibatch")
     ap.add_argument("--sweep-lr-schedule", default="2e-3:40,5e-4:30,1.25e-4:30",
                     help="MLP training stages lr:epochs[,lr:epochs...] (Adam state carried across stages)")
+    ap.add_argument("--sweep-recentre", type=int, default=1,
+                    help="1: move each predicted shock to the cold start's position (L/2); 0: as predicted")
     ap.add_argument("--sweep-plain", type=int, default=8)
     ap.add_argument("--sweep-plain-cap", type=float, default=10.0)
     ap.add_argument("--sweep-shock-frac", type=float, default=0.5)

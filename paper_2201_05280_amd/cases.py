@@ -196,8 +196,26 @@ def targets(cases, m):
     return np.concatenate(out)
 
 
-def fields_from_prediction(cases, y):
-    """Moment fields (for pgk_batch_init) from normalised network outputs."""
+def recentre_shock(L, ys):
+    """A predicted shock profile (normalised outputs of one line's sites)
+    shifted along x so that its density crosses the mean of the two states at
+    L/2, where the cold start puts its shock; the end plateaus extend."""
+    x = positions(L, 1, 1)[0]
+    o = np.argsort(x)
+    xs, f = x[o], ys[o, 0]
+    k = int(np.argmax(f > 0.5))
+    if k == 0 or not (f[k] > 0.5):
+        return ys
+    pos = xs[k - 1] + (0.5 - f[k - 1]) / (f[k] - f[k - 1]) * (xs[k] - xs[k - 1])
+    out = np.empty_like(ys)
+    for j in range(ys.shape[1]):
+        out[:, j] = np.interp(x + (pos - 0.5 * L), xs, ys[o, j])
+    return out
+
+
+def fields_from_prediction(cases, y, recentre_shocks=False):
+    """Moment fields (for pgk_batch_init) from normalised network outputs;
+    recentre_shocks: each shock profile moved to the cold start's position."""
     ns = y.shape[0]
     rho, u, thT, thR = np.empty(ns), np.zeros((3, ns)), np.empty(ns), np.empty(ns)
     o = 0
@@ -207,10 +225,11 @@ def fields_from_prediction(cases, y):
         sl = slice(o, o + n)
         if c["kind"] == SHOCK:
             (r1, u1, t1), (r2, u2, t2) = c["up"], c["down"]
-            rho[sl] = r1 + (r2 - r1) * y[sl, 0]
-            u[0, sl] = u1 + (u2 - u1) * y[sl, 1]
-            thT[sl] = t1 + (t2 - t1) * y[sl, 2]
-            thR[sl] = t1 + (t2 - t1) * y[sl, 3]
+            ys = recentre_shock(c["L"], y[sl]) if recentre_shocks else y[sl]
+            rho[sl] = r1 + (r2 - r1) * ys[:, 0]
+            u[0, sl] = u1 + (u2 - u1) * ys[:, 1]
+            thT[sl] = t1 + (t2 - t1) * ys[:, 2]
+            thR[sl] = t1 + (t2 - t1) * ys[:, 3]
         else:
             rho[sl] = 1.0 + U ** 2 * y[sl, 0]
             u[1, sl] = U * y[sl, 1]
