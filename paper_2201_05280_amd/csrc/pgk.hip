@@ -112,10 +112,11 @@ __global__ __launch_bounds__(TR_SMALL_WG) void k_tr_small(const double *__restri
 // launch (any length; at most TL_HMAX - 1 sub-steps).  Unlike the one-work-group
 // kernel it keeps every field of a sub-step in LDS, which also makes it the
 // faster of the two on short lines.  Along a line the transport is two
-// independent 1D problems, one per sublattice.  A work-group owns TL_WG - 2 H cells of
-// one sublattice and stages them with a halo of H = nsub + 1 cells on each
-// side (theta_hat, u_x, rho, kfac rho theta), TL_WG - 2 H cells in all so that
-// every thread holds one window cell; MacCormack and every FTCS
+// independent 1D problems, one per sublattice.  A work-group of WG threads owns
+// WG - 2 H cells of one sublattice and stages them with a halo of H = nsub + 1
+// cells on each side (theta_hat, u_x, rho, kfac rho theta), WG cells in all so
+// that every thread holds one window cell (WG = 128 while the halos take at
+// most a quarter of it, else 256); MacCormack and every FTCS
 // sub-step then run in LDS, the valid window shrinking by one cell per stage,
 // so the halo cells are recomputed by both neighbours and no work-group waits
 // for another.  The y and z terms of the stencils of mc_site / dif_site vanish
@@ -123,21 +124,21 @@ __global__ __launch_bounds__(TR_SMALL_WG) void k_tr_small(const double *__restri
 // the x terms are evaluated in the same order; the compiler's fused
 // multiply-adds may still round differently, so the results agree with
 // k_mc + k_dif to round-off (a last bit here and there), not bit for bit.
-#ifndef PGK_TL_WG
-#define PGK_TL_WG 256
-#endif
-constexpr int TL_WG = PGK_TL_WG, TL_HMAX = 64, TL_L = TL_WG;
+constexpr int TL_HMAX = 64;
 
-// cells of a line each work-group of k_tr_line produces (its window: these
-// and a halo of nsub + 1 cells on each side, one per thread)
-__host__ __device__ inline int tl_cells(int nsub) { return TL_WG - 2 * (nsub + 1); }
+// work-group size of k_tr_line for nsub sub-steps, and the cells of a line each
+// work-group produces (its window: these and a halo of nsub + 1 cells on each
+// side, one per thread)
+__host__ __device__ inline int tl_wg(int nsub) { return 2 * (nsub + 1) <= 32 ? 128 : 256; }
+__host__ __device__ inline int tl_cells(int nsub, int wg) { return wg - 2 * (nsub + 1); }
 
-template <typename A, int VAR, int BOUNDED>
+template <typename A, int VAR, int BOUNDED, int TL_WG>
 __global__ __launch_bounds__(TL_WG) void k_tr_line(const double *__restrict__ that_, const A *__restrict__ aux,
                                                    double *__restrict__ thR, Consts k)
 {
+    constexpr int TL_L = TL_WG;
     __shared__ double l_th[TL_L], l_u[TL_L], l_rho[TL_L], l_ks[TL_L], l_a[TL_L], l_b[TL_L];
-    const int C = tl_cells(k.nsub), nx = k.nx, nchunk = (nx + C - 1) / C;
+    const int C = tl_cells(k.nsub, TL_WG), nx = k.nx, nchunk = (nx + C - 1) / C;
     const int sub = blockIdx.x / nchunk, x0 = (blockIdx.x - sub * nchunk) * C;
     const int H = k.nsub + 1, nout = min(C, nx - x0), Lw = nout + 2 * H;   // Lw <= TL_WG
     const int base = sub * nx, tid = threadIdx.x;
@@ -1130,9 +1131,13 @@ static int step_t(pgk_ctx *c, int64_t n)
         mark(c, 0);
         if (!c->transport_ref && (BND || c->k.nsub > 1) && c->k.ny == 1 && c->k.nz == 1 &&
             c->k.nsub + 1 <= TL_HMAX) {
-            const int C = tl_cells(c->k.nsub), nchunk = (c->k.nx + C - 1) / C;
-            hipLaunchKernelGGL((k_tr_line<A, VAR, BND>), dim3(2 * nchunk), dim3(TL_WG), 0, c->stream, c->that_,
-                               (const A *)c->aux, (double *)c->buf[PGK_BUF_THETAR], c->k);
+            const int wg = tl_wg(c->k.nsub), C = tl_cells(c->k.nsub, wg), nchunk = (c->k.nx + C - 1) / C;
+            if (wg == 128)
+                hipLaunchKernelGGL((k_tr_line<A, VAR, BND, 128>), dim3(2 * nchunk), dim3(128), 0, c->stream,
+                                   c->that_, (const A *)c->aux, (double *)c->buf[PGK_BUF_THETAR], c->k);
+            else
+                hipLaunchKernelGGL((k_tr_line<A, VAR, BND, 256>), dim3(2 * nchunk), dim3(256), 0, c->stream,
+                                   c->that_, (const A *)c->aux, (double *)c->buf[PGK_BUF_THETAR], c->k);
             mark(c, 2);
         } else if (!c->transport_ref && (BND || c->k.nsub > 1) && c->k.ns <= TR_SMALL) {
             hipLaunchKernelGGL((k_tr_small<A, VAR, BND>), dim3(1), dim3(TR_SMALL_WG), sizeof(double) * 2 * c->k.ns,
