@@ -11,7 +11,10 @@
 // sum_i F_i phi_i phi_i^T gives the step.  It stops once the moments are met
 // to 1e-14 and the last step moved no exponent by more than 1e-8, so that the
 // result is the constrained minimiser to round-off, not a function of the
-// starting point.  The same code runs on the host (face states) and in the kernels.
+// starting point; a full step of at most 1e-8 taken where the moments were
+// already met to 1e-8 ends the solve at once (the check after it would pass
+// and return the same multipliers).  The same code runs on the host (face
+// states) and in the kernels.
 //
 // The opposite velocities +-c of a pair share the even part of the exponent
 // and differ in the sign of the odd part (the three linear multipliers), so
@@ -328,6 +331,11 @@ __host__ __device__ __forceinline__ int e2_newton(const double *w6, const double
 #pragma unroll
         for (int k = 0; k < E2_NL; k++) l[k] += damp * rhs[k];
         if (!(fabs(l[0]) < 1e300)) return -1;   // NaN or overflow
+        // a full step this small from a point this close leaves an error of
+        // the order of its square (Newton's quadratic convergence), below
+        // round-off: the confirming pass would find the moments met and return
+        // these same multipliers, so return them now
+        if (maxd <= 1e-8 && res <= 1e-8 * scale) return it;
     }
     return -1;
 }
