@@ -384,7 +384,11 @@ __global__ __launch_bounds__(NTH) void k_batch(BatchArgs a, int K)
         __syncthreads();
         for (int s = tid; s < ns; s += NTH) mc_site<double, BND_X>(s, that_, aux, tmc, k);
         __syncthreads();
-        if (k.nx <= 64 * DW_P) {
+        if (NTH == 512 && k.nx <= (NTH / 128) * 64 * 2) {
+            // short lines on every wavefront (two cells per lane): faster than two
+            // wavefronts alone with 512 threads, slower with 256
+            if constexpr (NTH == 512) dif_wchain<VAR, NTH, 2, false>(tmc, aux, that_, thR, k, xch, nullptr);
+        } else if (k.nx <= 64 * DW_P) {
             if (tid < 128) dif_chain<VAR>(tid >> 6, tmc, aux, that_, thR, k);
         } else if (k.nx <= (NTH / 128) * 64 * DQ_P && (NTH == 256 || ns > a.lds_sites)) {
             // (with 512 threads the LDS path below is the faster one where it fits)
