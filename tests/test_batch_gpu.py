@@ -44,6 +44,9 @@ def _cases():
         # 2060 sites: beyond the LDS path (2048 sites): the chain with its
         # conductances in LDS with 256 threads, the register chain with 512
         (1030, pgk.WALL, (0.3, 0.8, 1.0, 2.0), dict(u=((0, 0.01, 0), (0, 0.03, 0)), theta=(TH0 * 1.01, TH0))),
+        # 8192 sites: the chain with its conductances in LDS at its limit
+        # (128 KiB) with 256 threads, global memory with 512
+        (4096, pgk.WALL, (0.5, 0.75, 1.2, 2.0), dict(u=((0, 0.01, 0), (0, 0.0, 0)), theta=(TH0 * 1.02, TH0))),
         # 8400 sites: beyond every chain (8192 sites of conductances in LDS):
         # diffused in global memory
         (4200, pgk.WALL, (0.3, 0.8, 1.0, 2.0), dict(u=((0, 0.0, 0), (0, 0.02, 0)), theta=(TH0, TH0 * 1.01))),
