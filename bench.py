@@ -357,6 +357,18 @@ def shock_summary(max_steps=60000):
     return out
 
 
+def mlp_minibatch_summary(sizes=(4096, 8192)):
+    """The same training at larger minibatches: more points per Adam step run
+    the two kernels over more of the chip (higher points/s), and fewer Adam
+    steps per epoch leave a higher loss after the same epochs."""
+    out = []
+    for mb in sizes:
+        r = mlp_train_summary(batch=mb)
+        out.append({k: r[k] for k in ("minibatch", "seconds", "us_per_minibatch", "points_per_s", "TFLOPs",
+                                      "loss_first_last")})
+    return out
+
+
 def mlp_train_summary(n=291240, epochs=100, batch=2048):
     """Training rate of the warm-start network: n seeded synthetic points with
     the sweep's input shape (six features uniform in [-1, 1], four smooth
@@ -902,7 +914,8 @@ def main():
     # the side experiments report into the line; a failure in one of them is
     # recorded there and never costs the headline measurement
     for key, skip, fn in (("shear_wave", False, shear_wave_summary), ("shock", args.no_shock, shock_summary),
-                          ("mlp_train", args.no_sweep, mlp_train_summary)):
+                          ("mlp_train", args.no_sweep, mlp_train_summary),
+                          ("mlp_train_larger_minibatches", args.no_sweep, mlp_minibatch_summary)):
         if skip:
             continue
         try:
