@@ -354,6 +354,34 @@ __device__ __forceinline__ void load_all(const S *__restrict__ src, const S *__r
     load_bounded<S, BOUNDED>(src, gh, pull_map(x, y, z, sub, k), ghost_map<BOUNDED>(x, y, z, sub, k), k, v);
 }
 
+// The pull of one lane of a site pair (lane r = 0: the member +c of every
+// opposite pair, r = 1: the member -c): v[0] the rest population, v[1 + P] the
+// lane's member of pair P.  Both members' sources are computed and one
+// selected, so the two lanes run the same instructions.
+template <typename S, int BOUNDED, int P = 0>
+__device__ __forceinline__ void load_lane(const S *__restrict__ src, const S *__restrict__ gh, const PullMap &p,
+                                          const GhostMap<BOUNDED> &g, const Consts &k, int r, S *v)
+{
+    if constexpr (P == 0) v[0] = src[pull_off<0>(p)];   // c = 0 never crosses a face
+    if constexpr (P < NPAIR) {
+        constexpr int QP = 1 + P, QM = 1 + NPAIR + P;
+        const S *base;
+        size_t idx;
+        if constexpr (BOUNDED) {
+            int gp, gm;
+            const int ip = pull_index_b<QP, BOUNDED>(p, g, k, gp), im = pull_index_b<QM, BOUNDED>(p, g, k, gm);
+            const int ghost = r ? gm : gp;
+            base = ghost ? gh : src + (size_t)(r ? QM : QP) * k.ns;
+            idx = (size_t)(r ? im : ip);
+        } else {
+            base = src + (size_t)(r ? QM : QP) * k.ns;
+            idx = r ? pull_off<QM>(p) : pull_off<QP>(p);
+        }
+        v[1 + P] = base[idx];
+        load_lane<S, BOUNDED, P + 1>(src, gh, p, g, k, r, v);
+    }
+}
+
 // Sums over the stored values v (g, or h = g - w): rho, j, Pi.
 struct Mom {
     double rho, j[3], P[6];  // P: xx yy zz xy xz yz
@@ -390,6 +418,59 @@ __device__ __forceinline__ Mom moments(const S *v, const Consts &k)
     accumulate<S>(v, m);
     if (sizeof(S) == 4) {
         // deviations from w_i (rho0 = 1): add the moments of the weights
+        m.rho += 1.0;
+        m.P[0] += k.th0;
+        m.P[1] += k.th0;
+        m.P[2] += k.th0;
+    }
+    return m;
+}
+
+// value held by the other lane of a site pair (lane ^ 1), by a DPP quad
+// permutation [1, 0, 3, 2]; both lanes of the pair must be active
+__device__ __forceinline__ double pair_swap(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0xB1, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Moments of a site pulled by a lane pair (load_lane): each lane sums its own
+// members, the odd moments of the -c members change sign, and the pair adds
+// the two partial sums (x + y = y + x exactly, so both lanes hold the same bits).
+template <typename S, int P = 0>
+__device__ __forceinline__ void accumulate_lane(const S *v, Mom &m)
+{
+    if constexpr (P < NPAIR) {
+        constexpr int cx = Lattice::REP2[P][0], cy = Lattice::REP2[P][1], cz = Lattice::REP2[P][2];
+        const double a = (double)v[1 + P];
+        m.rho += a;
+        if (cx) m.j[0] += (0.5 * cx) * a;
+        if (cy) m.j[1] += (0.5 * cy) * a;
+        if (cz) m.j[2] += (0.5 * cz) * a;
+        if (cx) m.P[0] += (0.25 * cx * cx) * a;
+        if (cy) m.P[1] += (0.25 * cy * cy) * a;
+        if (cz) m.P[2] += (0.25 * cz * cz) * a;
+        if (cx * cy) m.P[3] += (0.25 * cx * cy) * a;
+        if (cx * cz) m.P[4] += (0.25 * cx * cz) * a;
+        if (cy * cz) m.P[5] += (0.25 * cy * cz) * a;
+        accumulate_lane<S, P + 1>(v, m);
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ Mom moments_pair(const S *v, const Consts &k, int r)
+{
+    Mom m;
+    m.rho = r ? 0.0 : (double)v[0];
+    m.j[0] = m.j[1] = m.j[2] = 0.0;
+    for (int i = 0; i < 6; i++) m.P[i] = 0.0;
+    accumulate_lane<S>(v, m);
+    for (int a = 0; a < 3; a++) m.j[a] = r ? -m.j[a] : m.j[a];
+    m.rho += pair_swap(m.rho);
+    for (int a = 0; a < 3; a++) m.j[a] += pair_swap(m.j[a]);
+    for (int i = 0; i < 6; i++) m.P[i] += pair_swap(m.P[i]);
+    if (sizeof(S) == 4) {
         m.rho += 1.0;
         m.P[0] += k.th0;
         m.P[1] += k.th0;
@@ -611,53 +692,52 @@ __device__ __forceinline__ void collide_store_e2(S *v, const double *l1, const d
     collide_e2_pairs<S>(v, p1, p2, k, dst, s);
 }
 
-// The same collide spread over the two lanes of a site pair (both hold v, l1
-// and l2): lane r stores the member +c (r = 0) or -c (r = 1) of every opposite
-// pair, lane 0 also the rest velocity; every population is the same bits as
-// in collide_store_e2.
+// The same collide spread over the two lanes of a site pair.  Lane r holds the
+// powers pw of its own final multipliers (r = 0: the lam_ES target, r = 1:
+// theta I) and stores the member +c (r = 0) or -c (r = 1) of every opposite
+// pair, lane 0 also the rest velocity.  Each lane forms the exponential of its
+// multipliers at both members and hands the partner the one the partner stores,
+// so each exponential is formed once, by the same instructions as in
+// collide_store_e2, and every population is the same bits.
 template <typename S, int P = 0>
-__device__ __forceinline__ void collide_e2_lane_pairs(const S *v, const E2Pow &p1, const E2Pow &p2, const Consts &k,
+__device__ __forceinline__ void collide_e2_lane_pairs(const S *v, const E2Pow &pw, const Consts &k,
                                                       S *__restrict__ dst, int s, int r)
 {
     if constexpr (P < NPAIR) {
-        double e1, x1p, x1m, e2, x2p, x2m;
-        e2_pair_exp<P>(p1, e1, x1p, x1m);
-        e2_pair_exp<P>(p2, e2, x2p, x2m);
-        const double x1 = r ? x1m : x1p, x2 = r ? x2m : x2p;
+        double e, xp, xm;
+        e2_pair_exp<P>(pw, e, xp, xm);
+        const double xo = r ? xm : xp, xg = r ? xp : xm;   // the own member, the partner's
         double w = k.w[Lattice::SHELL[P]];
         const size_t q = r ? 1 + NPAIR + P : 1 + P;
-        const S vq = r ? v[1 + NPAIR + P] : v[1 + P];
+        const S vq = v[1 + P];   // the lane's member (load_lane)
         if constexpr (sizeof(S) == 4) {
+            const double own = fma(e, xo, -1.0), got = pair_swap(fma(e, xg, -1.0));
+            const double t1 = r ? got : own, t2 = r ? own : got;   // ES term, theta I term
             S tb = (S)(2.0 * k.beta);
-            S F = (S)(w * (k.wt1 * fma(e1, x1, -1.0) + k.wt * fma(e2, x2, -1.0)));
+            S F = (S)(w * (k.wt1 * t1 + k.wt * t2));
             __builtin_nontemporal_store(vq + tb * (F - vq), &dst[q * k.ns + s]);
         } else {
+            const double own = e * xo, got = pair_swap(e * xg);
+            const double t1 = r ? got : own, t2 = r ? own : got;
             double omb = 1.0 - 2.0 * k.beta, tb = 2.0 * k.beta;
-            double F = w * (k.wt1 * (e1 * x1) + k.wt * (e2 * x2));
+            double F = w * (k.wt1 * t1 + k.wt * t2);
             __builtin_nontemporal_store(omb * vq + tb * F, &dst[q * k.ns + s]);
         }
-        collide_e2_lane_pairs<S, P + 1>(v, p1, p2, k, dst, s, r);
-    } else if (r == 0) {
-        double w0 = k.w[0];
-        if constexpr (sizeof(S) == 4) {
-            S tb = (S)(2.0 * k.beta);
-            S F0 = (S)(w0 * (k.wt1 * (p1.e0 - 1.0) + k.wt * (p2.e0 - 1.0)));
-            __builtin_nontemporal_store(v[0] + tb * (F0 - v[0]), &dst[s]);
-        } else {
-            double F0 = w0 * (k.wt1 * p1.e0 + k.wt * p2.e0);
-            __builtin_nontemporal_store((1.0 - 2.0 * k.beta) * v[0] + 2.0 * k.beta * F0, &dst[s]);
+        collide_e2_lane_pairs<S, P + 1>(v, pw, k, dst, s, r);
+    } else {
+        const double e2o = pair_swap(pw.e0);   // lane 0 receives theta I's exp(l0)
+        if (r == 0) {
+            double w0 = k.w[0];
+            if constexpr (sizeof(S) == 4) {
+                S tb = (S)(2.0 * k.beta);
+                S F0 = (S)(w0 * (k.wt1 * (pw.e0 - 1.0) + k.wt * (e2o - 1.0)));
+                __builtin_nontemporal_store(v[0] + tb * (F0 - v[0]), &dst[s]);
+            } else {
+                double F0 = w0 * (k.wt1 * pw.e0 + k.wt * e2o);
+                __builtin_nontemporal_store((1.0 - 2.0 * k.beta) * v[0] + 2.0 * k.beta * F0, &dst[s]);
+            }
         }
     }
-}
-
-template <typename S>
-__device__ __forceinline__ void collide_store_e2_lane(const S *v, const double *l1, const double *l2,
-                                                      const Consts &k, S *__restrict__ dst, int s, int r)
-{
-    E2Pow p1, p2;
-    e2_pow_bases(l1, p1);
-    e2_pow_bases(l2, p2);
-    collide_e2_lane_pairs<S>(v, p1, p2, k, dst, s, r);
 }
 
 // E2 multipliers of density rho, velocity u, covariance lam; a target out of
@@ -773,12 +853,15 @@ __device__ __forceinline__ Mom lb_site(int s, const S *__restrict__ src, S *__re
 }
 
 // E2 with the two Newton solves of site s on a pair of adjacent lanes (r = 0:
-// the lam_ES target, r = 1: theta I).  Both lanes pull the site and solve its
+// the lam_ES target, r = 1: theta I).  Each lane pulls the rest population
+// and one member of every opposite pair (the one it later stores), the pair
+// adds the two lanes' moment sums, and both lanes solve the site's
 // temperatures; each runs one Newton solve from its multipliers of the last
-// step (lmul, [2 E2_NL][ns], never null here); the pair swaps the results,
-// collides with each lane storing one member of every opposite pair, and lane
-// 0 hands the fields to the transport.
-// The arithmetic per site is that of lb_site<..., PGK_E2>.
+// step (lmul, [2 E2_NL][ns], never null here); the pair collides with each
+// lane storing its members (the exponentials of each solve formed by its own
+// lane and passed across), and lane 0 hands the fields to the transport.
+// The arithmetic per site is that of lb_site<..., PGK_E2> but for the order
+// in which the moments are summed.
 template <typename S, typename A, int VAR, int BOUNDED>
 __device__ __forceinline__ void lb_site_e2pair(int s, int r, const S *__restrict__ src, S *__restrict__ dst,
                                                const S *__restrict__ gh, double *__restrict__ thR,
@@ -787,10 +870,12 @@ __device__ __forceinline__ void lb_site_e2pair(int s, int r, const S *__restrict
 {
     int x, y, z, sub;
     decode(s, k, x, y, z, sub);
-    S v[NQ];
-    if constexpr (BOUNDED) load_all<S, BOUNDED>(src, gh, x, y, z, sub, k, v);
-    else load_periodic<S>(src, pull_map(x, y, z, sub, k), k.ns, v);
-    Mom m = moments<S>(v, k);
+    S v[1 + NPAIR];   // the rest population and the lane's member of every pair
+    if constexpr (BOUNDED)
+        load_lane<S, BOUNDED>(src, gh, pull_map(x, y, z, sub, k), ghost_map<BOUNDED>(x, y, z, sub, k), k, r, v);
+    else
+        load_lane<S, BOUNDED>(src, gh, pull_map(x, y, z, sub, k), GhostMap<BOUNDED>{}, k, r, v);
+    Mom m = moments_pair<S>(v, k, r);
     Solve so = site_solve(m, thR[s], k);
     double lam[6], l[E2_NL];
     double cb = k.bs / so.rho;
@@ -800,13 +885,9 @@ __device__ __forceinline__ void lb_site_e2pair(int s, int r, const S *__restrict
     for (int i = 0; i < E2_NL; i++) l[i] = lm[(size_t)i * k.ns];
     e2_site_from(so.rho, so.u, lam, k, l);
     for (int i = 0; i < E2_NL; i++) lm[(size_t)i * k.ns] = l[i];
-    double l1[E2_NL], l2[E2_NL];
-    for (int i = 0; i < E2_NL; i++) {
-        double o = __shfl_xor(l[i], 1);
-        l1[i] = r == 0 ? l[i] : o;
-        l2[i] = r == 0 ? o : l[i];
-    }
-    collide_store_e2_lane<S>(v, l1, l2, k, dst, s, r);
+    E2Pow pw;
+    e2_pow_bases(l, pw);
+    collide_e2_lane_pairs<S>(v, pw, k, dst, s, r);
     if (r != 0) return;
     that_[s] = so.R;
     if (VAR == PGK_LIT) thR[s] = so.T;
