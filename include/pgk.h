@@ -262,7 +262,7 @@ int pgk_set_transport_reference(pgk_ctx *ctx, int on);
  * transport kernel, advection + diffusion + second half), [2] the diffusion
  * and second half relaxation (on a bounded or sub-cycled line, ny = nz = 1,
  * with at most 63 sub-steps: the whole transport in one launch of work-groups
- * of WG threads, each producing WG - 2 (n_sub + 1) cells, WG = 128 up to 15
+ * of WG threads, each producing WG - 2 (n_sub + 1) cells, WG = 64 up to 15
  * sub-steps and 256 beyond; on another bounded
  * or sub-cycled grid of at most 4096 sites:
  * the whole transport in one work-group), [3] the ghost fill of the bounded faces, and clears the

@@ -122,8 +122,8 @@ __global__ __launch_bounds__(TR_SMALL_WG) void k_tr_small(const double *__restri
 // independent 1D problems, one per sublattice.  A work-group of WG threads owns
 // WG - 2 H cells of one sublattice and stages them with a halo of H = nsub + 1
 // cells on each side (theta_hat, u_x, rho, kfac rho theta), WG cells in all so
-// that every thread holds one window cell (WG = 128 while the halos take at
-// most a quarter of it, else 256); MacCormack and every FTCS
+// that every thread holds one window cell (WG = 64, one wavefront, while the
+// halos take at most half of it, else 256); MacCormack and every FTCS
 // sub-step then run in LDS, the valid window shrinking by one cell per stage,
 // so the halo cells are recomputed by both neighbours and no work-group waits
 // for another.  The y and z terms of the stencils of mc_site / dif_site vanish
@@ -136,7 +136,7 @@ constexpr int TL_HMAX = 64;
 // work-group size of k_tr_line for nsub sub-steps, and the cells of a line each
 // work-group produces (its window: these and a halo of nsub + 1 cells on each
 // side, one per thread)
-__host__ __device__ inline int tl_wg(int nsub) { return 2 * (nsub + 1) <= 32 ? 128 : 256; }
+__host__ __device__ inline int tl_wg(int nsub) { return 2 * (nsub + 1) <= 32 ? 64 : 256; }
 __host__ __device__ inline int tl_cells(int nsub, int wg) { return wg - 2 * (nsub + 1); }
 
 template <typename A, int VAR, int BOUNDED, int TL_WG>
@@ -161,6 +161,16 @@ __global__ __launch_bounds__(TL_WG) void k_tr_line(const double *__restrict__ th
         x %= nx;
         return x < 0 ? x + nx : x;
     };
+    // theta_R of the cell this thread updates in the last stage (cell
+    // tid + 1 + nsub: the stages' cell ranges shift by one each), read now so
+    // that its latency overlaps the staging and the sub-steps
+    double thR_old = 0.0;
+    {
+        const int i = tid + 1 + k.nsub;
+        bool in = false;
+        const int x = i < Lw - 1 - k.nsub ? cell(i, in) : 0;
+        if (in) thR_old = thR[base + x];
+    }
     for (int i = tid; i < Lw; i += TL_WG) {
         bool in;
         int x = cell(i, in);
@@ -229,7 +239,7 @@ __global__ __launch_bounds__(TL_WG) void k_tr_line(const double *__restrict__ th
                 tout[i] = tdif;
             } else {
                 int s = base + x;
-                double v = thR[s];
+                const double v = thR_old;   // this is the thread's cell tid + 1 + nsub
                 if (VAR == PGK_CN) thR[s] = tdif + (l_th[i] - v);
                 else thR[s] = (tdif + k.X * v) * k.inv1X;
             }
@@ -1140,8 +1150,8 @@ static int step_t(pgk_ctx *c, int64_t n)
         if (!c->transport_ref && (BND || c->k.nsub > 1) && c->k.ny == 1 && c->k.nz == 1 &&
             c->k.nsub + 1 <= TL_HMAX) {
             const int wg = tl_wg(c->k.nsub), C = tl_cells(c->k.nsub, wg), nchunk = (c->k.nx + C - 1) / C;
-            if (wg == 128)
-                hipLaunchKernelGGL((k_tr_line<A, VAR, BND, 128>), dim3(2 * nchunk), dim3(128), 0, c->stream,
+            if (wg == 64)
+                hipLaunchKernelGGL((k_tr_line<A, VAR, BND, 64>), dim3(2 * nchunk), dim3(64), 0, c->stream,
                                    c->that_, (const A *)c->aux, (double *)c->buf[PGK_BUF_THETAR], c->k);
             else
                 hipLaunchKernelGGL((k_tr_line<A, VAR, BND, 256>), dim3(2 * nchunk), dim3(256), 0, c->stream,

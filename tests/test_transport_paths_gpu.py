@@ -100,9 +100,11 @@ def _nu_for_substeps(n, th_max):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_line_kernel_at_its_sub_step_limit(precision):
-    """Lines between walls at 63 sub-steps (the line kernel's limit: each
-    work-group then produces 256 - 128 = 128 cells, so a 2100-cell line takes
-    17 work-groups per sublattice) and at 64 (beyond it; with 4200 sites, more
+    """Lines between walls at 15 and 16 sub-steps (the last count with
+    one-wavefront windows, each producing 64 - 32 = 32 cells, and the first
+    with 256-thread windows), at 63 (the line kernel's limit: each work-group
+    then produces 256 - 128 = 128 cells, so a 2100-cell line takes 17
+    work-groups per sublattice) and at 64 (beyond it; with 4200 sites, more
     than the one-work-group kernel takes, the reference kernels run): the
     timing records show which path ran, and the line kernel matches the
     reference kernels to round-off."""
@@ -111,7 +113,7 @@ def test_line_kernel_at_its_sub_step_limit(precision):
     walls = [(pgk.WALL, 1.0, (0.0, 0.0, 0.0), 0.95 * th0), (pgk.WALL, 1.0, (0.0, 0.03, 0.0), 1.05 * th0)]
     bar = 1e-13 if precision == 0 else 1e-6
     dims, steps = (2100, 1, 1), 12
-    for n in (63, 64):
+    for n in (15, 16, 63, 64):
         p = resolve(_nu_for_substeps(n, 1.05 * th0), 0.71, 0.8, 2.0)
         f = inputs.random_smooth(*dims, seed=n, amp_u=0.03, amp_th=0.05)
         s = pgk.Solver(*dims, precision=precision, bc_x=(pgk.WALL, pgk.WALL))
