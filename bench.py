@@ -209,11 +209,13 @@ def single_grid_run(case, fields, tol, max_steps, time_cap=1e30, K=128, stream=N
         s.step(1)
         b = s.moments()
         steps += K
-        resid = 0.0
+        rs = []
         for k, v in (("rho", None), ("u", axis), ("thT", None), ("thR", None)):
             x0 = a[k] if v is None else a[k][v]
             x1 = b[k] if v is None else b[k][v]
-            resid = max(resid, float(np.linalg.norm(x1 - x0) / max(np.linalg.norm(x1), 1e-300)))
+            rs.append(float(np.linalg.norm(x1 - x0) / max(np.linalg.norm(x1), 1e-300)))
+        # max() would pass over a NaN that is not its first argument
+        resid = max(rs) if np.isfinite(rs).all() else float("nan")
         if not np.isfinite(resid):
             status = 2
             break
@@ -297,7 +299,8 @@ def shock_summary(max_steps=60000):
         for k, v in (("rho", None), ("u", 0), ("thT", None), ("thR", None)):
             x0 = a[k] if v is None else a[k][v]
             x1 = b[k] if v is None else b[k][v]
-            r = max(r, float(np.linalg.norm(x1 - x0) / np.linalg.norm(x1)))
+            d = float(np.linalg.norm(x1 - x0) / np.linalg.norm(x1))
+            r = max(r, d) if d == d else d   # a NaN stays NaN
         return r
 
     out = {"cells": L, "sites": 2 * L, "equilibrium": "E2", "delta": 2.0, "Pr": 0.71, "mu_b/mu": 0.8,

@@ -435,48 +435,31 @@ __device__ __forceinline__ double pair_swap(double v)
     return __hiloint2double(hi, lo);
 }
 
-// Moments of a site pulled by a lane pair (load_lane): each lane sums its own
-// members, the odd moments of the -c members change sign, and the pair adds
-// the two partial sums (x + y = y + x exactly, so both lanes hold the same bits).
-template <typename S, int P = 0>
-__device__ __forceinline__ void accumulate_lane(const S *v, Mom &m)
+// Moments of a site pulled by a lane pair (load_lane): each lane receives the
+// partner's members by DPP and sums all 41 values as moments() does, so both
+// lanes hold the same bits as a lane that pulled the whole site.
+template <typename S>
+__device__ __forceinline__ S pair_swap_s(S v)
 {
-    if constexpr (P < NPAIR) {
-        constexpr int cx = Lattice::REP2[P][0], cy = Lattice::REP2[P][1], cz = Lattice::REP2[P][2];
-        const double a = (double)v[1 + P];
-        m.rho += a;
-        if (cx) m.j[0] += (0.5 * cx) * a;
-        if (cy) m.j[1] += (0.5 * cy) * a;
-        if (cz) m.j[2] += (0.5 * cz) * a;
-        if (cx) m.P[0] += (0.25 * cx * cx) * a;
-        if (cy) m.P[1] += (0.25 * cy * cy) * a;
-        if (cz) m.P[2] += (0.25 * cz * cz) * a;
-        if (cx * cy) m.P[3] += (0.25 * cx * cy) * a;
-        if (cx * cz) m.P[4] += (0.25 * cx * cz) * a;
-        if (cy * cz) m.P[5] += (0.25 * cy * cz) * a;
-        accumulate_lane<S, P + 1>(v, m);
+    if constexpr (sizeof(S) == 8) {
+        return pair_swap(v);
+    } else {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
     }
 }
 
 template <typename S>
 __device__ __forceinline__ Mom moments_pair(const S *v, const Consts &k, int r)
 {
-    Mom m;
-    m.rho = r ? 0.0 : (double)v[0];
-    m.j[0] = m.j[1] = m.j[2] = 0.0;
-    for (int i = 0; i < 6; i++) m.P[i] = 0.0;
-    accumulate_lane<S>(v, m);
-    for (int a = 0; a < 3; a++) m.j[a] = r ? -m.j[a] : m.j[a];
-    m.rho += pair_swap(m.rho);
-    for (int a = 0; a < 3; a++) m.j[a] += pair_swap(m.j[a]);
-    for (int i = 0; i < 6; i++) m.P[i] += pair_swap(m.P[i]);
-    if (sizeof(S) == 4) {
-        m.rho += 1.0;
-        m.P[0] += k.th0;
-        m.P[1] += k.th0;
-        m.P[2] += k.th0;
+    S w[NQ];
+    w[0] = v[0];
+#pragma unroll
+    for (int P = 0; P < NPAIR; P++) {
+        const S o = pair_swap_s(v[1 + P]);
+        w[1 + P] = r ? o : v[1 + P];
+        w[1 + NPAIR + P] = r ? v[1 + P] : o;
     }
-    return m;
+    return moments<S>(w, k);
 }
 
 // Per-site solve (Sec. 5): g->f temperature map with the backward-Euler half
@@ -854,14 +837,13 @@ __device__ __forceinline__ Mom lb_site(int s, const S *__restrict__ src, S *__re
 
 // E2 with the two Newton solves of site s on a pair of adjacent lanes (r = 0:
 // the lam_ES target, r = 1: theta I).  Each lane pulls the rest population
-// and one member of every opposite pair (the one it later stores), the pair
-// adds the two lanes' moment sums, and both lanes solve the site's
+// and one member of every opposite pair (the one it later stores), receives
+// the other members from its partner, and both lanes solve the site's
 // temperatures; each runs one Newton solve from its multipliers of the last
 // step (lmul, [2 E2_NL][ns], never null here); the pair collides with each
 // lane storing its members (the exponentials of each solve formed by its own
 // lane and passed across), and lane 0 hands the fields to the transport.
-// The arithmetic per site is that of lb_site<..., PGK_E2> but for the order
-// in which the moments are summed.
+// The arithmetic per site is that of lb_site<..., PGK_E2>.
 template <typename S, typename A, int VAR, int BOUNDED>
 __device__ __forceinline__ void lb_site_e2pair(int s, int r, const S *__restrict__ src, S *__restrict__ dst,
                                                const S *__restrict__ gh, double *__restrict__ thR,

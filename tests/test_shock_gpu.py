@@ -58,7 +58,8 @@ def _resid(a, b):
     for k, v in (("rho", None), ("u", 0), ("thT", None), ("thR", None)):
         x0 = a[k] if v is None else a[k][v]
         x1 = b[k] if v is None else b[k][v]
-        r = max(r, float(np.linalg.norm(x1 - x0) / np.linalg.norm(x1)))
+        d = float(np.linalg.norm(x1 - x0) / np.linalg.norm(x1))
+        r = max(r, d) if d == d else d   # a NaN stays NaN
     return r
 
 
@@ -167,3 +168,31 @@ def test_full_size_shock_reaches_its_steady_state():
     assert abs(pos[-1] - pos[-2]) < 1e-3   # cells moved over the last 5000 steps
     _, thick = profile_metrics(x, b["rho"], up, down)
     print("steady shock", done, r, pos[-1], thick)
+
+
+def test_fast_inflow_line_stays_on_the_oracle():
+    """A Mach 2.31 line with its upstream at theta0 (inflow speed 1.49, near the
+    end of what E2 reaches at theta0; nu 2.71, Pr 0.71, mu_b/mu 1.75, 2621
+    cells, 24 diffusion sub-steps) from the tanh start: after 576 FP64 steps the
+    line is finite and on the oracle.  A lane-pair kernel that summed each
+    lane's populations first and added the two sums (other last bits in the
+    moments) turned this line NaN between steps 512 and 576; the lane pair
+    sums the moments as one lane does."""
+    import paper_2201_05280_amd as pgk
+    from paper_2201_05280_amd.shock import discrete_rankine_hugoniot, tanh_profile
+    L, Ma, steps = 2621, 2.312666544905132, 576
+    up, down = discrete_rankine_hugoniot(Ma, 2.0, oracle.THETA0)
+    p = resolve(2.713688893895381, 0.7100164850878086, 1.7524045176004193, 2.0)
+    f = tanh_profile(L, up, down)
+    s = _solver(L, pgk.FP64, up, down, p, f)
+    s.step(steps)
+    g = s.moments()
+    s.close()
+    for k in ("rho", "thT", "thR"):
+        assert np.isfinite(g[k]).all(), k
+    o = _oracle(L, up, down, p, f)
+    o.step(steps)
+    e = _rel(g, o.moments())
+    print("Mach 2.31 line after", steps, "steps:", e)
+    for k, v in e.items():
+        assert v <= 1e-12, (k, v)
